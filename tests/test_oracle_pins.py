@@ -1,0 +1,322 @@
+"""Pins of the FP64 oracle against what the mathematics fixes.
+
+Each test checks the oracle against something other than itself: a direct
+O(N^6) DFT, closed forms (free electrons, a single Fourier component, the
+rank-1 secular equation), brute-force enumeration, exact invariants
+(translation by a grid vector, time reversal, reciprocal-lattice shift,
+Cauchy interlacing), LAPACK dense diagonalisation, and central finite
+differences.  A plausible slip in the oracle (a sign, an index, a dropped
+term, a transposed operand) fails at least one of them.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import davidson as dv
+from oracle import grid as gr
+from oracle import gsphere as gs
+from oracle import hamiltonian as ham
+from oracle import mlp
+
+
+def _rand_c(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+# ---------------------------------------------------------------- FFT grid
+@pytest.mark.parametrize("shape", [(4, 4, 4), (6, 6, 6), (3, 5, 8), (5, 9, 15)])
+def test_fft_matches_direct_sum(shape):
+    rng = np.random.default_rng(11)
+    g = _rand_c(rng, shape)
+    u = gr.inv_fft(g)
+    ud = gr.dft_direct(g, +1)
+    assert np.abs(u - ud).max() <= 1e-13 * np.abs(ud).max()
+    c = gr.fwd_fft(u)
+    cd = gr.dft_direct(u, -1) / u.size
+    assert np.abs(c - cd).max() <= 1e-13 * np.abs(cd).max()
+
+
+def test_fft_9cubed_direct_sum():
+    rng = np.random.default_rng(12)
+    g = _rand_c(rng, (9, 9, 9))
+    assert np.allclose(gr.inv_fft(g), gr.dft_direct(g, +1), rtol=0, atol=1e-11)
+
+
+def test_fft_roundtrip_and_parseval():
+    rng = np.random.default_rng(13)
+    g = _rand_c(rng, (24, 30, 20))
+    u = gr.inv_fft(g)
+    assert np.abs(gr.fwd_fft(u) - g).max() < 1e-13
+    # Parseval: sum_r |u|^2 = N^3 sum_G |c|^2
+    lhs = np.sum(np.abs(u) ** 2)
+    rhs = g.size * np.sum(np.abs(g) ** 2)
+    assert abs(lhs - rhs) <= 1e-13 * rhs
+
+
+def test_sphere_grid_roundtrip_zero_outside():
+    c = synth.make_cell(1)
+    m = gs.gsphere(c.A, c.kpts[0], c.ecut_ha)
+    rng = np.random.default_rng(3)
+    v = _rand_c(rng, len(m))
+    g = gr.sphere_to_grid(v, m, c.nr)
+    assert np.count_nonzero(g) == len(m)
+    assert np.array_equal(gr.grid_to_sphere(g, m, c.nr), v)
+
+
+# ---------------------------------------------------------------- sphere
+def test_sphere_count_cubic_gamma_column_formula():
+    """cfg1: |G|^2 < ecut_Ry with G = 2 pi n / a  <=>  n^2 <= 37 (integer)."""
+    c = synth.make_cell(1)
+    m = gs.gsphere(c.A, c.kpts[0], c.ecut_ha)
+    limit = 2.0 * c.ecut_ha * (10.0 / (2 * math.pi)) ** 2
+    nmax2 = int(math.floor(limit))
+    assert nmax2 == 37
+    count = 0
+    for h in range(-7, 8):
+        for k in range(-7, 8):
+            r = nmax2 - h * h - k * k
+            if r >= 0:
+                count += 2 * math.isqrt(r) + 1
+    assert len(m) == count == 949
+
+
+def test_sphere_bruteforce_general_cell():
+    rng = np.random.default_rng(5)
+    A = np.array([[5.0, 0.3, -0.2], [0.7, 6.1, 0.4], [-0.5, 0.2, 4.4]])
+    for _ in range(3):
+        k = rng.uniform(-0.5, 0.5, 3)
+        ecut = 3.0
+        m = gs.gsphere(A, k, ecut)
+        B = 2 * np.pi * np.linalg.inv(A).T
+        brute = set()
+        for h, kk, l in itertools.product(range(-12, 13), repeat=3):
+            q = (np.array([h, kk, l]) + k) @ B
+            if 0.5 * float(q @ q) < ecut:
+                brute.add((h, kk, l))
+        assert set(map(tuple, m.tolist())) == brute
+        t = gs.kinetic(A, k, m)
+        assert np.all(np.diff(t) >= -1e-12 * t.max())
+
+
+# ---------------------------------------------------------------- H closed forms
+def _tiny_problem(kfrac=(0.0, 0.0, 0.0), full_d=False, seed=7):
+    c = synth.make_cell(0, seed=seed)
+    if full_d:
+        c.lmax = np.full(c.natom, 2, dtype=np.int32)
+        rng = np.random.default_rng(seed + 100)
+        c.dij = synth.cells._dij(rng, c.lmax, full=True)
+    c.kpts = np.array([kfrac], dtype=np.float64)
+    return c, ham.problem_from_cell(c)
+
+
+def test_free_electrons_constant_potential():
+    c, p = _tiny_problem(kfrac=(0.13, -0.21, 0.37))
+    v0 = -0.731
+    p.vloc = np.full(p.vloc.shape, v0)
+    p.beta = np.zeros((0, p.npw), dtype=np.complex128)
+    p.proj_offset = np.zeros(1, dtype=np.int32)
+    p.dij = []
+    t = p.kinetic()
+    w = np.linalg.eigvalsh(ham.dense_h(p))
+    assert np.abs(w - np.sort(t + v0)).max() < 1e-13
+    rng = np.random.default_rng(1)
+    psi = _rand_c(rng, (3, p.npw))
+    assert np.abs(ham.hpsi(p, psi) - (t + v0) * psi).max() < 1e-12
+
+
+def test_single_fourier_component_sign():
+    """V = a cos(2 pi j0/N0) + b sin(2 pi j0/N0): V~(+x) = (a - ib)/2, V~(-x) = (a + ib)/2."""
+    c, p = _tiny_problem()
+    a, b = 0.4, -0.9
+    j0 = np.arange(p.nr[0])[:, None, None]
+    p.vloc = np.broadcast_to(a * np.cos(2 * np.pi * j0 / p.nr[0]) + b * np.sin(2 * np.pi * j0 / p.nr[0]),
+                             p.nr).copy()
+    p.beta = np.zeros((0, p.npw), dtype=np.complex128)
+    p.proj_offset = np.zeros(1, dtype=np.int32)
+    p.dij = []
+    m = p.miller.tolist()
+    i0 = m.index([0, 0, 0])
+    ip = m.index([1, 0, 0])
+    im = m.index([-1, 0, 0])
+    e = np.zeros((1, p.npw), dtype=np.complex128)
+    e[0, i0] = 1.0
+    out = ham.hpsi(p, e)[0]
+    assert abs(out[ip] - (a - 1j * b) / 2) < 1e-14
+    assert abs(out[im] - (a + 1j * b) / 2) < 1e-14
+    h = ham.dense_h(p)
+    assert abs(h[ip, i0] - (a - 1j * b) / 2) < 1e-14
+    assert abs(h[im, i0] - (a + 1j * b) / 2) < 1e-14
+
+
+def test_rank1_projector_secular_equation():
+    """V = 0, one projector, D = d: eigenvalues solve 1 = d sum_G |b(G)|^2 / (e - t_G)."""
+    c, p = _tiny_problem()
+    rng = np.random.default_rng(9)
+    beta = _rand_c(rng, p.npw)
+    beta /= np.linalg.norm(beta)
+    d = 0.63
+    p.vloc = np.zeros(p.vloc.shape)
+    p.beta = beta[None, :]
+    p.proj_offset = np.array([0, 1], dtype=np.int32)
+    p.dij = [np.array([[d]])]
+    t = p.kinetic()
+    w = np.linalg.eigvalsh(ham.dense_h(p))
+    levels = np.unique(np.round(t, 12))
+
+    def f(e):
+        return 1.0 - d * np.sum(np.abs(beta) ** 2 / (e - t))
+
+    for lo, hi in zip(levels[:4], levels[1:5]):
+        a_, b_ = lo + 1e-13, hi - 1e-13
+        for _ in range(200):
+            mid = 0.5 * (a_ + b_)
+            if f(mid) > 0:   # f increases from -inf to 1 across the interval
+                b_ = mid
+            else:
+                a_ = mid
+        root = 0.5 * (a_ + b_)
+        assert np.min(np.abs(w - root)) < 1e-12
+
+
+def test_hermiticity_of_hpsi():
+    c, p = _tiny_problem(kfrac=(0.2, 0.1, -0.3), full_d=True)
+    rng = np.random.default_rng(2)
+    phi = _rand_c(rng, (1, p.npw))
+    psi = _rand_c(rng, (1, p.npw))
+    lhs = np.vdot(phi[0], ham.hpsi(p, psi)[0])
+    rhs = np.conj(np.vdot(psi[0], ham.hpsi(p, phi)[0]))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+@pytest.mark.parametrize("cfg", [0, 1])
+def test_hpsi_equals_dense_matrix(cfg):
+    c = synth.make_cell(cfg)
+    p = ham.problem_from_cell(c)
+    psi = synth.psi_start(c.seed, 5, p.npw)
+    ref = (ham.dense_h(p) @ psi.T).T
+    assert np.abs(ham.hpsi(p, psi) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_hpsi_equals_dense_full_d_kpoint():
+    c, p = _tiny_problem(kfrac=(0.31, -0.17, 0.05), full_d=True)
+    psi = synth.psi_start(3, 4, p.npw)
+    ref = (ham.dense_h(p) @ psi.T).T
+    assert np.abs(ham.hpsi(p, psi) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------- invariants
+def _eigs(cell, ik=0, nb=10):
+    p = ham.problem_from_cell(cell, ik)
+    return np.linalg.eigvalsh(ham.dense_h(p))[:nb]
+
+
+def test_translation_by_grid_vector():
+    c = synth.make_cell(0)
+    e0 = _eigs(c)
+    shift = np.array([1, 2, 3]) * (np.diag(c.A) / np.array(c.nr))
+    c.pos = c.pos + shift[None, :]
+    assert np.abs(_eigs(c) - e0).max() < 1e-12
+
+
+def test_time_reversal_and_reciprocal_shift():
+    c = synth.make_cell(0)
+    k = np.array([0.17, -0.31, 0.23])
+    c.kpts = np.array([k, -k, k + np.array([1.0, 0.0, 0.0])])
+    e = [_eigs(c, ik) for ik in range(3)]
+    assert np.abs(e[0] - e[1]).max() < 1e-12
+    assert np.abs(e[0] - e[2]).max() < 1e-12
+
+
+# ---------------------------------------------------------------- Davidson
+@pytest.mark.parametrize("cfg", [0, 1])
+def test_davidson_matches_dense_eigh(cfg):
+    c = synth.make_cell(cfg)
+    p = ham.problem_from_cell(c)
+    nb = c.nbands
+    w, _ = ham.eigh_lowest(p, nb)
+    r = dv.davidson(p, synth.psi_start(c.seed, nb, p.npw), nb, tol=5e-9)
+    assert r["converged"]
+    assert np.abs(r["theta"] - w).max() < 1e-10
+    # residual bound |theta - lambda| <= rho (Weyl / Bauer-Fike for Hermitian H)
+    assert np.all(np.abs(r["theta"] - w) <= r["rho"] + 1e-13)
+    # Cauchy interlacing: Ritz values never increase from one iteration to the next
+    th = np.array([h[0] for h in r["history"]])
+    assert np.all(np.diff(th, axis=0) <= 1e-12)
+    X = r["X"]
+    assert np.abs(X.conj().T @ X - np.eye(nb)).max() < 1e-12
+
+
+def test_davidson_without_preconditioner_same_answer():
+    c = synth.make_cell(0)
+    p = ham.problem_from_cell(c)
+    w, _ = ham.eigh_lowest(p, c.nbands)
+    r = dv.davidson(p, synth.psi_start(c.seed, c.nbands, p.npw), c.nbands, 5e-9, precond="none")
+    assert np.abs(r["theta"] - w).max() < 1e-10
+
+
+def test_orthonormalize_drops_dependent_columns():
+    rng = np.random.default_rng(4)
+    T = _rand_c(rng, (50, 4))
+    T = np.concatenate([T, T[:, :1] * (2 - 1j)], axis=1)
+    Q = dv.orthonormalize(T)
+    assert Q.shape[1] == 4
+    assert np.abs(Q.conj().T @ Q - np.eye(4)).max() < 1e-12
+
+
+def test_tpa_closed_form_properties():
+    assert dv.tpa_k(0.0) == 1.0
+    x = np.linspace(0, 50, 2001)
+    k = dv.tpa_k(x)
+    assert np.all(np.diff(k) < 0)
+    big = np.array([1e3, 1e4])
+    assert np.allclose(dv.tpa_k(big) * 2 * big, 1.0, rtol=2e-3)
+
+
+# ---------------------------------------------------------------- MLP
+def test_mlp_gradient_central_differences():
+    rng = np.random.default_rng(21)
+    p = mlp.init_params(3)
+    npw, nbd = 40, 3
+    F = rng.standard_normal((npw * nbd, 4))
+    R = _rand_c(rng, (npw, nbd))
+    D = _rand_c(rng, (npw, nbd))
+    loss, g = mlp.batch_loss_grad(p, F, R, D)
+    h = 1e-6
+    for name in p:
+        flat = p[name].reshape(-1)
+        idx = rng.choice(flat.size, size=min(6, flat.size), replace=False)
+        for i in idx:
+            old = flat[i]
+            flat[i] = old + h
+            lp, _ = mlp.batch_loss_grad(p, F, R, D)
+            flat[i] = old - h
+            lm, _ = mlp.batch_loss_grad(p, F, R, D)
+            flat[i] = old
+            fd = (lp - lm) / (2 * h)
+            an = g[name].reshape(-1)[i]
+            assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)) + 1e-9, (name, i, fd, an)
+
+
+def test_mlp_loss_is_scale_invariant_and_zero_at_target():
+    rng = np.random.default_rng(22)
+    R = _rand_c(rng, 30)
+    s = rng.uniform(0.5, 2.0, 30)
+    l1, _ = mlp.band_loss_grad(s, R, s * R * (0.3 - 0.2j))
+    assert abs(l1) < 1e-14
+    d = _rand_c(rng, 30)
+    la, _ = mlp.band_loss_grad(s, R, d)
+    lb, _ = mlp.band_loss_grad(3.7 * s, R, d)
+    assert abs(la - lb) < 1e-14 and 0.0 <= la <= 1.0
+
+
+def test_adam_first_step_closed_form():
+    p = {"w": np.array([1.0, -2.0, 0.5])}
+    g = {"w": np.array([0.3, -4.0, 1e-3])}
+    st = {}
+    mlp.adam_step(p, g, st, lr=1e-2)
+    # first step: m_hat = g, v_hat = g^2 -> update = -lr g / (|g| + eps)
+    exp = np.array([1.0, -2.0, 0.5]) - 1e-2 * g["w"] / (np.abs(g["w"]) + 1e-8)
+    assert np.allclose(p["w"], exp, rtol=0, atol=1e-15)
