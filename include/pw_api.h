@@ -1,0 +1,207 @@
+/*
+ * pw_api.h -- C ABI of the MI355X plane-wave H*psi / block-Davidson library
+ * (libpwhip.so, gfx950).
+ *
+ * The operator is the scalar, norm-conserving reduction (one spin
+ * component, S = 1, no augmentation) of the Kohn-Sham equation the paper
+ * writes in its fully relativistic PAW section (eq. pauli_ks):
+ *
+ *   H = p^2/2 + V_LOC(r) + sum_I sum_mn D_I,mn |beta_m^I><beta_n^I|
+ *
+ * in Hartree atomic units, acting on bands expanded in plane waves
+ * c_{k,n}(G) (section "New parallelization levels": the largest array).
+ * The local term is applied on an FFT grid (the exchange paragraph's grid
+ * rule: G up to 2 G_c), the nonlocal term through the scalar products
+ * p_ij = <beta_j|psi_i> (same section), and the lowest bands are found by
+ * a Davidson-like iteration with subspace diagonalisation (the paper cites
+ * Davidson 1975 and names subspace diagonalisation as PWscf's dominant
+ * dense linear-algebra step).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns pw_status; 0 is success.  Negative values are
+ *     errors; PW_NOT_CONVERGED (1) is a non-fatal outcome.  No C++
+ *     exception crosses this boundary.  pw_last_error() returns a
+ *     thread-local message for the last non-OK status of the calling thread.
+ *   - Argument checks run on the host, synchronously, before any launch.
+ *   - Complex numbers are interleaved (re, im) doubles (complex128), the
+ *     layout of C99 double _Complex and of torch.complex128.
+ *   - Band blocks are band-major: element G of band n sits at
+ *     ptr[n * ld + G], ld >= npw.  Padding columns G >= npw are neither read
+ *     nor written.
+ *   - "device" pointers are HIP device memory on the current device;
+ *     "host" pointers are ordinary host memory.  The caller owns every
+ *     pointer it passes.  The library never frees caller memory; it owns
+ *     only what it allocates inside a handle (maps, twiddles, a reordered
+ *     copy of V_LOC, reduced-precision copies of beta, work buffers), all
+ *     released by the matching destroy call.
+ *   - stream: a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work of a call is enqueued on that stream; calls return
+ *     without waiting for it unless stated.  Buffers must stay valid until
+ *     the stream has reached the end of the call's work.
+ *   - Units: Hartree and bohr.  A cutoff given in Rydberg as ecutwfc is
+ *     ecut = ecutwfc / 2 here.
+ */
+#ifndef PW_API_H
+#define PW_API_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pw_status;
+#define PW_OK 0
+#define PW_NOT_CONVERGED 1
+#define PW_ERR_INVALID (-1)     /* bad argument (null, negative, inconsistent) */
+#define PW_ERR_SHAPE (-2)       /* sphere / grid / size does not fit */
+#define PW_ERR_NOMEM (-3)       /* device allocation failed */
+#define PW_ERR_HIP (-4)         /* HIP runtime error */
+#define PW_ERR_NOT_FINITE (-5)  /* non-finite eigenvalue or residual seen */
+#define PW_ERR_NUMERIC (-6)     /* breakdown (e.g. rank-deficient start block) */
+
+/* precision forms of H*psi (inputs and outputs stay complex128) */
+#define PW_FP64 0        /* FFT complex128, projector GEMMs FP64 MFMA */
+#define PW_MIXED_FP32 1  /* FFT complex64, projector GEMMs FP32 MFMA, FP32 accumulate */
+#define PW_MIXED_BF16 2  /* FFT complex64, projector GEMMs BF16 in / FP32 accumulate */
+
+/* terms of H applied by pw_hpsi (bit mask) */
+#define PW_TERM_KINETIC 1
+#define PW_TERM_LOCAL 2
+#define PW_TERM_NONLOCAL 4
+#define PW_TERM_ALL 7
+
+/* preconditioners */
+#define PW_PRECOND_NONE 0
+#define PW_PRECOND_TPA 1
+#define PW_PRECOND_MLP 2
+
+typedef struct pw_problem pw_problem;
+typedef struct pw_davidson pw_davidson;
+typedef struct pw_mlp pw_mlp;
+
+/*
+ * One plane-wave problem: one cell at one k-point.
+ */
+typedef struct {
+  double cell[9];      /* bohr; row-major 3x3, rows are a1, a2, a3 */
+  double kpt[3];       /* k in crystal coordinates (fractions of b1, b2, b3) */
+  double ecut;         /* Ha; the sphere is |k+G|^2/2 < ecut */
+  int32_t nr[3];       /* FFT grid N0, N1, N2; each 2^a 3^b 5^c, 2..128 */
+  int32_t precision;   /* PW_FP64 / PW_MIXED_FP32 / PW_MIXED_BF16 */
+  int64_t npw;         /* number of plane waves (> 0) */
+  const int32_t *miller; /* host [npw][3] Miller triples (h,k,l), any order;
+                            each |h_i| < N_i/2, else PW_ERR_SHAPE; no duplicates */
+  const double *vloc;  /* device [N0][N1][N2] real V_LOC(r_j), Ha, N2 fastest;
+                          r_j = (j0/N0) a1 + (j1/N1) a2 + (j2/N2) a3 */
+  int64_t nproj;       /* number of projectors (>= 0) */
+  int32_t natom;       /* number of atoms = D blocks (>= 0) */
+  const int32_t *proj_offset; /* host [natom+1], 0 = off[0] <= ... <= off[natom] = nproj;
+                                 projectors off[a]..off[a+1]-1 belong to atom a */
+  const double *dij;   /* host, per-atom real symmetric blocks, row-major,
+                          concatenated in atom order (sum of n_a^2 doubles), Ha */
+  const void *beta;    /* device complex128 [nproj][ld_beta]: beta_j(k+G), already
+                          carrying the structure factor and normalisation */
+  int64_t ld_beta;     /* >= npw */
+} pw_problem_desc;
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char *pw_last_error(void);
+
+/* Library version string. */
+const char *pw_version(void);
+
+/*
+ * Plane-wave sphere {G : |k+G|^2/2 < ecut} (host only, no GPU needed).
+ * Writes at most `cap` Miller triples to miller_out (host [cap][3]) in the
+ * reproducible order the paper asks for in its large-record file-format
+ * section: ascending kinetic energy, ties broken by (h, k, l) ascending.
+ * *npw_out receives the full count; with miller_out == NULL or cap too
+ * small only the count is produced (returns PW_OK).
+ */
+pw_status pw_gsphere(const double cell[9], const double kpt[3], double ecut,
+                     int32_t *miller_out, int64_t cap, int64_t *npw_out);
+
+/*
+ * Build a problem handle.  Copies everything it needs from desc (host
+ * arrays, V_LOC and beta are copied into library-owned device memory, so
+ * the caller's buffers may be freed after the stream has passed this call).
+ * max_bands bounds nbands of later pw_hpsi calls (work buffers are sized
+ * for it here; pw_hpsi then allocates nothing).  Synchronises `stream`.
+ * Errors: PW_ERR_INVALID, PW_ERR_SHAPE (sphere does not fit the grid, grid
+ * size not 2^a 3^b 5^c or outside 2..128, plane too large for LDS),
+ * PW_ERR_NOMEM, PW_ERR_HIP.
+ */
+pw_status pw_problem_create(const pw_problem_desc *desc, int64_t max_bands,
+                            void *stream, pw_problem **out);
+pw_status pw_problem_destroy(pw_problem *p);
+
+/* Realised sizes of a handle: npw, number of z-sticks, nproj. */
+pw_status pw_problem_info(const pw_problem *p, int64_t *npw, int64_t *nsticks,
+                          int64_t *nproj);
+
+/*
+ * hpsi[n] = H psi[n] for n < nbands (terms selected by `terms`, a mask of
+ * PW_TERM_*; PW_TERM_ALL for the full operator):
+ *   kinetic   t(G) psi(G), t = |k+G|^2 / 2
+ *   local     sum_G' V~(G - G') psi(G'),  V~(q) = N^-3 sum_j V(r_j) e^{-i q.r_j}
+ *             (applied as scatter -> inverse 3D FFT -> x V(r) -> forward 3D FFT -> gather)
+ *   nonlocal  sum_ij beta_i(G) D_ij <beta_j | psi>
+ * psi, hpsi: device complex128, band-major, ld_psi / ld_hpsi >= npw; they
+ * must not overlap.  0 <= nbands <= max_bands.  No allocation, no host sync.
+ */
+pw_status pw_hpsi(pw_problem *p, const void *psi, int64_t ld_psi, void *hpsi,
+                  int64_t ld_hpsi, int64_t nbands, int32_t terms, void *stream);
+
+/*
+ * P[n][j] = <beta_j | psi_n> (device complex128 [nbands][nproj]), the
+ * paper's p_ij scalar products, in the handle's precision form.
+ */
+pw_status pw_projections(pw_problem *p, const void *psi, int64_t ld_psi,
+                         void *proj_out, int64_t nbands, void *stream);
+
+/*
+ * Diagonal preconditioner: t[n](G) = K_n(G) r[n](G).
+ *   PW_PRECOND_TPA : Teter-Payne-Allan (1989) K(x) = (27+18x+12x^2+8x^3) /
+ *                    (27+18x+12x^2+8x^3+16x^4), x = t(G)/T_n, T_n the band
+ *                    kinetic energy <x_n|t|x_n>/<x_n|x_n> of the iterate x.
+ *   PW_PRECOND_NONE: K = 1.
+ *   PW_PRECOND_MLP : K = s(G, n) from the network `net` (see pw_mlp_*), with
+ *                    per-band fallback to TPA when any s of the band is not
+ *                    finite.
+ * theta: device double [nbands] Ritz values (used by MLP only);
+ * x, r, t: device complex128 band-major with leading dimension ld.
+ */
+pw_status pw_precond(pw_problem *p, int32_t kind, const double *theta,
+                     const void *x, const void *r, void *t, int64_t ld,
+                     int64_t nbands, const pw_mlp *net, void *stream);
+
+/*
+ * Stage timing (instrumentation, off by default).  When enabled, every
+ * kernel launch a call makes is bracketed by two HIP events recorded on the
+ * call's stream; pw_profile_read synchronises on those events and returns
+ * per-stage totals (milliseconds and launch counts, arrays of PW_NSTAGES).
+ * reset != 0 clears the totals after reading.
+ */
+#define PW_STAGE_ZFFT_INV 0   /* gather sphere + inverse z FFT          */
+#define PW_STAGE_PLANE 1      /* xy FFTs + V(r) product                 */
+#define PW_STAGE_ZFFT_FWD 2   /* forward z FFT + gather + kinetic       */
+#define PW_STAGE_KINETIC 3    /* kinetic-only (no local term)           */
+#define PW_STAGE_PROJ 4       /* <beta|psi> GEMM (+ split-K reduction)  */
+#define PW_STAGE_DMAT 5       /* D p                                    */
+#define PW_STAGE_NLUPD 6      /* H psi += beta (D p) GEMM               */
+#define PW_STAGE_PRECOND 7    /* preconditioner                         */
+#define PW_STAGE_SUBGEMM 8    /* Davidson subspace GEMMs (V^H W ...)    */
+#define PW_STAGE_UPDGEMM 9    /* Davidson basis updates (V Y ...)       */
+#define PW_STAGE_EIG 10       /* Davidson Hermitian eigensolve          */
+#define PW_STAGE_CHOL 11      /* Davidson Cholesky / triangular solves  */
+#define PW_STAGE_VEC 12       /* Davidson vector kernels (norms, copies)*/
+#define PW_NSTAGES 16
+pw_status pw_profile_enable(pw_problem *p, int32_t on);
+pw_status pw_profile_read(pw_problem *p, double *ms_total, int64_t *launches, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PW_API_H */

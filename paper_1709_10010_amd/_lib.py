@@ -1,0 +1,251 @@
+"""ctypes binding of libpwhip.so: argument marshalling only.
+
+Every function here has the name of the C entry point it wraps and does no
+arithmetic of the method: it checks dtypes / devices / shapes of torch
+tensors, passes raw pointers and sizes, and turns a non-zero status into
+``PwError``.  All device work runs in the library's HIP kernels on the
+caller's (torch current) stream.  Importing this module fails loudly when
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libpwhip.so")
+
+PW_OK = 0
+PW_NOT_CONVERGED = 1
+PW_FP64, PW_MIXED_FP32, PW_MIXED_BF16 = 0, 1, 2
+PW_TERM_KINETIC, PW_TERM_LOCAL, PW_TERM_NONLOCAL, PW_TERM_ALL = 1, 2, 4, 7
+PW_PRECOND_NONE, PW_PRECOND_TPA, PW_PRECOND_MLP = 0, 1, 2
+STATUS_NAMES = {0: "PW_OK", 1: "PW_NOT_CONVERGED", -1: "PW_ERR_INVALID", -2: "PW_ERR_SHAPE",
+                -3: "PW_ERR_NOMEM", -4: "PW_ERR_HIP", -5: "PW_ERR_NOT_FINITE",
+                -6: "PW_ERR_NUMERIC"}
+
+
+class PwError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Desc(C.Structure):
+    _fields_ = [
+        ("cell", C.c_double * 9),
+        ("kpt", C.c_double * 3),
+        ("ecut", C.c_double),
+        ("nr", C.c_int32 * 3),
+        ("precision", C.c_int32),
+        ("npw", C.c_int64),
+        ("miller", C.POINTER(C.c_int32)),
+        ("vloc", C.c_void_p),
+        ("nproj", C.c_int64),
+        ("natom", C.c_int32),
+        ("proj_offset", C.POINTER(C.c_int32)),
+        ("dij", C.POINTER(C.c_double)),
+        ("beta", C.c_void_p),
+        ("ld_beta", C.c_int64),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIBPATH):
+        raise ImportError(f"{LIBPATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950); there is no fallback path")
+    lib = C.CDLL(LIBPATH)
+    vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "pw_last_error": (C.c_char_p, []),
+        "pw_version": (C.c_char_p, []),
+        "pw_gsphere": (i32, [C.POINTER(f64), C.POINTER(f64), f64, C.POINTER(i32), i64, C.POINTER(i64)]),
+        "pw_problem_create": (i32, [C.POINTER(_Desc), i64, vp, C.POINTER(vp)]),
+        "pw_problem_destroy": (i32, [vp]),
+        "pw_problem_info": (i32, [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]),
+        "pw_hpsi": (i32, [vp, vp, i64, vp, i64, i64, i32, vp]),
+        "pw_projections": (i32, [vp, vp, i64, vp, i64, vp]),
+        "pw_precond": (i32, [vp, i32, vp, vp, vp, vp, i64, i64, vp, vp]),
+        "pw_profile_enable": (i32, [vp, i32]),
+        "pw_profile_read": (i32, [vp, C.POINTER(f64), C.POINTER(i64), i32]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        raise PwError(status, LIB.pw_last_error().decode())
+    return status
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name}: expected a torch tensor on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _band_block(t, name, npw):
+    """(ptr, ld, nbands) of a [nbands][ld] complex128 tensor with unit stride along G."""
+    import torch
+    ptr = _dev_ptr(t, torch.complex128, name)
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name}: expected a 2-D band-major block with unit stride along G")
+    ld = t.stride(0) if t.shape[0] > 1 else max(t.shape[1], npw)
+    if t.shape[1] < npw:
+        raise ValueError(f"{name}: second dimension {t.shape[1]} < npw {npw}")
+    return ptr, int(ld), int(t.shape[0])
+
+
+def pw_version() -> str:
+    return LIB.pw_version().decode()
+
+
+def pw_gsphere(cell, kpt, ecut: float) -> np.ndarray:
+    """Miller triples of {G : |k+G|^2/2 < ecut} in the library's canonical order."""
+    cell = np.ascontiguousarray(cell, dtype=np.float64).reshape(9)
+    kpt = np.ascontiguousarray(kpt, dtype=np.float64).reshape(3)
+    n = C.c_int64(0)
+    dp = C.POINTER(C.c_double)
+    _check(LIB.pw_gsphere(cell.ctypes.data_as(dp), kpt.ctypes.data_as(dp), float(ecut), None, 0,
+                          C.byref(n)))
+    out = np.zeros((n.value, 3), dtype=np.int32)
+    _check(LIB.pw_gsphere(cell.ctypes.data_as(dp), kpt.ctypes.data_as(dp), float(ecut),
+                          out.ctypes.data_as(C.POINTER(C.c_int32)), n.value, C.byref(n)))
+    return out
+
+
+class Problem:
+    """Owner of a pw_problem handle (destroyed with the object)."""
+
+    def __init__(self, handle, npw, nproj, max_bands, precision):
+        self._h = handle
+        self.npw = npw
+        self.nproj = nproj
+        self.max_bands = max_bands
+        self.precision = precision
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise PwError(-1, "problem handle already destroyed")
+        return self._h
+
+    def info(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(LIB.pw_problem_info(self.handle, C.byref(a), C.byref(b), C.byref(c)))
+        return dict(npw=a.value, nsticks=b.value, nproj=c.value)
+
+    def close(self):
+        if self._h:
+            LIB.pw_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pw_problem_create(cell, kpt, ecut, nr, miller, vloc, beta, proj_offset, dij,
+                      precision=PW_FP64, max_bands=1, stream=None) -> Problem:
+    """Wrap pw_problem_create.  vloc: cuda float64 [N0][N1][N2]; beta: cuda complex128
+    [nproj][ld] (or None with nproj = 0); miller / proj_offset / dij: host arrays."""
+    import torch
+    miller = np.ascontiguousarray(miller, dtype=np.int32).reshape(-1, 3)
+    d = _Desc()
+    d.cell[:] = [float(x) for x in np.asarray(cell, dtype=np.float64).reshape(9)]
+    d.kpt[:] = [float(x) for x in np.asarray(kpt, dtype=np.float64).reshape(3)]
+    d.ecut = float(ecut)
+    d.nr[:] = [int(x) for x in nr]
+    d.precision = int(precision)
+    d.npw = miller.shape[0]
+    d.miller = miller.ctypes.data_as(C.POINTER(C.c_int32))
+    if tuple(vloc.shape) != tuple(int(x) for x in nr):
+        raise ValueError("vloc shape must equal the grid")
+    vloc_c = vloc.contiguous()
+    d.vloc = _dev_ptr(vloc_c, torch.float64, "vloc")
+    keep = [miller, vloc_c]
+    if beta is not None and beta.shape[0] > 0:
+        po = np.ascontiguousarray(proj_offset, dtype=np.int32)
+        dj = np.ascontiguousarray(dij, dtype=np.float64)
+        if beta.stride(1) != 1:
+            raise ValueError("beta must have unit stride along G")
+        d.nproj = int(beta.shape[0])
+        d.natom = int(po.shape[0] - 1)
+        d.proj_offset = po.ctypes.data_as(C.POINTER(C.c_int32))
+        d.dij = dj.ctypes.data_as(C.POINTER(C.c_double))
+        d.beta = _dev_ptr(beta, torch.complex128, "beta")
+        d.ld_beta = int(beta.stride(0)) if beta.shape[0] > 1 else int(beta.shape[1])
+        keep += [po, dj, beta]
+    h = C.c_void_p()
+    _check(LIB.pw_problem_create(C.byref(d), int(max_bands), _stream(stream), C.byref(h)))
+    del keep
+    return Problem(h, int(d.npw), int(d.nproj), int(max_bands), int(precision))
+
+
+def pw_hpsi(prob: Problem, psi, hpsi, terms: int = PW_TERM_ALL, stream=None) -> None:
+    ps, ldp, nb = _band_block(psi, "psi", prob.npw)
+    hs, ldh, nbh = _band_block(hpsi, "hpsi", prob.npw)
+    if nbh < nb:
+        raise ValueError("hpsi has fewer bands than psi")
+    _check(LIB.pw_hpsi(prob.handle, ps, ldp, hs, ldh, nb, int(terms), _stream(stream)))
+
+
+def pw_projections(prob: Problem, psi, proj, stream=None) -> None:
+    import torch
+    ps, ldp, nb = _band_block(psi, "psi", prob.npw)
+    pp = _dev_ptr(proj, torch.complex128, "proj")
+    if not proj.is_contiguous() or tuple(proj.shape) != (nb, prob.nproj):
+        raise ValueError("proj must be a contiguous [nbands][nproj] tensor")
+    _check(LIB.pw_projections(prob.handle, ps, ldp, pp, nb, _stream(stream)))
+
+
+def pw_precond(prob: Problem, kind: int, theta, x, r, t, net=None, stream=None) -> None:
+    import torch
+    xs, ldx, nb = _band_block(x, "x", prob.npw)
+    rs, ldr, nbr = _band_block(r, "r", prob.npw)
+    ts, ldt, nbt = _band_block(t, "t", prob.npw)
+    if not (ldx == ldr == ldt) or nbr < nb or nbt < nb:
+        raise ValueError("x, r, t must share one leading dimension and band count")
+    th = _dev_ptr(theta, torch.float64, "theta") if theta is not None else None
+    nh = net.handle if net is not None else None
+    _check(LIB.pw_precond(prob.handle, int(kind), th, xs, rs, ts, ldx, nb, nh, _stream(stream)))
+
+
+PW_NSTAGES = 16
+STAGES = ["zfft_inv", "plane", "zfft_fwd", "kinetic", "proj", "dmat", "nlupd", "precond",
+          "subgemm", "updgemm", "eig", "chol", "vec"]
+
+
+def pw_profile_enable(prob: Problem, on: bool = True) -> None:
+    _check(LIB.pw_profile_enable(prob.handle, 1 if on else 0))
+
+
+def pw_profile_read(prob: Problem, reset: bool = True) -> dict:
+    """{stage: (total_ms, launches)} for stages with at least one launch."""
+    ms = (C.c_double * PW_NSTAGES)()
+    n = (C.c_int64 * PW_NSTAGES)()
+    _check(LIB.pw_profile_read(prob.handle, ms, n, 1 if reset else 0))
+    return {STAGES[i]: (ms[i], n[i]) for i in range(len(STAGES)) if n[i] > 0}

@@ -1,0 +1,496 @@
+// Local-potential part of H*psi on the FFT grid (CDNA4 / gfx950).
+//
+// Operation (paper, eq. pauli_ks: V_LOC acts on the FFT mesh; the
+// exchange paragraph's grid rule G_max = 2 G_c fixes the mesh):
+//   u(r) = sum_G psi(G) e^{+iG.r}          inverse 3D FFT of the sphere
+//   w(r) = V(r) u(r)                        pointwise, V real
+//   (V psi)(G) = N^-3 sum_r w(r) e^{-iG.r}  forward 3D FFT, kept on the sphere
+// The paper puts the non-linear scaling of the method on these FFTs and
+// spreads the bands of the V psi products over "task groups"; here the
+// bands of a block are the batch dimension of every launch.
+//
+// Three kernels, each staging its data through LDS exactly once:
+//   k_zfft_inv  per (tile of z-sticks, band): gather psi(G) of the tile's
+//               sticks into LDS, inverse FFT along z, store the tile to the
+//               stick buffer [band][z][stick] (coalesced across sticks).
+//   k_plane     per (z-plane, group of bands): scatter the plane's stick
+//               values into an LDS plane, inverse FFT along y on the rows
+//               that hold sticks, inverse along x, multiply by V / N^3,
+//               forward along x, forward along y on the stick rows, store
+//               the sticks back.  V's plane is re-read from L2 per band.
+//   k_zfft_fwd  per (tile, band): forward FFT along z, gather the sphere,
+//               add the kinetic term t(G) psi(G), write H psi.
+// Only the grid columns that hold sphere points (the z-sticks) ever travel
+// through HBM; the pruned y passes skip rows without sticks.
+//
+// FFTs are in-place Stockham passes in LDS: in each radix-R pass every
+// thread loads its butterflies' R inputs into registers, applies the
+// twiddles and the R-point DFT, all threads barrier, then every thread
+// stores its outputs at their autosorted positions.  Radices 2, 3, 4, 5, 8.
+#include "common.h"
+
+namespace pw {
+
+// ---------------------------------------------------------------- complex ops
+template <typename V> __device__ __forceinline__ V c_add(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
+template <typename V> __device__ __forceinline__ V c_sub(V a, V b) { return V{a.x - b.x, a.y - b.y}; }
+template <typename V> __device__ __forceinline__ V c_mul(V a, V b) {
+  return V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename V> __device__ __forceinline__ V c_mulconj(V a, V b) {  // a * conj(b)
+  return V{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename V, typename S> __device__ __forceinline__ V c_scale(V a, S s) { return V{a.x * s, a.y * s}; }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename V> __device__ __forceinline__ V c_rot(V a) {
+  return INV ? V{-a.y, a.x} : V{a.y, -a.x};
+}
+
+// ---------------------------------------------------------------- small DFTs
+template <int R, bool INV, typename V> struct Dft;
+
+template <bool INV, typename V> struct Dft<2, INV, V> {
+  static __device__ __forceinline__ void run(V *v) {
+    V a = v[0], b = v[1];
+    v[0] = c_add(a, b);
+    v[1] = c_sub(a, b);
+  }
+};
+
+template <bool INV, typename V> struct Dft<4, INV, V> {
+  static __device__ __forceinline__ void run(V *v) {
+    V t0 = c_add(v[0], v[2]), t1 = c_sub(v[0], v[2]);
+    V t2 = c_add(v[1], v[3]), t3 = c_rot<INV>(c_sub(v[1], v[3]));
+    v[0] = c_add(t0, t2);
+    v[2] = c_sub(t0, t2);
+    v[1] = c_add(t1, t3);
+    v[3] = c_sub(t1, t3);
+  }
+};
+
+template <bool INV, typename V> struct Dft<3, INV, V> {
+  static __device__ __forceinline__ void run(V *v) {
+    using S = decltype(v[0].x);
+    const S h = S(0.86602540378443864676372317075294);  // sqrt(3)/2
+    V t1 = c_add(v[1], v[2]);
+    V t2 = c_sub(v[0], c_scale(t1, S(0.5)));
+    V t3 = c_rot<INV>(c_scale(c_sub(v[1], v[2]), h));
+    v[0] = c_add(v[0], t1);
+    v[1] = c_add(t2, t3);
+    v[2] = c_sub(t2, t3);
+  }
+};
+
+template <bool INV, typename V> struct Dft<5, INV, V> {
+  static __device__ __forceinline__ void run(V *v) {
+    using S = decltype(v[0].x);
+    const S c1 = S(0.30901699437494742410229341718282);   // cos(2pi/5)
+    const S c2 = S(-0.80901699437494742410229341718282);  // cos(4pi/5)
+    const S s1 = S(0.95105651629515357211643933337938);   // sin(2pi/5)
+    const S s2 = S(0.58778525229247312916870595463907);   // sin(4pi/5)
+    V a1 = c_add(v[1], v[4]), b1 = c_sub(v[1], v[4]);
+    V a2 = c_add(v[2], v[3]), b2 = c_sub(v[2], v[3]);
+    V x0 = v[0];
+    V p1 = V{x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y};
+    V p2 = V{x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y};
+    V q1 = c_rot<INV>(V{s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y});
+    V q2 = c_rot<INV>(V{s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y});
+    v[0] = c_add(x0, c_add(a1, a2));
+    v[1] = c_add(p1, q1);
+    v[4] = c_sub(p1, q1);
+    v[2] = c_add(p2, q2);
+    v[3] = c_sub(p2, q2);
+  }
+};
+
+template <bool INV, typename V> struct Dft<8, INV, V> {
+  static __device__ __forceinline__ void run(V *v) {
+    using S = decltype(v[0].x);
+    const S r = S(0.70710678118654752440084436210485);
+    V e[4] = {v[0], v[2], v[4], v[6]};
+    V o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<4, INV, V>::run(e);
+    Dft<4, INV, V>::run(o);
+    // w^k O_k with w = e^{-i pi/4} (forward) or its conjugate
+    V w1 = INV ? V{r * (o[1].x - o[1].y), r * (o[1].x + o[1].y)}
+               : V{r * (o[1].x + o[1].y), r * (o[1].y - o[1].x)};
+    V w2 = c_rot<INV>(o[2]);
+    V w3 = INV ? V{-r * (o[3].x + o[3].y), r * (o[3].x - o[3].y)}
+               : V{r * (o[3].y - o[3].x), -r * (o[3].x + o[3].y)};
+    v[0] = c_add(e[0], o[0]);
+    v[4] = c_sub(e[0], o[0]);
+    v[1] = c_add(e[1], w1);
+    v[5] = c_sub(e[1], w1);
+    v[2] = c_add(e[2], w2);
+    v[6] = c_sub(e[2], w2);
+    v[3] = c_add(e[3], w3);
+    v[7] = c_sub(e[3], w3);
+  }
+};
+
+// ---------------------------------------------------------------- one Stockham pass
+constexpr int kCpt = 8;  // complex values per thread and pass (register budget)
+
+// Lines of length N live in LDS at base(line) + pos * estride.  base(line) is
+// line * lstride, or lbase[line] when INDIRECT.  LINE_FAST maps consecutive
+// threads to consecutive lines (strided lines), else to consecutive
+// butterflies of one line (contiguous lines).  Each thread holds at most
+// kCpt complex values: the host guarantees nlines * N <= kCpt * nthr.
+template <typename V, int R, bool INV, bool LINE_FAST, bool INDIRECT>
+__device__ __forceinline__ void stockham_pass(V *buf, int nlines, int lstride, int estride,
+                                              const int *lbase, int N, int Ns, const V *tw,
+                                              int tid, int nthr) {
+  constexpr int MAXB = (kCpt + R - 1) / R;
+  const int nbf = N / R;
+  const int total = nlines * nbf;
+  const int twstep = N / (Ns * R);
+  V v[MAXB][R];
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    const int idx = tid + c * nthr;
+    if (idx < total) {
+      int line, j;
+      if (LINE_FAST) {
+        line = idx % nlines;
+        j = idx / nlines;
+      } else {
+        j = idx % nbf;
+        line = idx / nbf;
+      }
+      const int base = INDIRECT ? lbase[line] : line * lstride;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[c][r] = buf[base + (j + r * nbf) * estride];
+      if (Ns > 1) {
+        const int k = j % Ns;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const V w = tw[k * r * twstep];
+          v[c][r] = INV ? c_mulconj(v[c][r], w) : c_mul(v[c][r], w);
+        }
+      }
+      Dft<R, INV, V>::run(v[c]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    const int idx = tid + c * nthr;
+    if (idx < total) {
+      int line, j;
+      if (LINE_FAST) {
+        line = idx % nlines;
+        j = idx / nlines;
+      } else {
+        j = idx % nbf;
+        line = idx / nbf;
+      }
+      const int base = INDIRECT ? lbase[line] : line * lstride;
+      const int k = j % Ns;
+      const int out0 = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[base + (out0 + r * Ns) * estride] = v[c][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename V, bool INV, bool LINE_FAST, bool INDIRECT>
+__device__ void fft_lines(V *buf, int nlines, int lstride, int estride, const int *lbase,
+                          const AxisPlan &pl, const V *tw, int tid, int nthr) {
+  int Ns = 1;
+  for (int p = 0; p < pl.npass; ++p) {
+    const int R = pl.radix[p];
+    switch (R) {
+      case 2: stockham_pass<V, 2, INV, LINE_FAST, INDIRECT>(buf, nlines, lstride, estride, lbase, pl.n, Ns, tw, tid, nthr); break;
+      case 3: stockham_pass<V, 3, INV, LINE_FAST, INDIRECT>(buf, nlines, lstride, estride, lbase, pl.n, Ns, tw, tid, nthr); break;
+      case 4: stockham_pass<V, 4, INV, LINE_FAST, INDIRECT>(buf, nlines, lstride, estride, lbase, pl.n, Ns, tw, tid, nthr); break;
+      case 5: stockham_pass<V, 5, INV, LINE_FAST, INDIRECT>(buf, nlines, lstride, estride, lbase, pl.n, Ns, tw, tid, nthr); break;
+      default: stockham_pass<V, 8, INV, LINE_FAST, INDIRECT>(buf, nlines, lstride, estride, lbase, pl.n, Ns, tw, tid, nthr); break;
+    }
+    Ns *= R;
+  }
+}
+
+// Block -> (tile, band) with every tile of a band on the same XCD (blocks
+// are dealt to the 8 XCDs round-robin), so the band's psi / H psi lines
+// are shared through one L2.  The grid is ntile * roundup(nb, 8) blocks.
+__device__ __forceinline__ void tile_band(int bid, int ntile, int *tile, int *band) {
+  const int xcd = bid & 7;
+  const int q = bid >> 3;
+  *tile = q % ntile;
+  *band = (q / ntile) * 8 + xcd;
+}
+
+// ---------------------------------------------------------------- kernels
+template <typename T, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_zfft_inv(FFTDev f, const double2 *__restrict__ psi,
+                                                   int64_t ld, cpx_t<T> *__restrict__ sticks,
+                                                   int nb) {
+  using V = cpx_t<T>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  V *tw = reinterpret_cast<V *>(smem);
+  V *buf = tw + f.n2;
+  int tile, b;
+  tile_band(blockIdx.x, f.ntile, &tile, &b);
+  if (b >= nb) return;
+  const int tid = threadIdx.x;
+  const V *twg = static_cast<const V *>(f.tw2);
+  for (int i = tid; i < f.n2; i += NTHR) tw[i] = twg[i];
+  const int nel = f.ts * f.n2;
+  for (int i = tid; i < nel; i += NTHR) buf[i] = V{0, 0};
+  __syncthreads();
+  const int e0 = f.tile_ptr[tile], e1 = f.tile_ptr[tile + 1];
+  const double2 *src = psi + (int64_t)b * ld;
+  for (int e = e0 + tid; e < e1; e += NTHR) {
+    const double2 v = src[f.gidx[e]];
+    buf[f.gpos[e]] = V{(T)v.x, (T)v.y};
+  }
+  __syncthreads();
+  fft_lines<V, true, true, false>(buf, f.ts, 1, f.ts, nullptr, f.pz, tw, tid, NTHR);
+  V *dst = sticks + (int64_t)b * f.n2 * f.nst_pad + (int64_t)tile * f.ts;
+  for (int i = tid; i < nel; i += NTHR) {
+    const int z = i / f.ts;
+    const int sl = i - z * f.ts;
+    dst[(int64_t)z * f.nst_pad + sl] = buf[i];
+  }
+}
+
+template <typename T, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_plane(FFTDev f, cpx_t<T> *__restrict__ sticks, int nb,
+                                                int group) {
+  using V = cpx_t<T>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  V *tw0 = reinterpret_cast<V *>(smem);
+  V *tw1 = tw0 + f.n0;
+  V *pl = tw1 + f.n1;
+  int *lb = reinterpret_cast<int *>(pl + f.n0 * f.n1);
+  const int z = blockIdx.x % f.n2;
+  const int g = blockIdx.x / f.n2;
+  const int tid = threadIdx.x;
+  const V *tw0g = static_cast<const V *>(f.tw0);
+  const V *tw1g = static_cast<const V *>(f.tw1);
+  for (int i = tid; i < f.n0; i += NTHR) tw0[i] = tw0g[i];
+  for (int i = tid; i < f.n1; i += NTHR) tw1[i] = tw1g[i];
+  for (int i = tid; i < f.nx; i += NTHR) lb[i] = f.xlist[i] * f.n1;
+  const int npl = f.n0 * f.n1;
+  const T *vp = static_cast<const T *>(f.vplanes) + (int64_t)z * npl;
+  for (int bb = 0; bb < group; ++bb) {
+    const int b = g * group + bb;
+    if (b >= nb) break;
+    for (int i = tid; i < npl; i += NTHR) pl[i] = V{0, 0};
+    __syncthreads();
+    V *col = sticks + (int64_t)b * f.n2 * f.nst_pad + (int64_t)z * f.nst_pad;
+    for (int s = tid; s < f.nst; s += NTHR) pl[f.stick_xy[s]] = col[s];
+    __syncthreads();
+    fft_lines<V, true, false, true>(pl, f.nx, 0, 1, lb, f.py, tw1, tid, NTHR);
+    fft_lines<V, true, true, false>(pl, f.n1, 1, f.n1, nullptr, f.px, tw0, tid, NTHR);
+    for (int i = tid; i < npl; i += NTHR) pl[i] = c_scale(pl[i], vp[i]);
+    __syncthreads();
+    fft_lines<V, false, true, false>(pl, f.n1, 1, f.n1, nullptr, f.px, tw0, tid, NTHR);
+    fft_lines<V, false, false, true>(pl, f.nx, 0, 1, lb, f.py, tw1, tid, NTHR);
+    for (int s = tid; s < f.nst; s += NTHR) col[s] = pl[f.stick_xy[s]];
+    __syncthreads();
+  }
+}
+
+template <typename T, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_zfft_fwd(FFTDev f, const cpx_t<T> *__restrict__ sticks,
+                                                   const double2 *__restrict__ psi, int64_t ld,
+                                                   double2 *__restrict__ hpsi, int64_t ldh, int nb,
+                                                   int kinetic) {
+  using V = cpx_t<T>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  V *tw = reinterpret_cast<V *>(smem);
+  V *buf = tw + f.n2;
+  int tile, b;
+  tile_band(blockIdx.x, f.ntile, &tile, &b);
+  if (b >= nb) return;
+  const int tid = threadIdx.x;
+  const V *twg = static_cast<const V *>(f.tw2);
+  for (int i = tid; i < f.n2; i += NTHR) tw[i] = twg[i];
+  const int nel = f.ts * f.n2;
+  const V *srcs = sticks + (int64_t)b * f.n2 * f.nst_pad + (int64_t)tile * f.ts;
+  for (int i = tid; i < nel; i += NTHR) {
+    const int z = i / f.ts;
+    const int sl = i - z * f.ts;
+    buf[i] = srcs[(int64_t)z * f.nst_pad + sl];
+  }
+  __syncthreads();
+  fft_lines<V, false, true, false>(buf, f.ts, 1, f.ts, nullptr, f.pz, tw, tid, NTHR);
+  const int e0 = f.tile_ptr[tile], e1 = f.tile_ptr[tile + 1];
+  const double2 *src = psi + (int64_t)b * ld;
+  double2 *dst = hpsi + (int64_t)b * ldh;
+  for (int e = e0 + tid; e < e1; e += NTHR) {
+    const int gi = f.gidx[e];
+    const V v = buf[f.gpos[e]];
+    double2 o = double2{(double)v.x, (double)v.y};
+    if (kinetic) {
+      const double2 p = src[gi];
+      const double t = f.kin[gi];
+      o.x += t * p.x;
+      o.y += t * p.y;
+    }
+    dst[gi] = o;
+  }
+}
+
+__global__ void k_kinetic_only(const double *__restrict__ kin, const double2 *__restrict__ psi,
+                               int64_t ld, double2 *__restrict__ hpsi, int64_t ldh, int64_t npw,
+                               int kinetic) {
+  const int b = blockIdx.y;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < npw;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    double2 o = double2{0.0, 0.0};
+    if (kinetic) {
+      const double2 p = psi[(int64_t)b * ld + g];
+      o = double2{kin[g] * p.x, kin[g] * p.y};
+    }
+    hpsi[(int64_t)b * ldh + g] = o;
+  }
+}
+
+// ---------------------------------------------------------------- host side
+bool make_axis_plan(int n, AxisPlan *out) {
+  AxisPlan p;
+  p.n = n;
+  int m = n, a = 0;
+  while (m % 2 == 0) {
+    m /= 2;
+    ++a;
+  }
+  auto push = [&](int r) {
+    if (p.npass >= kMaxPasses) return false;
+    p.radix[p.npass++] = r;
+    return true;
+  };
+  while (a > 0) {
+    bool ok;
+    if (a == 4) {
+      ok = push(4) && push(4);
+      a = 0;
+    } else if (a >= 3) {
+      ok = push(8);
+      a -= 3;
+    } else if (a == 2) {
+      ok = push(4);
+      a -= 2;
+    } else {
+      ok = push(2);
+      a -= 1;
+    }
+    if (!ok) return false;
+  }
+  while (m % 3 == 0) {
+    if (!push(3)) return false;
+    m /= 3;
+  }
+  while (m % 5 == 0) {
+    if (!push(5)) return false;
+    m /= 5;
+  }
+  if (m != 1) return false;
+  *out = p;
+  return true;
+}
+
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+static inline int nb_pad8(int nb) { return (nb + 7) / 8 * 8; }
+
+template <typename T, int NT>
+static int zinv_n(const FFTDev &f, const void *psi, int64_t ld, void *sticks, int nb, hipStream_t s) {
+  using V = cpx_t<T>;
+  const size_t lds = sizeof(V) * (size_t)f.n2 * (1 + f.ts);
+  const int blocks = f.ntile * nb_pad8(nb);
+  auto k = k_zfft_inv<T, NT>;
+  if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(NT), lds, s, f, static_cast<const double2 *>(psi), ld,
+                     static_cast<V *>(sticks), nb);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+template <typename T>
+static int zinv_t(const FFTDev &f, const void *psi, int64_t ld, void *sticks, int nb, hipStream_t s) {
+  return f.ts * f.n2 <= kCpt * 256 ? zinv_n<T, 256>(f, psi, ld, sticks, nb, s)
+                                   : zinv_n<T, 512>(f, psi, ld, sticks, nb, s);
+}
+
+template <typename T>
+static int plane_t(const FFTDev &f, void *sticks, int nb, int group, hipStream_t s) {
+  using V = cpx_t<T>;
+  const int npl = f.n0 * f.n1;
+  const size_t lds = sizeof(V) * (size_t)(f.n0 + f.n1 + npl) + sizeof(int) * (size_t)f.nx;
+  const int groups = (nb + group - 1) / group;
+  const int blocks = f.n2 * groups;
+  if (npl <= kCpt * 256) {
+    auto k = k_plane<T, 256>;
+    if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, s, f, static_cast<V *>(sticks), nb, group);
+  } else if (npl <= kCpt * 512) {
+    auto k = k_plane<T, 512>;
+    if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(512), lds, s, f, static_cast<V *>(sticks), nb, group);
+  } else {
+    auto k = k_plane<T, 1024>;
+    if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(1024), lds, s, f, static_cast<V *>(sticks), nb, group);
+  }
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
+template <typename T, int NT>
+static int zfwd_n(const FFTDev &f, const void *sticks, const void *psi, int64_t ld, void *hpsi,
+                  int64_t ldh, int nb, bool kinetic, hipStream_t s) {
+  using V = cpx_t<T>;
+  const size_t lds = sizeof(V) * (size_t)f.n2 * (1 + f.ts);
+  const int blocks = f.ntile * nb_pad8(nb);
+  auto k = k_zfft_fwd<T, NT>;
+  if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(NT), lds, s, f, static_cast<const V *>(sticks),
+                     static_cast<const double2 *>(psi), ld, static_cast<double2 *>(hpsi), ldh, nb,
+                     kinetic ? 1 : 0);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+template <typename T>
+static int zfwd_t(const FFTDev &f, const void *sticks, const void *psi, int64_t ld, void *hpsi,
+                  int64_t ldh, int nb, bool kinetic, hipStream_t s) {
+  return f.ts * f.n2 <= kCpt * 256
+             ? zfwd_n<T, 256>(f, sticks, psi, ld, hpsi, ldh, nb, kinetic, s)
+             : zfwd_n<T, 512>(f, sticks, psi, ld, hpsi, ldh, nb, kinetic, s);
+}
+
+int launch_zfft_inv(const FFTDev &f, int prec, const void *psi, int64_t ld, void *sticks, int nb,
+                    hipStream_t s) {
+  if (nb <= 0) return PW_OK;
+  return prec == PW_FP64 ? zinv_t<double>(f, psi, ld, sticks, nb, s)
+                         : zinv_t<float>(f, psi, ld, sticks, nb, s);
+}
+
+int launch_plane(const FFTDev &f, int prec, void *sticks, int nb, int group, hipStream_t s) {
+  if (nb <= 0) return PW_OK;
+  return prec == PW_FP64 ? plane_t<double>(f, sticks, nb, group, s)
+                         : plane_t<float>(f, sticks, nb, group, s);
+}
+
+int launch_zfft_fwd(const FFTDev &f, int prec, const void *sticks, const void *psi, int64_t ld,
+                    void *hpsi, int64_t ldh, int nb, bool kinetic, hipStream_t s) {
+  if (nb <= 0) return PW_OK;
+  return prec == PW_FP64 ? zfwd_t<double>(f, sticks, psi, ld, hpsi, ldh, nb, kinetic, s)
+                         : zfwd_t<float>(f, sticks, psi, ld, hpsi, ldh, nb, kinetic, s);
+}
+
+int launch_kinetic_only(const double *kin, const void *psi, int64_t ld, void *hpsi, int64_t ldh,
+                        int64_t npw, int nb, bool kinetic, hipStream_t s) {
+  if (nb <= 0) return PW_OK;
+  int bx = (int)((npw + 255) / 256);
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL(k_kinetic_only, dim3(bx, nb), dim3(256), 0, s, kin,
+                     static_cast<const double2 *>(psi), ld, static_cast<double2 *>(hpsi), ldh, npw,
+                     kinetic ? 1 : 0);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
+}  // namespace pw

@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+* the built library exports every function ``include/pw_api.h`` declares;
+* its host-only sphere enumeration agrees with the oracle's: the same set
+  bit for bit, and an order whose kinetic energies never decrease;
+* argument checks that return before any device work.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import gsphere as gs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pw_api.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pw_[a-z0-9_]+)\s*\(", src)))
+
+
+def _lib():
+    from paper_1709_10010_amd import _lib
+    return _lib
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for n in ("pw_hpsi", "pw_precond", "pw_problem_create", "pw_gsphere"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_lib().LIBPATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("cfg,ik", [(1, 0), (2, 0), (2, 3), (0, 0)])
+def test_gsphere_matches_oracle(cfg, ik):
+    L = _lib()
+    c = synth.make_cell(cfg)
+    m_lib = L.pw_gsphere(c.A, c.kpts[ik], c.ecut_ha)
+    m_or = gs.gsphere(c.A, c.kpts[ik], c.ecut_ha)
+    assert m_lib.shape == m_or.shape
+    key = lambda m: np.lexsort((m[:, 2], m[:, 1], m[:, 0]))
+    assert np.array_equal(m_lib[key(m_lib)], m_or[key(m_or)])
+    t = gs.kinetic(c.A, c.kpts[ik], m_lib)
+    assert np.all(np.diff(t) >= -1e-12 * t.max())
+
+
+def test_gsphere_general_cell_kpoint():
+    L = _lib()
+    A = np.array([[5.0, 0.3, -0.2], [0.7, 6.1, 0.4], [-0.5, 0.2, 4.4]])
+    k = np.array([0.21, -0.37, 0.08])
+    m_lib = L.pw_gsphere(A, k, 4.0)
+    m_or = gs.gsphere(A, k, 4.0)
+    assert set(map(tuple, m_lib.tolist())) == set(map(tuple, m_or.tolist()))
+
+
+def test_gsphere_rejects_bad_cutoff():
+    L = _lib()
+    with pytest.raises(L.PwError) as e:
+        L.pw_gsphere(np.eye(3) * 10, np.zeros(3), -1.0)
+    assert e.value.status == -1
+
+
+def test_problem_create_rejects_null_desc():
+    L = _lib()
+    h = ctypes.c_void_p()
+    st = L.LIB.pw_problem_create(None, 1, None, ctypes.byref(h))
+    assert st == -1 and b"null" in L.LIB.pw_last_error()
+
+
+def test_problem_create_rejects_bad_grid_before_device_work():
+    L = _lib()
+    d = L._Desc()
+    d.cell[:] = list(np.eye(3).reshape(9) * 10)
+    d.ecut = 7.5
+    d.nr[:] = [24, 24, 7]           # 7 is not 2^a 3^b 5^c
+    mill = np.zeros((1, 3), dtype=np.int32)
+    d.npw = 1
+    d.miller = mill.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    d.vloc = ctypes.c_void_p(1)     # never dereferenced: the grid check fails first
+    h = ctypes.c_void_p()
+    st = L.LIB.pw_problem_create(ctypes.byref(d), 4, None, ctypes.byref(h))
+    assert st == -2 and b"grid" in L.LIB.pw_last_error()

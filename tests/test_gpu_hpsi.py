@@ -1,0 +1,166 @@
+"""GPU parity of H*psi (pw_hpsi, FP64 form) against the FP64 oracle.
+
+Element-by-element on the same seeded inputs, at sizes the oracle finishes
+in seconds and that span several stick tiles, plane groups, band chunks and
+GEMM tiles with ragged tails; at the full config-2 size on sampled bands.
+Tolerance: the FP64 path reorders sums (FFT butterflies, split-K GEMM), so
+each output element carries a few ulps of the largest term it sums;
+max|d| <= 1e-12 * max|ref| bounds that with a wide margin (observed ~1e-15).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import davidson as odv
+from oracle import hamiltonian as ham
+
+from gpu_util import from_gpu_block, log, problems, rel_err, start_block, to_gpu_block
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1709_10010_amd import _lib
+    return _lib
+
+
+def _run(lib, pl, psi, terms=7, ld_pad=64):
+    import torch
+    x = to_gpu_block(psi, ld_pad)
+    y = torch.full_like(x, complex(np.nan, np.nan))
+    lib.pw_hpsi(pl, x, y, terms=terms)
+    return from_gpu_block(y, psi.shape[1])
+
+
+@pytest.mark.parametrize("terms", [1, 2, 4, 7])
+def test_hpsi_terms_config1(lib, terms):
+    c = synth.make_cell(1)
+    log("hpsi cfg1 terms", terms)
+    po, pl = problems(c)
+    psi = start_block(c, 16, po.npw)
+    got = _run(lib, pl, psi, terms)
+    ref = np.zeros_like(psi)
+    if terms & 1:
+        ref += po.kinetic()[None, :] * psi
+    if terms & 2:
+        ref += np.array([ham.apply_local(po, p) for p in psi])
+    if terms & 4:
+        ref += ham.apply_nonlocal(po, psi)
+    assert rel_err(got, ref) < TOL
+
+
+@pytest.mark.parametrize("nb", [1, 5, 13, 16])
+def test_hpsi_ragged_band_counts(lib, nb):
+    c = synth.make_cell(1)
+    log("hpsi cfg1 nb", nb)
+    po, pl = problems(c, max_bands=16)
+    psi = start_block(c, nb, po.npw)
+    assert rel_err(_run(lib, pl, psi), ham.hpsi(po, psi)) < TOL
+
+
+def test_hpsi_zero_bands_is_noop(lib):
+    import torch
+    c = synth.make_cell(1)
+    po, pl = problems(c)
+    x = torch.zeros((0, 960), dtype=torch.complex128, device="cuda")
+    lib.pw_hpsi(pl, x, x.clone())
+
+
+def test_hpsi_unpadded_ld_and_tiny_grid(lib):
+    c = synth.make_cell(0)
+    log("hpsi tiny 9^3 unpadded")
+    po, pl = problems(c, ld_pad=1)
+    psi = start_block(c, 8, po.npw)
+    assert rel_err(_run(lib, pl, psi, ld_pad=1), ham.hpsi(po, psi)) < TOL
+
+
+def test_hpsi_kpoint_full_d_matches_dense_h(lib):
+    """s+p+d projectors, full symmetric D, k != 0: compare with the dense matrix too."""
+    c = synth.make_cell(0, seed=19)
+    c.lmax = np.full(c.natom, 2, dtype=np.int32)
+    c.dij = synth.cells._dij(np.random.default_rng(5), c.lmax, full=True)
+    c.kpts = np.array([[0.31, -0.17, 0.05]])
+    log("hpsi tiny spd kpoint")
+    po, pl = problems(c)
+    psi = start_block(c, 6, po.npw)
+    got = _run(lib, pl, psi)
+    assert rel_err(got, ham.hpsi(po, psi)) < TOL
+    assert rel_err(got, (ham.dense_h(po) @ psi.T).T) < TOL
+
+
+def test_hpsi_non_cubic_grid(lib):
+    """N0 != N1 != N2 (3*5*8-like shapes exercise every radix and the pruned rows)."""
+    c = synth.make_cell(0, seed=23)
+    c.nr = (10, 12, 15)
+    log("hpsi grid 10x12x15")
+    po, pl = problems(c)
+    psi = start_block(c, 8, po.npw)
+    assert rel_err(_run(lib, pl, psi), ham.hpsi(po, psi)) < TOL
+
+
+def test_projections_match_oracle(lib):
+    import torch
+    c = synth.make_cell(1)
+    po, pl = problems(c)
+    psi = start_block(c, 16, po.npw)
+    x = to_gpu_block(psi)
+    P = torch.zeros((16, po.nproj), dtype=torch.complex128, device="cuda")
+    lib.pw_projections(pl, x, P)
+    torch.cuda.synchronize()
+    ref = ham.projections(po, psi).T
+    assert rel_err(P.cpu().numpy(), ref) < TOL
+
+
+def test_hpsi_config2_kpoint_bands(lib):
+    """Config-2 k-point 1 (72^3, s+p+d, 576 projectors): 24 bands, all checked."""
+    c = synth.make_cell(2)
+    log("hpsi cfg2 k1 24 bands")
+    po, pl = problems(c, ik=1, max_bands=24)
+    psi = start_block(c, 24, po.npw, ik=1)
+    got = _run(lib, pl, psi)
+    ref = ham.hpsi(po, psi)
+    assert rel_err(got, ref) < TOL
+
+
+def test_hpsi_config2_full_block_sampled(lib):
+    """Full config-2 launch (256 bands, one k-point): sampled bands vs the oracle,
+    plus Hermiticity <phi|H psi> = <H phi|psi>^* over pairs of GPU bands."""
+    c = synth.make_cell(2)
+    log("hpsi cfg2 gamma 256 bands")
+    po, pl = problems(c, ik=0, max_bands=256)
+    psi = start_block(c, 256, po.npw, ik=0)
+    got = _run(lib, pl, psi)
+    for n in (0, 97, 200, 255):
+        ref = ham.hpsi(po, psi[n:n + 1])[0]
+        assert rel_err(got[n], ref) < TOL, n
+    a = psi.conj() @ got.T           # <psi_m | H psi_n>
+    assert np.abs(a - a.conj().T).max() <= 1e-12 * np.abs(a).max()
+
+
+def test_precond_tpa_matches_oracle(lib):
+    import torch
+    c = synth.make_cell(1)
+    po, pl = problems(c)
+    rng = np.random.default_rng(8)
+    X = start_block(c, 16, po.npw)
+    R = rng.standard_normal(X.shape) + 1j * rng.standard_normal(X.shape)
+    xg, rg = to_gpu_block(X), to_gpu_block(R)
+    tg = torch.zeros_like(xg)
+    lib.pw_precond(pl, lib.PW_PRECOND_TPA, None, xg, rg, tg)
+    got = from_gpu_block(tg, po.npw)
+    ref = odv.tpa_apply(po.kinetic(), X.T, R.T).T
+    assert rel_err(got, ref) < TOL
+
+
+def test_sphere_outside_grid_is_shape_error(lib):
+    import torch
+    c = synth.make_cell(1)
+    po = ham.problem_from_cell(c)
+    v = torch.zeros((8, 8, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.PwError) as e:
+        lib.pw_problem_create(po.A, po.kfrac, c.ecut_ha, (8, 8, 8), po.miller, v, None, None, None)
+    assert e.value.status == -2
