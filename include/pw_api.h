@@ -178,6 +178,47 @@ pw_status pw_precond(pw_problem *p, int32_t kind, const double *theta,
                      int64_t nbands, const pw_mlp *net, void *stream);
 
 /*
+ * Block-Davidson state for the lowest nbands eigenpairs of one problem.
+ * max_subspace (>= 2*nbands; 0 = 3*nbands) bounds the search space; tol is
+ * the residual 2-norm target in Ha (|H x - theta x| < tol for every band).
+ * All subspace work (H_s = V^H H V, Cholesky orthonormalisation, the
+ * Hermitian eigensolve, Ritz vectors, residual norms) runs in FP64 on the
+ * GPU whatever the problem's precision form.  Allocates its device state.
+ */
+pw_status pw_davidson_create(pw_problem *p, int64_t nbands, int64_t max_subspace,
+                             double tol, void *stream, pw_davidson **out);
+pw_status pw_davidson_destroy(pw_davidson *d);
+
+/* Load and orthonormalise the start block (device complex128 [nbands][ld]),
+ * apply H, build the first subspace matrix.  PW_ERR_NUMERIC if rank deficient. */
+pw_status pw_davidson_init(pw_davidson *d, const void *psi0, int64_t ld, void *stream);
+
+/*
+ * One Davidson iteration: Rayleigh-Ritz in the current space, Ritz vectors,
+ * residuals and their norms; if not converged, preconditioned corrections
+ * for the unconverged bands, restart when the space is full, two rounds of
+ * classical Gram-Schmidt + Cholesky-QR, H on the new vectors and the
+ * bordered subspace matrix.  Reads the residual norms back (one host sync)
+ * and sets *converged.  Returns PW_ERR_NOT_FINITE on a non-finite norm.
+ */
+pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *net,
+                           void *stream, int32_t *converged);
+
+/* Up to max_iter calls of pw_davidson_step; PW_OK when converged, else
+ * PW_NOT_CONVERGED (positive) with the state left after max_iter steps. */
+pw_status pw_davidson_run(pw_davidson *d, int32_t max_iter, int32_t precond_kind,
+                          const pw_mlp *net, void *stream, int32_t *converged);
+
+/* Host copies of the current Ritz values / residual norms ([nbands] each,
+ * either may be NULL), the iteration count and the number of bands H has
+ * been applied to.  Synchronises the stream. */
+pw_status pw_davidson_query(pw_davidson *d, double *theta, double *resid,
+                            int32_t *iterations, int64_t *n_hpsi, void *stream);
+
+/* Copy the current Ritz vectors to x (device complex128 [nbands][ld]). */
+pw_status pw_davidson_vectors(pw_davidson *d, void *x, int64_t ld, void *stream);
+
+/*
  * Stage timing (instrumentation, off by default).  When enabled, every
  * kernel launch a call makes is bracketed by two HIP events recorded on the
  * call's stream; pw_profile_read synchronises on those events and returns

@@ -68,6 +68,14 @@ def _load():
         "pw_hpsi": (i32, [vp, vp, i64, vp, i64, i64, i32, vp]),
         "pw_projections": (i32, [vp, vp, i64, vp, i64, vp]),
         "pw_precond": (i32, [vp, i32, vp, vp, vp, vp, i64, i64, vp, vp]),
+        "pw_davidson_create": (i32, [vp, i64, i64, f64, vp, C.POINTER(vp)]),
+        "pw_davidson_destroy": (i32, [vp]),
+        "pw_davidson_init": (i32, [vp, vp, i64, vp]),
+        "pw_davidson_step": (i32, [vp, i32, vp, vp, C.POINTER(i32)]),
+        "pw_davidson_run": (i32, [vp, i32, i32, vp, vp, C.POINTER(i32)]),
+        "pw_davidson_query": (i32, [vp, C.POINTER(f64), C.POINTER(f64), C.POINTER(i32),
+                                    C.POINTER(i64), vp]),
+        "pw_davidson_vectors": (i32, [vp, vp, i64, vp]),
         "pw_profile_enable": (i32, [vp, i32]),
         "pw_profile_read": (i32, [vp, C.POINTER(f64), C.POINTER(i64), i32]),
     }
@@ -249,3 +257,95 @@ def pw_profile_read(prob: Problem, reset: bool = True) -> dict:
     n = (C.c_int64 * PW_NSTAGES)()
     _check(LIB.pw_profile_read(prob.handle, ms, n, 1 if reset else 0))
     return {STAGES[i]: (ms[i], n[i]) for i in range(len(STAGES)) if n[i] > 0}
+
+
+class Davidson:
+    """Owner of a pw_davidson handle."""
+
+    def __init__(self, prob: Problem, nbands: int, max_subspace: int = 0, tol: float = 5e-9,
+                 stream=None):
+        h = C.c_void_p()
+        _check(LIB.pw_davidson_create(prob.handle, int(nbands), int(max_subspace), float(tol),
+                                      _stream(stream), C.byref(h)))
+        self._h = h
+        self.prob = prob
+        self.nbands = int(nbands)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise PwError(-1, "Davidson handle already destroyed")
+        return self._h
+
+    def close(self):
+        if self._h:
+            LIB.pw_davidson_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pw_davidson_init(d: Davidson, psi0, stream=None) -> None:
+    ps, ld, nb = _band_block(psi0, "psi0", d.prob.npw)
+    if nb < d.nbands:
+        raise ValueError("psi0 has fewer bands than the solver")
+    _check(LIB.pw_davidson_init(d.handle, ps, ld, _stream(stream)))
+
+
+def pw_davidson_step(d: Davidson, precond: int = PW_PRECOND_TPA, net=None, stream=None) -> bool:
+    c = C.c_int32(0)
+    _check(LIB.pw_davidson_step(d.handle, int(precond), net.handle if net is not None else None,
+                                _stream(stream), C.byref(c)))
+    return bool(c.value)
+
+
+def pw_davidson_run(d: Davidson, max_iter: int = 200, precond: int = PW_PRECOND_TPA, net=None,
+                    stream=None) -> bool:
+    c = C.c_int32(0)
+    _check(LIB.pw_davidson_run(d.handle, int(max_iter), int(precond),
+                               net.handle if net is not None else None, _stream(stream), C.byref(c)))
+    return bool(c.value)
+
+
+def pw_davidson_query(d: Davidson, stream=None) -> dict:
+    th = np.zeros(d.nbands)
+    rh = np.zeros(d.nbands)
+    it = C.c_int32()
+    nh = C.c_int64()
+    dp = C.POINTER(C.c_double)
+    _check(LIB.pw_davidson_query(d.handle, th.ctypes.data_as(dp), rh.ctypes.data_as(dp),
+                                 C.byref(it), C.byref(nh), _stream(stream)))
+    return dict(theta=th, rho=rh, iterations=it.value, n_hpsi=nh.value)
+
+
+def pw_davidson_vectors(d: Davidson, x, stream=None) -> None:
+    ps, ld, nb = _band_block(x, "x", d.prob.npw)
+    if nb < d.nbands:
+        raise ValueError("x has fewer bands than the solver")
+    _check(LIB.pw_davidson_vectors(d.handle, ps, ld, _stream(stream)))
+
+
+def davidson_solve(prob: Problem, psi0, tol: float = 5e-9, max_subspace: int = 0,
+                   max_iter: int = 200, precond: int = PW_PRECOND_TPA, net=None,
+                   want_vectors: bool = False, stream=None) -> dict:
+    """create + init + run + query (+ vectors) on one problem."""
+    import torch
+    nb = int(psi0.shape[0])
+    d = Davidson(prob, nb, max_subspace, tol, stream)
+    try:
+        pw_davidson_init(d, psi0, stream)
+        conv = pw_davidson_run(d, max_iter, precond, net, stream)
+        out = pw_davidson_query(d, stream)
+        out["converged"] = conv
+        if want_vectors:
+            x = torch.zeros_like(psi0)
+            pw_davidson_vectors(d, x, stream)
+            torch.cuda.synchronize()
+            out["X"] = x
+    finally:
+        d.close()
+    return out

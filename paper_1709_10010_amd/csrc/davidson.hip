@@ -1,0 +1,366 @@
+// Block Davidson driver (host side of the C ABI; all arithmetic in kernels).
+//
+// One iteration, in the order of the block Davidson method (Davidson 1975,
+// which the paper cites for its Davidson-like solver; subspace
+// diagonalisation as in PWscf's iterative diagonalisation):
+//   1. Hermitian eigensolve of the subspace matrix H_s = V^H H V (FP64);
+//   2. Ritz vectors X = V Y, HX = W Y (W = H V kept alongside V);
+//   3. residuals R = HX - X theta and their norms -> host (the one sync);
+//   4. if not converged: preconditioned corrections for the unconverged
+//      bands (soft locking), restart V = X, W = HX, H_s = diag(theta) when
+//      the space is full, two rounds of classical Gram-Schmidt (twice)
+//      + Cholesky-QR against the space (rank-revealing fallback through
+//      an eigendecomposition when Cholesky breaks down), H on the new
+//      vectors, and the bordered subspace matrix.
+// Everything runs in FP64 on the GPU; the problem's precision form only
+// changes how H is applied.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace pw {
+int eig_herm(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz, void *rot_ws,
+             double *acc_ws, int *sweeps, int coop_blocks, hipStream_t s);
+int coop_jacobi_blocks();
+int eig_select(const double *w, int m, int nsel, double *wsel, int *idx, const double2 *Z, int64_t ldz,
+               double2 *Y, int64_t ldy, hipStream_t s);
+int cholesky(const double2 *S, int64_t lds, int n, double2 *L, int64_t ldl, double rel, int *flag,
+             hipStream_t s);
+int trinv_h(const double2 *L, int64_t ldl, int n, double2 *X, int64_t ldx, double2 *B, int64_t ldb,
+            hipStream_t s);
+int residual(const double2 *X, const double2 *HX, const double *theta, double2 *R, int64_t ld,
+             int64_t npw, int nb, double *rho, hipStream_t s);
+int hermitize(double2 *H, int64_t ldh, int m0, int m1, hipStream_t s);
+int set_diag(double2 *H, int64_t ldh, int n, const double *theta, hipStream_t s);
+int copy_mat(const double2 *src, int64_t lds, double2 *dst, int64_t ldd, int m, int n, hipStream_t s);
+int scaled_cols(const double2 *U, int64_t ldu, const double *lam, const int *keep, int n, int nk,
+                double2 *B, int64_t ldb, hipStream_t s);
+int precond_idx(const double *kin, const double *tn, const int *idx, const double2 *R, int64_t ldr,
+                double2 *T, int64_t ldt, int64_t npw, int nu, int kind, hipStream_t s);
+int band_kinetic(const double *kin, const void *x, int64_t ld, int64_t npw, int nb, double *tn,
+                 hipStream_t s);
+}  // namespace pw
+
+using namespace pw;
+
+struct pw_davidson {
+  pw_problem *p = nullptr;
+  int nb = 0, mmax = 0, lde = 0;
+  double tol = 0;
+  int64_t ld = 0, npw = 0;
+  int m = 0, iter = 0, coop = 0;
+  int64_t n_hpsi = 0;
+  bool inited = false, converged = false;
+  double2 *V = nullptr, *W = nullptr, *X = nullptr, *HX = nullptr, *R = nullptr, *T = nullptr;
+  double2 *Hs = nullptr, *Ae = nullptr, *Ze = nullptr, *Y = nullptr, *C = nullptr;
+  double2 *S = nullptr, *L = nullptr, *Xi = nullptr, *Bi = nullptr;
+  double *w_all = nullptr, *theta = nullptr, *rho = nullptr, *tn = nullptr, *lam = nullptr;
+  int *idx_sel = nullptr, *dU = nullptr, *keep = nullptr, *flag = nullptr, *sweeps = nullptr;
+  void *rot_ws = nullptr;
+  double *acc_ws = nullptr;
+  void *part = nullptr;
+  size_t part_bytes = 0;
+  // pinned host mirrors
+  double *h_theta = nullptr, *h_rho = nullptr, *h_lam = nullptr;
+  int *h_U = nullptr, *h_flag = nullptr, *h_keep = nullptr;
+};
+
+namespace {
+
+void free_dav(pw_davidson *d) {
+  if (!d) return;
+  void *dev[] = {d->V,  d->W,  d->X,  d->HX,    d->R,     d->T,    d->Hs,    d->Ae,  d->Ze,
+                 d->Y,  d->C,  d->S,  d->L,     d->Xi,    d->Bi,   d->w_all, d->theta, d->rho,
+                 d->tn, d->lam, d->idx_sel, d->dU, d->keep, d->flag, d->sweeps, d->rot_ws,
+                 d->acc_ws, d->part};
+  for (void *b : dev)
+    if (b) (void)hipFree(b);
+  void *host[] = {d->h_theta, d->h_rho, d->h_lam, d->h_U, d->h_flag, d->h_keep};
+  for (void *b : host)
+    if (b) (void)hipHostFree(b);
+  delete d;
+}
+
+template <typename T>
+bool dalloc(T **p, size_t n) {
+  return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T)) == hipSuccess;
+}
+template <typename T>
+bool halloc(T **p, size_t n) {
+  return hipHostMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T), hipHostMallocDefault) == hipSuccess;
+}
+
+int cn(pw_davidson *d, int64_t M, int64_t N, const double2 *A, const double2 *B, double2 *Cm,
+       int64_t ldc, hipStream_t s) {
+  ProfScope ps(&d->p->prof, PW_STAGE_SUBGEMM, s);
+  int splits = choose_splits(M, N, d->npw);
+  while (splits > 1 && (size_t)splits * M * N * 16 > d->part_bytes) --splits;
+  return zgemm_cn(M, N, d->npw, A, d->ld, B, d->ld, Cm, ldc, splits, d->part, s);
+}
+
+int nn(pw_davidson *d, int64_t N, int64_t K, double alpha, const double2 *A, const double2 *B,
+       int64_t ldb, double beta, double2 *Cm, hipStream_t s) {
+  ProfScope ps(&d->p->prof, PW_STAGE_UPDGEMM, s);
+  return zgemm_nn(d->npw, N, K, alpha, A, d->ld, B, ldb, beta, Cm, d->ld, s);
+}
+
+#define DV_RC(x)              \
+  do {                        \
+    const int rc_ = (x);      \
+    if (rc_ != PW_OK) {       \
+      if (set_error_if_empty) \
+        set_error(where);     \
+      return rc_;             \
+    }                         \
+  } while (0)
+
+// Orthonormalise n columns at T against V[0:m] into dst; *n_out columns kept.
+int ortho_block(pw_davidson *d, int m, double2 *T, int n, double2 *dst, int *n_out, hipStream_t s) {
+  const bool set_error_if_empty = true;
+  const char *where = "pw_davidson: orthonormalisation failed";
+  double2 *src = T, *out = dst;
+  for (int round = 0; round < 2 && n > 0; ++round) {
+    if (m > 0) {
+      for (int c = 0; c < 2; ++c) {
+        DV_RC(cn(d, m, n, d->V, src, d->C, d->lde, s));
+        DV_RC(nn(d, n, m, -1.0, d->V, d->C, d->lde, 1.0, src, s));
+      }
+    }
+    DV_RC(cn(d, n, n, src, src, d->S, n, s));
+    {
+      ProfScope ps(&d->p->prof, PW_STAGE_CHOL, s);
+      DV_RC(cholesky(d->S, n, n, d->L, n, 1e-12, d->flag, s));
+    }
+    PW_HIP(hipMemcpyAsync(d->h_flag, d->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    PW_HIP(hipStreamSynchronize(s));
+    if (*d->h_flag == 0) {
+      {
+        ProfScope ps(&d->p->prof, PW_STAGE_CHOL, s);
+        DV_RC(trinv_h(d->L, n, n, d->Xi, n, d->Bi, n, s));
+      }
+      DV_RC(nn(d, n, n, 1.0, src, d->Bi, n, 0.0, out, s));
+    } else {
+      // rank-revealing path: S = U diag(lam) U^H, keep lam > 1e-12 max
+      {
+        ProfScope ps(&d->p->prof, PW_STAGE_EIG, s);
+        DV_RC(copy_mat(d->S, n, d->Ae, d->lde, n, n, s));
+        DV_RC(eig_herm(d->Ae, d->lde, n, d->lam, d->Ze, d->lde, d->rot_ws, d->acc_ws, d->sweeps,
+                       d->coop, s));
+      }
+      PW_HIP(hipMemcpyAsync(d->h_lam, d->lam, n * sizeof(double), hipMemcpyDeviceToHost, s));
+      PW_HIP(hipStreamSynchronize(s));
+      double lmax = 0;
+      for (int i = 0; i < n; ++i) lmax = std::max(lmax, d->h_lam[i]);
+      int nk = 0;
+      for (int i = 0; i < n; ++i)
+        if (std::isfinite(d->h_lam[i]) && d->h_lam[i] > 1e-12 * lmax) d->h_keep[nk++] = i;
+      PW_HIP(hipMemcpyAsync(d->keep, d->h_keep, nk * sizeof(int), hipMemcpyHostToDevice, s));
+      if (nk > 0) {
+        DV_RC(scaled_cols(d->Ze, d->lde, d->lam, d->keep, n, nk, d->Bi, n, s));
+        DV_RC(nn(d, nk, n, 1.0, src, d->Bi, n, 0.0, out, s));
+      }
+      n = nk;
+    }
+    std::swap(src, out);
+  }
+  // after two rounds the result sits in T (src after the final swap)
+  if (src != dst && n > 0)
+    PW_HIP(hipMemcpyAsync(dst, src, (size_t)n * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  *n_out = n;
+  return PW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pw_status pw_davidson_create(pw_problem *p, int64_t nbands, int64_t max_subspace, double tol,
+                             void *stream, pw_davidson **out) {
+  PW_CHECK_ARG(p && out, PW_ERR_INVALID, "pw_davidson_create: null argument");
+  *out = nullptr;
+  PW_CHECK_ARG(nbands >= 1 && nbands <= p->max_bands && nbands <= p->npw, PW_ERR_INVALID,
+               "pw_davidson_create: nbands must be in 1 .. min(max_bands, npw)");
+  if (max_subspace == 0) max_subspace = 3 * nbands;
+  PW_CHECK_ARG(max_subspace >= 2 * nbands && max_subspace <= p->npw && max_subspace <= 8192,
+               PW_ERR_INVALID, "pw_davidson_create: max_subspace must be in 2*nbands .. min(npw, 8192)");
+  PW_CHECK_ARG(tol > 0 && std::isfinite(tol), PW_ERR_INVALID, "pw_davidson_create: tol must be > 0");
+  pw_davidson *d = new pw_davidson();
+  d->p = p;
+  d->nb = (int)nbands;
+  d->mmax = (int)max_subspace;
+  d->lde = (d->mmax + 1) & ~1;
+  d->tol = tol;
+  d->npw = p->npw;
+  d->ld = (p->npw + 63) / 64 * 64;
+  const size_t blk = (size_t)d->ld;
+  const size_t nb = d->nb, lde = d->lde;
+  bool ok = dalloc(&d->V, lde * blk) && dalloc(&d->W, lde * blk) && dalloc(&d->X, nb * blk) &&
+            dalloc(&d->HX, nb * blk) && dalloc(&d->R, nb * blk) && dalloc(&d->T, nb * blk) &&
+            dalloc(&d->Hs, lde * lde) && dalloc(&d->Ae, lde * lde) && dalloc(&d->Ze, lde * lde) &&
+            dalloc(&d->Y, lde * nb) && dalloc(&d->C, lde * nb) && dalloc(&d->S, nb * nb) &&
+            dalloc(&d->L, nb * nb) && dalloc(&d->Xi, nb * nb) && dalloc(&d->Bi, nb * nb) &&
+            dalloc(&d->w_all, lde) && dalloc(&d->theta, nb) && dalloc(&d->rho, nb) &&
+            dalloc(&d->tn, nb) && dalloc(&d->lam, lde) && dalloc(&d->idx_sel, nb) &&
+            dalloc(&d->dU, nb) && dalloc(&d->keep, nb) && dalloc(&d->flag, 1) &&
+            dalloc(&d->sweeps, 1) && dalloc((char **)&d->rot_ws, lde * 32) &&
+            dalloc(&d->acc_ws, 128) && halloc(&d->h_theta, nb) && halloc(&d->h_rho, nb) &&
+            halloc(&d->h_lam, lde) && halloc(&d->h_U, nb) && halloc(&d->h_flag, 1) &&
+            halloc(&d->h_keep, nb);
+  d->part_bytes = (size_t)32 * lde * nb * sizeof(double2);
+  ok = ok && dalloc((char **)&d->part, d->part_bytes);
+  if (!ok) {
+    free_dav(d);
+    set_error("pw_davidson_create: device allocation failed");
+    return PW_ERR_NOMEM;
+  }
+  (void)hipMemsetAsync(d->Hs, 0, lde * lde * sizeof(double2), static_cast<hipStream_t>(stream));
+  d->coop = coop_jacobi_blocks();
+  if (d->coop <= 0 && d->lde > 64) {
+    free_dav(d);
+    set_error("pw_davidson_create: cooperative launch not available");
+    return PW_ERR_HIP;
+  }
+  *out = d;
+  return PW_OK;
+}
+
+pw_status pw_davidson_destroy(pw_davidson *d) {
+  if (d) {
+    (void)hipDeviceSynchronize();
+    free_dav(d);
+  }
+  return PW_OK;
+}
+
+pw_status pw_davidson_init(pw_davidson *d, const void *psi0, int64_t ld, void *stream) {
+  PW_CHECK_ARG(d && psi0, PW_ERR_INVALID, "pw_davidson_init: null argument");
+  PW_CHECK_ARG(ld >= d->npw, PW_ERR_INVALID, "pw_davidson_init: ld < npw");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool set_error_if_empty = true;
+  const char *where = "pw_davidson_init: launch failed";
+  PW_HIP(hipMemsetAsync(d->T, 0, (size_t)d->nb * d->ld * sizeof(double2), s));
+  PW_HIP(hipMemcpy2DAsync(d->T, d->ld * sizeof(double2), psi0, ld * sizeof(double2),
+                          d->npw * sizeof(double2), d->nb, hipMemcpyDeviceToDevice, s));
+  int nk = 0;
+  DV_RC(ortho_block(d, 0, d->T, d->nb, d->V, &nk, s));
+  PW_CHECK_ARG(nk == d->nb, PW_ERR_NUMERIC, "pw_davidson_init: start block is rank deficient");
+  DV_RC(pw_hpsi(d->p, d->V, d->ld, d->W, d->ld, d->nb, PW_TERM_ALL, s));
+  DV_RC(cn(d, d->nb, d->nb, d->V, d->W, d->Hs, d->lde, s));
+  DV_RC(hermitize(d->Hs, d->lde, 0, d->nb, s));
+  d->m = d->nb;
+  d->iter = 0;
+  d->n_hpsi = d->nb;
+  d->inited = true;
+  d->converged = false;
+  return PW_OK;
+}
+
+pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *net, void *stream,
+                           int32_t *converged) {
+  PW_CHECK_ARG(d && d->inited, PW_ERR_INVALID, "pw_davidson_step: state not initialised");
+  (void)net;
+  PW_CHECK_ARG(precond_kind == PW_PRECOND_NONE || precond_kind == PW_PRECOND_TPA, PW_ERR_INVALID,
+               "pw_davidson_step: unknown preconditioner");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool set_error_if_empty = true;
+  const char *where = "pw_davidson_step: launch failed";
+  const int nb = d->nb;
+  // 1. Rayleigh-Ritz
+  {
+    ProfScope ps(&d->p->prof, PW_STAGE_EIG, s);
+    DV_RC(copy_mat(d->Hs, d->lde, d->Ae, d->lde, d->m, d->m, s));
+    DV_RC(eig_herm(d->Ae, d->lde, d->m, d->w_all, d->Ze, d->lde, d->rot_ws, d->acc_ws, d->sweeps,
+                   d->coop, s));
+    DV_RC(eig_select(d->w_all, d->m, nb, d->theta, d->idx_sel, d->Ze, d->lde, d->Y, d->lde, s));
+  }
+  // 2. Ritz vectors
+  DV_RC(nn(d, nb, d->m, 1.0, d->V, d->Y, d->lde, 0.0, d->X, s));
+  DV_RC(nn(d, nb, d->m, 1.0, d->W, d->Y, d->lde, 0.0, d->HX, s));
+  // 3. residuals
+  {
+    ProfScope ps(&d->p->prof, PW_STAGE_VEC, s);
+    DV_RC(residual(d->X, d->HX, d->theta, d->R, d->ld, d->npw, nb, d->rho, s));
+  }
+  PW_HIP(hipMemcpyAsync(d->h_theta, d->theta, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+  PW_HIP(hipMemcpyAsync(d->h_rho, d->rho, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+  PW_HIP(hipStreamSynchronize(s));
+  d->iter++;
+  for (int n = 0; n < nb; ++n)
+    if (!std::isfinite(d->h_theta[n]) || !std::isfinite(d->h_rho[n])) {
+      set_error("pw_davidson_step: non-finite Ritz value or residual");
+      return PW_ERR_NOT_FINITE;
+    }
+  int nu = 0;
+  for (int n = 0; n < nb; ++n)
+    if (d->h_rho[n] >= d->tol) d->h_U[nu++] = n;
+  d->converged = (nu == 0);
+  if (converged) *converged = d->converged ? 1 : 0;
+  if (d->converged) return PW_OK;
+  PW_HIP(hipMemcpyAsync(d->dU, d->h_U, nu * sizeof(int), hipMemcpyHostToDevice, s));
+  // 4. preconditioned corrections for the unconverged bands
+  {
+    ProfScope ps(&d->p->prof, PW_STAGE_PRECOND, s);
+    DV_RC(band_kinetic(d->p->d_kin, d->X, d->ld, d->npw, nb, d->tn, s));
+    DV_RC(precond_idx(d->p->d_kin, d->tn, d->dU, d->R, d->ld, d->T, d->ld, d->npw, nu,
+                      precond_kind, s));
+  }
+  // 5. restart with the Ritz vectors when the space is full
+  if (d->m + nu > d->mmax) {
+    PW_HIP(hipMemcpyAsync(d->V, d->X, (size_t)nb * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    PW_HIP(hipMemcpyAsync(d->W, d->HX, (size_t)nb * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    DV_RC(set_diag(d->Hs, d->lde, nb, d->theta, s));
+    d->m = nb;
+  }
+  // 6. orthonormalise against the space
+  int nk = 0;
+  double2 *Vn = d->V + (size_t)d->m * d->ld;
+  double2 *Wn = d->W + (size_t)d->m * d->ld;
+  DV_RC(ortho_block(d, d->m, d->T, nu, Vn, &nk, s));
+  if (nk == 0) {
+    set_error("pw_davidson_step: every correction was linearly dependent on the space");
+    return PW_ERR_NUMERIC;
+  }
+  // 7. H on the new vectors, bordered subspace matrix
+  DV_RC(pw_hpsi(d->p, Vn, d->ld, Wn, d->ld, nk, PW_TERM_ALL, s));
+  d->n_hpsi += nk;
+  DV_RC(cn(d, d->m + nk, nk, d->V, Wn, d->Hs + (size_t)d->m * d->lde, d->lde, s));
+  DV_RC(hermitize(d->Hs, d->lde, d->m, d->m + nk, s));
+  d->m += nk;
+  return PW_OK;
+}
+
+pw_status pw_davidson_run(pw_davidson *d, int32_t max_iter, int32_t precond_kind, const pw_mlp *net,
+                          void *stream, int32_t *converged) {
+  PW_CHECK_ARG(d && max_iter >= 1, PW_ERR_INVALID, "pw_davidson_run: bad argument");
+  int32_t c = 0;
+  for (int it = 0; it < max_iter; ++it) {
+    const int rc = pw_davidson_step(d, precond_kind, net, stream, &c);
+    if (rc != PW_OK) return rc;
+    if (c) break;
+  }
+  if (converged) *converged = c;
+  return c ? PW_OK : PW_NOT_CONVERGED;
+}
+
+pw_status pw_davidson_query(pw_davidson *d, double *theta, double *resid, int32_t *iterations,
+                            int64_t *n_hpsi, void *stream) {
+  PW_CHECK_ARG(d, PW_ERR_INVALID, "pw_davidson_query: null state");
+  PW_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  if (theta) std::copy(d->h_theta, d->h_theta + d->nb, theta);
+  if (resid) std::copy(d->h_rho, d->h_rho + d->nb, resid);
+  if (iterations) *iterations = d->iter;
+  if (n_hpsi) *n_hpsi = d->n_hpsi;
+  return PW_OK;
+}
+
+pw_status pw_davidson_vectors(pw_davidson *d, void *x, int64_t ld, void *stream) {
+  PW_CHECK_ARG(d && x && ld >= d->npw, PW_ERR_INVALID, "pw_davidson_vectors: bad argument");
+  PW_HIP(hipMemcpy2DAsync(x, ld * sizeof(double2), d->X, d->ld * sizeof(double2),
+                          d->npw * sizeof(double2), d->nb, hipMemcpyDeviceToDevice,
+                          static_cast<hipStream_t>(stream)));
+  return PW_OK;
+}
+
+}  // extern "C"

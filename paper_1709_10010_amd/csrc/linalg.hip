@@ -1,0 +1,576 @@
+// Dense FP64 linear algebra of the Davidson subspace (gfx950).
+//
+// The paper names subspace diagonalisation as the most expensive dense
+// linear-algebra step of PWscf's iterative diagonalisation, done there with
+// ScaLAPACK / ELPA on the linear-algebra group (section on new
+// parallelization levels).  Here the subspace matrix lives on the GPU and
+// is diagonalised by a cyclic two-sided Jacobi method (Hermitian case),
+// chosen because every rotation of one round is independent:
+//
+//   round r pairs the indices (p, q) by the round-robin (circle) schedule;
+//   phase 1 computes each pair's unitary J = D R, with D = diag(1, e^{-i phi})
+//           taking a_pq = |a_pq| e^{i phi} to a real number and R the real
+//           rotation (c, s) that zeroes it (t = tan of the smaller angle);
+//   phase 2 applies  A <- J^H A J  block by block (each 2x2 block (a, b)
+//           becomes J_a^H A_ab J_b) and accumulates  Z <- Z J.
+// A sweep is m'-1 rounds (m' = m rounded up to even; a padding index has a
+// zero row so its rotations are the identity).  Sweeps repeat until the
+// off-diagonal mass is below (1e-15)^2 of the total, at most kMaxSweeps.
+//
+// Small matrices (m' <= 64) run in one workgroup with A and Z in LDS; larger
+// ones run as a cooperative grid with both phases separated by grid-wide
+// barriers.  Both are bounded: every wave leaves after at most kMaxSweeps.
+//
+// Also here: eigenvalue sort / Ritz-vector selection, Cholesky of a small
+// Hermitian positive matrix with breakdown detection, the inverse of its
+// triangular factor, and the small elementwise kernels of a Davidson step.
+#include <hip/hip_cooperative_groups.h>
+
+#include "common.h"
+
+namespace cg = cooperative_groups;
+
+namespace pw {
+
+constexpr int kMaxSweeps = 40;
+
+struct Rot {
+  double c, s, er, ei;  // J = [[c, s], [-s e, c e]],  e = er + i ei = e^{-i phi}
+};
+
+__device__ __forceinline__ double2 cm(double2 a, double2 b) {
+  return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ double2 cmc(double2 a, double2 b) {  // conj(a) * b
+  return double2{a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return double2{a.x + b.x, a.y + b.y}; }
+
+__device__ __forceinline__ Rot make_rot(double alpha, double gamma, double2 beta) {
+  Rot r{1.0, 0.0, 1.0, 0.0};
+  const double ab = sqrt(beta.x * beta.x + beta.y * beta.y);
+  if (ab == 0.0 || ab <= 1e-300) return r;
+  const double tau = (gamma - alpha) / (2.0 * ab);
+  const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  r.c = c;
+  r.s = t * c;
+  r.er = beta.x / ab;   // e^{-i phi} = conj(beta) / |beta|
+  r.ei = -beta.y / ab;
+  return r;
+}
+
+// J entries: j11 = c, j12 = s, j21 = -s e, j22 = c e.
+__device__ __forceinline__ void rot_entries(const Rot &r, double2 &j11, double2 &j12, double2 &j21,
+                                            double2 &j22) {
+  j11 = double2{r.c, 0.0};
+  j12 = double2{r.s, 0.0};
+  j21 = double2{-r.s * r.er, -r.s * r.ei};
+  j22 = double2{r.c * r.er, r.c * r.ei};
+}
+
+// Indices of pair k in round r for m' (even) indices.
+__device__ __forceinline__ void pair_of(int k, int r, int mp, int *p, int *q) {
+  const int n1 = mp - 1;
+  if (k == 0) {
+    *p = 0;
+    *q = 1 + (r % n1);
+  } else {
+    *p = 1 + ((k + r) % n1);
+    *q = 1 + ((mp - 1 - k + r) % n1);
+  }
+}
+
+// New 2x2 block = Ja^H [a b; c d] Jb, with [a b; c d] = A[{pa,qa}][{pb,qb}].
+__device__ __forceinline__ void update_block(double2 &a, double2 &b, double2 &c, double2 &d,
+                                             const Rot &ra, const Rot &rb) {
+  double2 a11, a12, a21, a22, b11, b12, b21, b22;
+  rot_entries(ra, a11, a12, a21, a22);
+  rot_entries(rb, b11, b12, b21, b22);
+  // T = X Jb
+  const double2 t11 = cadd(cm(a, b11), cm(b, b21));
+  const double2 t12 = cadd(cm(a, b12), cm(b, b22));
+  const double2 t21 = cadd(cm(c, b11), cm(d, b21));
+  const double2 t22 = cadd(cm(c, b12), cm(d, b22));
+  // Ja^H T: (Ja^H)_11 = conj(a11), _12 = conj(a21), _21 = conj(a12), _22 = conj(a22)
+  a = cadd(cmc(a11, t11), cmc(a21, t21));
+  b = cadd(cmc(a11, t12), cmc(a21, t22));
+  c = cadd(cmc(a12, t11), cmc(a22, t21));
+  d = cadd(cmc(a12, t12), cmc(a22, t22));
+}
+
+__device__ __forceinline__ void update_zrow(double2 &zp, double2 &zq, const Rot &r) {
+  double2 j11, j12, j21, j22;
+  rot_entries(r, j11, j12, j21, j22);
+  const double2 np = cadd(cm(zp, j11), cm(zq, j21));
+  const double2 nq = cadd(cm(zp, j12), cm(zq, j22));
+  zp = np;
+  zq = nq;
+}
+
+// ---------------------------------------------------------------- LDS Jacobi
+// A: m x m (lda), Hermitian; on exit w[i] = eigenvalue i (unsorted) and
+// Z (ldz) the eigenvectors (column i).  mp = m rounded up to even <= 64.
+__global__ __launch_bounds__(256) void k_jacobi_lds(const double2 *__restrict__ Ain, int64_t lda,
+                                                    int m, double *__restrict__ w,
+                                                    double2 *__restrict__ Z, int64_t ldz,
+                                                    int *__restrict__ sweeps_out) {
+  constexpr int MP = 64;
+  __shared__ double2 A[MP][MP + 1];
+  __shared__ double2 Zs[MP][MP + 1];
+  __shared__ Rot rot[MP / 2];
+  __shared__ double red[256];
+  __shared__ int done;
+  const int tid = threadIdx.x;
+  const int mp = (m + 1) & ~1;
+  const int np = mp / 2;
+  for (int e = tid; e < mp * mp; e += 256) {
+    const int i = e % mp, j = e / mp;
+    A[i][j] = (i < m && j < m) ? Ain[i + j * lda] : double2{0.0, 0.0};
+    Zs[i][j] = double2{i == j ? 1.0 : 0.0, 0.0};
+  }
+  __syncthreads();
+  int sweep = 0;
+  for (; sweep < kMaxSweeps; ++sweep) {
+    // convergence test on the current matrix
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < mp * mp; e += 256) {
+      const int i = e % mp, j = e / mp;
+      const double v = A[i][j].x * A[i][j].x + A[i][j].y * A[i][j].y;
+      tot += v;
+      if (i != j) off += v;
+    }
+    red[tid] = off;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) red[tid] += red[tid + s];
+      __syncthreads();
+    }
+    const double offs = red[0];
+    __syncthreads();
+    red[tid] = tot;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) red[tid] += red[tid + s];
+      __syncthreads();
+    }
+    if (tid == 0) done = (offs <= 1e-30 * red[0]) ? 1 : 0;
+    __syncthreads();
+    if (done) break;
+    for (int r = 0; r < mp - 1; ++r) {
+      if (tid < np) {
+        int p, q;
+        pair_of(tid, r, mp, &p, &q);
+        rot[tid] = make_rot(A[p][p].x, A[q][q].x, A[p][q]);
+      }
+      __syncthreads();
+      for (int e = tid; e < np * np; e += 256) {
+        const int ka = e % np, kb = e / np;
+        int pa, qa, pb, qb;
+        pair_of(ka, r, mp, &pa, &qa);
+        pair_of(kb, r, mp, &pb, &qb);
+        double2 a = A[pa][pb], b = A[pa][qb], c = A[qa][pb], d = A[qa][qb];
+        update_block(a, b, c, d, rot[ka], rot[kb]);
+        A[pa][pb] = a;
+        A[pa][qb] = b;
+        A[qa][pb] = c;
+        A[qa][qb] = d;
+      }
+      for (int e = tid; e < mp * np; e += 256) {
+        const int i = e % mp, kb = e / mp;
+        int pb, qb;
+        pair_of(kb, r, mp, &pb, &qb);
+        update_zrow(Zs[i][pb], Zs[i][qb], rot[kb]);
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < m; i += 256) w[i] = A[i][i].x;
+  for (int e = tid; e < m * m; e += 256) {
+    const int i = e % m, j = e / m;
+    Z[i + j * ldz] = Zs[i][j];
+  }
+  if (tid == 0 && sweeps_out) *sweeps_out = sweep;
+}
+
+// ---------------------------------------------------------------- cooperative Jacobi
+// A (lda) is overwritten; Z (ldz) must hold mp x mp; rot holds mp/2 Rot;
+// acc holds 2*kMaxSweeps doubles (zeroed here).
+__global__ __launch_bounds__(256) void k_jacobi_coop(double2 *__restrict__ A, int64_t lda, int m,
+                                                     double *__restrict__ w,
+                                                     double2 *__restrict__ Z, int64_t ldz,
+                                                     Rot *__restrict__ rot,
+                                                     double *__restrict__ acc,
+                                                     int *__restrict__ sweeps_out) {
+  cg::grid_group grid = cg::this_grid();
+  const int mp = (m + 1) & ~1;
+  const int np = mp / 2;
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+  __shared__ double red[2][256];
+  // pad row / column of an odd m, identity Z, zero the accumulators
+  for (int64_t e = gtid; e < (int64_t)mp * mp; e += gsz) {
+    const int i = (int)(e % mp), j = (int)(e / mp);
+    if (i >= m || j >= m) A[i + j * lda] = double2{0.0, 0.0};
+    Z[i + j * ldz] = double2{i == j ? 1.0 : 0.0, 0.0};
+  }
+  for (int64_t e = gtid; e < 2 * kMaxSweeps; e += gsz) acc[e] = 0.0;
+  grid.sync();
+  int sweep = 0;
+  for (; sweep < kMaxSweeps; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int64_t e = gtid; e < (int64_t)mp * mp; e += gsz) {
+      const int i = (int)(e % mp), j = (int)(e / mp);
+      const double2 v = A[i + j * lda];
+      const double a2 = v.x * v.x + v.y * v.y;
+      tot += a2;
+      if (i != j) off += a2;
+    }
+    red[0][threadIdx.x] = off;
+    red[1][threadIdx.x] = tot;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) {
+        red[0][threadIdx.x] += red[0][threadIdx.x + s];
+        red[1][threadIdx.x] += red[1][threadIdx.x + s];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      atomicAdd(&acc[2 * sweep], red[0][0]);
+      atomicAdd(&acc[2 * sweep + 1], red[1][0]);
+    }
+    grid.sync();
+    const double offs = __hip_atomic_load(&acc[2 * sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double tots = __hip_atomic_load(&acc[2 * sweep + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (offs <= 1e-30 * tots) break;  // uniform: every thread reads the same totals
+    for (int r = 0; r < mp - 1; ++r) {
+      for (int64_t k = gtid; k < np; k += gsz) {
+        int p, q;
+        pair_of((int)k, r, mp, &p, &q);
+        rot[k] = make_rot(A[p + p * lda].x, A[q + q * lda].x, A[p + q * lda]);
+      }
+      grid.sync();
+      for (int64_t e = gtid; e < (int64_t)np * np; e += gsz) {
+        const int ka = (int)(e % np), kb = (int)(e / np);
+        int pa, qa, pb, qb;
+        pair_of(ka, r, mp, &pa, &qa);
+        pair_of(kb, r, mp, &pb, &qb);
+        double2 a = A[pa + pb * lda], b = A[pa + qb * lda], c = A[qa + pb * lda], d = A[qa + qb * lda];
+        const Rot ra = rot[ka], rb = rot[kb];
+        update_block(a, b, c, d, ra, rb);
+        A[pa + pb * lda] = a;
+        A[pa + qb * lda] = b;
+        A[qa + pb * lda] = c;
+        A[qa + qb * lda] = d;
+      }
+      for (int64_t e = gtid; e < (int64_t)mp * np; e += gsz) {
+        const int i = (int)(e % mp), kb = (int)(e / mp);
+        int pb, qb;
+        pair_of(kb, r, mp, &pb, &qb);
+        const Rot rb = rot[kb];
+        update_zrow(Z[i + pb * ldz], Z[i + qb * ldz], rb);
+      }
+      grid.sync();
+    }
+  }
+  for (int64_t i = gtid; i < m; i += gsz) w[i] = A[i + i * lda].x;
+  if (gtid == 0 && sweeps_out) *sweeps_out = sweep;
+}
+
+// ---------------------------------------------------------------- sort / select
+// rank of each eigenvalue (ties by index); idx[rank] = i for rank < nsel.
+__global__ void k_eig_rank(const double *__restrict__ w, int m, int nsel, double *__restrict__ wsel,
+                           int *__restrict__ idx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double wi = w[i];
+  int r = 0;
+  for (int j = 0; j < m; ++j) {
+    const double wj = w[j];
+    r += (wj < wi || (wj == wi && j < i)) ? 1 : 0;
+  }
+  if (r < nsel) {
+    wsel[r] = wi;
+    idx[r] = i;
+  }
+}
+
+// Y[:, r] = Z[:, idx[r]] for r < nsel (Y: m x nsel, ldy).
+__global__ void k_gather_cols(const double2 *__restrict__ Z, int64_t ldz, const int *__restrict__ idx,
+                              int m, int nsel, double2 *__restrict__ Y, int64_t ldy) {
+  const int64_t tot = (int64_t)m * nsel;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / m), i = (int)(e % m);
+    Y[i + r * ldy] = Z[i + (int64_t)idx[r] * ldz];
+  }
+}
+
+// ---------------------------------------------------------------- Cholesky
+// S (lds) Hermitian positive n x n -> L lower (ldl, upper part zeroed).
+// flag[0] = first column whose pivot fell to <= rel * S_jj (or was not
+// finite) + 1, else 0.  One workgroup.
+__global__ __launch_bounds__(1024) void k_cholesky(const double2 *__restrict__ S, int64_t lds, int n,
+                                                   double2 *__restrict__ L, int64_t ldl, double rel,
+                                                   int *__restrict__ flag) {
+  __shared__ double piv;
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int64_t e = tid; e < (int64_t)n * n; e += blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    L[i + j * ldl] = (i >= j) ? S[i + j * lds] : double2{0.0, 0.0};
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (tid == 0) {
+      double d = L[j + j * ldl].x;
+      for (int k = 0; k < j; ++k) {
+        const double2 v = L[j + k * ldl];
+        d -= v.x * v.x + v.y * v.y;
+      }
+      const double s0 = S[j + j * lds].x;
+      if (!(d > rel * s0) || !isfinite(d)) {
+        if (!bad) bad = j + 1;
+        d = 1.0;
+      }
+      piv = sqrt(d);
+      L[j + j * ldl] = double2{piv, 0.0};
+    }
+    __syncthreads();
+    const double inv = 1.0 / piv;
+    for (int i = j + 1 + tid; i < n; i += blockDim.x) {
+      double2 acc = L[i + j * ldl];
+      for (int k = 0; k < j; ++k) {
+        const double2 a = L[i + k * ldl], b = L[j + k * ldl];  // a * conj(b)
+        acc.x -= a.x * b.x + a.y * b.y;
+        acc.y -= a.y * b.x - a.x * b.y;
+      }
+      L[i + j * ldl] = double2{acc.x * inv, acc.y * inv};
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *flag = bad;
+}
+
+// B = (L^{-1})^H (upper triangular, ldb): column c of X = L^{-1} e_c by
+// forward substitution, one thread per column; B[c][i] = conj(X[i][c]).
+__global__ void k_trinv_h(const double2 *__restrict__ L, int64_t ldl, int n, double2 *__restrict__ X,
+                          int64_t ldx, double2 *__restrict__ B, int64_t ldb) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  for (int i = 0; i < c; ++i) X[i + (int64_t)c * ldx] = double2{0.0, 0.0};
+  for (int i = c; i < n; ++i) {
+    double2 acc = double2{i == c ? 1.0 : 0.0, 0.0};
+    for (int k = c; k < i; ++k) {
+      const double2 a = L[i + k * ldl], x = X[k + (int64_t)c * ldx];
+      acc.x -= a.x * x.x - a.y * x.y;
+      acc.y -= a.x * x.y + a.y * x.x;
+    }
+    const double d = L[i + i * ldl].x;
+    X[i + (int64_t)c * ldx] = double2{acc.x / d, acc.y / d};
+  }
+  for (int i = 0; i < n; ++i) {
+    const double2 x = X[i + (int64_t)c * ldx];
+    B[c + (int64_t)i * ldb] = double2{x.x, -x.y};
+  }
+}
+
+// ---------------------------------------------------------------- small kernels
+// R = HX - X diag(theta);  rho2[n] = ||R_n||^2 (one block per band).
+__global__ __launch_bounds__(256) void k_residual(const double2 *__restrict__ X,
+                                                  const double2 *__restrict__ HX,
+                                                  const double *__restrict__ theta,
+                                                  double2 *__restrict__ R, int64_t ld, int64_t npw,
+                                                  double *__restrict__ rho) {
+  __shared__ double red[256];
+  const int b = blockIdx.x;
+  const double th = theta[b];
+  double s = 0.0;
+  for (int64_t g = threadIdx.x; g < npw; g += 256) {
+    const double2 x = X[b * ld + g], h = HX[b * ld + g];
+    const double2 r = double2{h.x - th * x.x, h.y - th * x.y};
+    R[b * ld + g] = r;
+    s += r.x * r.x + r.y * r.y;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rho[b] = sqrt(red[0]);
+}
+
+// Hermitise the new columns [m0, m1) of H (ldh): mirror the off-diagonal
+// rectangle into rows, average the new diagonal block with its adjoint.
+__global__ void k_hermitize(double2 *__restrict__ H, int64_t ldh, int m0, int m1) {
+  const int64_t nn = (int64_t)(m1 - m0) * m1;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nn;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = m0 + (int)(e / m1);
+    const int i = (int)(e % m1);
+    if (i < m0) {
+      const double2 v = H[i + j * ldh];
+      H[j + i * ldh] = double2{v.x, -v.y};
+    } else if (i < j) {
+      const double2 a = H[i + j * ldh], b = H[j + i * ldh];
+      const double2 v = double2{0.5 * (a.x + b.x), 0.5 * (a.y - b.y)};
+      H[i + j * ldh] = v;
+      H[j + i * ldh] = double2{v.x, -v.y};
+    } else if (i == j) {
+      H[i + j * ldh].y = 0.0;
+    }
+  }
+}
+
+// H[0:n, 0:n] = diag(theta)
+__global__ void k_set_diag(double2 *__restrict__ H, int64_t ldh, int n, const double *__restrict__ theta) {
+  const int64_t nn = (int64_t)n * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nn;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    H[i + j * ldh] = double2{i == j ? theta[i] : 0.0, 0.0};
+  }
+}
+
+// dst (m x n, ldd) = src (m x n, lds)
+__global__ void k_copy_mat(const double2 *__restrict__ src, int64_t lds, double2 *__restrict__ dst,
+                           int64_t ldd, int m, int n) {
+  const int64_t nn = (int64_t)m * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nn;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    dst[i + j * ldd] = src[i + j * lds];
+  }
+}
+
+// B[:, c] = U[:, keep[c]] / sqrt(lam[keep[c]]) (rank-revealing orthonormalisation)
+__global__ void k_scaled_cols(const double2 *__restrict__ U, int64_t ldu, const double *__restrict__ lam,
+                              const int *__restrict__ keep, int n, int nk, double2 *__restrict__ B,
+                              int64_t ldb) {
+  const int64_t nn = (int64_t)n * nk;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nn;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), c = (int)(e / n);
+    const int k = keep[c];
+    const double s = 1.0 / sqrt(lam[k]);
+    const double2 u = U[i + (int64_t)k * ldu];
+    B[i + (int64_t)c * ldb] = double2{u.x * s, u.y * s};
+  }
+}
+
+// T[i] = K(t/T_{idx[i]}) R[idx[i]] (TPA, or K = 1); tn from k_band_kinetic over X.
+__device__ __forceinline__ double tpa_k2(double x) {
+  const double num = 27.0 + x * (18.0 + x * (12.0 + x * 8.0));
+  const double x2 = x * x;
+  return num / (num + 16.0 * x2 * x2);
+}
+__global__ void k_precond_idx(const double *__restrict__ kin, const double *__restrict__ tn,
+                              const int *__restrict__ idx, const double2 *__restrict__ R, int64_t ldr,
+                              double2 *__restrict__ T, int64_t ldt, int64_t npw, int kind) {
+  const int i = blockIdx.y;
+  const int n = idx[i];
+  const double inv = 1.0 / tn[n];
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < npw;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const double2 v = R[(int64_t)n * ldr + g];
+    const double k = (kind == PW_PRECOND_TPA) ? tpa_k2(kin[g] * inv) : 1.0;
+    T[(int64_t)i * ldt + g] = double2{k * v.x, k * v.y};
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+static int grid_for(int64_t n, int bs = 256, int cap = 2048) {
+  int64_t b = (n + bs - 1) / bs;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+int eig_herm(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz, void *rot_ws,
+             double *acc_ws, int *sweeps, int coop_blocks, hipStream_t s) {
+  if (m <= 0) return PW_OK;
+  const int mp = (m + 1) & ~1;
+  if (mp <= 64) {
+    hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(256), 0, s, A, lda, m, w, Z, ldz, sweeps);
+    return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+  }
+  Rot *rot = static_cast<Rot *>(rot_ws);
+  void *args[] = {&A, &lda, &m, &w, &Z, &ldz, &rot, &acc_ws, &sweeps};
+  const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_jacobi_coop),
+                                                  dim3(coop_blocks), dim3(256), args, 0, s);
+  return e == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
+int coop_jacobi_blocks() {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void *>(k_jacobi_coop),
+                                                   256, 0) != hipSuccess)
+    return 0;
+  if (per > 2) per = 2;
+  return per * ncu;
+}
+
+int eig_select(const double *w, int m, int nsel, double *wsel, int *idx, const double2 *Z, int64_t ldz,
+               double2 *Y, int64_t ldy, hipStream_t s) {
+  hipLaunchKernelGGL(k_eig_rank, dim3((m + 255) / 256), dim3(256), 0, s, w, m, nsel, wsel, idx);
+  if (hipGetLastError() != hipSuccess) return PW_ERR_HIP;
+  hipLaunchKernelGGL(k_gather_cols, dim3(grid_for((int64_t)m * nsel)), dim3(256), 0, s, Z, ldz, idx, m,
+                     nsel, Y, ldy);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
+int cholesky(const double2 *S, int64_t lds, int n, double2 *L, int64_t ldl, double rel, int *flag,
+             hipStream_t s) {
+  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, S, lds, n, L, ldl, rel, flag);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
+int trinv_h(const double2 *L, int64_t ldl, int n, double2 *X, int64_t ldx, double2 *B, int64_t ldb,
+            hipStream_t s) {
+  hipLaunchKernelGGL(k_trinv_h, dim3((n + 63) / 64), dim3(64), 0, s, L, ldl, n, X, ldx, B, ldb);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
+int residual(const double2 *X, const double2 *HX, const double *theta, double2 *R, int64_t ld,
+             int64_t npw, int nb, double *rho, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(256), 0, s, X, HX, theta, R, ld, npw, rho);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
+int hermitize(double2 *H, int64_t ldh, int m0, int m1, hipStream_t s) {
+  hipLaunchKernelGGL(k_hermitize, dim3(grid_for((int64_t)(m1 - m0) * m1)), dim3(256), 0, s, H, ldh, m0, m1);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
+int set_diag(double2 *H, int64_t ldh, int n, const double *theta, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_diag, dim3(grid_for((int64_t)n * n)), dim3(256), 0, s, H, ldh, n, theta);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
+int copy_mat(const double2 *src, int64_t lds, double2 *dst, int64_t ldd, int m, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_mat, dim3(grid_for((int64_t)m * n)), dim3(256), 0, s, src, lds, dst, ldd, m, n);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
+int scaled_cols(const double2 *U, int64_t ldu, const double *lam, const int *keep, int n, int nk,
+                double2 *B, int64_t ldb, hipStream_t s) {
+  hipLaunchKernelGGL(k_scaled_cols, dim3(grid_for((int64_t)n * nk)), dim3(256), 0, s, U, ldu, lam, keep,
+                     n, nk, B, ldb);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
+int precond_idx(const double *kin, const double *tn, const int *idx, const double2 *R, int64_t ldr,
+                double2 *T, int64_t ldt, int64_t npw, int nu, int kind, hipStream_t s) {
+  if (nu <= 0) return PW_OK;
+  int bx = (int)((npw + 255) / 256);
+  if (bx > 256) bx = 256;
+  hipLaunchKernelGGL(k_precond_idx, dim3(bx, nu), dim3(256), 0, s, kin, tn, idx, R, ldr, T, ldt, npw, kind);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
+}  // namespace pw

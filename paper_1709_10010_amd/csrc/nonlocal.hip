@@ -93,6 +93,14 @@ __global__ void k_tpa(const double *__restrict__ kin, const double *__restrict__
   }
 }
 
+int band_kinetic(const double *kin, const void *x, int64_t ld, int64_t npw, int nb, double *tn,
+                 hipStream_t s) {
+  if (nb <= 0) return PW_OK;
+  hipLaunchKernelGGL(k_band_kinetic, dim3(nb), dim3(256), 0, s, kin, static_cast<const double2 *>(x),
+                     ld, npw, tn);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
 int launch_tpa(const double *kin, const void *x, const void *r, void *t, int64_t ld, int64_t npw,
                int nb, int kind, double *tn_work, hipStream_t s) {
   if (nb <= 0) return PW_OK;

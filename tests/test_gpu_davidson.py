@@ -1,0 +1,144 @@
+"""GPU block Davidson (pw_davidson_*) against dense diagonalisation and the oracle.
+
+Eigenvalues are unique, eigenvectors are not (phases, rotations inside
+degenerate clusters), so the checks are: Ritz values against LAPACK eigh of
+the oracle's dense H to the 1e-8 Ry target (5e-9 Ha) and within each band's
+residual norm (Weyl / Bauer-Fike); Ritz vectors orthonormal; and the residual
+||H x - theta x|| recomputed by the oracle's own H*psi below the tolerance.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import hamiltonian as ham
+
+from gpu_util import from_gpu_block, log, problems, start_block, to_gpu_block
+
+pytestmark = pytest.mark.gpu
+TOL = 5e-9  # Ha = 1e-8 Ry
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1709_10010_amd import _lib
+    return _lib
+
+
+def _solve(lib, cell, nb, ik=0, mmax=0, precond=1, seed_ik=0):
+    po, pl = problems(cell, ik=ik, max_bands=nb)
+    psi0 = start_block(cell, nb, po.npw, ik=seed_ik)
+    x0 = to_gpu_block(psi0)
+    res = lib.davidson_solve(pl, x0, tol=TOL, max_subspace=mmax, precond=precond, want_vectors=True)
+    X = from_gpu_block(res["X"], po.npw)
+    return po, res, X
+
+
+def _check_against_eigh(po, res, X, nb):
+    w, _ = ham.eigh_lowest(po, nb)
+    th = res["theta"]
+    assert res["converged"]
+    assert np.all(res["rho"] < TOL)
+    assert np.abs(th - w).max() < TOL
+    assert np.all(np.abs(th - w) <= res["rho"] + 1e-13)
+    G = X.conj() @ X.T
+    assert np.abs(G - np.eye(nb)).max() < 1e-11
+    R = ham.hpsi(po, X) - th[:, None] * X
+    rho_or = np.sqrt((np.abs(R) ** 2).sum(axis=1))
+    assert np.all(rho_or < TOL * 1.001), rho_or.max()
+
+
+def test_davidson_tiny_cell_lds_jacobi(lib):
+    c = synth.make_cell(0)
+    log("davidson tiny nb=8")
+    po, res, X = _solve(lib, c, 8)
+    log("iterations", res["iterations"], "n_hpsi", res["n_hpsi"])
+    _check_against_eigh(po, res, X, 8)
+
+
+def test_davidson_config1(lib):
+    c = synth.make_cell(1)
+    log("davidson cfg1 nb=16")
+    po, res, X = _solve(lib, c, 16)
+    log("iterations", res["iterations"], "n_hpsi", res["n_hpsi"])
+    _check_against_eigh(po, res, X, 16)
+
+
+def test_davidson_cooperative_jacobi_path(lib):
+    """nb = 40 -> subspace up to 120 > 64: the grid-synchronised eigensolver."""
+    c = synth.make_cell(1)
+    log("davidson cfg1 nb=40 (coop jacobi)")
+    po, res, X = _solve(lib, c, 40)
+    log("iterations", res["iterations"])
+    _check_against_eigh(po, res, X, 40)
+
+
+def test_davidson_tight_subspace_restarts(lib):
+    c = synth.make_cell(1)
+    log("davidson cfg1 mmax=2nb")
+    po, res, X = _solve(lib, c, 16, mmax=32)
+    _check_against_eigh(po, res, X, 16)
+
+
+def test_davidson_no_preconditioner(lib):
+    c = synth.make_cell(0)
+    po, res, X = _solve(lib, c, 8, precond=0)
+    _check_against_eigh(po, res, X, 8)
+
+
+def test_davidson_kpoint_full_d(lib):
+    c = synth.make_cell(0, seed=31)
+    c.lmax = np.full(c.natom, 2, dtype=np.int32)
+    c.dij = synth.cells._dij(np.random.default_rng(2), c.lmax, full=True)
+    c.kpts = np.array([[0.27, 0.11, -0.42]])
+    log("davidson tiny spd kpoint")
+    po, res, X = _solve(lib, c, 8)
+    _check_against_eigh(po, res, X, 8)
+
+
+def test_davidson_config2_kpoint_residuals(lib):
+    """Config-2 k-point 1 (npw 22232, 72^3, 576 projectors), 32 bands: the oracle
+    recomputes H x for sampled Ritz vectors; every residual must be below tol."""
+    c = synth.make_cell(2)
+    log("davidson cfg2 k1 nb=32")
+    po, res, X = _solve(lib, c, 32, ik=1, seed_ik=1)
+    log("iterations", res["iterations"], "n_hpsi", res["n_hpsi"])
+    assert res["converged"]
+    G = X.conj() @ X.T
+    assert np.abs(G - np.eye(32)).max() < 1e-11
+    for n in (0, 13, 31):
+        r = ham.hpsi(po, X[n:n + 1])[0] - res["theta"][n] * X[n]
+        assert np.linalg.norm(r) < TOL * 1.001
+    assert np.all(np.diff(res["theta"]) >= -1e-12)
+
+
+def test_davidson_rank_deficient_start(lib):
+    import torch
+    c = synth.make_cell(0)
+    po, pl = problems(c, max_bands=8)
+    psi0 = start_block(c, 8, po.npw)
+    psi0[3] = psi0[1] * (0.5 - 2j)
+    x0 = to_gpu_block(psi0)
+    with pytest.raises(lib.PwError) as e:
+        lib.davidson_solve(pl, x0, tol=TOL)
+    assert e.value.status == -6
+    torch.cuda.synchronize()
+
+
+def test_davidson_nan_start_is_reported(lib):
+    c = synth.make_cell(0)
+    po, pl = problems(c, max_bands=8)
+    psi0 = start_block(c, 8, po.npw)
+    psi0[2, 5] = np.nan
+    with pytest.raises(lib.PwError) as e:
+        lib.davidson_solve(pl, to_gpu_block(psi0), tol=TOL)
+    assert e.value.status in (-5, -6)
+
+
+def test_davidson_max_iter_not_converged(lib):
+    c = synth.make_cell(1)
+    po, pl = problems(c, max_bands=16)
+    x0 = to_gpu_block(start_block(c, 16, po.npw))
+    res = lib.davidson_solve(pl, x0, tol=TOL, max_iter=2)
+    assert not res["converged"] and res["iterations"] == 2
