@@ -139,7 +139,7 @@ def main():
             a[0] += ms
             a[1] += n
         _lib.pw_profile_enable(p, False)
-    group = int(os.environ.get("PW_PLANE_GROUP", "4"))
+    group = int(os.environ.get("PW_PLANE_GROUP", "8"))
     models = [stage_model(inf, cell.nbands, prec, group) for inf in infos]
     dom = max(stages, key=lambda k: stages[k][0])
     avg_ms = stages[dom][0] / stages[dom][1]

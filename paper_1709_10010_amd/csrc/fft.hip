@@ -27,6 +27,8 @@
 // thread loads its butterflies' R inputs into registers, applies the
 // twiddles and the R-point DFT, all threads barrier, then every thread
 // stores its outputs at their autosorted positions.  Radices 2, 3, 4, 5, 8.
+#include <cstdlib>
+
 #include "common.h"
 
 namespace pw {
@@ -131,6 +133,18 @@ template <bool INV, typename V> struct Dft<8, INV, V> {
 // ---------------------------------------------------------------- one Stockham pass
 constexpr int kCpt = 8;  // complex values per thread and pass (register budget)
 
+// q = a / d for 0 <= a < 2^22, 0 < d < 2^11, with inv = 1.0f / d: the float
+// product is within 1/2 of a/d, so the truncated quotient is off by at most
+// one and a single correction step makes it exact.  A few VALU instructions
+// instead of the generic integer-division sequence.
+__device__ __forceinline__ int qdiv(int a, int d, float inv) {
+  int q = (int)((float)a * inv);
+  const int r = a - q * d;
+  q += (r >= d) ? 1 : 0;
+  q -= (r < 0) ? 1 : 0;
+  return q;
+}
+
 // Lines of length N live in LDS at base(line) + pos * estride.  base(line) is
 // line * lstride, or lbase[line] when INDIRECT.  LINE_FAST maps consecutive
 // threads to consecutive lines (strided lines), else to consecutive
@@ -139,29 +153,32 @@ constexpr int kCpt = 8;  // complex values per thread and pass (register budget)
 template <typename V, int R, bool INV, bool LINE_FAST, bool INDIRECT>
 __device__ __forceinline__ void stockham_pass(V *buf, int nlines, int lstride, int estride,
                                               const int *lbase, int N, int Ns, const V *tw,
-                                              int tid, int nthr) {
+                                              int tid_in, int nthr) {
+  int tid = tid_in;  // opaque: see wave_pass
+  asm volatile("" : "+v"(tid));
   constexpr int MAXB = (kCpt + R - 1) / R;
   const int nbf = N / R;
   const int total = nlines * nbf;
   const int twstep = N / (Ns * R);
+  const int dsplit = LINE_FAST ? nlines : nbf;
+  const float isplit = 1.0f / (float)dsplit;
+  const float ins = 1.0f / (float)Ns;
   V v[MAXB][R];
+  int bo[MAXB], oo[MAXB];
 #pragma unroll
   for (int c = 0; c < MAXB; ++c) {
     const int idx = tid + c * nthr;
     if (idx < total) {
-      int line, j;
-      if (LINE_FAST) {
-        line = idx % nlines;
-        j = idx / nlines;
-      } else {
-        j = idx % nbf;
-        line = idx / nbf;
-      }
+      const int q = qdiv(idx, dsplit, isplit);
+      const int rem = idx - q * dsplit;
+      const int line = LINE_FAST ? rem : q;
+      const int j = LINE_FAST ? q : rem;
       const int base = INDIRECT ? lbase[line] : line * lstride;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[c][r] = buf[base + (j + r * nbf) * estride];
+      int k = 0;
       if (Ns > 1) {
-        const int k = j % Ns;
+        k = j - qdiv(j, Ns, ins) * Ns;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
           const V w = tw[k * r * twstep];
@@ -169,6 +186,8 @@ __device__ __forceinline__ void stockham_pass(V *buf, int nlines, int lstride, i
         }
       }
       Dft<R, INV, V>::run(v[c]);
+      bo[c] = base;
+      oo[c] = (j - k) * R + k;
     }
   }
   __syncthreads();
@@ -176,19 +195,8 @@ __device__ __forceinline__ void stockham_pass(V *buf, int nlines, int lstride, i
   for (int c = 0; c < MAXB; ++c) {
     const int idx = tid + c * nthr;
     if (idx < total) {
-      int line, j;
-      if (LINE_FAST) {
-        line = idx % nlines;
-        j = idx / nlines;
-      } else {
-        j = idx % nbf;
-        line = idx / nbf;
-      }
-      const int base = INDIRECT ? lbase[line] : line * lstride;
-      const int k = j % Ns;
-      const int out0 = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[base + (out0 + r * Ns) * estride] = v[c][r];
+      for (int r = 0; r < R; ++r) buf[bo[c] + (oo[c] + r * Ns) * estride] = v[c][r];
     }
   }
   __syncthreads();
@@ -206,6 +214,88 @@ __device__ void fft_lines(V *buf, int nlines, int lstride, int estride, const in
       case 4: stockham_pass<V, 4, INV, LINE_FAST, INDIRECT>(buf, nlines, lstride, estride, lbase, pl.n, Ns, tw, tid, nthr); break;
       case 5: stockham_pass<V, 5, INV, LINE_FAST, INDIRECT>(buf, nlines, lstride, estride, lbase, pl.n, Ns, tw, tid, nthr); break;
       default: stockham_pass<V, 8, INV, LINE_FAST, INDIRECT>(buf, nlines, lstride, estride, lbase, pl.n, Ns, tw, tid, nthr); break;
+    }
+    Ns *= R;
+  }
+}
+
+// ---------------------------------------------------------------- wave-local FFTs
+// One wavefront transforms lines it owns alone, so the read and write halves
+// of a Stockham pass need no workgroup barrier: the wave's LDS operations
+// execute in issue order and the compiler is kept from moving memory
+// operations across the pass boundary.  Lines are taken in register-sized
+// groups (ng * N <= kCpt * 64 values per pass) and each group runs all
+// passes before the next group starts.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <typename V, int R, bool INV, bool LINE_FAST, typename Base>
+__device__ __forceinline__ void wave_pass(V *buf, int ng, Base base, int estride, int N, int Ns,
+                                          const V *tw, int lane_in) {
+  // keep the per-lane index arithmetic inside the pass: hoisted out of the
+  // pass loop it would stay live for every radix case at once
+  int lane = lane_in;
+  asm volatile("" : "+v"(lane));
+  constexpr int MAXB = (kCpt + R - 1) / R;
+  const int nbf = N / R;
+  const int total = ng * nbf;
+  const int twstep = N / (Ns * R);
+  const int dsplit = LINE_FAST ? ng : nbf;
+  const float isplit = 1.0f / (float)dsplit;
+  const float ins = 1.0f / (float)Ns;
+  V v[MAXB][R];
+  int bo[MAXB], oo[MAXB];
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    const int idx = lane + c * 64;
+    if (idx < total) {
+      const int q = qdiv(idx, dsplit, isplit);
+      const int rem = idx - q * dsplit;
+      const int line = LINE_FAST ? rem : q;
+      const int j = LINE_FAST ? q : rem;
+      const int b0 = base(line);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[c][r] = buf[b0 + (j + r * nbf) * estride];
+      int k = 0;
+      if (Ns > 1) {
+        k = j - qdiv(j, Ns, ins) * Ns;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const V w = tw[k * r * twstep];
+          v[c][r] = INV ? c_mulconj(v[c][r], w) : c_mul(v[c][r], w);
+        }
+      }
+      Dft<R, INV, V>::run(v[c]);
+      bo[c] = b0;
+      oo[c] = (j - k) * R + k;
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    const int idx = lane + c * 64;
+    if (idx < total) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[bo[c] + (oo[c] + r * Ns) * estride] = v[c][r];
+    }
+  }
+  wave_sync();
+}
+
+template <typename V, bool INV, bool LINE_FAST, typename Base>
+__device__ __forceinline__ void wave_fft_group(V *buf, int ng, Base base, int estride,
+                                               const AxisPlan &pl, const V *tw, int lane) {
+  int Ns = 1;
+  for (int p = 0; p < pl.npass; ++p) {
+    const int R = pl.radix[p];
+    switch (R) {
+      case 2: wave_pass<V, 2, INV, LINE_FAST>(buf, ng, base, estride, pl.n, Ns, tw, lane); break;
+      case 3: wave_pass<V, 3, INV, LINE_FAST>(buf, ng, base, estride, pl.n, Ns, tw, lane); break;
+      case 4: wave_pass<V, 4, INV, LINE_FAST>(buf, ng, base, estride, pl.n, Ns, tw, lane); break;
+      case 5: wave_pass<V, 5, INV, LINE_FAST>(buf, ng, base, estride, pl.n, Ns, tw, lane); break;
+      default: wave_pass<V, 8, INV, LINE_FAST>(buf, ng, base, estride, pl.n, Ns, tw, lane); break;
     }
     Ns *= R;
   }
@@ -288,6 +378,76 @@ __global__ __launch_bounds__(NTHR) void k_plane(FFTDev f, cpx_t<T> *__restrict__
     __syncthreads();
     fft_lines<V, false, true, false>(pl, f.n1, 1, f.n1, nullptr, f.px, tw0, tid, NTHR);
     fft_lines<V, false, false, true>(pl, f.nx, 0, 1, lb, f.py, tw1, tid, NTHR);
+    for (int s = tid; s < f.nst; s += NTHR) col[s] = pl[f.stick_xy[s]];
+    __syncthreads();
+  }
+}
+
+// Plane pass with wave-owned lines: rows (y transforms) and columns (x
+// transforms) are dealt to the waves in contiguous ranges; a wave runs the
+// inverse x transform, the V(r) product and the forward x transform of its
+// columns back to back.  Four workgroup barriers per band-plane.
+template <typename T, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_plane_w(FFTDev f, cpx_t<T> *__restrict__ sticks, int nb,
+                                                  int group) {
+  using V = cpx_t<T>;
+  constexpr int NW = NTHR / 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  V *tw0 = reinterpret_cast<V *>(smem);
+  V *tw1 = tw0 + f.n0;
+  V *pl = tw1 + f.n1;
+  int *lb = reinterpret_cast<int *>(pl + f.n0 * f.n1);
+  const int z = blockIdx.x % f.n2;
+  const int g = blockIdx.x / f.n2;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const V *tw0g = static_cast<const V *>(f.tw0);
+  const V *tw1g = static_cast<const V *>(f.tw1);
+  for (int i = tid; i < f.n0; i += NTHR) tw0[i] = tw0g[i];
+  for (int i = tid; i < f.n1; i += NTHR) tw1[i] = tw1g[i];
+  for (int i = tid; i < f.nx; i += NTHR) lb[i] = f.xlist[i] * f.n1;
+  const int npl = f.n0 * f.n1;
+  const T *vp = static_cast<const T *>(f.vplanes) + (int64_t)z * npl;
+  // this wave's rows (indices into xlist) and columns
+  const int rpw = (f.nx + NW - 1) / NW;
+  const int r0 = min(f.nx, wv * rpw), r1 = min(f.nx, r0 + rpw);
+  const int cpw = (f.n1 + NW - 1) / NW;
+  const int c0 = min(f.n1, wv * cpw), c1 = min(f.n1, c0 + cpw);
+  const int rg = max(1, (kCpt * 64) / f.n1);  // rows per register group
+  const int cg = max(1, (kCpt * 64) / f.n0);  // columns per register group
+  for (int bb = 0; bb < group; ++bb) {
+    const int b = g * group + bb;
+    if (b >= nb) break;
+    for (int i = tid; i < npl; i += NTHR) pl[i] = V{0, 0};
+    __syncthreads();
+    V *col = sticks + (int64_t)b * f.n2 * f.nst_pad + (int64_t)z * f.nst_pad;
+    for (int s = tid; s < f.nst; s += NTHR) pl[f.stick_xy[s]] = col[s];
+    __syncthreads();
+    for (int q = r0; q < r1; q += rg) {
+      const int ng = min(rg, r1 - q);
+      wave_fft_group<V, true, false>(pl, ng, [&](int l) { return lb[q + l]; }, 1, f.py, tw1, lane);
+    }
+    __syncthreads();
+    for (int q = c0; q < c1; q += cg) {
+      const int ng = min(cg, c1 - q);
+      auto base = [&](int l) { return q + l; };
+      wave_fft_group<V, true, true>(pl, ng, base, f.n1, f.px, tw0, lane);
+      const float ing = 1.0f / (float)ng;
+      for (int e = lane; e < ng * f.n0; e += 64) {
+        const int x = qdiv(e, ng, ing);
+        const int o = x * f.n1 + q + (e - x * ng);
+        pl[o] = c_scale(pl[o], vp[o]);
+      }
+      wave_sync();
+      wave_fft_group<V, false, true>(pl, ng, base, f.n1, f.px, tw0, lane);
+    }
+    __syncthreads();
+    for (int q = r0; q < r1; q += rg) {
+      const int ng = min(rg, r1 - q);
+      wave_fft_group<V, false, false>(pl, ng, [&](int l) { return lb[q + l]; }, 1, f.py, tw1, lane);
+    }
+    __syncthreads();
     for (int s = tid; s < f.nst; s += NTHR) col[s] = pl[f.stick_xy[s]];
     __syncthreads();
   }
@@ -418,6 +578,25 @@ static int zinv_t(const FFTDev &f, const void *psi, int64_t ld, void *sticks, in
                                    : zinv_n<T, 512>(f, psi, ld, sticks, nb, s);
 }
 
+static int plane_impl() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = std::getenv("PW_PLANE_IMPL");
+    v = (e && *e) ? std::atoi(e) : 0;
+  }
+  return v;
+}
+
+template <typename T, int NT>
+static int plane_w_n(const FFTDev &f, void *sticks, int nb, int group, size_t lds, int blocks,
+                     hipStream_t s) {
+  using V = cpx_t<T>;
+  auto k = k_plane_w<T, NT>;
+  if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(NT), lds, s, f, static_cast<V *>(sticks), nb, group);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
 template <typename T>
 static int plane_t(const FFTDev &f, void *sticks, int nb, int group, hipStream_t s) {
   using V = cpx_t<T>;
@@ -425,6 +604,11 @@ static int plane_t(const FFTDev &f, void *sticks, int nb, int group, hipStream_t
   const size_t lds = sizeof(V) * (size_t)(f.n0 + f.n1 + npl) + sizeof(int) * (size_t)f.nx;
   const int groups = (nb + group - 1) / group;
   const int blocks = f.n2 * groups;
+  if (plane_impl() == 1) {
+    if (npl <= 2048) return plane_w_n<T, 256>(f, sticks, nb, group, lds, blocks, s);
+    if (npl <= 4096) return plane_w_n<T, 512>(f, sticks, nb, group, lds, blocks, s);
+    return plane_w_n<T, 1024>(f, sticks, nb, group, lds, blocks, s);
+  }
   if (npl <= kCpt * 256) {
     auto k = k_plane<T, 256>;
     if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
