@@ -204,6 +204,15 @@ pw_status pw_davidson_init(pw_davidson *d, const void *psi0, int64_t ld, void *s
 pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *net,
                            void *stream, int32_t *converged);
 
+/* Switch a solve to another problem on the same sphere (same npw and G
+ * order, max_bands >= nbands), typically the FP64 form of a mixed-precision
+ * problem: W = H V and H_s = V^H W are recomputed for the current space, so
+ * the following steps converge on the new operator ("refinement"). */
+pw_status pw_davidson_set_problem(pw_davidson *d, pw_problem *p, void *stream);
+
+/* Change the residual target of a solve (Ha, > 0). */
+pw_status pw_davidson_set_tol(pw_davidson *d, double tol);
+
 /* Up to max_iter calls of pw_davidson_step; PW_OK when converged, else
  * PW_NOT_CONVERGED (positive) with the state left after max_iter steps. */
 pw_status pw_davidson_run(pw_davidson *d, int32_t max_iter, int32_t precond_kind,

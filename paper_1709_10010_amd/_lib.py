@@ -76,6 +76,8 @@ def _load():
         "pw_davidson_query": (i32, [vp, C.POINTER(f64), C.POINTER(f64), C.POINTER(i32),
                                     C.POINTER(i64), vp]),
         "pw_davidson_vectors": (i32, [vp, vp, i64, vp]),
+        "pw_davidson_set_problem": (i32, [vp, vp, vp]),
+        "pw_davidson_set_tol": (i32, [vp, f64]),
         "pw_profile_enable": (i32, [vp, i32]),
         "pw_profile_read": (i32, [vp, C.POINTER(f64), C.POINTER(i64), i32]),
     }
@@ -329,10 +331,24 @@ def pw_davidson_vectors(d: Davidson, x, stream=None) -> None:
     _check(LIB.pw_davidson_vectors(d.handle, ps, ld, _stream(stream)))
 
 
+def pw_davidson_set_tol(d: Davidson, tol: float) -> None:
+    _check(LIB.pw_davidson_set_tol(d.handle, float(tol)))
+
+
+def pw_davidson_set_problem(d: Davidson, prob: Problem, stream=None) -> None:
+    _check(LIB.pw_davidson_set_problem(d.handle, prob.handle, _stream(stream)))
+    d.prob = prob
+
+
 def davidson_solve(prob: Problem, psi0, tol: float = 5e-9, max_subspace: int = 0,
                    max_iter: int = 200, precond: int = PW_PRECOND_TPA, net=None,
-                   want_vectors: bool = False, stream=None) -> dict:
-    """create + init + run + query (+ vectors) on one problem."""
+                   want_vectors: bool = False, refine: Problem = None, refine_tol: float = None,
+                   stream=None) -> dict:
+    """create + init + run + query (+ vectors) on one problem.
+
+    With ``refine``: run on ``prob`` down to ``tol``, then switch the solve to
+    ``refine`` (same sphere, e.g. the FP64 form) and run down to ``refine_tol``.
+    """
     import torch
     nb = int(psi0.shape[0])
     d = Davidson(prob, nb, max_subspace, tol, stream)
@@ -340,6 +356,12 @@ def davidson_solve(prob: Problem, psi0, tol: float = 5e-9, max_subspace: int = 0
         pw_davidson_init(d, psi0, stream)
         conv = pw_davidson_run(d, max_iter, precond, net, stream)
         out = pw_davidson_query(d, stream)
+        if refine is not None:
+            first = out["iterations"]
+            pw_davidson_set_problem(d, refine, stream)
+            pw_davidson_set_tol(d, refine_tol if refine_tol else tol)
+            conv = pw_davidson_run(d, max_iter, precond, net, stream)
+            out = dict(pw_davidson_query(d, stream), iterations_first=first)
         out["converged"] = conv
         if want_vectors:
             x = torch.zeros_like(psi0)

@@ -383,6 +383,14 @@ pw_status pw_problem_create(const pw_problem_desc *d, int64_t max_bands, void *s
       set_error("pw_problem_create: cannot copy beta (device pointer expected)");
       return fail(PW_ERR_HIP);
     }
+    if (d->precision != PW_FP64) {
+      const size_t eb = d->precision == PW_MIXED_FP32 ? 8 : 4;
+      if (hipMalloc(&p->d_beta_lp, (size_t)d->nproj * p->ldb * eb) != hipSuccess) return fail(PW_ERR_NOMEM);
+      if ((rc = convert_beta(p->d_beta, p->d_beta_lp, d->nproj * p->ldb, d->precision, s)) != PW_OK) {
+        set_error("pw_problem_create: beta conversion failed");
+        return fail(rc);
+      }
+    }
     std::vector<int32_t> pj(d->nproj), poff(d->proj_offset, d->proj_offset + d->natom + 1),
         doff(d->natom);
     int64_t tot = 0;
@@ -472,7 +480,8 @@ static int projections_impl(pw_problem *p, const void *psi, int64_t ld, void *P,
   const int64_t M = p->nproj, N = nb, K = p->npw;
   int splits = p->ksplit > 0 ? p->ksplit : choose_splits(M, N, K);
   while (splits > 1 && (size_t)splits * M * N * 16 > p->part_bytes) --splits;
-  return zgemm_cn(M, N, K, p->d_beta, p->ldb, psi, ld, P, M, splits, p->d_part, s);
+  const void *A = p->precision == PW_FP64 ? p->d_beta : p->d_beta_lp;
+  return zgemm_cn_p(p->precision, M, N, K, A, p->ldb, psi, ld, P, M, splits, p->d_part, s);
 }
 
 pw_status pw_hpsi(pw_problem *p, const void *psi, int64_t ld_psi, void *hpsi, int64_t ld_hpsi,
@@ -536,8 +545,9 @@ pw_status pw_hpsi(pw_problem *p, const void *psi, int64_t ld_psi, void *hpsi, in
     }
     if (rc == PW_OK) {
       ProfScope ps_(&p->prof, PW_STAGE_NLUPD, s);
-      rc = zgemm_nn(p->npw, nbands, p->nproj, 1.0, p->d_beta, p->ldb, p->d_Q, p->nproj, 1.0,
-                    hpsi, ld_hpsi, s);
+      const void *A = p->precision == PW_FP64 ? p->d_beta : p->d_beta_lp;
+      rc = zgemm_nn_p(p->precision, p->npw, nbands, p->nproj, 1.0, A, p->ldb, p->d_Q, p->nproj, 1.0,
+                      hpsi, ld_hpsi, s);
     }
     if (rc != PW_OK) {
       set_error("pw_hpsi: nonlocal launch failed");

@@ -159,6 +159,13 @@ int zgemm_cn(int64_t M, int64_t N, int64_t K, const void *A, int64_t lda, const 
 int zgemm_nn(int64_t M, int64_t N, int64_t K, double alpha, const void *A, int64_t lda,
              const void *B, int64_t ldb, double beta, void *C, int64_t ldc, hipStream_t s);
 int choose_splits(int64_t M, int64_t N, int64_t K);
+// Same shapes in a precision form: A in the form's storage (complex128,
+// float2 or bf16 pairs), B and C complex128, accumulation FP64 / FP32 / FP32.
+int zgemm_cn_p(int prec, int64_t M, int64_t N, int64_t K, const void *A, int64_t lda, const void *B,
+               int64_t ldb, void *C, int64_t ldc, int splits, void *part, hipStream_t s);
+int zgemm_nn_p(int prec, int64_t M, int64_t N, int64_t K, double alpha, const void *A, int64_t lda,
+               const void *B, int64_t ldb, double beta, void *C, int64_t ldc, hipStream_t s);
+int convert_beta(const void *src, void *dst, int64_t n, int prec, hipStream_t s);
 
 // Nonlocal D application (nonlocal.hip): Q[n][j] = sum_j' D_a(j,j') P[n][j'].
 int launch_apply_d(const double *dij, const int32_t *pj_atom, const int32_t *proj_off,

@@ -331,6 +331,32 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   return PW_OK;
 }
 
+pw_status pw_davidson_set_problem(pw_davidson *d, pw_problem *p, void *stream) {
+  PW_CHECK_ARG(d && p, PW_ERR_INVALID, "pw_davidson_set_problem: null argument");
+  PW_CHECK_ARG(p->npw == d->npw && p->max_bands >= d->nb, PW_ERR_INVALID,
+               "pw_davidson_set_problem: problem must share npw and allow nbands bands");
+  d->p = p;
+  if (!d->inited) return PW_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool set_error_if_empty = true;
+  const char *where = "pw_davidson_set_problem: launch failed";
+  for (int c0 = 0; c0 < d->m; c0 += d->nb) {
+    const int nc = std::min(d->nb, d->m - c0);
+    DV_RC(pw_hpsi(p, d->V + (size_t)c0 * d->ld, d->ld, d->W + (size_t)c0 * d->ld, d->ld, nc,
+                  PW_TERM_ALL, s));
+  }
+  d->n_hpsi += d->m;
+  DV_RC(cn(d, d->m, d->m, d->V, d->W, d->Hs, d->lde, s));
+  DV_RC(hermitize(d->Hs, d->lde, 0, d->m, s));
+  return PW_OK;
+}
+
+pw_status pw_davidson_set_tol(pw_davidson *d, double tol) {
+  PW_CHECK_ARG(d && tol > 0 && std::isfinite(tol), PW_ERR_INVALID, "pw_davidson_set_tol: bad argument");
+  d->tol = tol;
+  return PW_OK;
+}
+
 pw_status pw_davidson_run(pw_davidson *d, int32_t max_iter, int32_t precond_kind, const pw_mlp *net,
                           void *stream, int32_t *converged) {
   PW_CHECK_ARG(d && max_iter >= 1, PW_ERR_INVALID, "pw_davidson_run: bad argument");

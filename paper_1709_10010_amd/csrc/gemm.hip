@@ -24,34 +24,62 @@
 namespace pw {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
 
 constexpr int GB_M = 64;
 constexpr int GB_N = 64;
 constexpr int GB_K = 16;
 constexpr int G_THR = 256;
 
-__device__ __forceinline__ d4_t mfma64(double a, double b, d4_t c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
+// MFMA flavours with K = 4 per instruction: operand lanes hold A[i = l%16][k = l/16]
+// and B[k = l/16][j = l%16].  The accumulator's row for register r of lane l
+// differs: l/16 + 4r for the f64 instruction, 4(l/16) + r for the f32 one.
+struct MF64 {
+  using S = double;
+  using S2 = double2;
+  using acc_t = d4_t;
+  static __device__ __forceinline__ acc_t mfma(S a, S b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+struct MF32 {
+  using S = float;
+  using S2 = float2;
+  using acc_t = f4_t;
+  static __device__ __forceinline__ acc_t mfma(S a, S b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <typename S2> __device__ __forceinline__ S2 cvt2(double2 v);
+template <> __device__ __forceinline__ double2 cvt2<double2>(double2 v) { return v; }
+template <> __device__ __forceinline__ float2 cvt2<float2>(double2 v) { return float2{(float)v.x, (float)v.y}; }
+template <typename S2> __device__ __forceinline__ S2 cvt2(float2 v);
+template <> __device__ __forceinline__ float2 cvt2<float2>(float2 v) { return v; }
+template <> __device__ __forceinline__ double2 cvt2<double2>(float2 v) { return double2{v.x, v.y}; }
 
 // Load a 16(k) x 64(mn) tile of a K-contiguous column-major matrix
 // (element (k, c) at P[c * ld + k]) into registers: thread t covers column
 // t/4 and k = 4*(t%4) .. +3.
-__device__ __forceinline__ void load_kcontig(const double2 *__restrict__ P, int64_t ld, int64_t k0,
-                                             int64_t c0, int64_t K, int64_t C, double2 r[4]) {
+template <typename T, typename S2>
+__device__ __forceinline__ void load_kcontig(const T *__restrict__ P, int64_t ld, int64_t k0,
+                                             int64_t c0, int64_t K, int64_t C, S2 r[4]) {
   const int t = threadIdx.x;
   const int64_t c = c0 + (t >> 2);
   const int64_t k = k0 + ((t & 3) << 2);
   if (c < C) {
-    const double2 *p = P + c * ld + k;
+    const T *p = P + c * ld + k;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) r[u] = (k + u < K) ? p[u] : double2{0.0, 0.0};
+    for (int u = 0; u < 4; ++u) r[u] = (k + u < K) ? cvt2<S2>(p[u]) : S2{0, 0};
   } else {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) r[u] = double2{0.0, 0.0};
+    for (int u = 0; u < 4; ++u) r[u] = S2{0, 0};
   }
 }
-__device__ __forceinline__ void store_kcontig(double2 (*S)[GB_M + 1], const double2 r[4]) {
+template <typename S2>
+__device__ __forceinline__ void store_kcontig(S2 (*S)[GB_M + 1], const S2 r[4]) {
   const int t = threadIdx.x;
   const int c = t >> 2;
   const int k = (t & 3) << 2;
@@ -62,21 +90,23 @@ __device__ __forceinline__ void store_kcontig(double2 (*S)[GB_M + 1], const doub
 // Load a 64(m) x 16(k) tile of an M-contiguous column-major matrix
 // (element (m, k) at P[k * ld + m]): thread t covers k = t/16 and
 // m = 4*(t%16) .. +3.
-__device__ __forceinline__ void load_mcontig(const double2 *__restrict__ P, int64_t ld, int64_t m0,
-                                             int64_t k0, int64_t M, int64_t K, double2 r[4]) {
+template <typename T, typename S2>
+__device__ __forceinline__ void load_mcontig(const T *__restrict__ P, int64_t ld, int64_t m0,
+                                             int64_t k0, int64_t M, int64_t K, S2 r[4]) {
   const int t = threadIdx.x;
   const int64_t k = k0 + (t >> 4);
   const int64_t m = m0 + ((t & 15) << 2);
   if (k < K) {
-    const double2 *p = P + k * ld + m;
+    const T *p = P + k * ld + m;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) r[u] = (m + u < M) ? p[u] : double2{0.0, 0.0};
+    for (int u = 0; u < 4; ++u) r[u] = (m + u < M) ? cvt2<S2>(p[u]) : S2{0, 0};
   } else {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) r[u] = double2{0.0, 0.0};
+    for (int u = 0; u < 4; ++u) r[u] = S2{0, 0};
   }
 }
-__device__ __forceinline__ void store_mcontig(double2 (*S)[GB_M + 1], const double2 r[4]) {
+template <typename S2>
+__device__ __forceinline__ void store_mcontig(S2 (*S)[GB_M + 1], const S2 r[4]) {
   const int t = threadIdx.x;
   const int k = t >> 4;
   const int m = (t & 15) << 2;
@@ -84,19 +114,21 @@ __device__ __forceinline__ void store_mcontig(double2 (*S)[GB_M + 1], const doub
   for (int u = 0; u < 4; ++u) S[k][m + u] = r[u];
 }
 
-struct Acc {
-  d4_t rr[2][2], ii[2][2], ri[2][2], ir[2][2];
+template <typename MF> struct Acc {
+  typename MF::acc_t rr[2][2], ii[2][2], ri[2][2], ir[2][2];
 };
 
 // One LDS stage: As[k][m], Bs[k][n], 16 complex k.
-__device__ __forceinline__ void mma_stage(const double2 (*As)[GB_M + 1],
-                                          const double2 (*Bs)[GB_M + 1], Acc &acc, int wm, int wn) {
+template <typename MF>
+__device__ __forceinline__ void mma_stage(const typename MF::S2 (*As)[GB_M + 1],
+                                          const typename MF::S2 (*Bs)[GB_M + 1], Acc<MF> &acc,
+                                          int wm, int wn) {
   const int lane = threadIdx.x & 63;
   const int lr = lane & 15;
   const int lk = lane >> 4;
 #pragma unroll
   for (int kk = 0; kk < GB_K; kk += 4) {
-    double2 a[2], b[2];
+    typename MF::S2 a[2], b[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) a[i] = As[kk + lk][wm * 32 + i * 16 + lr];
 #pragma unroll
@@ -106,36 +138,37 @@ __device__ __forceinline__ void mma_stage(const double2 (*As)[GB_M + 1],
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         // first operand: N side (rows of the accumulator), second: M side
-        acc.rr[i][j] = mfma64(b[j].x, a[i].x, acc.rr[i][j]);
-        acc.ii[i][j] = mfma64(b[j].y, a[i].y, acc.ii[i][j]);
-        acc.ri[i][j] = mfma64(b[j].y, a[i].x, acc.ri[i][j]);  // re(A) im(B)
-        acc.ir[i][j] = mfma64(b[j].x, a[i].y, acc.ir[i][j]);  // im(A) re(B)
+        acc.rr[i][j] = MF::mfma(b[j].x, a[i].x, acc.rr[i][j]);
+        acc.ii[i][j] = MF::mfma(b[j].y, a[i].y, acc.ii[i][j]);
+        acc.ri[i][j] = MF::mfma(b[j].y, a[i].x, acc.ri[i][j]);  // re(A) im(B)
+        acc.ir[i][j] = MF::mfma(b[j].x, a[i].y, acc.ir[i][j]);  // im(A) re(B)
       }
     }
   }
 }
 
-// Accumulator element r of a lane: row n = lane/16 + 4*r of the block's
-// N side, column m = lane%16 of its M side (v_mfma_f64_16x16x4f64 layout).
-template <bool CONJ_A, typename F>
-__device__ __forceinline__ void for_each_out(const Acc &acc, int wm, int wn, F &&f) {
+// Accumulator element r of a lane: row n = MF::row(lane, r) of the block's
+// N side, column m = lane%16 of its M side.
+template <typename MF, bool CONJ_A, typename F>
+__device__ __forceinline__ void for_each_out(const Acc<MF> &acc, int wm, int wn, F &&f) {
   const int lane = threadIdx.x & 63;
   const int lm = lane & 15;
-  const int ln = lane >> 4;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const double re = CONJ_A ? acc.rr[i][j][r] + acc.ii[i][j][r] : acc.rr[i][j][r] - acc.ii[i][j][r];
-        const double im = CONJ_A ? acc.ri[i][j][r] - acc.ir[i][j][r] : acc.ri[i][j][r] + acc.ir[i][j][r];
-        f(wm * 32 + i * 16 + lm, wn * 32 + j * 16 + ln + 4 * r, re, im);
+        const double rr = acc.rr[i][j][r], ii = acc.ii[i][j][r];
+        const double ri = acc.ri[i][j][r], ir = acc.ir[i][j][r];
+        const double re = CONJ_A ? rr + ii : rr - ii;
+        const double im = CONJ_A ? ri - ir : ri + ir;
+        f(wm * 32 + i * 16 + lm, wn * 32 + j * 16 + MF::row(lane, r), re, im);
       }
 }
 
-__device__ __forceinline__ void zero_acc(Acc &acc) {
-  const d4_t z = {0.0, 0.0, 0.0, 0.0};
+template <typename MF> __device__ __forceinline__ void zero_acc(Acc<MF> &acc) {
+  const typename MF::acc_t z = {0, 0, 0, 0};
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -143,22 +176,25 @@ __device__ __forceinline__ void zero_acc(Acc &acc) {
 }
 
 // CN: grid (tilesM, tilesN, splits).  out = C (splits == 1) or part[split] (M x N, ld M).
+// A in storage type TA (double2 or float2), B complex128 rounded to MF::S on load.
+template <typename MF, typename TA>
 __global__ __launch_bounds__(G_THR, 2) void k_zgemm_cn(int64_t M, int64_t N, int64_t K,
-                                                    const double2 *__restrict__ A, int64_t lda,
-                                                    const double2 *__restrict__ B, int64_t ldb,
-                                                    double2 *__restrict__ C, int64_t ldc,
-                                                    int64_t kchunk, int direct) {
-  __shared__ double2 As[GB_K][GB_M + 1];
-  __shared__ double2 Bs[GB_K][GB_M + 1];
+                                                       const TA *__restrict__ A, int64_t lda,
+                                                       const double2 *__restrict__ B, int64_t ldb,
+                                                       double2 *__restrict__ C, int64_t ldc,
+                                                       int64_t kchunk, int direct) {
+  using S2 = typename MF::S2;
+  __shared__ S2 As[GB_K][GB_M + 1];
+  __shared__ S2 Bs[GB_K][GB_M + 1];
   const int64_t m0 = (int64_t)blockIdx.x * GB_M;
   const int64_t n0 = (int64_t)blockIdx.y * GB_N;
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
   const int wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  Acc acc;
+  Acc<MF> acc;
   zero_acc(acc);
-  double2 ra[4], rb[4];
+  S2 ra[4], rb[4];
   if (kb < ke) {
     load_kcontig(A, lda, kb, m0, ke, M, ra);
     load_kcontig(B, ldb, kb, n0, ke, N, rb);
@@ -171,12 +207,12 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_cn(int64_t M, int64_t N, int
       load_kcontig(A, lda, k0 + GB_K, m0, ke, M, ra);
       load_kcontig(B, ldb, k0 + GB_K, n0, ke, N, rb);
     }
-    mma_stage(As, Bs, acc, wm, wn);
+    mma_stage<MF>(As, Bs, acc, wm, wn);
     __syncthreads();
   }
   double2 *out = direct ? C : C + (int64_t)blockIdx.z * M * N;
   const int64_t ldo = direct ? ldc : M;
-  for_each_out<true>(acc, wm, wn, [&](int mi, int ni, double re, double im) {
+  for_each_out<MF, true>(acc, wm, wn, [&](int mi, int ni, double re, double im) {
     const int64_t m = m0 + mi, n = n0 + ni;
     if (m < M && n < N) out[n * ldo + m] = double2{re, im};
   });
@@ -198,21 +234,23 @@ __global__ void k_splitk_reduce(int64_t M, int64_t N, int splits, const double2 
   }
 }
 
-// NN: grid (tilesM, tilesN).  C = alpha A B + beta C.
+// NN: grid (tilesM, tilesN).  C = alpha A B + beta C (C complex128, combined in FP64).
+template <typename MF, typename TA>
 __global__ __launch_bounds__(G_THR, 2) void k_zgemm_nn(int64_t M, int64_t N, int64_t K, double alpha,
-                                                    const double2 *__restrict__ A, int64_t lda,
-                                                    const double2 *__restrict__ B, int64_t ldb,
-                                                    double beta, double2 *__restrict__ C,
-                                                    int64_t ldc) {
-  __shared__ double2 As[GB_K][GB_M + 1];
-  __shared__ double2 Bs[GB_K][GB_M + 1];
+                                                       const TA *__restrict__ A, int64_t lda,
+                                                       const double2 *__restrict__ B, int64_t ldb,
+                                                       double beta, double2 *__restrict__ C,
+                                                       int64_t ldc) {
+  using S2 = typename MF::S2;
+  __shared__ S2 As[GB_K][GB_M + 1];
+  __shared__ S2 Bs[GB_K][GB_M + 1];
   const int64_t m0 = (int64_t)blockIdx.x * GB_M;
   const int64_t n0 = (int64_t)blockIdx.y * GB_N;
   const int wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  Acc acc;
+  Acc<MF> acc;
   zero_acc(acc);
-  double2 ra[4], rb[4];
+  S2 ra[4], rb[4];
   if (K > 0) {
     load_mcontig(A, lda, m0, 0, M, K, ra);
     load_kcontig(B, ldb, 0, n0, K, N, rb);
@@ -225,10 +263,10 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_nn(int64_t M, int64_t N, int
       load_mcontig(A, lda, m0, k0 + GB_K, M, K, ra);
       load_kcontig(B, ldb, k0 + GB_K, n0, K, N, rb);
     }
-    mma_stage(As, Bs, acc, wm, wn);
+    mma_stage<MF>(As, Bs, acc, wm, wn);
     __syncthreads();
   }
-  for_each_out<false>(acc, wm, wn, [&](int mi, int ni, double re, double im) {
+  for_each_out<MF, false>(acc, wm, wn, [&](int mi, int ni, double re, double im) {
     const int64_t m = m0 + mi, n = n0 + ni;
     if (m < M && n < N) {
       double2 o = double2{alpha * re, alpha * im};
@@ -242,6 +280,258 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_nn(int64_t M, int64_t N, int
   });
 }
 
+// ---------------------------------------------------------------- BF16 inputs, FP32 accumulation
+// v_mfma_f32_16x16x16_bf16: operand lanes hold 4 consecutive k,
+// A[i = l%16][k = 4(l/16) + v], B[k = 4(l/16) + v][j = l%16]; LDS tiles are
+// [mn][k] (k contiguous) so each lane fetches its 4 values in one read.
+// Complex storage of a bf16 matrix: (re, im) pairs, 4 bytes per element.
+typedef short s4_t __attribute__((ext_vector_type(4)));
+constexpr int BB_K = 32;
+
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
+
+struct BfTile {
+  unsigned short re[GB_M][BB_K + 4];
+  unsigned short im[GB_M][BB_K + 4];
+};
+
+// K-contiguous source of complex128 (convert) or bf16 pairs: 64 columns x 32 k.
+// Thread t: column t/4, k = 8*(t%4) .. +7.
+__device__ __forceinline__ void bf_load_kc(const double2 *__restrict__ P, int64_t ld, int64_t k0,
+                                           int64_t c0, int64_t K, int64_t C, unsigned short re[8],
+                                           unsigned short im[8]) {
+  const int t = threadIdx.x;
+  const int64_t c = c0 + (t >> 2);
+  const int64_t k = k0 + ((t & 3) << 3);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    double2 v = double2{0.0, 0.0};
+    if (c < C && k + u < K) v = P[c * ld + k + u];
+    re[u] = bf16_rne((float)v.x);
+    im[u] = bf16_rne((float)v.y);
+  }
+}
+__device__ __forceinline__ void bf_load_kc(const ushort2 *__restrict__ P, int64_t ld, int64_t k0,
+                                           int64_t c0, int64_t K, int64_t C, unsigned short re[8],
+                                           unsigned short im[8]) {
+  const int t = threadIdx.x;
+  const int64_t c = c0 + (t >> 2);
+  const int64_t k = k0 + ((t & 3) << 3);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    ushort2 v = ushort2{0, 0};
+    if (c < C && k + u < K) v = P[c * ld + k + u];
+    re[u] = v.x;
+    im[u] = v.y;
+  }
+}
+__device__ __forceinline__ void bf_store_kc(BfTile &T, const unsigned short re[8], const unsigned short im[8]) {
+  const int t = threadIdx.x;
+  const int c = t >> 2;
+  const int k = (t & 3) << 3;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    T.re[c][k + u] = re[u];
+    T.im[c][k + u] = im[u];
+  }
+}
+// M-contiguous bf16 source, 64 m x 32 k: thread t: k = t/8, m = 8*(t%8) .. +7.
+__device__ __forceinline__ void bf_load_mc(const ushort2 *__restrict__ P, int64_t ld, int64_t m0,
+                                           int64_t k0, int64_t M, int64_t K, unsigned short re[8],
+                                           unsigned short im[8]) {
+  const int t = threadIdx.x;
+  const int64_t k = k0 + (t >> 3);
+  const int64_t m = m0 + ((t & 7) << 3);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    ushort2 v = ushort2{0, 0};
+    if (k < K && m + u < M) v = P[k * ld + m + u];
+    re[u] = v.x;
+    im[u] = v.y;
+  }
+}
+__device__ __forceinline__ void bf_store_mc(BfTile &T, const unsigned short re[8], const unsigned short im[8]) {
+  const int t = threadIdx.x;
+  const int k = t >> 3;
+  const int m = (t & 7) << 3;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    T.re[m + u][k] = re[u];
+    T.im[m + u][k] = im[u];
+  }
+}
+
+struct AccF {
+  f4_t rr[2][2], ii[2][2], ri[2][2], ir[2][2];
+};
+
+__device__ __forceinline__ s4_t bf_frag(const unsigned short (*S)[BB_K + 4], int row, int k) {
+  const unsigned short *p = &S[row][k];
+  return s4_t{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
+}
+
+__device__ __forceinline__ void bf_stage(const BfTile &At, const BfTile &Bt, AccF &acc, int wm, int wn) {
+  const int lane = threadIdx.x & 63;
+  const int lr = lane & 15;
+  const int lk = (lane >> 4) << 2;
+#pragma unroll
+  for (int kk = 0; kk < BB_K; kk += 16) {
+    s4_t ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      ar[i] = bf_frag(At.re, wm * 32 + i * 16 + lr, kk + lk);
+      ai[i] = bf_frag(At.im, wm * 32 + i * 16 + lr, kk + lk);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      br[j] = bf_frag(Bt.re, wn * 32 + j * 16 + lr, kk + lk);
+      bi[j] = bf_frag(Bt.im, wn * 32 + j * 16 + lr, kk + lk);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        acc.rr[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(br[j], ar[i], acc.rr[i][j], 0, 0, 0);
+        acc.ii[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bi[j], ai[i], acc.ii[i][j], 0, 0, 0);
+        acc.ri[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bi[j], ar[i], acc.ri[i][j], 0, 0, 0);
+        acc.ir[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(br[j], ai[i], acc.ir[i][j], 0, 0, 0);
+      }
+  }
+}
+
+template <bool CONJ_A, typename F>
+__device__ __forceinline__ void bf_out(const AccF &acc, int wm, int wn, F &&f) {
+  const int lane = threadIdx.x & 63;
+  const int lm = lane & 15;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double rr = acc.rr[i][j][r], ii = acc.ii[i][j][r];
+        const double ri = acc.ri[i][j][r], ir = acc.ir[i][j][r];
+        const double re = CONJ_A ? rr + ii : rr - ii;
+        const double im = CONJ_A ? ri - ir : ri + ir;
+        f(wm * 32 + i * 16 + lm, wn * 32 + j * 16 + 4 * (lane >> 4) + r, re, im);
+      }
+}
+
+__global__ __launch_bounds__(G_THR, 2) void k_zgemm_cn_bf16(int64_t M, int64_t N, int64_t K,
+                                                            const ushort2 *__restrict__ A, int64_t lda,
+                                                            const double2 *__restrict__ B, int64_t ldb,
+                                                            double2 *__restrict__ C, int64_t ldc,
+                                                            int64_t kchunk, int direct) {
+  __shared__ BfTile At, Bt;
+  const int64_t m0 = (int64_t)blockIdx.x * GB_M;
+  const int64_t n0 = (int64_t)blockIdx.y * GB_N;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  AccF acc;
+  const f4_t z = {0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc.rr[i][j] = acc.ii[i][j] = acc.ri[i][j] = acc.ir[i][j] = z;
+  unsigned short ar[8], ai[8], br[8], bi[8];
+  if (kb < ke) {
+    bf_load_kc(A, lda, kb, m0, ke, M, ar, ai);
+    bf_load_kc(B, ldb, kb, n0, ke, N, br, bi);
+  }
+  for (int64_t k0 = kb; k0 < ke; k0 += BB_K) {
+    bf_store_kc(At, ar, ai);
+    bf_store_kc(Bt, br, bi);
+    __syncthreads();
+    if (k0 + BB_K < ke) {
+      bf_load_kc(A, lda, k0 + BB_K, m0, ke, M, ar, ai);
+      bf_load_kc(B, ldb, k0 + BB_K, n0, ke, N, br, bi);
+    }
+    bf_stage(At, Bt, acc, wm, wn);
+    __syncthreads();
+  }
+  double2 *out = direct ? C : C + (int64_t)blockIdx.z * M * N;
+  const int64_t ldo = direct ? ldc : M;
+  bf_out<true>(acc, wm, wn, [&](int mi, int ni, double re, double im) {
+    const int64_t m = m0 + mi, n = n0 + ni;
+    if (m < M && n < N) out[n * ldo + m] = double2{re, im};
+  });
+}
+
+__global__ __launch_bounds__(G_THR, 2) void k_zgemm_nn_bf16(int64_t M, int64_t N, int64_t K,
+                                                            double alpha, const ushort2 *__restrict__ A,
+                                                            int64_t lda, const double2 *__restrict__ B,
+                                                            int64_t ldb, double beta,
+                                                            double2 *__restrict__ C, int64_t ldc) {
+  __shared__ BfTile At, Bt;
+  const int64_t m0 = (int64_t)blockIdx.x * GB_M;
+  const int64_t n0 = (int64_t)blockIdx.y * GB_N;
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  AccF acc;
+  const f4_t z = {0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc.rr[i][j] = acc.ii[i][j] = acc.ri[i][j] = acc.ir[i][j] = z;
+  unsigned short ar[8], ai[8], br[8], bi[8];
+  if (K > 0) {
+    bf_load_mc(A, lda, m0, 0, M, K, ar, ai);
+    bf_load_kc(B, ldb, 0, n0, K, N, br, bi);
+  }
+  for (int64_t k0 = 0; k0 < K; k0 += BB_K) {
+    bf_store_mc(At, ar, ai);
+    bf_store_kc(Bt, br, bi);
+    __syncthreads();
+    if (k0 + BB_K < K) {
+      bf_load_mc(A, lda, m0, k0 + BB_K, M, K, ar, ai);
+      bf_load_kc(B, ldb, k0 + BB_K, n0, K, N, br, bi);
+    }
+    bf_stage(At, Bt, acc, wm, wn);
+    __syncthreads();
+  }
+  bf_out<false>(acc, wm, wn, [&](int mi, int ni, double re, double im) {
+    const int64_t m = m0 + mi, n = n0 + ni;
+    if (m < M && n < N) {
+      double2 o = double2{alpha * re, alpha * im};
+      if (beta != 0.0) {
+        const double2 c = C[n * ldc + m];
+        o.x += beta * c.x;
+        o.y += beta * c.y;
+      }
+      C[n * ldc + m] = o;
+    }
+  });
+}
+
+// complex128 -> float2 / bf16 pairs (round to nearest even), [rows][ld] layout kept
+__global__ void k_cvt_c64(const double2 *__restrict__ src, float2 *__restrict__ dst, int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = float2{(float)src[e].x, (float)src[e].y};
+}
+__global__ void k_cvt_bf16(const double2 *__restrict__ src, ushort2 *__restrict__ dst, int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = ushort2{bf16_rne((float)src[e].x), bf16_rne((float)src[e].y)};
+}
+
+int convert_beta(const void *src, void *dst, int64_t n, int prec, hipStream_t s) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (prec == PW_MIXED_FP32)
+    hipLaunchKernelGGL(k_cvt_c64, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const double2 *>(src),
+                       static_cast<float2 *>(dst), n);
+  else
+    hipLaunchKernelGGL(k_cvt_bf16, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const double2 *>(src),
+                       static_cast<ushort2 *>(dst), n);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
 int choose_splits(int64_t M, int64_t N, int64_t K) {
   const int64_t tiles = ((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N);
   // aim for >= 2 workgroups per CU on 256 CUs, each with >= 32 K stages
@@ -253,37 +543,66 @@ int choose_splits(int64_t M, int64_t N, int64_t K) {
   return (int)s;
 }
 
-int zgemm_cn(int64_t M, int64_t N, int64_t K, const void *A, int64_t lda, const void *B,
-             int64_t ldb, void *C, int64_t ldc, int splits, void *part, hipStream_t s) {
+static int launch_reduce(int64_t M, int64_t N, int splits, void *part, void *C, int64_t ldc, hipStream_t s) {
+  int64_t blocks = (M * N + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, s, M, N, splits,
+                     static_cast<const double2 *>(part), static_cast<double2 *>(C), ldc);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
+int zgemm_cn_p(int prec, int64_t M, int64_t N, int64_t K, const void *A, int64_t lda, const void *B,
+               int64_t ldb, void *C, int64_t ldc, int splits, void *part, hipStream_t s) {
   if (M <= 0 || N <= 0) return PW_OK;
   if (splits < 1) splits = 1;
+  const int kq = prec == PW_MIXED_BF16 ? BB_K : GB_K;
   int64_t kchunk = (K + splits - 1) / splits;
-  kchunk = (kchunk + GB_K - 1) / GB_K * GB_K;
-  if (kchunk <= 0) kchunk = GB_K;
+  kchunk = (kchunk + kq - 1) / kq * kq;
+  if (kchunk <= 0) kchunk = kq;
   const int direct = (splits == 1) ? 1 : 0;
+  void *out = direct ? C : part;
   dim3 grid((unsigned)((M + GB_M - 1) / GB_M), (unsigned)((N + GB_N - 1) / GB_N), (unsigned)splits);
-  hipLaunchKernelGGL(k_zgemm_cn, grid, dim3(G_THR), 0, s, M, N, K, static_cast<const double2 *>(A),
-                     lda, static_cast<const double2 *>(B), ldb,
-                     static_cast<double2 *>(direct ? C : part), ldc, kchunk, direct);
+  const double2 *Bd = static_cast<const double2 *>(B);
+  double2 *O = static_cast<double2 *>(out);
+  if (prec == PW_FP64)
+    hipLaunchKernelGGL((k_zgemm_cn<MF64, double2>), grid, dim3(G_THR), 0, s, M, N, K,
+                       static_cast<const double2 *>(A), lda, Bd, ldb, O, ldc, kchunk, direct);
+  else if (prec == PW_MIXED_FP32)
+    hipLaunchKernelGGL((k_zgemm_cn<MF32, float2>), grid, dim3(G_THR), 0, s, M, N, K,
+                       static_cast<const float2 *>(A), lda, Bd, ldb, O, ldc, kchunk, direct);
+  else
+    hipLaunchKernelGGL(k_zgemm_cn_bf16, grid, dim3(G_THR), 0, s, M, N, K,
+                       static_cast<const ushort2 *>(A), lda, Bd, ldb, O, ldc, kchunk, direct);
   if (hipGetLastError() != hipSuccess) return PW_ERR_HIP;
-  if (!direct) {
-    int64_t blocks = (M * N + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, s, M, N, splits,
-                       static_cast<const double2 *>(part), static_cast<double2 *>(C), ldc);
-    if (hipGetLastError() != hipSuccess) return PW_ERR_HIP;
-  }
-  return PW_OK;
+  return direct ? PW_OK : launch_reduce(M, N, splits, part, C, ldc, s);
+}
+
+int zgemm_nn_p(int prec, int64_t M, int64_t N, int64_t K, double alpha, const void *A, int64_t lda,
+               const void *B, int64_t ldb, double beta, void *C, int64_t ldc, hipStream_t s) {
+  if (M <= 0 || N <= 0) return PW_OK;
+  dim3 grid((unsigned)((M + GB_M - 1) / GB_M), (unsigned)((N + GB_N - 1) / GB_N));
+  const double2 *Bd = static_cast<const double2 *>(B);
+  double2 *Cd = static_cast<double2 *>(C);
+  if (prec == PW_FP64)
+    hipLaunchKernelGGL((k_zgemm_nn<MF64, double2>), grid, dim3(G_THR), 0, s, M, N, K, alpha,
+                       static_cast<const double2 *>(A), lda, Bd, ldb, beta, Cd, ldc);
+  else if (prec == PW_MIXED_FP32)
+    hipLaunchKernelGGL((k_zgemm_nn<MF32, float2>), grid, dim3(G_THR), 0, s, M, N, K, alpha,
+                       static_cast<const float2 *>(A), lda, Bd, ldb, beta, Cd, ldc);
+  else
+    hipLaunchKernelGGL(k_zgemm_nn_bf16, grid, dim3(G_THR), 0, s, M, N, K, alpha,
+                       static_cast<const ushort2 *>(A), lda, Bd, ldb, beta, Cd, ldc);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
+int zgemm_cn(int64_t M, int64_t N, int64_t K, const void *A, int64_t lda, const void *B,
+             int64_t ldb, void *C, int64_t ldc, int splits, void *part, hipStream_t s) {
+  return zgemm_cn_p(PW_FP64, M, N, K, A, lda, B, ldb, C, ldc, splits, part, s);
 }
 
 int zgemm_nn(int64_t M, int64_t N, int64_t K, double alpha, const void *A, int64_t lda,
              const void *B, int64_t ldb, double beta, void *C, int64_t ldc, hipStream_t s) {
-  if (M <= 0 || N <= 0) return PW_OK;
-  dim3 grid((unsigned)((M + GB_M - 1) / GB_M), (unsigned)((N + GB_N - 1) / GB_N));
-  hipLaunchKernelGGL(k_zgemm_nn, grid, dim3(G_THR), 0, s, M, N, K, alpha,
-                     static_cast<const double2 *>(A), lda, static_cast<const double2 *>(B), ldb,
-                     beta, static_cast<double2 *>(C), ldc);
-  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+  return zgemm_nn_p(PW_FP64, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
 }
 
 }  // namespace pw
