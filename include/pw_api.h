@@ -224,8 +224,95 @@ pw_status pw_davidson_run(pw_davidson *d, int32_t max_iter, int32_t precond_kind
 pw_status pw_davidson_query(pw_davidson *d, double *theta, double *resid,
                             int32_t *iterations, int64_t *n_hpsi, void *stream);
 
+/* Device copies of the last step's Ritz vectors x, residuals r (complex128
+ * [nbands][ld], either may be NULL), Ritz values and residual norms (double
+ * [nbands], either may be NULL).  Stream-ordered, no sync. */
+pw_status pw_davidson_snapshot(pw_davidson *d, void *x, void *r, double *theta, double *rho,
+                               int64_t ld, void *stream);
+
 /* Copy the current Ritz vectors to x (device complex128 [nbands][ld]). */
 pw_status pw_davidson_vectors(pw_davidson *d, void *x, int64_t ld, void *stream);
+
+/*
+ * Batched H*psi over independent problems (cells or k-points with ragged
+ * npw, grids and band counts): the paper runs such units side by side as
+ * images and k-point pools.  A batch lists, per problem, its input and
+ * output band blocks (device complex128, band-major) and band count; the
+ * caller keeps every pointer valid for the batch's lifetime.
+ *   pw_batch_hpsi     eager sweep (pw_hpsi on every problem, in order)
+ *   pw_batch_capture  records the sweep into a HIP graph on `stream` (a
+ *                     non-null stream; profiling must be off) and
+ *                     instantiates it
+ *   pw_batch_launch   replays the graph: one launch per sweep
+ */
+typedef struct pw_batch pw_batch;
+pw_status pw_batch_create(pw_problem *const *probs, int32_t n, const void *const *psi,
+                          const int64_t *ld_psi, void *const *hpsi, const int64_t *ld_hpsi,
+                          const int64_t *nbands, pw_batch **out);
+pw_status pw_batch_destroy(pw_batch *b);
+pw_status pw_batch_hpsi(pw_batch *b, void *stream);
+pw_status pw_batch_capture(pw_batch *b, void *stream);
+pw_status pw_batch_launch(pw_batch *b, void *stream);
+
+/*
+ * Autotuner: times pw_hpsi on nbands scratch bands (reps timed calls per
+ * shape) over the bands per plane workgroup, the bands per FFT sweep and the
+ * split-K factor of the projection GEMM, keeps the fastest in the handle and
+ * returns its time (ms per call, may be NULL).  Allocates and frees its own
+ * scratch bands; synchronises the stream.
+ */
+pw_status pw_problem_autotune(pw_problem *p, int64_t nbands, int32_t reps, void *stream,
+                              double *best_ms);
+pw_status pw_problem_tuning(const pw_problem *p, int32_t *plane_group, int64_t *band_chunk,
+                            int32_t *ksplit);
+
+/*
+ * Learned diagonal preconditioner (FP32 network 4 -> 64 -> 64 -> 1, SiLU,
+ * softplus output; not part of the paper).  Parameters are one packed float
+ * array of pw_mlp_num_params() values: W1 [64][4], b1 [64], W2 [64][64],
+ * b2 [64], W3 [64], b3 [1] (row-major, y = W x + b).  The scaler holds the
+ * feature means mu[4] and inverse standard deviations is[4]; features are
+ * standardised as (f - mu) * is.  Features of sample (G, n), float4:
+ * (t(G), theta_n, |r_n(G)| sqrt(npw) / ||r_n||, <V_LOC>).
+ */
+int32_t pw_mlp_num_params(void);
+/* params / scaler: host arrays (NULL: zeros / identity scaling). */
+pw_status pw_mlp_create(const float *params, const float *scaler, pw_mlp **out);
+pw_status pw_mlp_destroy(pw_mlp *net);
+/* Host copies (any may be NULL); grad is the last train step's gradient. Syncs the device. */
+pw_status pw_mlp_get(pw_mlp *net, float *params, float *scaler, float *grad);
+pw_status pw_mlp_set(pw_mlp *net, const float *params, const float *scaler);
+/* Raw features of nbands bands: theta, rnorm device double [nbands]; r device
+ * complex128 [nbands][ld]; F device float4 [nbands * npw] (band-major). */
+pw_status pw_mlp_features(pw_problem *p, const double *theta, const void *r, const double *rnorm,
+                          int64_t ld, int64_t nbands, void *F, void *stream);
+/* scaler <- mean and 1/std of the raw features F (device float4 [nsamples]). */
+pw_status pw_mlp_fit_scaler(pw_mlp *net, const void *F, int64_t nsamples, void *stream);
+/* s[i] = network output for raw features F[i] (device float [nsamples]). */
+pw_status pw_mlp_forward(pw_mlp *net, const void *F, int64_t nsamples, float *s, void *stream);
+/*
+ * One training step on a batch of band samples.  F: raw features (float4),
+ * R: residual values, D: target corrections (complex128), one entry per
+ * sample; band b owns samples band_off[b] .. band_off[b+1]-1 (device int64
+ * [nbands+1]); band_of[i] is the band of sample i (device int32).  Loss =
+ * mean over bands of 1 - |<d, sR>|^2 / (||d||^2 ||sR||^2); its gradient is
+ * left in the network (pw_mlp_get), and with update != 0 one Adam step (lr,
+ * 0.9, 0.999, 1e-8) is applied.  s_work: device float [nsamples].  loss_out
+ * (host, may be NULL) syncs the stream.
+ */
+pw_status pw_mlp_train_step(pw_mlp *net, const void *F, const void *R, const void *D,
+                            const int64_t *band_off, const int32_t *band_of, int64_t nbands,
+                            int64_t nsamples, float *s_work, float lr, int32_t update,
+                            double *loss_out, void *stream);
+/*
+ * Target corrections from converged bands: with Xc the converged vectors
+ * (complex128 [nbands][ld]) and cluster[m] the degenerate-cluster id of
+ * converged band m (device int32), D[n] = y_n/||y_n|| - x_n where
+ * y_n = sum_{m in cluster(n)} Xc_m <Xc_m | x_n> and x_n = Xit[n].
+ * work: device scratch of 17 * nbands^2 complex128.
+ */
+pw_status pw_mlp_targets(pw_problem *p, const void *Xc, const int32_t *cluster, const void *Xit,
+                         int64_t ld, int64_t nbands, void *D, void *work, void *stream);
 
 /*
  * Stage timing (instrumentation, off by default).  When enabled, every

@@ -78,6 +78,26 @@ def _load():
         "pw_davidson_vectors": (i32, [vp, vp, i64, vp]),
         "pw_davidson_set_problem": (i32, [vp, vp, vp]),
         "pw_davidson_set_tol": (i32, [vp, f64]),
+        "pw_davidson_snapshot": (i32, [vp, vp, vp, vp, vp, i64, vp]),
+        "pw_mlp_num_params": (i32, []),
+        "pw_mlp_create": (i32, [vp, vp, C.POINTER(vp)]),
+        "pw_mlp_destroy": (i32, [vp]),
+        "pw_mlp_get": (i32, [vp, vp, vp, vp]),
+        "pw_mlp_set": (i32, [vp, vp, vp]),
+        "pw_mlp_features": (i32, [vp, vp, vp, vp, i64, i64, vp, vp]),
+        "pw_mlp_fit_scaler": (i32, [vp, vp, i64, vp]),
+        "pw_mlp_forward": (i32, [vp, vp, i64, vp, vp]),
+        "pw_mlp_train_step": (i32, [vp, vp, vp, vp, vp, vp, i64, i64, vp, C.c_float, i32,
+                                    C.POINTER(f64), vp]),
+        "pw_mlp_targets": (i32, [vp, vp, vp, vp, i64, i64, vp, vp, vp]),
+        "pw_batch_create": (i32, [C.POINTER(vp), i32, C.POINTER(vp), C.POINTER(i64), C.POINTER(vp),
+                                  C.POINTER(i64), C.POINTER(i64), C.POINTER(vp)]),
+        "pw_batch_destroy": (i32, [vp]),
+        "pw_batch_hpsi": (i32, [vp, vp]),
+        "pw_batch_capture": (i32, [vp, vp]),
+        "pw_batch_launch": (i32, [vp, vp]),
+        "pw_problem_autotune": (i32, [vp, i64, i32, vp, C.POINTER(f64)]),
+        "pw_problem_tuning": (i32, [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32)]),
         "pw_profile_enable": (i32, [vp, i32]),
         "pw_profile_read": (i32, [vp, C.POINTER(f64), C.POINTER(i64), i32]),
     }
@@ -371,3 +391,206 @@ def davidson_solve(prob: Problem, psi0, tol: float = 5e-9, max_subspace: int = 0
     finally:
         d.close()
     return out
+
+
+def pw_davidson_snapshot(d: Davidson, x=None, r=None, theta=None, rho=None, stream=None) -> None:
+    """Copies of the last step's Ritz vectors / residuals / values / norms (device tensors)."""
+    import torch
+    ld = None
+    ptrs = []
+    for t, name in ((x, "x"), (r, "r")):
+        if t is None:
+            ptrs.append(None)
+        else:
+            p_, ld_, nb_ = _band_block(t, name, d.prob.npw)
+            if ld is not None and ld_ != ld:
+                raise ValueError("x and r must share one leading dimension")
+            ld = ld_
+            ptrs.append(p_)
+    th = _dev_ptr(theta, torch.float64, "theta") if theta is not None else None
+    rh = _dev_ptr(rho, torch.float64, "rho") if rho is not None else None
+    _check(LIB.pw_davidson_snapshot(d.handle, ptrs[0], ptrs[1], th, rh, ld or d.prob.npw,
+                                    _stream(stream)))
+
+
+MLP_NPARAM = int(LIB.pw_mlp_num_params())
+
+
+def pack_params(p: dict) -> np.ndarray:
+    """Packed float32 parameter vector (W1, b1, W2, b2, W3, b3) from a dict of arrays."""
+    return np.concatenate([np.asarray(p[k], dtype=np.float32).reshape(-1)
+                           for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+
+def unpack_params(v: np.ndarray) -> dict:
+    v = np.asarray(v, dtype=np.float64)
+    shapes = (("W1", (64, 4)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (1, 64)),
+              ("b3", (1,)))
+    out, o = {}, 0
+    for k, shp in shapes:
+        n = int(np.prod(shp))
+        out[k] = v[o:o + n].reshape(shp).copy()
+        o += n
+    return out
+
+
+class Mlp:
+    """Owner of a pw_mlp handle (FP32 network on the GPU)."""
+
+    def __init__(self, params=None, scaler=None):
+        h = C.c_void_p()
+        pv = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        sv = None if scaler is None else np.ascontiguousarray(scaler, dtype=np.float32)
+        if pv is not None and pv.size != MLP_NPARAM:
+            raise ValueError("params must hold pw_mlp_num_params() floats")
+        _check(LIB.pw_mlp_create(None if pv is None else pv.ctypes.data_as(C.c_void_p),
+                                 None if sv is None else sv.ctypes.data_as(C.c_void_p), C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise PwError(-1, "network handle already destroyed")
+        return self._h
+
+    def get(self):
+        p = np.zeros(MLP_NPARAM, dtype=np.float32)
+        s = np.zeros(8, dtype=np.float32)
+        g = np.zeros(MLP_NPARAM, dtype=np.float32)
+        _check(LIB.pw_mlp_get(self.handle, p.ctypes.data_as(C.c_void_p), s.ctypes.data_as(C.c_void_p),
+                              g.ctypes.data_as(C.c_void_p)))
+        return p, s, g
+
+    def set(self, params=None, scaler=None):
+        pv = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        sv = None if scaler is None else np.ascontiguousarray(scaler, dtype=np.float32)
+        _check(LIB.pw_mlp_set(self.handle, None if pv is None else pv.ctypes.data_as(C.c_void_p),
+                              None if sv is None else sv.ctypes.data_as(C.c_void_p)))
+
+    def close(self):
+        if self._h:
+            LIB.pw_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pw_mlp_features(prob: Problem, theta, r, rnorm, F, stream=None) -> None:
+    import torch
+    rp, ld, nb = _band_block(r, "r", prob.npw)
+    if F.dtype != torch.float32 or F.numel() < 4 * nb * prob.npw:
+        raise ValueError("F must be float32 with room for nbands*npw*4 values")
+    _check(LIB.pw_mlp_features(prob.handle, _dev_ptr(theta, torch.float64, "theta"), rp,
+                               _dev_ptr(rnorm, torch.float64, "rnorm"), ld, nb,
+                               _dev_ptr(F, torch.float32, "F"), _stream(stream)))
+
+
+def pw_mlp_fit_scaler(net: Mlp, F, stream=None) -> None:
+    import torch
+    _check(LIB.pw_mlp_fit_scaler(net.handle, _dev_ptr(F, torch.float32, "F"), F.numel() // 4,
+                                 _stream(stream)))
+
+
+def pw_mlp_forward(net: Mlp, F, s, stream=None) -> None:
+    import torch
+    n = F.numel() // 4
+    if s.numel() < n:
+        raise ValueError("s too small")
+    _check(LIB.pw_mlp_forward(net.handle, _dev_ptr(F, torch.float32, "F"), n,
+                              _dev_ptr(s, torch.float32, "s"), _stream(stream)))
+
+
+def pw_mlp_train_step(net: Mlp, F, R, D, band_off, band_of, s_work, lr=1e-3, update=True,
+                      want_loss=True, stream=None):
+    import torch
+    n = F.numel() // 4
+    nb = band_off.numel() - 1
+    loss = C.c_double(0.0)
+    _check(LIB.pw_mlp_train_step(net.handle, _dev_ptr(F, torch.float32, "F"),
+                                 _dev_ptr(R, torch.complex128, "R"), _dev_ptr(D, torch.complex128, "D"),
+                                 _dev_ptr(band_off, torch.int64, "band_off"),
+                                 _dev_ptr(band_of, torch.int32, "band_of"), nb, n,
+                                 _dev_ptr(s_work, torch.float32, "s_work"), float(lr),
+                                 1 if update else 0, C.byref(loss) if want_loss else None,
+                                 _stream(stream)))
+    return loss.value if want_loss else None
+
+
+def pw_mlp_targets(prob: Problem, Xc, cluster, Xit, D, work, stream=None) -> None:
+    import torch
+    xp, ld, nb = _band_block(Xc, "Xc", prob.npw)
+    ip, ld2, nb2 = _band_block(Xit, "Xit", prob.npw)
+    dp, ld3, nb3 = _band_block(D, "D", prob.npw)
+    if not (ld == ld2 == ld3 and nb == nb2 == nb3):
+        raise ValueError("Xc, Xit, D must share shape")
+    if work.numel() < 17 * nb * nb:
+        raise ValueError("work must hold 17*nbands^2 complex128")
+    _check(LIB.pw_mlp_targets(prob.handle, xp, _dev_ptr(cluster, torch.int32, "cluster"), ip, ld, nb,
+                              dp, _dev_ptr(work, torch.complex128, "work"), _stream(stream)))
+
+
+class Batch:
+    """Owner of a pw_batch: problems with their input / output band blocks."""
+
+    def __init__(self, probs, psis, hpsis):
+        n = len(probs)
+        if not (n == len(psis) == len(hpsis)) or n == 0:
+            raise ValueError("one psi and one hpsi block per problem")
+        ph = (C.c_void_p * n)(*[p.handle for p in probs])
+        xs, ys = (C.c_void_p * n)(), (C.c_void_p * n)()
+        lx, ly, nb = (C.c_int64 * n)(), (C.c_int64 * n)(), (C.c_int64 * n)()
+        for i, (p, x, y) in enumerate(zip(probs, psis, hpsis)):
+            xp, ldx, nbx = _band_block(x, "psi", p.npw)
+            yp, ldy, nby = _band_block(y, "hpsi", p.npw)
+            if nby < nbx:
+                raise ValueError("hpsi has fewer bands than psi")
+            xs[i], ys[i], lx[i], ly[i], nb[i] = xp.value, yp.value, ldx, ldy, nbx
+        h = C.c_void_p()
+        _check(LIB.pw_batch_create(ph, n, xs, lx, ys, ly, nb, C.byref(h)))
+        self._h = h
+        self._keep = (list(probs), list(psis), list(hpsis))
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise PwError(-1, "batch already destroyed")
+        return self._h
+
+    def close(self):
+        if self._h:
+            LIB.pw_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pw_batch_hpsi(b: Batch, stream=None) -> None:
+    _check(LIB.pw_batch_hpsi(b.handle, _stream(stream)))
+
+
+def pw_batch_capture(b: Batch, stream) -> None:
+    _check(LIB.pw_batch_capture(b.handle, _stream(stream)))
+
+
+def pw_batch_launch(b: Batch, stream=None) -> None:
+    _check(LIB.pw_batch_launch(b.handle, _stream(stream)))
+
+
+def pw_problem_autotune(prob: Problem, nbands: int, reps: int = 3, stream=None) -> float:
+    ms = C.c_double(0.0)
+    _check(LIB.pw_problem_autotune(prob.handle, int(nbands), int(reps), _stream(stream), C.byref(ms)))
+    return ms.value
+
+
+def pw_problem_tuning(prob: Problem) -> dict:
+    g, c, k = C.c_int32(), C.c_int64(), C.c_int32()
+    _check(LIB.pw_problem_tuning(prob.handle, C.byref(g), C.byref(c), C.byref(k)))
+    return dict(plane_group=g.value, band_chunk=c.value, ksplit=k.value)

@@ -369,6 +369,9 @@ pw_status pw_problem_create(const pw_problem_desc *d, int64_t max_bands, void *s
         set_error("pw_problem_create: vloc holds a non-finite value");
         return fail(PW_ERR_INVALID);
       }
+    double vs = 0.0;
+    for (double x : v) vs += x;
+    p->vavg = vs / (double)v.size();
     rc = d->precision == PW_FP64 ? make_vplanes<double>(p, v) : make_vplanes<float>(p, v);
     if (rc != PW_OK) return fail(rc);
   }

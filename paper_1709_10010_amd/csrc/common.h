@@ -114,6 +114,7 @@ struct pw_problem {
   int nr[3];
   int64_t npw = 0, nproj = 0, max_bands = 0;
   int natom = 0;
+  double vavg = 0;          // mean of V_LOC over the grid (a feature of the learned preconditioner)
   int64_t band_chunk = 0;   // bands per FFT sweep (stick-buffer height)
   int plane_group = 8;      // bands per plane-pass workgroup
   int ksplit = 0;           // split-K factor for projections (0 = auto)

@@ -41,6 +41,11 @@ int precond_idx(const double *kin, const double *tn, const int *idx, const doubl
                 double2 *T, int64_t ldt, int64_t npw, int nu, int kind, hipStream_t s);
 int band_kinetic(const double *kin, const void *x, int64_t ld, int64_t npw, int nb, double *tn,
                  hipStream_t s);
+int mlp_precond_idx(const pw_mlp *net, pw_problem *p, const double *theta, const double *rnorm,
+                    const int *idx, const double2 *R, int64_t ld, double2 *T, int nu, int *bad,
+                    hipStream_t s);
+int mlp_fallback(const int *bad, pw_problem *p, const double *tn, const int *idx, const double2 *R,
+                 int64_t ld, double2 *T, int nu, hipStream_t s);
 }  // namespace pw
 
 using namespace pw;
@@ -58,6 +63,7 @@ struct pw_davidson {
   double2 *S = nullptr, *L = nullptr, *Xi = nullptr, *Bi = nullptr;
   double *w_all = nullptr, *theta = nullptr, *rho = nullptr, *tn = nullptr, *lam = nullptr;
   int *idx_sel = nullptr, *dU = nullptr, *keep = nullptr, *flag = nullptr, *sweeps = nullptr;
+  int *bad = nullptr;
   void *rot_ws = nullptr;
   double *acc_ws = nullptr;
   void *part = nullptr;
@@ -74,7 +80,7 @@ void free_dav(pw_davidson *d) {
   void *dev[] = {d->V,  d->W,  d->X,  d->HX,    d->R,     d->T,    d->Hs,    d->Ae,  d->Ze,
                  d->Y,  d->C,  d->S,  d->L,     d->Xi,    d->Bi,   d->w_all, d->theta, d->rho,
                  d->tn, d->lam, d->idx_sel, d->dU, d->keep, d->flag, d->sweeps, d->rot_ws,
-                 d->acc_ws, d->part};
+                 d->acc_ws, d->part, d->bad};
   for (void *b : dev)
     if (b) (void)hipFree(b);
   void *host[] = {d->h_theta, d->h_rho, d->h_lam, d->h_U, d->h_flag, d->h_keep};
@@ -204,7 +210,7 @@ pw_status pw_davidson_create(pw_problem *p, int64_t nbands, int64_t max_subspace
             dalloc(&d->w_all, lde) && dalloc(&d->theta, nb) && dalloc(&d->rho, nb) &&
             dalloc(&d->tn, nb) && dalloc(&d->lam, lde) && dalloc(&d->idx_sel, nb) &&
             dalloc(&d->dU, nb) && dalloc(&d->keep, nb) && dalloc(&d->flag, 1) &&
-            dalloc(&d->sweeps, 1) && dalloc((char **)&d->rot_ws, lde * 32) &&
+            dalloc(&d->sweeps, 1) && dalloc(&d->bad, nb) && dalloc((char **)&d->rot_ws, lde * 32) &&
             dalloc(&d->acc_ws, 128) && halloc(&d->h_theta, nb) && halloc(&d->h_rho, nb) &&
             halloc(&d->h_lam, lde) && halloc(&d->h_U, nb) && halloc(&d->h_flag, 1) &&
             halloc(&d->h_keep, nb);
@@ -260,9 +266,10 @@ pw_status pw_davidson_init(pw_davidson *d, const void *psi0, int64_t ld, void *s
 pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *net, void *stream,
                            int32_t *converged) {
   PW_CHECK_ARG(d && d->inited, PW_ERR_INVALID, "pw_davidson_step: state not initialised");
-  (void)net;
-  PW_CHECK_ARG(precond_kind == PW_PRECOND_NONE || precond_kind == PW_PRECOND_TPA, PW_ERR_INVALID,
+  PW_CHECK_ARG(precond_kind >= PW_PRECOND_NONE && precond_kind <= PW_PRECOND_MLP, PW_ERR_INVALID,
                "pw_davidson_step: unknown preconditioner");
+  PW_CHECK_ARG(precond_kind != PW_PRECOND_MLP || net, PW_ERR_INVALID,
+               "pw_davidson_step: the MLP preconditioner needs a network");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool set_error_if_empty = true;
   const char *where = "pw_davidson_step: launch failed";
@@ -303,8 +310,13 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   {
     ProfScope ps(&d->p->prof, PW_STAGE_PRECOND, s);
     DV_RC(band_kinetic(d->p->d_kin, d->X, d->ld, d->npw, nb, d->tn, s));
-    DV_RC(precond_idx(d->p->d_kin, d->tn, d->dU, d->R, d->ld, d->T, d->ld, d->npw, nu,
-                      precond_kind, s));
+    if (precond_kind == PW_PRECOND_MLP) {
+      DV_RC(mlp_precond_idx(net, d->p, d->theta, d->rho, d->dU, d->R, d->ld, d->T, nu, d->bad, s));
+      DV_RC(mlp_fallback(d->bad, d->p, d->tn, d->dU, d->R, d->ld, d->T, nu, s));
+    } else {
+      DV_RC(precond_idx(d->p->d_kin, d->tn, d->dU, d->R, d->ld, d->T, d->ld, d->npw, nu,
+                        precond_kind, s));
+    }
   }
   // 5. restart with the Ritz vectors when the space is full
   if (d->m + nu > d->mmax) {
@@ -378,6 +390,18 @@ pw_status pw_davidson_query(pw_davidson *d, double *theta, double *resid, int32_
   if (resid) std::copy(d->h_rho, d->h_rho + d->nb, resid);
   if (iterations) *iterations = d->iter;
   if (n_hpsi) *n_hpsi = d->n_hpsi;
+  return PW_OK;
+}
+
+pw_status pw_davidson_snapshot(pw_davidson *d, void *x, void *r, double *theta, double *rho,
+                               int64_t ld, void *stream) {
+  PW_CHECK_ARG(d && ld >= d->npw, PW_ERR_INVALID, "pw_davidson_snapshot: bad argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t row = d->npw * sizeof(double2), lds = ld * sizeof(double2), ldd = d->ld * sizeof(double2);
+  if (x) PW_HIP(hipMemcpy2DAsync(x, lds, d->X, ldd, row, d->nb, hipMemcpyDeviceToDevice, s));
+  if (r) PW_HIP(hipMemcpy2DAsync(r, lds, d->R, ldd, row, d->nb, hipMemcpyDeviceToDevice, s));
+  if (theta) PW_HIP(hipMemcpyAsync(theta, d->theta, d->nb * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (rho) PW_HIP(hipMemcpyAsync(rho, d->rho, d->nb * sizeof(double), hipMemcpyDeviceToDevice, s));
   return PW_OK;
 }
 

@@ -219,6 +219,125 @@ __device__ void fft_lines(V *buf, int nlines, int lstride, int estride, const in
   }
 }
 
+// ---------------------------------------------------------------- compile-time plans
+// For the grid sizes of the workloads the whole pass sequence is known at
+// compile time: radix, butterfly count, twiddle stride and the j mod Ns
+// divisor become constants, which removes most of the per-butterfly index
+// arithmetic of the runtime passes above.
+struct CtPlan {
+  int n;
+  int r[kMaxPasses];
+};
+constexpr CtPlan ct_plan(int N) {
+  CtPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0}};
+  int m = N, a = 0;
+  while (m % 2 == 0) {
+    m /= 2;
+    ++a;
+  }
+  while (a > 0) {
+    if (a == 4) {
+      p.r[p.n++] = 4;
+      p.r[p.n++] = 4;
+      a = 0;
+    } else if (a >= 3) {
+      p.r[p.n++] = 8;
+      a -= 3;
+    } else if (a == 2) {
+      p.r[p.n++] = 4;
+      a -= 2;
+    } else {
+      p.r[p.n++] = 2;
+      a -= 1;
+    }
+  }
+  while (m % 3 == 0) {
+    p.r[p.n++] = 3;
+    m /= 3;
+  }
+  while (m % 5 == 0) {
+    p.r[p.n++] = 5;
+    m /= 5;
+  }
+  return p;
+}
+constexpr int ct_npass(int N) { return ct_plan(N).n; }
+constexpr int ct_radix(int N, int P) { return ct_plan(N).r[P]; }
+
+template <typename V, int N, int NS, int R, bool INV, bool LINE_FAST, bool INDIRECT>
+__device__ __forceinline__ void ct_pass(V *buf, int nlines, int lstride, int estride,
+                                        const int *lbase, const V *tw, int tid_in, int nthr) {
+  int tid = tid_in;
+  asm volatile("" : "+v"(tid));
+  constexpr int MAXB = (kCpt + R - 1) / R;
+  constexpr int nbf = N / R;
+  constexpr int twstep = N / (NS * R);
+  const int total = nlines * nbf;
+  const float inl = 1.0f / (float)nlines;
+  V v[MAXB][R];
+  int bo[MAXB], oo[MAXB];
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    const int idx = tid + c * nthr;
+    if (idx < total) {
+      int line, j;
+      if (LINE_FAST) {
+        j = qdiv(idx, nlines, inl);
+        line = idx - j * nlines;
+      } else {
+        line = idx / nbf;
+        j = idx - line * nbf;
+      }
+      const int base = INDIRECT ? lbase[line] : line * lstride;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[c][r] = buf[base + (j + r * nbf) * estride];
+      int k = 0;
+      if constexpr (NS > 1) {
+        k = j % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const V w = tw[k * r * twstep];
+          v[c][r] = INV ? c_mulconj(v[c][r], w) : c_mul(v[c][r], w);
+        }
+      }
+      Dft<R, INV, V>::run(v[c]);
+      bo[c] = base;
+      oo[c] = (j - k) * R + k;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    const int idx = tid + c * nthr;
+    if (idx < total) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[bo[c] + (oo[c] + r * NS) * estride] = v[c][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename V, int N, int P, int NS, bool INV, bool LINE_FAST, bool INDIRECT>
+__device__ __forceinline__ void ct_fft(V *buf, int nlines, int lstride, int estride, const int *lbase,
+                                       const V *tw, int tid, int nthr) {
+  if constexpr (P < ct_npass(N)) {
+    constexpr int R = ct_radix(N, P);
+    ct_pass<V, N, NS, R, INV, LINE_FAST, INDIRECT>(buf, nlines, lstride, estride, lbase, tw, tid, nthr);
+    ct_fft<V, N, P + 1, NS * R, INV, LINE_FAST, INDIRECT>(buf, nlines, lstride, estride, lbase, tw, tid,
+                                                         nthr);
+  }
+}
+
+// NC > 0: compile-time length NC (must equal pl.n); NC == 0: runtime plan.
+template <typename V, bool INV, bool LINE_FAST, bool INDIRECT, int NC>
+__device__ __forceinline__ void fft_axis(V *buf, int nlines, int lstride, int estride, const int *lbase,
+                                         const AxisPlan &pl, const V *tw, int tid, int nthr) {
+  if constexpr (NC > 0)
+    ct_fft<V, NC, 0, 1, INV, LINE_FAST, INDIRECT>(buf, nlines, lstride, estride, lbase, tw, tid, nthr);
+  else
+    fft_lines<V, INV, LINE_FAST, INDIRECT>(buf, nlines, lstride, estride, lbase, pl, tw, tid, nthr);
+}
+
 // ---------------------------------------------------------------- wave-local FFTs
 // One wavefront transforms lines it owns alone, so the read and write halves
 // of a Stockham pass need no workgroup barrier: the wave's LDS operations
@@ -312,7 +431,7 @@ __device__ __forceinline__ void tile_band(int bid, int ntile, int *tile, int *ba
 }
 
 // ---------------------------------------------------------------- kernels
-template <typename T, int NTHR>
+template <typename T, int NTHR, int NC>
 __global__ __launch_bounds__(NTHR) void k_zfft_inv(FFTDev f, const double2 *__restrict__ psi,
                                                    int64_t ld, cpx_t<T> *__restrict__ sticks,
                                                    int nb) {
@@ -336,7 +455,7 @@ __global__ __launch_bounds__(NTHR) void k_zfft_inv(FFTDev f, const double2 *__re
     buf[f.gpos[e]] = V{(T)v.x, (T)v.y};
   }
   __syncthreads();
-  fft_lines<V, true, true, false>(buf, f.ts, 1, f.ts, nullptr, f.pz, tw, tid, NTHR);
+  fft_axis<V, true, true, false, NC>(buf, f.ts, 1, f.ts, nullptr, f.pz, tw, tid, NTHR);
   V *dst = sticks + (int64_t)b * f.n2 * f.nst_pad + (int64_t)tile * f.ts;
   for (int i = tid; i < nel; i += NTHR) {
     const int z = i / f.ts;
@@ -345,7 +464,7 @@ __global__ __launch_bounds__(NTHR) void k_zfft_inv(FFTDev f, const double2 *__re
   }
 }
 
-template <typename T, int NTHR>
+template <typename T, int NTHR, int NC>
 __global__ __launch_bounds__(NTHR) void k_plane(FFTDev f, cpx_t<T> *__restrict__ sticks, int nb,
                                                 int group) {
   using V = cpx_t<T>;
@@ -372,12 +491,12 @@ __global__ __launch_bounds__(NTHR) void k_plane(FFTDev f, cpx_t<T> *__restrict__
     V *col = sticks + (int64_t)b * f.n2 * f.nst_pad + (int64_t)z * f.nst_pad;
     for (int s = tid; s < f.nst; s += NTHR) pl[f.stick_xy[s]] = col[s];
     __syncthreads();
-    fft_lines<V, true, false, true>(pl, f.nx, 0, 1, lb, f.py, tw1, tid, NTHR);
-    fft_lines<V, true, true, false>(pl, f.n1, 1, f.n1, nullptr, f.px, tw0, tid, NTHR);
+    fft_axis<V, true, false, true, NC>(pl, f.nx, 0, 1, lb, f.py, tw1, tid, NTHR);
+    fft_axis<V, true, true, false, NC>(pl, f.n1, 1, f.n1, nullptr, f.px, tw0, tid, NTHR);
     for (int i = tid; i < npl; i += NTHR) pl[i] = c_scale(pl[i], vp[i]);
     __syncthreads();
-    fft_lines<V, false, true, false>(pl, f.n1, 1, f.n1, nullptr, f.px, tw0, tid, NTHR);
-    fft_lines<V, false, false, true>(pl, f.nx, 0, 1, lb, f.py, tw1, tid, NTHR);
+    fft_axis<V, false, true, false, NC>(pl, f.n1, 1, f.n1, nullptr, f.px, tw0, tid, NTHR);
+    fft_axis<V, false, false, true, NC>(pl, f.nx, 0, 1, lb, f.py, tw1, tid, NTHR);
     for (int s = tid; s < f.nst; s += NTHR) col[s] = pl[f.stick_xy[s]];
     __syncthreads();
   }
@@ -453,7 +572,7 @@ __global__ __launch_bounds__(NTHR) void k_plane_w(FFTDev f, cpx_t<T> *__restrict
   }
 }
 
-template <typename T, int NTHR>
+template <typename T, int NTHR, int NC>
 __global__ __launch_bounds__(NTHR) void k_zfft_fwd(FFTDev f, const cpx_t<T> *__restrict__ sticks,
                                                    const double2 *__restrict__ psi, int64_t ld,
                                                    double2 *__restrict__ hpsi, int64_t ldh, int nb,
@@ -476,7 +595,7 @@ __global__ __launch_bounds__(NTHR) void k_zfft_fwd(FFTDev f, const cpx_t<T> *__r
     buf[i] = srcs[(int64_t)z * f.nst_pad + sl];
   }
   __syncthreads();
-  fft_lines<V, false, true, false>(buf, f.ts, 1, f.ts, nullptr, f.pz, tw, tid, NTHR);
+  fft_axis<V, false, true, false, NC>(buf, f.ts, 1, f.ts, nullptr, f.pz, tw, tid, NTHR);
   const int e0 = f.tile_ptr[tile], e1 = f.tile_ptr[tile + 1];
   const double2 *src = psi + (int64_t)b * ld;
   double2 *dst = hpsi + (int64_t)b * ldh;
@@ -561,21 +680,49 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
 
 static inline int nb_pad8(int nb) { return (nb + 7) / 8 * 8; }
 
-template <typename T, int NT>
+// cubic grids of the workloads run compile-time-planned kernels
+#define PW_CT_SIZES(X) X(24) X(36) X(40) X(45) X(48) X(50) X(54) X(60) X(64) X(72) X(81) X(90)
+
+static int ct_size(const FFTDev &f, int prec) {
+  static int off = -1;
+  if (off < 0) {
+    const char *e = std::getenv("PW_FFT_GENERIC");
+    off = (e && *e && std::atoi(e)) ? 1 : 0;
+  }
+  if (off || f.n0 != f.n1 || f.n1 != f.n2) return 0;
+  if (f.ts != (prec == PW_FP64 ? 16 : 32)) return 0;
+  switch (f.n0) {
+#define PW_CASE(n) case n: return n;
+    PW_CT_SIZES(PW_CASE)
+#undef PW_CASE
+    default: return 0;
+  }
+}
+
+template <typename T, int NT, int NC>
 static int zinv_n(const FFTDev &f, const void *psi, int64_t ld, void *sticks, int nb, hipStream_t s) {
   using V = cpx_t<T>;
   const size_t lds = sizeof(V) * (size_t)f.n2 * (1 + f.ts);
   const int blocks = f.ntile * nb_pad8(nb);
-  auto k = k_zfft_inv<T, NT>;
+  auto k = k_zfft_inv<T, NT, NC>;
   if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
   hipLaunchKernelGGL(k, dim3(blocks), dim3(NT), lds, s, f, static_cast<const double2 *>(psi), ld,
                      static_cast<V *>(sticks), nb);
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
+template <typename T, int NC>
+static int zinv_c(const FFTDev &f, const void *psi, int64_t ld, void *sticks, int nb, hipStream_t s) {
+  return f.ts * f.n2 <= kCpt * 256 ? zinv_n<T, 256, NC>(f, psi, ld, sticks, nb, s)
+                                   : zinv_n<T, 512, NC>(f, psi, ld, sticks, nb, s);
+}
 template <typename T>
 static int zinv_t(const FFTDev &f, const void *psi, int64_t ld, void *sticks, int nb, hipStream_t s) {
-  return f.ts * f.n2 <= kCpt * 256 ? zinv_n<T, 256>(f, psi, ld, sticks, nb, s)
-                                   : zinv_n<T, 512>(f, psi, ld, sticks, nb, s);
+  switch (ct_size(f, sizeof(T) == 8 ? PW_FP64 : PW_MIXED_FP32)) {
+#define PW_CASE(n) case n: return zinv_c<T, n>(f, psi, ld, sticks, nb, s);
+    PW_CT_SIZES(PW_CASE)
+#undef PW_CASE
+    default: return zinv_c<T, 0>(f, psi, ld, sticks, nb, s);
+  }
 }
 
 static int plane_impl() {
@@ -597,6 +744,24 @@ static int plane_w_n(const FFTDev &f, void *sticks, int nb, int group, size_t ld
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
 
+template <typename T, int NT, int NC>
+static int plane_n(const FFTDev &f, void *sticks, int nb, int group, size_t lds, int blocks,
+                   hipStream_t s) {
+  using V = cpx_t<T>;
+  auto k = k_plane<T, NT, NC>;
+  if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(NT), lds, s, f, static_cast<V *>(sticks), nb, group);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+template <typename T, int NC>
+static int plane_c(const FFTDev &f, void *sticks, int nb, int group, size_t lds, int blocks,
+                   hipStream_t s) {
+  const int npl = f.n0 * f.n1;
+  if (npl <= kCpt * 256) return plane_n<T, 256, NC>(f, sticks, nb, group, lds, blocks, s);
+  if (npl <= kCpt * 512) return plane_n<T, 512, NC>(f, sticks, nb, group, lds, blocks, s);
+  return plane_n<T, 1024, NC>(f, sticks, nb, group, lds, blocks, s);
+}
+
 template <typename T>
 static int plane_t(const FFTDev &f, void *sticks, int nb, int group, hipStream_t s) {
   using V = cpx_t<T>;
@@ -609,41 +774,43 @@ static int plane_t(const FFTDev &f, void *sticks, int nb, int group, hipStream_t
     if (npl <= 4096) return plane_w_n<T, 512>(f, sticks, nb, group, lds, blocks, s);
     return plane_w_n<T, 1024>(f, sticks, nb, group, lds, blocks, s);
   }
-  if (npl <= kCpt * 256) {
-    auto k = k_plane<T, 256>;
-    if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, s, f, static_cast<V *>(sticks), nb, group);
-  } else if (npl <= kCpt * 512) {
-    auto k = k_plane<T, 512>;
-    if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(512), lds, s, f, static_cast<V *>(sticks), nb, group);
-  } else {
-    auto k = k_plane<T, 1024>;
-    if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(1024), lds, s, f, static_cast<V *>(sticks), nb, group);
+  switch (ct_size(f, sizeof(T) == 8 ? PW_FP64 : PW_MIXED_FP32)) {
+#define PW_CASE(n) case n: return plane_c<T, n>(f, sticks, nb, group, lds, blocks, s);
+    PW_CT_SIZES(PW_CASE)
+#undef PW_CASE
+    default: return plane_c<T, 0>(f, sticks, nb, group, lds, blocks, s);
   }
-  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
 
-template <typename T, int NT>
+template <typename T, int NT, int NC>
 static int zfwd_n(const FFTDev &f, const void *sticks, const void *psi, int64_t ld, void *hpsi,
                   int64_t ldh, int nb, bool kinetic, hipStream_t s) {
   using V = cpx_t<T>;
   const size_t lds = sizeof(V) * (size_t)f.n2 * (1 + f.ts);
   const int blocks = f.ntile * nb_pad8(nb);
-  auto k = k_zfft_fwd<T, NT>;
+  auto k = k_zfft_fwd<T, NT, NC>;
   if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
   hipLaunchKernelGGL(k, dim3(blocks), dim3(NT), lds, s, f, static_cast<const V *>(sticks),
                      static_cast<const double2 *>(psi), ld, static_cast<double2 *>(hpsi), ldh, nb,
                      kinetic ? 1 : 0);
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
+template <typename T, int NC>
+static int zfwd_c(const FFTDev &f, const void *sticks, const void *psi, int64_t ld, void *hpsi,
+                  int64_t ldh, int nb, bool kinetic, hipStream_t s) {
+  return f.ts * f.n2 <= kCpt * 256
+             ? zfwd_n<T, 256, NC>(f, sticks, psi, ld, hpsi, ldh, nb, kinetic, s)
+             : zfwd_n<T, 512, NC>(f, sticks, psi, ld, hpsi, ldh, nb, kinetic, s);
+}
 template <typename T>
 static int zfwd_t(const FFTDev &f, const void *sticks, const void *psi, int64_t ld, void *hpsi,
                   int64_t ldh, int nb, bool kinetic, hipStream_t s) {
-  return f.ts * f.n2 <= kCpt * 256
-             ? zfwd_n<T, 256>(f, sticks, psi, ld, hpsi, ldh, nb, kinetic, s)
-             : zfwd_n<T, 512>(f, sticks, psi, ld, hpsi, ldh, nb, kinetic, s);
+  switch (ct_size(f, sizeof(T) == 8 ? PW_FP64 : PW_MIXED_FP32)) {
+#define PW_CASE(n) case n: return zfwd_c<T, n>(f, sticks, psi, ld, hpsi, ldh, nb, kinetic, s);
+    PW_CT_SIZES(PW_CASE)
+#undef PW_CASE
+    default: return zfwd_c<T, 0>(f, sticks, psi, ld, hpsi, ldh, nb, kinetic, s);
+  }
 }
 
 int launch_zfft_inv(const FFTDev &f, int prec, const void *psi, int64_t ld, void *sticks, int nb,

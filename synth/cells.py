@@ -112,6 +112,12 @@ def _positions(rng, nat: int, a: float, min_sep: float | None) -> np.ndarray:
     return pos
 
 
+def _min_sep(nat: int, a: float, want: float = 3.0) -> float:
+    """Requested separation, capped at 0.7x the mean spacing (a^3/nat)^(1/3) so that
+    random sequential placement stays feasible in dense cells."""
+    return min(want, 0.7 * (a ** 3 / nat) ** (1.0 / 3.0))
+
+
 def _haar_orthogonal(rng, n: int) -> np.ndarray:
     g = rng.standard_normal((n, n))
     q, r = np.linalg.qr(g)
@@ -166,7 +172,7 @@ def make_cell(config: int, index: int = 0, seed: int | None = None) -> Cell:
         rng = np.random.default_rng(s)
         a, ecut_ry, nat, nb = 20.0, 30.0, 64, 256
         n = smooth_grid(alias_free_min(a, ecut_ry))
-        pos = _positions(rng, nat, a, 3.0)
+        pos = _positions(rng, nat, a, _min_sep(nat, a))
         depth = rng.uniform(0.5, 2.0, size=nat)
         lmax = np.full(nat, 2, dtype=np.int32)
         dij = _dij(rng, lmax, full=True)
@@ -181,7 +187,7 @@ def make_cell(config: int, index: int = 0, seed: int | None = None) -> Cell:
         nat = int(rng.integers(8, 49))
         nb = int(rng.integers(32, 193))
         n = smooth_grid(alias_free_min(a, ecut_ry))
-        pos = _positions(rng, nat, a, 3.0 if nat * 27.0 < a ** 3 else None)
+        pos = _positions(rng, nat, a, _min_sep(nat, a))
         depth = rng.uniform(0.5, 2.0, size=nat)
         lmax = np.ones(nat, dtype=np.int32)
         dij = _dij(rng, lmax, full=False)
@@ -201,7 +207,7 @@ def make_cell(config: int, index: int = 0, seed: int | None = None) -> Cell:
             nat = int(rng.integers(32, 97))
             nb = 4 * nat
         n = smooth_grid(alias_free_min(a, ecut_ry))
-        pos = _positions(rng, nat, a, 3.0 if nat * 27.0 < a ** 3 else None)
+        pos = _positions(rng, nat, a, _min_sep(nat, a))
         depth = rng.uniform(0.5, 2.0, size=nat)
         lmax = np.ones(nat, dtype=np.int32)
         dij = _dij(rng, lmax, full=False)
