@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--kpoints", type=int, default=5)
     ap.add_argument("--no-davidson", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-cells", type=int, default=64)
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--davidson-reps", type=int, default=3)
     return ap.parse_args()
 
@@ -116,6 +119,70 @@ def davidson_section(reps: int):
         if "iterations_first" in r:
             out[name]["iterations_reduced_precision"] = r["iterations_first"]
         out[name]["_theta"] = r["theta"]
+    return out
+
+
+def batched_section(ncells: int, steps: int):
+    """64 ragged cells (a 10-18 bohr, 20-40 Ry, 8-48 atoms, 32-192 bands): one H*psi
+    sweep per step, eager launches vs one HIP-graph launch per step."""
+    import torch
+    import synth
+    from paper_1709_10010_amd import _lib
+    from paper_1709_10010_amd.problems import band_block, build_problem
+
+    probs, xs, ys, nbs, npws = [], [], [], [], []
+    for i in range(ncells):
+        c = synth.make_cell(4, i)
+        p, _ = build_problem(c, 0, max_bands=c.nbands)
+        x = band_block(c.nbands, p.npw)
+        x[:, :p.npw] = torch.from_numpy(synth.psi_start(c.seed, c.nbands, p.npw)).cuda()
+        probs.append(p)
+        xs.append(x)
+        ys.append(torch.zeros_like(x))
+        nbs.append(c.nbands)
+        npws.append(p.npw)
+    b = _lib.Batch(probs, xs, ys)
+    s = torch.cuda.Stream()
+    out = {"cells": ncells, "bands_per_step": int(sum(nbs)), "npw_range": [min(npws), max(npws)]}
+    with torch.cuda.stream(s):
+        _lib.pw_batch_hpsi(b, s)
+        s.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _lib.pw_batch_hpsi(b, s)
+        s.synchronize()
+        te = (time.perf_counter() - t0) / steps
+        _lib.pw_batch_capture(b, s)
+        _lib.pw_batch_launch(b, s)
+        s.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _lib.pw_batch_launch(b, s)
+        s.synchronize()
+        tg = (time.perf_counter() - t0) / steps
+    out["eager"] = {"ms_per_step": round(te * 1e3, 3), "band-H*psi/s": round(sum(nbs) / te, 1)}
+    out["graph"] = {"ms_per_step": round(tg * 1e3, 3), "band-H*psi/s": round(sum(nbs) / tg, 1),
+                    "launches_per_step": 1}
+    b.close()
+    return out
+
+
+def learned_section():
+    """TPA vs trained-MLP Davidson on a held-out training-family cell (FP32 form, 1e-6 Ry)."""
+    from paper_1709_10010_amd import learned
+    import synth
+    path = os.path.join(ROOT, "paper_1709_10010_amd", "weights", "precond_mlp.npz")
+    if not os.path.exists(path):
+        return {"note": "no trained weights in the tree"}
+    net = learned.load(path)
+    cell = synth.make_cell(5, 199)
+    r = learned.evaluate(cell, net, tol=5e-7)
+    out = {"cell": f"{cell.name}: a={cell.A[0, 0]:.2f} bohr, {int(2 * cell.ecut_ha)} Ry, "
+                   f"{cell.natom} atoms, {cell.nbands} bands, grid {cell.nr[0]}^3, form fp32",
+           "tol_Ry": 1e-6, "max_theta_diff_Ry": round(2 * r["max_theta_diff_Ha"], 12)}
+    for k in ("tpa", "mlp"):
+        out[k] = {"iterations": r[k]["iterations"], "seconds": round(r[k]["seconds"], 4),
+                  "n_hpsi": r[k]["n_hpsi"], "converged": bool(r[k]["converged"])}
     return out
 
 
@@ -248,6 +315,10 @@ def main():
         "ms_per_step_profiled": round(dt_prof / args.steps * 1e3, 4),
     }
     dav = None if args.no_davidson else davidson_section(args.davidson_reps)
+    if not args.no_batched:
+        out["batched_ragged_cells"] = batched_section(args.batched_cells, max(3, args.steps // 2))
+    if not args.no_learned:
+        out["learned_preconditioner"] = learned_section()
     if not args.no_cpu_baseline:
         cb = cpu_baseline(cell, 0, args.cpu_seconds)
         out["cpu_baseline"] = cb

@@ -210,7 +210,7 @@ pw_status pw_davidson_create(pw_problem *p, int64_t nbands, int64_t max_subspace
             dalloc(&d->w_all, lde) && dalloc(&d->theta, nb) && dalloc(&d->rho, nb) &&
             dalloc(&d->tn, nb) && dalloc(&d->lam, lde) && dalloc(&d->idx_sel, nb) &&
             dalloc(&d->dU, nb) && dalloc(&d->keep, nb) && dalloc(&d->flag, 1) &&
-            dalloc(&d->sweeps, 1) && dalloc(&d->bad, nb) && dalloc((char **)&d->rot_ws, lde * 32) &&
+            dalloc(&d->sweeps, 1) && dalloc(&d->bad, nb) && dalloc((double2 **)&d->rot_ws, lde * lde) &&
             dalloc(&d->acc_ws, 128) && halloc(&d->h_theta, nb) && halloc(&d->h_rho, nb) &&
             halloc(&d->h_lam, lde) && halloc(&d->h_U, nb) && halloc(&d->h_flag, 1) &&
             halloc(&d->h_keep, nb);

@@ -18,8 +18,10 @@
 // off-diagonal mass is below (1e-15)^2 of the total, at most kMaxSweeps.
 //
 // Small matrices (m' <= 64) run in one workgroup with A and Z in LDS; larger
-// ones run as a cooperative grid with both phases separated by grid-wide
-// barriers.  Both are bounded: every wave leaves after at most kMaxSweeps.
+// ones run as a cooperative grid in which each thread recomputes the two
+// rotations of its block from the previous round's matrix and writes into
+// a second buffer, so a round costs one grid-wide barrier.  Both are
+// bounded: every wave leaves after at most kMaxSweeps sweeps.
 //
 // Also here: eigenvalue sort / Ritz-vector selection, Cholesky of a small
 // Hermitian positive matrix with breakdown detection, the inverse of its
@@ -194,12 +196,19 @@ __global__ __launch_bounds__(256) void k_jacobi_lds(const double2 *__restrict__ 
 }
 
 // ---------------------------------------------------------------- cooperative Jacobi
-// A (lda) is overwritten; Z (ldz) must hold mp x mp; rot holds mp/2 Rot;
-// acc holds 2*kMaxSweeps doubles (zeroed here).
-__global__ __launch_bounds__(256) void k_jacobi_coop(double2 *__restrict__ A, int64_t lda, int m,
-                                                     double *__restrict__ w,
+// A (lda) and B (same shape) alternate as input / output of a round, so one
+// grid barrier per round suffices: every thread recomputes, from the input
+// matrix, the two rotations its 2x2 block needs and writes the block to the
+// output; Z (ldz, mp x mp) is updated in place, each (row, pair) by one
+// thread.  acc holds 2*kMaxSweeps doubles (zeroed here).  On exit the
+// eigenvalues are in w; *which = 0 if the final matrix is in A, 1 if in B.
+__device__ __forceinline__ Rot rot_of(const double2 *M, int64_t ld, int p, int q) {
+  return make_rot(M[p + p * ld].x, M[q + q * ld].x, M[p + q * ld]);
+}
+
+__global__ __launch_bounds__(256) void k_jacobi_coop(double2 *__restrict__ A, double2 *__restrict__ B,
+                                                     int64_t lda, int m, double *__restrict__ w,
                                                      double2 *__restrict__ Z, int64_t ldz,
-                                                     Rot *__restrict__ rot,
                                                      double *__restrict__ acc,
                                                      int *__restrict__ sweeps_out) {
   cg::grid_group grid = cg::this_grid();
@@ -208,7 +217,6 @@ __global__ __launch_bounds__(256) void k_jacobi_coop(double2 *__restrict__ A, in
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
   __shared__ double red[2][256];
-  // pad row / column of an odd m, identity Z, zero the accumulators
   for (int64_t e = gtid; e < (int64_t)mp * mp; e += gsz) {
     const int i = (int)(e % mp), j = (int)(e / mp);
     if (i >= m || j >= m) A[i + j * lda] = double2{0.0, 0.0};
@@ -216,12 +224,13 @@ __global__ __launch_bounds__(256) void k_jacobi_coop(double2 *__restrict__ A, in
   }
   for (int64_t e = gtid; e < 2 * kMaxSweeps; e += gsz) acc[e] = 0.0;
   grid.sync();
+  double2 *cur = A, *nxt = B;
   int sweep = 0;
   for (; sweep < kMaxSweeps; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int64_t e = gtid; e < (int64_t)mp * mp; e += gsz) {
       const int i = (int)(e % mp), j = (int)(e / mp);
-      const double2 v = A[i + j * lda];
+      const double2 v = cur[i + j * lda];
       const double a2 = v.x * v.x + v.y * v.y;
       tot += a2;
       if (i != j) off += a2;
@@ -245,36 +254,34 @@ __global__ __launch_bounds__(256) void k_jacobi_coop(double2 *__restrict__ A, in
     const double tots = __hip_atomic_load(&acc[2 * sweep + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (offs <= 1e-30 * tots) break;  // uniform: every thread reads the same totals
     for (int r = 0; r < mp - 1; ++r) {
-      for (int64_t k = gtid; k < np; k += gsz) {
-        int p, q;
-        pair_of((int)k, r, mp, &p, &q);
-        rot[k] = make_rot(A[p + p * lda].x, A[q + q * lda].x, A[p + q * lda]);
-      }
-      grid.sync();
       for (int64_t e = gtid; e < (int64_t)np * np; e += gsz) {
         const int ka = (int)(e % np), kb = (int)(e / np);
         int pa, qa, pb, qb;
         pair_of(ka, r, mp, &pa, &qa);
         pair_of(kb, r, mp, &pb, &qb);
-        double2 a = A[pa + pb * lda], b = A[pa + qb * lda], c = A[qa + pb * lda], d = A[qa + qb * lda];
-        const Rot ra = rot[ka], rb = rot[kb];
+        const Rot ra = rot_of(cur, lda, pa, qa);
+        const Rot rb = (ka == kb) ? ra : rot_of(cur, lda, pb, qb);
+        double2 a = cur[pa + pb * lda], b = cur[pa + qb * lda], c = cur[qa + pb * lda], d = cur[qa + qb * lda];
         update_block(a, b, c, d, ra, rb);
-        A[pa + pb * lda] = a;
-        A[pa + qb * lda] = b;
-        A[qa + pb * lda] = c;
-        A[qa + qb * lda] = d;
+        nxt[pa + pb * lda] = a;
+        nxt[pa + qb * lda] = b;
+        nxt[qa + pb * lda] = c;
+        nxt[qa + qb * lda] = d;
       }
       for (int64_t e = gtid; e < (int64_t)mp * np; e += gsz) {
         const int i = (int)(e % mp), kb = (int)(e / mp);
         int pb, qb;
         pair_of(kb, r, mp, &pb, &qb);
-        const Rot rb = rot[kb];
+        const Rot rb = rot_of(cur, lda, pb, qb);
         update_zrow(Z[i + pb * ldz], Z[i + qb * ldz], rb);
       }
+      double2 *t = cur;
+      cur = nxt;
+      nxt = t;
       grid.sync();
     }
   }
-  for (int64_t i = gtid; i < m; i += gsz) w[i] = A[i + i * lda].x;
+  for (int64_t i = gtid; i < m; i += gsz) w[i] = cur[i + i * lda].x;
   if (gtid == 0 && sweeps_out) *sweeps_out = sweep;
 }
 
@@ -489,6 +496,7 @@ static int grid_for(int64_t n, int bs = 256, int cap = 2048) {
   return (int)b;
 }
 
+// rot_ws: second matrix buffer of the same shape as A (lda x lda).
 int eig_herm(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz, void *rot_ws,
              double *acc_ws, int *sweeps, int coop_blocks, hipStream_t s) {
   if (m <= 0) return PW_OK;
@@ -497,8 +505,8 @@ int eig_herm(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz,
     hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(256), 0, s, A, lda, m, w, Z, ldz, sweeps);
     return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
   }
-  Rot *rot = static_cast<Rot *>(rot_ws);
-  void *args[] = {&A, &lda, &m, &w, &Z, &ldz, &rot, &acc_ws, &sweeps};
+  double2 *B = static_cast<double2 *>(rot_ws);
+  void *args[] = {&A, &B, &lda, &m, &w, &Z, &ldz, &acc_ws, &sweeps};
   const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_jacobi_coop),
                                                   dim3(coop_blocks), dim3(256), args, 0, s);
   return e == hipSuccess ? PW_OK : PW_ERR_HIP;
