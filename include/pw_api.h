@@ -234,6 +234,17 @@ pw_status pw_davidson_snapshot(pw_davidson *d, void *x, void *r, double *theta, 
 pw_status pw_davidson_vectors(pw_davidson *d, void *x, int64_t ld, void *stream);
 
 /*
+ * Hermitian eigensolver of the subspace step (cyclic two-sided Jacobi, FP64):
+ * eigenvalues ascending in w (device double [m]) and the matching
+ * orthonormal eigenvectors as the columns of Z (device complex128, column-
+ * major, ldz >= m).  A (device complex128, column-major, lda >= m) is read,
+ * not modified.  work: device scratch of pw_eigh_workspace(m) bytes.
+ */
+pw_status pw_eigh_workspace(int32_t m, size_t *bytes);
+pw_status pw_eigh(const void *A, int64_t lda, int32_t m, double *w, void *Z, int64_t ldz, void *work,
+                  size_t work_bytes, void *stream);
+
+/*
  * Batched H*psi over independent problems (cells or k-points with ragged
  * npw, grids and band counts): the paper runs such units side by side as
  * images and k-point pools.  A batch lists, per problem, its input and

@@ -53,6 +53,10 @@ class _Desc(C.Structure):
 
 
 def _load():
+    # torch ships its own HIP runtime with the same soname (libamdhip64.so.7);
+    # loading torch first makes the library bind to that one, so the process
+    # holds a single HIP runtime whichever module the caller imports first
+    import torch  # noqa: F401
     if not os.path.exists(LIBPATH):
         raise ImportError(f"{LIBPATH} is missing: build it with __graft_entry__.build() "
                           "(hipcc --offload-arch=gfx950); there is no fallback path")
@@ -98,6 +102,8 @@ def _load():
         "pw_batch_launch": (i32, [vp, vp]),
         "pw_problem_autotune": (i32, [vp, i64, i32, vp, C.POINTER(f64)]),
         "pw_problem_tuning": (i32, [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32)]),
+        "pw_eigh_workspace": (i32, [i32, C.POINTER(C.c_size_t)]),
+        "pw_eigh": (i32, [vp, i64, i32, vp, vp, i64, vp, C.c_size_t, vp]),
         "pw_profile_enable": (i32, [vp, i32]),
         "pw_profile_read": (i32, [vp, C.POINTER(f64), C.POINTER(i64), i32]),
     }
@@ -594,3 +600,22 @@ def pw_problem_tuning(prob: Problem) -> dict:
     g, c, k = C.c_int32(), C.c_int64(), C.c_int32()
     _check(LIB.pw_problem_tuning(prob.handle, C.byref(g), C.byref(c), C.byref(k)))
     return dict(plane_group=g.value, band_chunk=c.value, ksplit=k.value)
+
+
+def pw_eigh(A, stream=None):
+    """Eigen-decomposition of a Hermitian complex128 matrix (torch, column-major
+    as stored: A[:, j] is column j) -> (w ascending, Z) on the GPU."""
+    import torch
+    m = int(A.shape[0])
+    if A.dim() != 2 or A.shape[1] != m or A.dtype != torch.complex128 or not A.is_cuda:
+        raise ValueError("A must be a square complex128 GPU tensor")
+    At = A.t().contiguous()          # column-major storage of A
+    nbytes = C.c_size_t(0)
+    _check(LIB.pw_eigh_workspace(m, C.byref(nbytes)))
+    work = torch.empty(int(nbytes.value), dtype=torch.uint8, device=A.device)
+    w = torch.empty(m, dtype=torch.float64, device=A.device)
+    Zt = torch.empty((m, m), dtype=torch.complex128, device=A.device)
+    _check(LIB.pw_eigh(C.c_void_p(At.data_ptr()), m, m, C.c_void_p(w.data_ptr()),
+                       C.c_void_p(Zt.data_ptr()), m, C.c_void_p(work.data_ptr()), nbytes.value,
+                       _stream(stream)))
+    return w, Zt.t()

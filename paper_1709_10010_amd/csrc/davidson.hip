@@ -59,6 +59,9 @@ struct pw_davidson {
   int64_t n_hpsi = 0;
   bool inited = false, converged = false;
   double2 *V = nullptr, *W = nullptr, *X = nullptr, *HX = nullptr, *R = nullptr, *T = nullptr;
+  double2 *Vt = nullptr, *Wt = nullptr;  // rotation targets (swapped with V, W each step)
+  double *w_sorted = nullptr;
+  int *idx_all = nullptr;
   double2 *Hs = nullptr, *Ae = nullptr, *Ze = nullptr, *Y = nullptr, *C = nullptr;
   double2 *S = nullptr, *L = nullptr, *Xi = nullptr, *Bi = nullptr;
   double *w_all = nullptr, *theta = nullptr, *rho = nullptr, *tn = nullptr, *lam = nullptr;
@@ -80,7 +83,7 @@ void free_dav(pw_davidson *d) {
   void *dev[] = {d->V,  d->W,  d->X,  d->HX,    d->R,     d->T,    d->Hs,    d->Ae,  d->Ze,
                  d->Y,  d->C,  d->S,  d->L,     d->Xi,    d->Bi,   d->w_all, d->theta, d->rho,
                  d->tn, d->lam, d->idx_sel, d->dU, d->keep, d->flag, d->sweeps, d->rot_ws,
-                 d->acc_ws, d->part, d->bad};
+                 d->acc_ws, d->part, d->bad, d->Vt, d->Wt, d->w_sorted, d->idx_all};
   for (void *b : dev)
     if (b) (void)hipFree(b);
   void *host[] = {d->h_theta, d->h_rho, d->h_lam, d->h_U, d->h_flag, d->h_keep};
@@ -196,13 +199,15 @@ pw_status pw_davidson_create(pw_problem *p, int64_t nbands, int64_t max_subspace
   d->p = p;
   d->nb = (int)nbands;
   d->mmax = (int)max_subspace;
-  d->lde = (d->mmax + 1) & ~1;
+  d->lde = (d->mmax + 31) / 32 * 32;  // room for the block eigensolver's padding
   d->tol = tol;
   d->npw = p->npw;
   d->ld = (p->npw + 63) / 64 * 64;
   const size_t blk = (size_t)d->ld;
   const size_t nb = d->nb, lde = d->lde;
   bool ok = dalloc(&d->V, lde * blk) && dalloc(&d->W, lde * blk) && dalloc(&d->X, nb * blk) &&
+            dalloc(&d->Vt, lde * blk) && dalloc(&d->Wt, lde * blk) && dalloc(&d->w_sorted, lde) &&
+            dalloc(&d->idx_all, lde) &&
             dalloc(&d->HX, nb * blk) && dalloc(&d->R, nb * blk) && dalloc(&d->T, nb * blk) &&
             dalloc(&d->Hs, lde * lde) && dalloc(&d->Ae, lde * lde) && dalloc(&d->Ze, lde * lde) &&
             dalloc(&d->Y, lde * nb) && dalloc(&d->C, lde * nb) && dalloc(&d->S, nb * nb) &&
@@ -274,17 +279,25 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   const bool set_error_if_empty = true;
   const char *where = "pw_davidson_step: launch failed";
   const int nb = d->nb;
-  // 1. Rayleigh-Ritz
+  // 1. Rayleigh-Ritz: H_s = Z diag(w) Z^H, eigenpairs sorted ascending
   {
     ProfScope ps(&d->p->prof, PW_STAGE_EIG, s);
     DV_RC(copy_mat(d->Hs, d->lde, d->Ae, d->lde, d->m, d->m, s));
     DV_RC(eig_herm(d->Ae, d->lde, d->m, d->w_all, d->Ze, d->lde, d->rot_ws, d->acc_ws, d->sweeps,
                    d->coop, s));
-    DV_RC(eig_select(d->w_all, d->m, nb, d->theta, d->idx_sel, d->Ze, d->lde, d->Y, d->lde, s));
+    DV_RC(eig_select(d->w_all, d->m, d->m, d->w_sorted, d->idx_all, d->Ze, d->lde, d->Ae, d->lde, s));
   }
-  // 2. Ritz vectors
-  DV_RC(nn(d, nb, d->m, 1.0, d->V, d->Y, d->lde, 0.0, d->X, s));
-  DV_RC(nn(d, nb, d->m, 1.0, d->W, d->Y, d->lde, 0.0, d->HX, s));
+  // 2. rotate the whole space into the Ritz basis (V <- V Z, W <- W Z): the
+  //    first nb columns are the Ritz vectors, H_s becomes diag(w), and the
+  //    next bordered H_s is nearly diagonal, so its Jacobi solve is short
+  DV_RC(nn(d, d->m, d->m, 1.0, d->V, d->Ae, d->lde, 0.0, d->Vt, s));
+  DV_RC(nn(d, d->m, d->m, 1.0, d->W, d->Ae, d->lde, 0.0, d->Wt, s));
+  std::swap(d->V, d->Vt);
+  std::swap(d->W, d->Wt);
+  DV_RC(set_diag(d->Hs, d->lde, d->m, d->w_sorted, s));
+  PW_HIP(hipMemcpyAsync(d->theta, d->w_sorted, nb * sizeof(double), hipMemcpyDeviceToDevice, s));
+  PW_HIP(hipMemcpyAsync(d->X, d->V, (size_t)nb * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  PW_HIP(hipMemcpyAsync(d->HX, d->W, (size_t)nb * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
   // 3. residuals
   {
     ProfScope ps(&d->p->prof, PW_STAGE_VEC, s);
@@ -318,13 +331,9 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
                         precond_kind, s));
     }
   }
-  // 5. restart with the Ritz vectors when the space is full
-  if (d->m + nu > d->mmax) {
-    PW_HIP(hipMemcpyAsync(d->V, d->X, (size_t)nb * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
-    PW_HIP(hipMemcpyAsync(d->W, d->HX, (size_t)nb * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
-    DV_RC(set_diag(d->Hs, d->lde, nb, d->theta, s));
-    d->m = nb;
-  }
+  // 5. restart with the Ritz vectors when the space is full (they already
+  //    are the first nb columns of V, with H_s = diag(theta) there)
+  if (d->m + nu > d->mmax) d->m = nb;
   // 6. orthonormalise against the space
   int nk = 0;
   double2 *Vn = d->V + (size_t)d->m * d->ld;

@@ -15,7 +15,8 @@
 //           becomes J_a^H A_ab J_b) and accumulates  Z <- Z J.
 // A sweep is m'-1 rounds (m' = m rounded up to even; a padding index has a
 // zero row so its rotations are the identity).  Sweeps repeat until the
-// off-diagonal mass is below (1e-15)^2 of the total, at most kMaxSweeps.
+// off-diagonal mass is at the rounding level (4 m eps^2 of the total), at
+// most kMaxSweeps; elements below eps sqrt(|a_pp a_qq|) are not rotated.
 //
 // Small matrices (m' <= 64) run in one workgroup with A and Z in LDS; larger
 // ones run as a cooperative grid in which each thread recomputes the two
@@ -28,6 +29,9 @@
 // triangular factor, and the small elementwise kernels of a Davidson step.
 #include <hip/hip_cooperative_groups.h>
 
+#include <algorithm>
+#include <cstdlib>
+
 #include "common.h"
 
 namespace cg = cooperative_groups;
@@ -35,6 +39,11 @@ namespace cg = cooperative_groups;
 namespace pw {
 
 constexpr int kMaxSweeps = 40;
+// Stop when the off-diagonal mass is at most 4 m eps^2 of the total: after
+// convergence every off-diagonal element sits at the rounding level eps |a|
+// of its row, which leaves about m eps^2 of relative mass that no further
+// sweep can remove.
+constexpr double kOffRel = 4.0 * 4.93e-32;
 
 struct Rot {
   double c, s, er, ei;  // J = [[c, s], [-s e, c e]],  e = er + i ei = e^{-i phi}
@@ -51,7 +60,9 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return double2{a
 __device__ __forceinline__ Rot make_rot(double alpha, double gamma, double2 beta) {
   Rot r{1.0, 0.0, 1.0, 0.0};
   const double ab = sqrt(beta.x * beta.x + beta.y * beta.y);
-  if (ab == 0.0 || ab <= 1e-300) return r;
+  // threshold Jacobi: an element below the rounding level of its diagonal
+  // pair is left alone (no rotation), so converged matrices stop changing
+  if (ab == 0.0 || ab <= 1e-300 || ab <= 1e-16 * sqrt(fabs(alpha * gamma))) return r;
   const double tau = (gamma - alpha) / (2.0 * ab);
   const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
   const double c = 1.0 / sqrt(1.0 + t * t);
@@ -156,7 +167,7 @@ __global__ __launch_bounds__(256) void k_jacobi_lds(const double2 *__restrict__ 
       if (tid < s) red[tid] += red[tid + s];
       __syncthreads();
     }
-    if (tid == 0) done = (offs <= 1e-30 * red[0]) ? 1 : 0;
+    if (tid == 0) done = (offs <= kOffRel * (double)mp * red[0]) ? 1 : 0;
     __syncthreads();
     if (done) break;
     for (int r = 0; r < mp - 1; ++r) {
@@ -252,7 +263,7 @@ __global__ __launch_bounds__(256) void k_jacobi_coop(double2 *__restrict__ A, do
     grid.sync();
     const double offs = __hip_atomic_load(&acc[2 * sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const double tots = __hip_atomic_load(&acc[2 * sweep + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (offs <= 1e-30 * tots) break;  // uniform: every thread reads the same totals
+    if (offs <= kOffRel * (double)mp * tots) break;  // uniform: all threads read the same totals
     for (int r = 0; r < mp - 1; ++r) {
       for (int64_t e = gtid; e < (int64_t)np * np; e += gsz) {
         const int ka = (int)(e % np), kb = (int)(e / np);
@@ -283,6 +294,213 @@ __global__ __launch_bounds__(256) void k_jacobi_coop(double2 *__restrict__ A, do
   }
   for (int64_t i = gtid; i < m; i += gsz) w[i] = cur[i + i * lda].x;
   if (gtid == 0 && sweeps_out) *sweeps_out = sweep;
+}
+
+// ---------------------------------------------------------------- block Jacobi
+// Indices are grouped into blocks of kBJ; a round pairs the 2k blocks by the
+// circle schedule, and
+//   k_bj_inner  (one workgroup per block pair) diagonalises the pair's
+//               2kBJ x 2kBJ sub-matrix completely in LDS with the scalar
+//               Jacobi rotations above and stores its unitary U_P;
+//   k_bj_apply  replaces every 2kBJ x 2kBJ block A_PQ by U_P^H A_PQ U_Q and
+//               every row chunk of Z[:, Q] by Z[:, Q] U_Q (each block owned by
+//               one workgroup, so the update is in place).
+// A sweep is 2k-1 rounds, i.e. 2m/kBJ global steps instead of m for the
+// element-wise schedule, and the inner solves run at workgroup-barrier cost.
+constexpr int kBJ = 16;
+constexpr int kSub = 2 * kBJ;
+
+__device__ __forceinline__ int bj_index(int blk, int i) { return blk * kBJ + i; }
+
+// rows / columns of pair p in round r of 2k blocks: local i < kBJ -> block I, else block J
+__device__ __forceinline__ int bj_global(int p, int r, int nblk, int i) {
+  int I, J;
+  pair_of(p, r, nblk, &I, &J);
+  return i < kBJ ? bj_index(I, i) : bj_index(J, i - kBJ);
+}
+
+__global__ __launch_bounds__(256) void k_bj_inner(const double2 *__restrict__ A, int64_t lda, int nblk,
+                                                  int r, double2 *__restrict__ U, int max_sweeps) {
+  __shared__ double2 S[kSub][kSub + 1];
+  __shared__ double2 Q[kSub][kSub + 1];
+  __shared__ Rot rot[kSub / 2];
+  __shared__ double red[256];
+  __shared__ int done;
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kSub * kSub; e += 256) {
+    const int i = e % kSub, j = e / kSub;
+    S[i][j] = A[bj_global(p, r, nblk, i) + (int64_t)bj_global(p, r, nblk, j) * lda];
+    Q[i][j] = double2{i == j ? 1.0 : 0.0, 0.0};
+  }
+  __syncthreads();
+  constexpr int np = kSub / 2;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < kSub * kSub; e += 256) {
+      const int i = e % kSub, j = e / kSub;
+      const double v = S[i][j].x * S[i][j].x + S[i][j].y * S[i][j].y;
+      tot += v;
+      if (i != j) off += v;
+    }
+    red[tid] = off;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    const double offs = red[0];
+    __syncthreads();
+    red[tid] = tot;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    if (tid == 0) done = (offs <= kOffRel * (double)kSub * red[0]) ? 1 : 0;
+    __syncthreads();
+    if (done) break;
+    for (int rr = 0; rr < kSub - 1; ++rr) {
+      if (tid < np) {
+        int a, b;
+        pair_of(tid, rr, kSub, &a, &b);
+        rot[tid] = make_rot(S[a][a].x, S[b][b].x, S[a][b]);
+      }
+      __syncthreads();
+      for (int e = tid; e < np * np; e += 256) {
+        const int ka = e % np, kb = e / np;
+        int pa, qa, pb, qb;
+        pair_of(ka, rr, kSub, &pa, &qa);
+        pair_of(kb, rr, kSub, &pb, &qb);
+        double2 a = S[pa][pb], b = S[pa][qb], c = S[qa][pb], d = S[qa][qb];
+        update_block(a, b, c, d, rot[ka], rot[kb]);
+        S[pa][pb] = a;
+        S[pa][qb] = b;
+        S[qa][pb] = c;
+        S[qa][qb] = d;
+      }
+      for (int e = tid; e < kSub * np; e += 256) {
+        const int i = e % kSub, kb = e / kSub;
+        int pb, qb;
+        pair_of(kb, rr, kSub, &pb, &qb);
+        update_zrow(Q[i][pb], Q[i][qb], rot[kb]);
+      }
+      __syncthreads();
+    }
+  }
+  double2 *Up = U + (int64_t)p * kSub * kSub;
+  for (int e = tid; e < kSub * kSub; e += 256) {
+    const int i = e % kSub, j = e / kSub;
+    Up[i + j * kSub] = Q[i][j];
+  }
+}
+
+// grid (npair, npair, 2): z = 0 updates A block (P, Q), z = 1 the Z chunk (rows
+// 2kBJ*P .. +2kBJ, columns of pair Q)
+__global__ __launch_bounds__(256) void k_bj_apply(double2 *__restrict__ A, int64_t lda,
+                                                  double2 *__restrict__ Z, int64_t ldz, int nblk, int r,
+                                                  const double2 *__restrict__ U) {
+  __shared__ double2 X[kSub][kSub + 1];
+  __shared__ double2 UQ[kSub][kSub + 1];
+  __shared__ double2 UP[kSub][kSub + 1];
+  const int P = blockIdx.x, Qp = blockIdx.y;
+  const bool isZ = blockIdx.z == 1;
+  const int tid = threadIdx.x;
+  const double2 *uq = U + (int64_t)Qp * kSub * kSub;
+  const double2 *up = U + (int64_t)P * kSub * kSub;
+  for (int e = tid; e < kSub * kSub; e += 256) {
+    const int i = e % kSub, j = e / kSub;
+    UQ[i][j] = uq[i + j * kSub];
+    if (!isZ) UP[i][j] = up[i + j * kSub];
+    const int col = bj_global(Qp, r, nblk, j);
+    const int64_t row = isZ ? (int64_t)P * kSub + i : bj_global(P, r, nblk, i);
+    X[i][j] = isZ ? Z[row + (int64_t)col * ldz] : A[row + (int64_t)col * lda];
+  }
+  __syncthreads();
+  // T = X U_Q  (each thread: 4 entries)
+  double2 t[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + 256 * q;
+    const int i = e % kSub, j = e / kSub;
+    double2 acc = double2{0.0, 0.0};
+    for (int k = 0; k < kSub; ++k) acc = cadd(acc, cm(X[i][k], UQ[k][j]));
+    t[q] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + 256 * q;
+    X[e % kSub][e / kSub] = t[q];
+  }
+  __syncthreads();
+  if (!isZ) {
+    // out = U_P^H T
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int i = e % kSub, j = e / kSub;
+      double2 acc = double2{0.0, 0.0};
+      for (int k = 0; k < kSub; ++k) acc = cadd(acc, cmc(UP[k][i], X[k][j]));
+      t[q] = acc;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + 256 * q;
+    const int i = e % kSub, j = e / kSub;
+    const int col = bj_global(Qp, r, nblk, j);
+    if (isZ)
+      Z[(int64_t)P * kSub + i + (int64_t)col * ldz] = t[q];
+    else
+      A[bj_global(P, r, nblk, i) + (int64_t)col * lda] = t[q];
+  }
+}
+
+// off-diagonal and total mass of the mpb x mpb matrix -> acc[0..1] (acc zeroed by caller)
+__global__ __launch_bounds__(256) void k_offnorm(const double2 *__restrict__ A, int64_t lda, int n,
+                                                 double *__restrict__ acc) {
+  __shared__ double red[2][256];
+  double off = 0.0, tot = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)n * n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    const double2 v = A[i + (int64_t)j * lda];
+    const double a2 = v.x * v.x + v.y * v.y;
+    tot += a2;
+    if (i != j) off += a2;
+  }
+  red[0][threadIdx.x] = off;
+  red[1][threadIdx.x] = tot;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&acc[0], red[0][0]);
+    atomicAdd(&acc[1], red[1][0]);
+  }
+}
+
+// pad to mpb (multiple of 2 kBJ): zero rows / columns m .. mpb-1, identity Z
+__global__ void k_bj_init(double2 *__restrict__ A, int64_t lda, int m, int mpb, double2 *__restrict__ Z,
+                          int64_t ldz) {
+  const int64_t tot = (int64_t)mpb * mpb;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % mpb), j = (int)(e / mpb);
+    if (i >= m || j >= m) A[i + (int64_t)j * lda] = double2{0.0, 0.0};
+    Z[i + (int64_t)j * ldz] = double2{i == j ? 1.0 : 0.0, 0.0};
+  }
+}
+
+__global__ void k_diag_out(const double2 *__restrict__ A, int64_t lda, int m, double *__restrict__ w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) w[i] = A[i + (int64_t)i * lda].x;
 }
 
 // ---------------------------------------------------------------- sort / select
@@ -496,6 +714,55 @@ static int grid_for(int64_t n, int bs = 256, int cap = 2048) {
   return (int)b;
 }
 
+static int eig_impl() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = std::getenv("PW_EIG_IMPL");
+    v = (e && *e) ? std::atoi(e) : 0;  // 0: block Jacobi, 1: element-wise cooperative
+  }
+  return v;
+}
+
+// Block Jacobi driver: A (lda >= mpb, mpb = m rounded up to 2 kBJ) is
+// overwritten; Z (ldz >= mpb) receives the eigenvectors; uws holds the
+// per-pair unitaries (mpb/kBJ/2 * (2 kBJ)^2 complex); acc >= 2 doubles.  One
+// host sync per sweep reads the off-diagonal mass.
+static int eig_block(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz, void *uws,
+                     double *acc, hipStream_t s) {
+  const int mpb = (m + kSub - 1) / kSub * kSub;
+  const int nblk = mpb / kBJ;
+  const int npair = nblk / 2;
+  static double *h_acc = nullptr;
+  if (!h_acc && hipHostMalloc((void **)&h_acc, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return PW_ERR_NOMEM;
+  double2 *U = static_cast<double2 *>(uws);
+  // inner sweeps per pair solve: the outer iteration converges with partial
+  // inner diagonalisation, and a pair problem is the cost of a round
+  static int inner = -1;
+  if (inner < 0) {
+    const char *e = std::getenv("PW_BJ_INNER");
+    inner = (e && *e) ? std::max(1, std::atoi(e)) : 1;
+  }
+  hipLaunchKernelGGL(k_bj_init, dim3(grid_for((int64_t)mpb * mpb)), dim3(256), 0, s, A, lda, m, mpb, Z, ldz);
+  if (hipGetLastError() != hipSuccess) return PW_ERR_HIP;
+  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+    if (hipMemsetAsync(acc, 0, 2 * sizeof(double), s) != hipSuccess) return PW_ERR_HIP;
+    hipLaunchKernelGGL(k_offnorm, dim3(grid_for((int64_t)mpb * mpb, 256, 256)), dim3(256), 0, s, A, lda,
+                       mpb, acc);
+    if (hipMemcpyAsync(h_acc, acc, 2 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return PW_ERR_HIP;
+    if (!(h_acc[0] > kOffRel * (double)mpb * h_acc[1])) break;  // converged (or NaN)
+    for (int r = 0; r < nblk - 1; ++r) {
+      hipLaunchKernelGGL(k_bj_inner, dim3(npair), dim3(256), 0, s, A, lda, nblk, r, U, inner);
+      hipLaunchKernelGGL(k_bj_apply, dim3(npair, npair, 2), dim3(256), 0, s, A, lda, Z, ldz, nblk, r, U);
+    }
+    if (hipGetLastError() != hipSuccess) return PW_ERR_HIP;
+  }
+  hipLaunchKernelGGL(k_diag_out, dim3((m + 255) / 256), dim3(256), 0, s, A, lda, m, w);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
 // rot_ws: second matrix buffer of the same shape as A (lda x lda).
 int eig_herm(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz, void *rot_ws,
              double *acc_ws, int *sweeps, int coop_blocks, hipStream_t s) {
@@ -505,10 +772,22 @@ int eig_herm(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz,
     hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(256), 0, s, A, lda, m, w, Z, ldz, sweeps);
     return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
   }
+  if (eig_impl() == 0) return eig_block(A, lda, m, w, Z, ldz, rot_ws, acc_ws, s);
   double2 *B = static_cast<double2 *>(rot_ws);
   void *args[] = {&A, &B, &lda, &m, &w, &Z, &ldz, &acc_ws, &sweeps};
+  // about 8 block updates per thread: fewer workgroups make each grid barrier cheaper
+  const int np = mp / 2;
+  int blocks = (int)(((int64_t)np * np + 2047) / 2048);
+  if (blocks < 8) blocks = 8;
+  static int force = -1;
+  if (force < 0) {
+    const char *e = std::getenv("PW_JACOBI_BLOCKS");
+    force = (e && *e) ? std::atoi(e) : 0;
+  }
+  if (force > 0) blocks = force;
+  if (blocks > coop_blocks) blocks = coop_blocks;
   const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_jacobi_coop),
-                                                  dim3(coop_blocks), dim3(256), args, 0, s);
+                                                  dim3(blocks), dim3(256), args, 0, s);
   return e == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
 
@@ -582,3 +861,41 @@ int precond_idx(const double *kin, const double *tn, const int *idx, const doubl
 }
 
 }  // namespace pw
+
+using namespace pw;
+
+extern "C" {
+
+pw_status pw_eigh_workspace(int32_t m, size_t *bytes) {
+  PW_CHECK_ARG(m >= 1 && bytes, PW_ERR_INVALID, "pw_eigh_workspace: bad argument");
+  const size_t mp = (size_t)((m + kSub - 1) / kSub * kSub);
+  *bytes = (3 * mp * mp) * sizeof(double2) + (mp + 2 * kMaxSweeps + 2) * sizeof(double) + mp * sizeof(int);
+  return PW_OK;
+}
+
+pw_status pw_eigh(const void *A, int64_t lda, int32_t m, double *w, void *Z, int64_t ldz, void *work,
+                  size_t work_bytes, void *stream) {
+  PW_CHECK_ARG(A && w && Z && work && m >= 1 && lda >= m && ldz >= m, PW_ERR_INVALID,
+               "pw_eigh: bad argument");
+  size_t need = 0;
+  pw_eigh_workspace(m, &need);
+  PW_CHECK_ARG(work_bytes >= need, PW_ERR_INVALID, "pw_eigh: workspace too small");
+  static int coop = -1;
+  if (coop < 0) coop = coop_jacobi_blocks();
+  const int64_t mp = (m + kSub - 1) / kSub * kSub;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double2 *Ac = static_cast<double2 *>(work);
+  double2 *Bw = Ac + mp * mp;
+  double2 *Zw = Bw + mp * mp;
+  double *wu = reinterpret_cast<double *>(Zw + mp * mp);
+  double *acc = wu + mp;
+  int *idx = reinterpret_cast<int *>(acc + 2 * kMaxSweeps + 2);
+  int rc = copy_mat(static_cast<const double2 *>(A), lda, Ac, mp, m, m, s);
+  if (rc == PW_OK) rc = eig_herm(Ac, mp, m, wu, Zw, mp, Bw, acc, nullptr, coop, s);
+  if (rc == PW_OK)
+    rc = eig_select(wu, m, m, w, idx, Zw, mp, static_cast<double2 *>(Z), ldz, s);
+  if (rc != PW_OK) set_error("pw_eigh: launch failed");
+  return rc;
+}
+
+}  // extern "C"
