@@ -167,9 +167,11 @@ pw_status pw_projections(pw_problem *p, const void *psi, int64_t ld_psi,
  *                    (27+18x+12x^2+8x^3+16x^4), x = t(G)/T_n, T_n the band
  *                    kinetic energy <x_n|t|x_n>/<x_n|x_n> of the iterate x.
  *   PW_PRECOND_NONE: K = 1.
- *   PW_PRECOND_MLP : K = s(G, n) from the network `net` (see pw_mlp_*), with
+ *   PW_PRECOND_MLP : K = s(G, n) K_TPA(G, n), s from the network `net` (see
+ *                    pw_mlp_*): a learned per-G scale on top of TPA, with
  *                    per-band fallback to TPA when any s of the band is not
- *                    finite.
+ *                    finite, or (inside pw_davidson_step) once the band's
+ *                    residual has not decreased for two consecutive steps.
  * theta: device double [nbands] Ritz values (used by MLP only);
  * x, r, t: device complex128 band-major with leading dimension ld.
  */
@@ -279,7 +281,10 @@ pw_status pw_problem_tuning(const pw_problem *p, int32_t *plane_group, int64_t *
 
 /*
  * Learned diagonal preconditioner (FP32 network 4 -> 64 -> 64 -> 1, SiLU,
- * softplus output; not part of the paper).  Parameters are one packed float
+ * output z mapped to s = 1/4 + (15/4) sigmoid(z), so 1/4 < s < 4; not part
+ * of the paper).  In a Davidson step the
+ * correction of band n is T(G) = s(G, n) K_TPA(G, n) R(G), so s = 1 is TPA;
+ * training therefore takes K_TPA R as its residual samples.  Parameters are one packed float
  * array of pw_mlp_num_params() values: W1 [64][4], b1 [64], W2 [64][64],
  * b2 [64], W3 [64], b3 [1] (row-major, y = W x + b).  The scaler holds the
  * feature means mu[4] and inverse standard deviations is[4]; features are
@@ -318,8 +323,11 @@ pw_status pw_mlp_train_step(pw_mlp *net, const void *F, const void *R, const voi
 /*
  * Target corrections from converged bands: with Xc the converged vectors
  * (complex128 [nbands][ld]) and cluster[m] the degenerate-cluster id of
- * converged band m (device int32), D[n] = y_n/||y_n|| - x_n where
- * y_n = sum_{m in cluster(n)} Xc_m <Xc_m | x_n> and x_n = Xit[n].
+ * converged band m (device int32), d_n = y_n/||y_n|| - x_n where
+ * y_n = sum_{m in cluster(n)} Xc_m <Xc_m | x_n> and x_n = Xit[n], and
+ * D[n] = d_n - sum_m x_m <x_m | d_n>: the part of the move outside the
+ * iterate block (Xit is expected to have orthonormal columns, as Ritz
+ * vectors do; the formula is applied as written either way).
  * work: device scratch of 17 * nbands^2 complex128.
  */
 pw_status pw_mlp_targets(pw_problem *p, const void *Xc, const int32_t *cluster, const void *Xit,

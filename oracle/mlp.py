@@ -4,11 +4,14 @@ The paper has no learned component; the workload defines it.  The reading:
   * per sample (G, n) four features
       f = (t(G), theta_n, |R_n(G)| sqrt(npw) / ||R_n||, <V_loc>)
     standardised with stored mean / std;
-  * three linear layers 4 -> 64 -> 64 -> 1, SiLU after the first two,
-    softplus at the output, so the scale s(G, n) is positive;
-  * correction T_n(G) = s(G, n) R_n(G);
+  * three linear layers 4 -> 64 -> 64 -> 1, SiLU after the first two, and
+    the output z mapped to s = S_LO + (S_HI - S_LO) sigmoid(z) with
+    S_LO = 1/4, S_HI = 4, so the scale is positive and bounded;
+  * correction T_n(G) = s(G, n) K_n(G) R_n(G) with K_n the Teter-Payne-Allan
+    diagonal (the residual samples handed to the loss are K_n R_n);
   * loss for one band sample (n, iteration): 1 - |<d, sR>|^2 / (||d||^2 ||sR||^2)
-    where d is the target correction (scale invariant, since the Davidson
+    where d is the target correction, the part outside the iterate block of
+    the move to the converged cluster (scale invariant, since the Davidson
     update uses only span(T));
   * Adam (Kingma & Ba 2015) with bias correction.
 
@@ -49,12 +52,15 @@ def dsilu(z):
     return s * (1.0 + z * (1.0 - s))
 
 
-def softplus(z):
-    return np.logaddexp(0.0, z)
+S_LO, S_HI = 0.25, 4.0
 
 
 def sigmoid(z):
     return 1.0 / (1.0 + np.exp(-z))
+
+
+def scale_out(z):
+    return S_LO + (S_HI - S_LO) * sigmoid(z)
 
 
 def forward(p: dict, F: np.ndarray):
@@ -64,14 +70,15 @@ def forward(p: dict, F: np.ndarray):
     z2 = a1 @ p["W2"].T + p["b2"]
     a2 = silu(z2)
     z3 = a2 @ p["W3"].T + p["b3"]
-    s = softplus(z3[:, 0])
+    s = scale_out(z3[:, 0])
     return s, (F, z1, a1, z2, a2, z3)
 
 
 def backward(p: dict, cache, ds: np.ndarray) -> dict:
     """Gradients of sum_i ds_i * s_i with respect to every parameter."""
     F, z1, a1, z2, a2, z3 = cache
-    g3 = (ds * sigmoid(z3[:, 0]))[:, None]          # d/dz3
+    q = sigmoid(z3[:, 0])
+    g3 = (ds * (S_HI - S_LO) * q * (1.0 - q))[:, None]   # d/dz3
     gW3 = g3.T @ a2
     gb3 = g3.sum(axis=0)
     g2 = (g3 @ p["W3"]) * dsilu(z2)
@@ -139,7 +146,13 @@ def adam_step(p: dict, g: dict, state: dict, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8
         p[k] = p[k] - lr * mh / (np.sqrt(vh) + eps)
 
 
-def target_correction(Xn: np.ndarray, Pc: np.ndarray) -> np.ndarray:
-    """d = P_c x / ||P_c x|| - x: the move from iterate x to the converged cluster."""
+def target_correction(Xn: np.ndarray, Pc: np.ndarray, X: np.ndarray | None = None) -> np.ndarray:
+    """d = P_c x / ||P_c x|| - x: the move from iterate x to the converged cluster
+    (Pc: orthonormal columns spanning the cluster).  With the iterate block X
+    (npw x nb, orthonormal columns) given, the part inside span(X) is removed,
+    d - X X^H d, since the Rayleigh-Ritz step supplies that part itself."""
     y = Pc @ (Pc.conj().T @ Xn)
-    return y / np.linalg.norm(y) - Xn
+    d = y / np.linalg.norm(y) - Xn
+    if X is not None:
+        d = d - X @ (X.conj().T @ d)
+    return d

@@ -43,7 +43,7 @@ int band_kinetic(const double *kin, const void *x, int64_t ld, int64_t npw, int 
                  hipStream_t s);
 int mlp_precond_idx(const pw_mlp *net, pw_problem *p, const double *theta, const double *rnorm,
                     const int *idx, const double2 *R, int64_t ld, double2 *T, int nu, int *bad,
-                    hipStream_t s);
+                    const double *tn, hipStream_t s);
 int mlp_fallback(const int *bad, pw_problem *p, const double *tn, const int *idx, const double2 *R,
                  int64_t ld, double2 *T, int nu, hipStream_t s);
 }  // namespace pw
@@ -74,6 +74,13 @@ struct pw_davidson {
   // pinned host mirrors
   double *h_theta = nullptr, *h_rho = nullptr, *h_lam = nullptr;
   int *h_U = nullptr, *h_flag = nullptr, *h_keep = nullptr;
+  // learned-preconditioner fallback: residual of the previous step and the
+  // number of consecutive non-decreasing steps, per band; bands that stall
+  // for two steps use TPA for the rest of the solve
+  std::vector<double> prev_rho;
+  std::vector<int> stall;
+  std::vector<uint8_t> tpa_only;
+  int *h_bad = nullptr;
 };
 
 namespace {
@@ -86,7 +93,7 @@ void free_dav(pw_davidson *d) {
                  d->acc_ws, d->part, d->bad, d->Vt, d->Wt, d->w_sorted, d->idx_all};
   for (void *b : dev)
     if (b) (void)hipFree(b);
-  void *host[] = {d->h_theta, d->h_rho, d->h_lam, d->h_U, d->h_flag, d->h_keep};
+  void *host[] = {d->h_theta, d->h_rho, d->h_lam, d->h_U, d->h_flag, d->h_keep, d->h_bad};
   for (void *b : host)
     if (b) (void)hipHostFree(b);
   delete d;
@@ -218,7 +225,7 @@ pw_status pw_davidson_create(pw_problem *p, int64_t nbands, int64_t max_subspace
             dalloc(&d->sweeps, 1) && dalloc(&d->bad, nb) && dalloc((double2 **)&d->rot_ws, lde * lde) &&
             dalloc(&d->acc_ws, 128) && halloc(&d->h_theta, nb) && halloc(&d->h_rho, nb) &&
             halloc(&d->h_lam, lde) && halloc(&d->h_U, nb) && halloc(&d->h_flag, 1) &&
-            halloc(&d->h_keep, nb);
+            halloc(&d->h_keep, nb) && halloc(&d->h_bad, nb);
   d->part_bytes = (size_t)32 * lde * nb * sizeof(double2);
   ok = ok && dalloc((char **)&d->part, d->part_bytes);
   if (!ok) {
@@ -263,6 +270,9 @@ pw_status pw_davidson_init(pw_davidson *d, const void *psi0, int64_t ld, void *s
   d->m = d->nb;
   d->iter = 0;
   d->n_hpsi = d->nb;
+  d->prev_rho.assign(d->nb, INFINITY);
+  d->stall.assign(d->nb, 0);
+  d->tpa_only.assign(d->nb, 0);
   d->inited = true;
   d->converged = false;
   return PW_OK;
@@ -313,8 +323,12 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
       return PW_ERR_NOT_FINITE;
     }
   int nu = 0;
-  for (int n = 0; n < nb; ++n)
+  for (int n = 0; n < nb; ++n) {
     if (d->h_rho[n] >= d->tol) d->h_U[nu++] = n;
+    d->stall[n] = (d->h_rho[n] >= d->prev_rho[n]) ? d->stall[n] + 1 : 0;
+    if (d->stall[n] >= 2) d->tpa_only[n] = 1;
+    d->prev_rho[n] = d->h_rho[n];
+  }
   d->converged = (nu == 0);
   if (converged) *converged = d->converged ? 1 : 0;
   if (d->converged) return PW_OK;
@@ -324,7 +338,9 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
     ProfScope ps(&d->p->prof, PW_STAGE_PRECOND, s);
     DV_RC(band_kinetic(d->p->d_kin, d->X, d->ld, d->npw, nb, d->tn, s));
     if (precond_kind == PW_PRECOND_MLP) {
-      DV_RC(mlp_precond_idx(net, d->p, d->theta, d->rho, d->dU, d->R, d->ld, d->T, nu, d->bad, s));
+      for (int i = 0; i < nu; ++i) d->h_bad[i] = d->tpa_only[d->h_U[i]];
+      PW_HIP(hipMemcpyAsync(d->bad, d->h_bad, nu * sizeof(int), hipMemcpyHostToDevice, s));
+      DV_RC(mlp_precond_idx(net, d->p, d->theta, d->rho, d->dU, d->R, d->ld, d->T, nu, d->bad, d->tn, s));
       DV_RC(mlp_fallback(d->bad, d->p, d->tn, d->dU, d->R, d->ld, d->T, nu, s));
     } else {
       DV_RC(precond_idx(d->p->d_kin, d->tn, d->dU, d->R, d->ld, d->T, d->ld, d->npw, nu,

@@ -3,10 +3,17 @@
 // Not in the paper (it names the iterative diagonalisation, not its
 // preconditioner); the workload defines it.  Per sample (G, n):
 //   f = (t(G), theta_n, |R_n(G)| sqrt(npw) / ||R_n||, <V_LOC>), standardised
-//   s = softplus(W3 silu(W2 silu(W1 f + b1) + b2) + b3)     (4 -> 64 -> 64 -> 1)
-//   T_n(G) = s R_n(G); a band with any non-finite s falls back to TPA.
+//   z = W3 silu(W2 silu(W1 f + b1) + b2) + b3                (4 -> 64 -> 64 -> 1)
+//   s = S_LO + (S_HI - S_LO) sigmoid(z),  S_LO = 1/4, S_HI = 4
+//   T_n(G) = s K_TPA(t(G)/T_n) R_n(G): the network learns a per-G scale on
+//   top of the Teter-Payne-Allan diagonal (s = 1 reproduces TPA).  The
+//   bounded range keeps the learned operator spectrally equivalent to TPA
+//   (condition number of the ratio at most 16): an unbounded scale learns to
+//   switch G components off, and a Davidson space never regains them.  A band
+//   with any non-finite s falls back to plain TPA.
 // Training minimises, per band sample, 1 - |<d, sR>|^2 / (||d||^2 ||sR||^2)
-// (d: the correction from the iterate to the converged cluster), averaged
+// (d: the part outside the current Ritz vectors of the move from the
+// iterate to its converged cluster), averaged
 // over the bands of a batch, with Adam (Kingma & Ba 2015).
 //
 // Parameters live in one packed float array (see kOff*).  Gradients are
@@ -35,8 +42,13 @@ __device__ __forceinline__ float dsilu(float z) {
   const float s = 1.0f / (1.0f + expf(-z));
   return s * (1.0f + z * (1.0f - s));
 }
-__device__ __forceinline__ float softplus(float z) { return z > 20.0f ? z : log1pf(expf(z)); }
+constexpr float kSLo = 0.25f, kSHi = 4.0f;
 __device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
+__device__ __forceinline__ float scale_out(float z) { return kSLo + (kSHi - kSLo) * sigm(z); }
+__device__ __forceinline__ float dscale_out(float z) {
+  const float q = sigm(z);
+  return (kSHi - kSLo) * q * (1.0f - q);
+}
 
 // standardised features of sample (g, n)
 __device__ __forceinline__ void features(const double *kin, int64_t g, double theta, double2 r,
@@ -48,7 +60,7 @@ __device__ __forceinline__ void features(const double *kin, int64_t g, double th
   for (int k = 0; k < 4; ++k) f[k] = (float)((raw[k] - (double)scaler[k]) * (double)scaler[4 + k]);
 }
 
-// forward of one sample with weights in LDS; returns z3 (pre-softplus)
+// forward of one sample with weights in LDS; returns z3 (before the output map)
 __device__ __forceinline__ float mlp_z3(const float *W, const float f[4]) {
   float a1[H];
 #pragma unroll
@@ -107,11 +119,13 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ W
     const float4 r = F[e];
     const float f[4] = {(r.x - mu[0]) * is[0], (r.y - mu[1]) * is[1], (r.z - mu[2]) * is[2],
                         (r.w - mu[3]) * is[3]};
-    s[e] = softplus(mlp_z3(Ws, f));
+    s[e] = scale_out(mlp_z3(Ws, f));
   }
 }
 
-// T[i](G) = s(G, idx[i]) R[idx[i]](G); bad[i] = 1 if any s of the band is not finite
+__device__ __forceinline__ double tpa_k3(double x);
+
+// T[i](G) = s(G, idx[i]) K_TPA R[idx[i]](G); bad[i] = 1 if any s of the band is not finite
 __global__ __launch_bounds__(256) void k_mlp_precond(const float *__restrict__ W,
                                                      const float *__restrict__ scaler,
                                                      const double *__restrict__ kin,
@@ -119,22 +133,24 @@ __global__ __launch_bounds__(256) void k_mlp_precond(const float *__restrict__ W
                                                      const double2 *__restrict__ R, int64_t ld,
                                                      const double *__restrict__ rnorm,
                                                      const int *__restrict__ idx, int64_t npw,
-                                                     double vavg, double2 *__restrict__ T,
-                                                     int64_t ldt, int *__restrict__ bad) {
+                                                     double vavg, const double *__restrict__ tn,
+                                                     double2 *__restrict__ T, int64_t ldt,
+                                                     int *__restrict__ bad) {
   __shared__ __align__(16) float Ws[kNParam + 3];
   load_weights(Ws, W);
   const int i = blockIdx.y;
   const int n = idx[i];
   const double sq = sqrt((double)npw);
-  const double th = theta[n], rn = rnorm[n];
+  const double th = theta[n], rn = rnorm[n], itn = 1.0 / tn[n];
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < npw;
        g += (int64_t)gridDim.x * blockDim.x) {
     const double2 r = R[(int64_t)n * ld + g];
     float f[4];
     features(kin, g, th, r, rn, sq, vavg, scaler, f);
-    const float sv = softplus(mlp_z3(Ws, f));
+    const float sv = scale_out(mlp_z3(Ws, f));
     if (!isfinite(sv)) bad[i] = 1;
-    T[(int64_t)i * ldt + g] = double2{sv * r.x, sv * r.y};
+    const double k = (double)sv * tpa_k3(kin[g] * itn);
+    T[(int64_t)i * ldt + g] = double2{k * r.x, k * r.y};
   }
 }
 
@@ -259,7 +275,7 @@ __global__ __launch_bounds__(64) void k_train_bwd(const float *__restrict__ W,
       const double da2 = 2.0 * (st[0] * cdr_re + st[1] * cdr_im);
       const double dnu = 2.0 * sv * (r.x * r.x + r.y * r.y);
       const double ds = -(da2 * st[2] - a2abs * dnu) / (st[3] * st[2] * st[2]) * inv_nbands;
-      dz3 = (float)ds * sigm(z3);
+      dz3 = (float)ds * dscale_out(z3);
       float dz2[H];
       for (int i = 0; i < H; ++i) {
         dz2[i] = dz3 * Ws[kOffW3 + i] * dsilu(z2s[i]);
@@ -408,13 +424,14 @@ struct pw_mlp {
 namespace pw {
 int mlp_precond_idx(const pw_mlp *net, pw_problem *p, const double *theta, const double *rnorm,
                     const int *idx, const double2 *R, int64_t ld, double2 *T, int nu, int *bad,
-                    hipStream_t s) {
+                    const double *tn, hipStream_t s) {
   if (nu <= 0) return PW_OK;
-  if (hipMemsetAsync(bad, 0, nu * sizeof(int), s) != hipSuccess) return PW_ERR_HIP;
+  // bad[] arrives holding the bands already routed to TPA; the kernel adds
+  // bands with a non-finite network output
   int bx = (int)((p->npw + 255) / 256);
   if (bx > 128) bx = 128;
   hipLaunchKernelGGL(k_mlp_precond, dim3(bx, nu), dim3(256), 0, s, net->W, net->scaler, p->d_kin,
-                     theta, R, ld, rnorm, idx, p->npw, p->vavg, T, ld, bad);
+                     theta, R, ld, rnorm, idx, p->npw, p->vavg, tn, T, ld, bad);
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
 
@@ -586,7 +603,11 @@ pw_status pw_mlp_targets(pw_problem *p, const void *Xc, const int32_t *cluster, 
   hipLaunchKernelGGL(k_target_finish, dim3((unsigned)nbands), dim3(256), 0, s,
                      static_cast<const double2 *>(Xit), static_cast<double2 *>(D), ld, p->npw);
   PW_HIP(hipGetLastError());
-  return PW_OK;
+  // keep only the part outside span(Xit): the Rayleigh-Ritz step supplies
+  // the rest, so it is no part of what a correction has to carry
+  rc = zgemm_cn(nbands, nbands, p->npw, Xit, ld, D, ld, C, nbands, splits, part, s);
+  if (rc != PW_OK) return rc;
+  return zgemm_nn(p->npw, nbands, nbands, -1.0, Xit, ld, C, nbands, 1.0, D, ld, s);
 }
 
 }  // extern "C"

@@ -21,7 +21,9 @@ import synth
 from . import _lib
 from .problems import band_block, build_problem
 
-SNAP_ITERS = (2, 4, 7, 11, 16)
+SNAP_ITERS = (2, 4, 7, 11, 16, 22, 29, 37, 46)
+# output map s = 1/4 + 15/4 sigmoid(z): s = 1 at z = log(1/4)
+B3_TPA = float(np.log(0.25))
 
 
 def cluster_ids(theta: np.ndarray, gap: float = 1e-6) -> np.ndarray:
@@ -51,6 +53,7 @@ def collect(cell, ik: int = 0, precision: int = _lib.PW_FP64, tol: float = 5e-7,
     X = torch.zeros_like(x0)
     R = torch.zeros_like(x0)
     Dt = torch.zeros_like(x0)
+    RK = torch.zeros_like(x0)
     th = torch.zeros(nb, dtype=torch.float64, device="cuda")
     rh = torch.zeros(nb, dtype=torch.float64, device="cuda")
     work = torch.zeros(17 * nb * nb, dtype=torch.complex128, device="cuda")
@@ -63,6 +66,8 @@ def collect(cell, ik: int = 0, precision: int = _lib.PW_FP64, tol: float = 5e-7,
             _lib.pw_davidson_snapshot(d, X, R, th, rh)
             _lib.pw_mlp_targets(prob, Xc, cid, X, Dt, work)
             _lib.pw_mlp_features(prob, th, R, rh, F)
+            # the network scales the TPA correction: its residual samples are K_TPA R
+            _lib.pw_precond(prob, _lib.PW_PRECOND_TPA, None, X, R, RK)
             torch.cuda.synchronize()
             rho = rh.cpu().numpy()
             bands = np.nonzero(rho >= tol)[0]
@@ -71,7 +76,7 @@ def collect(cell, ik: int = 0, precision: int = _lib.PW_FP64, tol: float = 5e-7,
             if len(bands):
                 bi = torch.from_numpy(bands).cuda()
                 Fs.append(F.view(nb, npw, 4)[bi].reshape(-1, 4))
-                Rs.append(R[bi, :npw].reshape(-1))
+                Rs.append(RK[bi, :npw].reshape(-1))
                 Ds.append(Dt[bi, :npw].reshape(-1))
                 sizes += [npw] * len(bands)
         if conv:
@@ -130,14 +135,41 @@ def train(ds, epochs: int = 30, bands_per_batch: int = 64, lr: float = 1e-3, see
     return net, hist
 
 
+def baseline_loss(ds, bands_per_batch: int = 64) -> float:
+    """Mean band loss of s = 1 everywhere, i.e. of plain TPA on the same samples."""
+    import torch
+    p = np.zeros(_lib.MLP_NPARAM, dtype=np.float32)
+    p[-1] = B3_TPA
+    net = _lib.Mlp(p)
+    off, nbd = ds["off"], ds["nbands"]
+    smax = int(max(off[b + 1] - off[b] for b in range(nbd))) * bands_per_batch
+    s_work = torch.zeros(smax, dtype=torch.float32, device="cuda")
+    tot, n = 0.0, 0
+    for b0 in range(0, nbd, bands_per_batch):
+        sel = np.arange(b0, min(nbd, b0 + bands_per_batch))
+        sizes = off[sel + 1] - off[sel]
+        lo, hi = int(off[sel[0]]), int(off[sel[-1] + 1])
+        boff = torch.from_numpy(np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)).cuda()
+        bof = torch.from_numpy(np.repeat(np.arange(len(sel), dtype=np.int32), sizes)).cuda()
+        l = _lib.pw_mlp_train_step(net, ds["F"][lo:hi].contiguous(), ds["R"][lo:hi].contiguous(),
+                                   ds["D"][lo:hi].contiguous(), boff, bof, s_work, update=False)
+        tot += l * len(sel)
+        n += len(sel)
+    net.close()
+    return tot / n
+
+
 def init_params(seed: int) -> np.ndarray:
-    """Kaiming-uniform weights (bound sqrt(6 / fan_in)), zero biases, packed float32."""
+    """Kaiming-uniform weights (bound sqrt(6 / fan_in)), zero biases, packed float32;
+    the last layer starts small with b3 = B3_TPA, so s ~ 1 (plain TPA) at the start."""
     rng = np.random.default_rng(seed)
     p = {}
     for name, shp in (("W1", (64, 4)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)),
                       ("W3", (1, 64)), ("b3", (1,))):
         p[name] = rng.uniform(-np.sqrt(6.0 / shp[1]), np.sqrt(6.0 / shp[1]), size=shp) \
             if name.startswith("W") else np.zeros(shp)
+    p["W3"] *= 0.1
+    p["b3"][:] = B3_TPA
     return _lib.pack_params(p)
 
 

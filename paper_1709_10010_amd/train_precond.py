@@ -49,6 +49,8 @@ def main():
               f"{len(parts[-1][3])} band samples, {time.perf_counter() - tc:.1f} s", flush=True)
     ds = learned.build_dataset(parts)
     print(f"dataset: {ds['nbands']} band samples, {ds['F'].shape[0]} (G, n) samples", flush=True)
+    base = learned.baseline_loss(ds)
+    print(f"plain TPA (s = 1) mean band loss on the training samples: {base:.4f}", flush=True)
     tt = time.perf_counter()
     net, hist = learned.train(ds, epochs=args.epochs, lr=args.lr,
                               log=lambda m: print(m, flush=True))
@@ -58,7 +60,7 @@ def main():
     cell = synth.make_cell(5, args.eval_index)
     r = learned.evaluate(cell, net, tol=5e-7)
     out = {"train_cells": args.cells, "band_samples": ds["nbands"], "samples": int(ds["F"].shape[0]),
-           "epochs": args.epochs, "loss_first": hist[0], "loss_last": hist[-1],
+           "epochs": args.epochs, "loss_tpa": base, "loss_first": hist[0], "loss_last": hist[-1],
            "train_seconds": round(train_s, 2), "total_seconds": round(time.perf_counter() - t0, 1),
            "eval_cell": cell.name, "eval": {k: {"iterations": r[k]["iterations"],
                                                 "seconds": round(r[k]["seconds"], 3),

@@ -112,7 +112,7 @@ def test_targets_and_features_match_oracle(lib):
     w, V = ham.eigh_lowest(po, 16)
     rng = np.random.default_rng(3)
     Xit = V + 0.05 * (rng.standard_normal(V.shape) + 1j * rng.standard_normal(V.shape))
-    Xit /= np.linalg.norm(Xit, axis=1)[:, None]
+    Xit = np.linalg.qr(Xit.T)[0].T          # orthonormal iterate block, as Ritz vectors are
     # clusters: bands with eigenvalue gaps < 1e-6 Ha share an id
     cid = np.zeros(16, dtype=np.int32)
     for i in range(1, 16):
@@ -124,7 +124,7 @@ def test_targets_and_features_match_oracle(lib):
     got = from_gpu_block(Dg, po.npw)
     for n in range(16):
         members = np.nonzero(cid == cid[n])[0]
-        ref = omlp.target_correction(Xit[n], V[members].T)
+        ref = omlp.target_correction(Xit[n], V[members].T, Xit.T)
         assert np.abs(got[n] - ref).max() < 1e-12
     # features
     theta = torch.from_numpy(w.copy()).cuda()
@@ -138,7 +138,7 @@ def test_targets_and_features_match_oracle(lib):
 
 
 def test_davidson_with_untrained_network_converges(lib):
-    """A zero network (s = ln 2 everywhere) is a valid if weak preconditioner:
+    """A zero network (s = 1/4 + 15/8 everywhere, a constant multiple of TPA) is a valid preconditioner:
     the solve must still reach the dense eigenvalues."""
     c = synth.make_cell(0)
     po, pl = problems(c, max_bands=8)

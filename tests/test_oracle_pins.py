@@ -320,3 +320,37 @@ def test_adam_first_step_closed_form():
     # first step: m_hat = g, v_hat = g^2 -> update = -lr g / (|g| + eps)
     exp = np.array([1.0, -2.0, 0.5]) - 1e-2 * g["w"] / (np.abs(g["w"]) + 1e-8)
     assert np.allclose(p["w"], exp, rtol=0, atol=1e-15)
+
+
+def test_mlp_output_range_and_tpa_point():
+    # the scale map is bounded in (1/4, 4) and equals 1 at z = log(1/4)
+    z = np.array([-700.0, -40.0, np.log(0.25), 0.0, 40.0, 700.0])
+    s, _ = mlp.forward({"W1": np.zeros((64, 4)), "b1": np.zeros(64), "W2": np.zeros((64, 64)),
+                        "b2": np.zeros(64), "W3": np.zeros((1, 64)), "b3": np.array([0.0])},
+                       np.zeros((1, 4)))
+    assert abs(s[0] - 2.125) < 1e-15
+    v = mlp.scale_out(z)
+    assert np.all(v >= 0.25) and np.all(v <= 4.0)
+    assert abs(v[2] - 1.0) < 1e-15 and abs(v[0] - 0.25) < 1e-15 and abs(v[-1] - 4.0) < 1e-15
+
+
+def test_target_correction_geometry():
+    # a converged iterate needs no move; the projected target is orthogonal
+    # to the iterate block, and with a one-band block it reduces to
+    # d - x <x|d> computed by hand from the unit vectors involved
+    rng = np.random.default_rng(23)
+    npw = 25
+    Q = np.linalg.qr(_rand_c(rng, (npw, 6)))[0]
+    Pc = Q[:, :2]
+    x_conv = Pc @ np.array([0.6, 0.8j])
+    assert np.abs(mlp.target_correction(x_conv, Pc)).max() < 1e-14
+    X = np.linalg.qr(Q[:, 1:4] + 0.1 * _rand_c(rng, (npw, 3)))[0]
+    d = mlp.target_correction(X[:, 0], Pc, X)
+    assert np.abs(X.conj().T @ d).max() < 1e-14
+    # a one-dimensional cluster {q}: y = q <q|x>, y/|y| = q phase, phase = <q|x>/|<q|x>|
+    q = Q[:, 0:1]
+    x = X[:, 0]
+    ph = (q[:, 0].conj() @ x) / abs(q[:, 0].conj() @ x)
+    raw = q[:, 0] * ph - x
+    exp = raw - x * (x.conj() @ raw)
+    assert np.abs(mlp.target_correction(x, q, X[:, :1]) - exp).max() < 1e-14
