@@ -298,10 +298,13 @@ pw_status pw_mlp_destroy(pw_mlp *net);
 /* Host copies (any may be NULL); grad is the last train step's gradient. Syncs the device. */
 pw_status pw_mlp_get(pw_mlp *net, float *params, float *scaler, float *grad);
 pw_status pw_mlp_set(pw_mlp *net, const float *params, const float *scaler);
-/* Raw features of nbands bands: theta, rnorm device double [nbands]; r device
- * complex128 [nbands][ld]; F device float4 [nbands * npw] (band-major). */
-pw_status pw_mlp_features(pw_problem *p, const double *theta, const void *r, const double *rnorm,
-                          int64_t ld, int64_t nbands, void *F, void *stream);
+/* Raw features of nbands bands (nbands <= the problem's max_bands):
+ * F[n][G] = (t(G)/T_n, theta_n, |r_n(G)| sqrt(npw)/rnorm_n, <V_loc>) with
+ * T_n = <x_n|t|x_n>/<x_n|x_n>.  theta, rnorm device double [nbands]; x, r
+ * device complex128 [nbands][ld] (iterates and residuals); F device float4
+ * [nbands * npw] (band-major). */
+pw_status pw_mlp_features(pw_problem *p, const double *theta, const void *x, const void *r,
+                          const double *rnorm, int64_t ld, int64_t nbands, void *F, void *stream);
 /* scaler <- mean and 1/std of the raw features F (device float4 [nsamples]). */
 pw_status pw_mlp_fit_scaler(pw_mlp *net, const void *F, int64_t nsamples, void *stream);
 /* s[i] = network output for raw features F[i] (device float [nsamples]). */

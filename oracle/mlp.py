@@ -2,7 +2,8 @@
 
 The paper has no learned component; the workload defines it.  The reading:
   * per sample (G, n) four features
-      f = (t(G), theta_n, |R_n(G)| sqrt(npw) / ||R_n||, <V_loc>)
+      f = (t(G) / T_n, theta_n, |R_n(G)| sqrt(npw) / ||R_n||, <V_loc>),
+    T_n = <x_n|t|x_n> / <x_n|x_n> the band's kinetic energy (the TPA argument);
     standardised with stored mean / std;
   * three linear layers 4 -> 64 -> 64 -> 1, SiLU after the first two, and
     the output z mapped to s = S_LO + (S_HI - S_LO) sigmoid(z) with
@@ -90,12 +91,17 @@ def backward(p: dict, cache, ds: np.ndarray) -> dict:
     return dict(W1=gW1, b1=gb1, W2=gW2, b2=gb2, W3=gW3, b3=gb3)
 
 
-def features(t: np.ndarray, theta: np.ndarray, R: np.ndarray, vavg: float) -> np.ndarray:
-    """Raw features for every (G, n) of a residual block R (npw x nbands), band-major rows."""
+def features(t: np.ndarray, theta: np.ndarray, X: np.ndarray, R: np.ndarray,
+             vavg: float) -> np.ndarray:
+    """Raw features for every (G, n) of iterates X and residuals R (npw x nbands),
+    band-major rows; the kinetic feature is t(G) / T_n with T_n the band's
+    kinetic energy <x|t|x> / <x|x>."""
     npw, nbd = R.shape
     amp = np.abs(R) * np.sqrt(npw) / np.sqrt((np.abs(R) ** 2).sum(axis=0))[None, :]
+    w = np.abs(X) ** 2
+    tn = (t[:, None] * w).sum(axis=0) / w.sum(axis=0)
     f = np.empty((nbd, npw, NF))
-    f[:, :, 0] = t[None, :]
+    f[:, :, 0] = (t[:, None] / tn[None, :]).T
     f[:, :, 1] = theta[:, None]
     f[:, :, 2] = amp.T
     f[:, :, 3] = vavg

@@ -88,7 +88,7 @@ def _load():
         "pw_mlp_destroy": (i32, [vp]),
         "pw_mlp_get": (i32, [vp, vp, vp, vp]),
         "pw_mlp_set": (i32, [vp, vp, vp]),
-        "pw_mlp_features": (i32, [vp, vp, vp, vp, i64, i64, vp, vp]),
+        "pw_mlp_features": (i32, [vp, vp, vp, vp, vp, i64, i64, vp, vp]),
         "pw_mlp_fit_scaler": (i32, [vp, vp, i64, vp]),
         "pw_mlp_forward": (i32, [vp, vp, i64, vp, vp]),
         "pw_mlp_train_step": (i32, [vp, vp, vp, vp, vp, vp, i64, i64, vp, C.c_float, i32,
@@ -485,12 +485,15 @@ class Mlp:
             pass
 
 
-def pw_mlp_features(prob: Problem, theta, r, rnorm, F, stream=None) -> None:
+def pw_mlp_features(prob: Problem, theta, x, r, rnorm, F, stream=None) -> None:
     import torch
     rp, ld, nb = _band_block(r, "r", prob.npw)
+    xp, ldx, nbx = _band_block(x, "x", prob.npw)
+    if ldx != ld or nbx != nb:
+        raise ValueError("x and r must have the same shape")
     if F.dtype != torch.float32 or F.numel() < 4 * nb * prob.npw:
         raise ValueError("F must be float32 with room for nbands*npw*4 values")
-    _check(LIB.pw_mlp_features(prob.handle, _dev_ptr(theta, torch.float64, "theta"), rp,
+    _check(LIB.pw_mlp_features(prob.handle, _dev_ptr(theta, torch.float64, "theta"), xp, rp,
                                _dev_ptr(rnorm, torch.float64, "rnorm"), ld, nb,
                                _dev_ptr(F, torch.float32, "F"), _stream(stream)))
 

@@ -175,4 +175,7 @@ int launch_apply_d(const double *dij, const int32_t *pj_atom, const int32_t *pro
 // Diagonal preconditioner (nonlocal.hip): t = K r, K per PW_PRECOND_TPA / _NONE.
 int launch_tpa(const double *kin, const void *x, const void *r, void *t, int64_t ld, int64_t npw,
                int nb, int kind, double *tn_work, hipStream_t s);
+// tn[n] = <x_n|t|x_n> / <x_n|x_n> for nb bands (nonlocal.hip).
+int band_kinetic(const double *kin, const void *x, int64_t ld, int64_t npw, int nb, double *tn,
+                 hipStream_t s);
 }  // namespace pw

@@ -39,8 +39,6 @@ int scaled_cols(const double2 *U, int64_t ldu, const double *lam, const int *kee
                 double2 *B, int64_t ldb, hipStream_t s);
 int precond_idx(const double *kin, const double *tn, const int *idx, const double2 *R, int64_t ldr,
                 double2 *T, int64_t ldt, int64_t npw, int nu, int kind, hipStream_t s);
-int band_kinetic(const double *kin, const void *x, int64_t ld, int64_t npw, int nb, double *tn,
-                 hipStream_t s);
 int mlp_precond_idx(const pw_mlp *net, pw_problem *p, const double *theta, const double *rnorm,
                     const int *idx, const double2 *R, int64_t ld, double2 *T, int nu, int *bad,
                     const double *tn, hipStream_t s);

@@ -2,7 +2,9 @@
 //
 // Not in the paper (it names the iterative diagonalisation, not its
 // preconditioner); the workload defines it.  Per sample (G, n):
-//   f = (t(G), theta_n, |R_n(G)| sqrt(npw) / ||R_n||, <V_LOC>), standardised
+//   f = (t(G)/T_n, theta_n, |R_n(G)| sqrt(npw) / ||R_n||, <V_LOC>), standardised,
+//   with T_n = <x_n|t|x_n> / <x_n|x_n> the band's kinetic energy, so the
+//   first feature is the TPA argument and carries over between cutoffs
 //   z = W3 silu(W2 silu(W1 f + b1) + b2) + b3                (4 -> 64 -> 64 -> 1)
 //   s = S_LO + (S_HI - S_LO) sigmoid(z),  S_LO = 1/4, S_HI = 4
 //   T_n(G) = s K_TPA(t(G)/T_n) R_n(G): the network learns a per-G scale on
@@ -51,11 +53,11 @@ __device__ __forceinline__ float dscale_out(float z) {
 }
 
 // standardised features of sample (g, n)
-__device__ __forceinline__ void features(const double *kin, int64_t g, double theta, double2 r,
-                                         double rnorm, double sqrt_npw, double vavg,
+__device__ __forceinline__ void features(const double *kin, int64_t g, double itn, double theta,
+                                         double2 r, double rnorm, double sqrt_npw, double vavg,
                                          const float *scaler, float f[4]) {
   const double amp = sqrt(r.x * r.x + r.y * r.y) * sqrt_npw / rnorm;
-  const double raw[4] = {kin[g], theta, amp, vavg};
+  const double raw[4] = {kin[g] * itn, theta, amp, vavg};
 #pragma unroll
   for (int k = 0; k < 4; ++k) f[k] = (float)((raw[k] - (double)scaler[k]) * (double)scaler[4 + k]);
 }
@@ -90,18 +92,19 @@ __device__ __forceinline__ void load_weights(float *Ws, const float *W) {
 
 // ---------------------------------------------------------------- features (raw)
 // F[(i*npw + g)] = raw features of band idx[i] (idx may be null: i itself).
-__global__ void k_features(const double *__restrict__ kin, const double *__restrict__ theta,
-                           const double2 *__restrict__ R, int64_t ld, const double *__restrict__ rnorm,
-                           const int *__restrict__ idx, int64_t npw, double vavg, float4 *__restrict__ F) {
+__global__ void k_features(const double *__restrict__ kin, const double *__restrict__ tn,
+                           const double *__restrict__ theta, const double2 *__restrict__ R, int64_t ld,
+                           const double *__restrict__ rnorm, const int *__restrict__ idx, int64_t npw,
+                           double vavg, float4 *__restrict__ F) {
   const int i = blockIdx.y;
   const int n = idx ? idx[i] : i;
   const double sq = sqrt((double)npw);
-  const double th = theta[n], rn = rnorm[n];
+  const double th = theta[n], rn = rnorm[n], itn = 1.0 / tn[n];
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < npw;
        g += (int64_t)gridDim.x * blockDim.x) {
     const double2 r = R[(int64_t)n * ld + g];
     const double amp = sqrt(r.x * r.x + r.y * r.y) * sq / rn;
-    F[(int64_t)i * npw + g] = float4{(float)kin[g], (float)th, (float)amp, (float)vavg};
+    F[(int64_t)i * npw + g] = float4{(float)(kin[g] * itn), (float)th, (float)amp, (float)vavg};
   }
 }
 
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(256) void k_mlp_precond(const float *__restrict__ W
        g += (int64_t)gridDim.x * blockDim.x) {
     const double2 r = R[(int64_t)n * ld + g];
     float f[4];
-    features(kin, g, th, r, rn, sq, vavg, scaler, f);
+    features(kin, g, itn, th, r, rn, sq, vavg, scaler, f);
     const float sv = scale_out(mlp_z3(Ws, f));
     if (!isfinite(sv)) bad[i] = 1;
     const double k = (double)sv * tpa_k3(kin[g] * itn);
@@ -503,16 +506,20 @@ pw_status pw_mlp_set(pw_mlp *n, const float *params, const float *scaler) {
   return PW_OK;
 }
 
-pw_status pw_mlp_features(pw_problem *p, const double *theta, const void *r, const double *rnorm,
-                          int64_t ld, int64_t nbands, void *F, void *stream) {
-  PW_CHECK_ARG(p && theta && r && rnorm && F && ld >= p->npw && nbands >= 0, PW_ERR_INVALID,
-               "pw_mlp_features: bad argument");
+pw_status pw_mlp_features(pw_problem *p, const double *theta, const void *x, const void *r,
+                          const double *rnorm, int64_t ld, int64_t nbands, void *F, void *stream) {
+  PW_CHECK_ARG(p && theta && x && r && rnorm && F && ld >= p->npw && nbands >= 0 &&
+                   nbands <= p->max_bands,
+               PW_ERR_INVALID, "pw_mlp_features: bad argument");
   if (nbands == 0) return PW_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc = band_kinetic(p->d_kin, x, ld, p->npw, (int)nbands, p->d_tn, s);
+  if (rc != PW_OK) return rc;
   int bx = (int)((p->npw + 255) / 256);
   if (bx > 256) bx = 256;
-  hipLaunchKernelGGL(k_features, dim3(bx, (unsigned)nbands), dim3(256), 0,
-                     static_cast<hipStream_t>(stream), p->d_kin, theta, static_cast<const double2 *>(r),
-                     ld, rnorm, (const int *)nullptr, p->npw, p->vavg, static_cast<float4 *>(F));
+  hipLaunchKernelGGL(k_features, dim3(bx, (unsigned)nbands), dim3(256), 0, s, p->d_kin, p->d_tn, theta,
+                     static_cast<const double2 *>(r), ld, rnorm, (const int *)nullptr, p->npw, p->vavg,
+                     static_cast<float4 *>(F));
   PW_HIP(hipGetLastError());
   return PW_OK;
 }

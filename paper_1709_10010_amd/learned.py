@@ -65,7 +65,7 @@ def collect(cell, ik: int = 0, precision: int = _lib.PW_FP64, tol: float = 5e-7,
         if it in snap_iters:
             _lib.pw_davidson_snapshot(d, X, R, th, rh)
             _lib.pw_mlp_targets(prob, Xc, cid, X, Dt, work)
-            _lib.pw_mlp_features(prob, th, R, rh, F)
+            _lib.pw_mlp_features(prob, th, X, R, rh, F)
             # the network scales the TPA correction: its residual samples are K_TPA R
             _lib.pw_precond(prob, _lib.PW_PRECOND_TPA, None, X, R, RK)
             torch.cuda.synchronize()
@@ -102,8 +102,13 @@ def build_dataset(parts):
 
 
 def train(ds, epochs: int = 30, bands_per_batch: int = 64, lr: float = 1e-3, seed: int = 0,
-          net=None, log=print):
-    """Adam over minibatches of whole bands; returns the network and the loss history."""
+          net=None, log=print, validate=None, val_every: int = 2):
+    """Adam over minibatches of whole bands; returns the network and the loss history.
+
+    With ``validate`` (a function of the network returning a score, lower is
+    better) the network is scored every ``val_every`` epochs and the
+    parameters with the best score are the ones returned; the history of
+    (epoch, score) pairs is in ``net.val_history``."""
     import torch
     init = init_params(seed)
     if net is None:
@@ -112,7 +117,7 @@ def train(ds, epochs: int = 30, bands_per_batch: int = 64, lr: float = 1e-3, see
     rng = np.random.default_rng(seed)
     off = ds["off"]
     nbd = ds["nbands"]
-    hist = []
+    hist, val_hist, best = [], [], None
     smax = int(max(off[b + 1] - off[b] for b in range(nbd))) * bands_per_batch
     s_work = torch.zeros(smax, dtype=torch.float32, device="cuda")
     for ep in range(epochs):
@@ -132,6 +137,17 @@ def train(ds, epochs: int = 30, bands_per_batch: int = 64, lr: float = 1e-3, see
         hist.append(tot / max(nbat, 1))
         if log:
             log(f"epoch {ep}: mean band loss {hist[-1]:.4f}")
+        if validate is not None and ((ep + 1) % val_every == 0 or ep + 1 == epochs):
+            score = validate(net)
+            val_hist.append((ep + 1, score))
+            if log:
+                log(f"epoch {ep}: validation score {score:.4f}")
+            if best is None or score < best[0]:
+                p, sc, _ = net.get()
+                best = (score, p.copy(), sc.copy())
+    if best is not None:
+        net.set(params=best[1], scaler=best[2])
+    net.val_history = val_hist
     return net, hist
 
 
@@ -184,14 +200,17 @@ def load(path: str):
 
 
 def evaluate(cell, net, ik: int = 0, precision: int = _lib.PW_MIXED_FP32, tol: float = 5e-7,
-             max_iter: int = 300):
+             max_iter: int = 300, prob=None, which=("tpa", "mlp")):
     """TPA vs MLP solves of one cell from the same start: iterations, wall time, eigenvalues."""
     import torch
     nb = cell.nbands
-    prob, _ = build_problem(cell, ik, precision=precision, max_bands=nb)
+    if prob is None:
+        prob, _ = build_problem(cell, ik, precision=precision, max_bands=nb)
     npw = prob.npw
     out = {}
     for name, kind, nt in (("tpa", _lib.PW_PRECOND_TPA, None), ("mlp", _lib.PW_PRECOND_MLP, net)):
+        if name not in which:
+            continue
         x0 = band_block(nb, npw)
         x0[:, :npw] = torch.from_numpy(synth.psi_start(cell.seed, nb, npw, ik)).cuda()
         torch.cuda.synchronize()
@@ -200,5 +219,6 @@ def evaluate(cell, net, ik: int = 0, precision: int = _lib.PW_MIXED_FP32, tol: f
         torch.cuda.synchronize()
         r["seconds"] = time.perf_counter() - t0
         out[name] = r
-    out["max_theta_diff_Ha"] = float(np.abs(out["tpa"]["theta"] - out["mlp"]["theta"]).max())
+    if "tpa" in out and "mlp" in out:
+        out["max_theta_diff_Ha"] = float(np.abs(out["tpa"]["theta"] - out["mlp"]["theta"]).max())
     return out

@@ -131,9 +131,9 @@ def test_targets_and_features_match_oracle(lib):
     Rr = rng.standard_normal(V.shape) + 1j * rng.standard_normal(V.shape)
     rn = np.linalg.norm(Rr, axis=1)
     F = torch.zeros(16 * po.npw * 4, dtype=torch.float32, device="cuda")
-    lib.pw_mlp_features(pl, theta, to_gpu_block(Rr), torch.from_numpy(rn).cuda(), F)
+    lib.pw_mlp_features(pl, theta, Xi_g, to_gpu_block(Rr), torch.from_numpy(rn).cuda(), F)
     torch.cuda.synchronize()
-    ref = omlp.features(po.kinetic(), w, Rr.T, float(po.vloc.mean()))
+    ref = omlp.features(po.kinetic(), w, Xit.T, Rr.T, float(po.vloc.mean()))
     assert np.abs(F.cpu().numpy().reshape(-1, 4) - ref).max() <= 1e-6 * np.abs(ref).max()
 
 

@@ -354,3 +354,20 @@ def test_target_correction_geometry():
     raw = q[:, 0] * ph - x
     exp = raw - x * (x.conj() @ raw)
     assert np.abs(mlp.target_correction(x, q, X[:, :1]) - exp).max() < 1e-14
+
+
+def test_mlp_features_by_hand():
+    # a band that is one plane wave G0 has T_n = t(G0): its kinetic feature
+    # is 1 at G0 and t(G) / t(G0) elsewhere; amplitudes of a flat residual are 1
+    npw = 12
+    t = np.linspace(0.5, 6.0, npw)
+    X = np.zeros((npw, 2), dtype=complex)
+    X[3, 0] = 1j
+    X[[1, 5], 1] = [0.6, 0.8]
+    R = np.full((npw, 2), 0.3 - 0.4j)
+    f = mlp.features(t, np.array([-0.2, 0.7]), X, R, 0.125).reshape(2, npw, 4)
+    assert np.allclose(f[0, :, 0], t / t[3], rtol=1e-15, atol=0)
+    tn1 = 0.36 * t[1] + 0.64 * t[5]
+    assert np.allclose(f[1, :, 0], t / tn1, rtol=1e-15, atol=0)
+    assert np.allclose(f[:, :, 1], [[-0.2], [0.7]]) and np.allclose(f[:, :, 2], 1.0)
+    assert np.all(f[:, :, 3] == 0.125)
