@@ -25,7 +25,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}       # dense MFMA
+# vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz for FP64;
+# FP32 counts the packed (two-wide) rate
+PEAK_VALU_TFLOPS = {"f64": 78.6, "f32": 157.3}
+
+# HBM bytes per launch measured with rocprofv3 (FETCH_SIZE x 2.0 + WRITE_SIZE
+# x 1.0, factors from a plain device copy), valid only for the kernel source
+# and launch choices they were taken with
+MEASURED_TRAFFIC = {
+    "plane": {"source": "paper_1709_10010_amd/csrc/fft.hip", "sha256_16": "3225c77f8a5b8964",
+              "precision": 0, "band_chunk": 128, "plane_group": 2, "plane_kernel": 0,
+              "bytes_per_launch": 580435690.5},
+}
+
+
+def measured_traffic(kernel, prec, tuning):
+    """Counter-measured bytes per launch of `kernel`, or None once the kernel
+    source or its launch choices differ from those of the measurement."""
+    import hashlib
+    m = MEASURED_TRAFFIC.get(kernel)
+    if m is None or tuning is None or prec != m["precision"]:
+        return None
+    if (tuning.get("band_chunk"), tuning.get("plane_group"), tuning.get("plane_kernel_id")) != \
+            (m["band_chunk"], m["plane_group"], m["plane_kernel"]):
+        return None
+    try:
+        with open(os.path.join(ROOT, m["source"]), "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return m["bytes_per_launch"] if h == m["sha256_16"] else None
 
 
 def parse():
@@ -42,18 +72,31 @@ def parse():
     ap.add_argument("--batched-cells", type=int, default=64)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--davidson-reps", type=int, default=3)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch choices")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (the reference "
+                         "kernel that scales HBM byte counters) and exit")
     return ap.parse_args()
 
 
-def stage_model(info, nb, prec, group):
-    """Algorithmic bytes / flops per launch of each H*psi stage (one k-point, nb bands)."""
-    npw, nst, nproj, n = info["npw"], info["nsticks"], info["nproj"], info["n"]
+def stage_model(info, nb, prec):
+    """Algorithmic work of each H*psi stage for one call (one k-point, nb bands):
+    HBM bytes for the memory-bound stages, flops for the arithmetic-bound ones.
+
+    z passes: each band's sphere in (16 B per G) and its z-sticks out (nst * n
+    values), and back.  Plane pass (arithmetic intensity ~16 flop/B in FP64,
+    above the ridge 78.6e12 / 8e12): per band the FFT lines of a plane pass --
+    nx columns inverse and forward along y, n rows inverse and forward along x,
+    on each of n planes -- at 5 m log2(m) flops per m-point line, plus the
+    V(r) product (2 flops per grid point).  Projector GEMMs: 8 real flops per
+    complex multiply-add."""
+    npw, nst, nproj, n, nx = info["npw"], info["nsticks"], info["nproj"], info["n"], info["nx"]
     s = 16 if prec == 0 else 8
-    sv = 8 if prec == 0 else 4
     col = nst * n * s                       # one band's z-sticks
+    fft_line = 5.0 * n * np.log2(n)
     return {
         "zfft_inv": ("hbm", nb * (16 * npw + col)),
-        "plane": ("hbm", nb * (2 * col) + n ** 3 * sv * ((nb + group - 1) // group)),
+        "plane": ("alu", nb * (n * (2 * nx + 2 * n) * fft_line + 2.0 * n ** 3)),
         "zfft_fwd": ("hbm", nb * (col + 32 * npw)),
         "proj": ("mfma", 8.0 * npw * nproj * nb),
         "nlupd": ("mfma", 8.0 * npw * nproj * nb),
@@ -122,9 +165,10 @@ def davidson_section(reps: int):
     return out
 
 
-def batched_section(ncells: int, steps: int):
+def batched_section(ncells: int, steps: int, autotune: bool = True):
     """64 ragged cells (a 10-18 bohr, 20-40 Ry, 8-48 atoms, 32-192 bands): one H*psi
-    sweep per step, eager launches vs one HIP-graph launch per step."""
+    sweep per step, eager launches vs one HIP-graph launch per step; each cell's
+    launch choices autotuned first (outside the timed region)."""
     import torch
     import synth
     from paper_1709_10010_amd import _lib
@@ -141,9 +185,16 @@ def batched_section(ncells: int, steps: int):
         ys.append(torch.zeros_like(x))
         nbs.append(c.nbands)
         npws.append(p.npw)
+    kinds = {}
+    if autotune:
+        for p, nb in zip(probs, nbs):
+            _lib.pw_problem_autotune(p, nb, reps=2)
+            k = _lib.pw_problem_tuning(p)["plane_kernel"]
+            kinds[k] = kinds.get(k, 0) + 1
     b = _lib.Batch(probs, xs, ys)
     s = torch.cuda.Stream()
-    out = {"cells": ncells, "bands_per_step": int(sum(nbs)), "npw_range": [min(npws), max(npws)]}
+    out = {"cells": ncells, "bands_per_step": int(sum(nbs)), "npw_range": [min(npws), max(npws)],
+           "autotuned": autotune, "plane_kernels": {("register", "wave", "lds")[k]: v for k, v in kinds.items()}}
     with torch.cuda.stream(s):
         _lib.pw_batch_hpsi(b, s)
         s.synchronize()
@@ -216,6 +267,15 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8, "dispatches": 5}))
+        return
     import synth
     from paper_1709_10010_amd import _lib
     from paper_1709_10010_amd.problems import band_block, build_problem
@@ -228,12 +288,26 @@ def main():
         p, m = build_problem(cell, ik, precision=prec, max_bands=cell.nbands)
         inf = p.info()
         inf["n"] = cell.nr[0]
+        inf["nx"] = int(len(np.unique(np.asarray(m)[:, 0] % cell.nr[0])))   # grid x rows holding sticks
         x = band_block(cell.nbands, inf["npw"])
         x[:, :inf["npw"]] = torch.from_numpy(synth.psi_start(cell.seed, cell.nbands, inf["npw"], ik)).cuda()
         probs.append(p)
         psis.append(x)
         hpsis.append(torch.zeros_like(x))
         infos.append(inf)
+    tuning = None
+    if args.no_autotune:
+        tuning = _lib.pw_problem_tuning(probs[0])
+        tuning["plane_kernel_id"] = tuning["plane_kernel"]
+        tuning["plane_kernel"] = ("register", "wave", "lds")[tuning["plane_kernel"]]
+    else:
+        # launch choices (plane kernel, bands per workgroup, sweep height,
+        # split-K) searched once per problem, outside the timed region
+        for p in probs:
+            _lib.pw_problem_autotune(p, cell.nbands, reps=3)
+        tuning = _lib.pw_problem_tuning(probs[0])
+        tuning["plane_kernel_id"] = tuning["plane_kernel"]
+        tuning["plane_kernel"] = ("register", "wave", "lds")[tuning["plane_kernel"]]
     torch.cuda.synchronize()
 
     def step():
@@ -268,32 +342,45 @@ def main():
             a[0] += ms
             a[1] += n
         _lib.pw_profile_enable(p, False)
-    group = int(os.environ.get("PW_PLANE_GROUP", "8"))
-    models = [stage_model(inf, cell.nbands, prec, group) for inf in infos]
-    dom = max(stages, key=lambda k: stages[k][0])
-    avg_ms = stages[dom][0] / stages[dom][1]
-    kind, _ = models[0][dom]
-    per_launch = float(np.mean([m[dom][1] for m in models]))
+    models = [stage_model(inf, cell.nbands, prec) for inf in infos]
     gemm_dtype = {0: "f64", 1: "f32", 2: "bf16"}[prec]
+    vec_dtype = "f64" if prec == 0 else "f32"
+
+    def rate(k):
+        # modelled work of every profiled call / the stage's total time: the
+        # algorithmic amount per launch over the average launch duration
+        work = args.steps * sum(m[k][1] for m in models)
+        return work / (stages[k][0] * 1e-3)
+
+    dom = max(stages, key=lambda k: stages[k][0])
+    kind = models[0][dom][0]
     if kind == "hbm":
-        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        achieved = rate(dom) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None}
     else:
-        achieved = per_launch / (avg_ms * 1e-3) / 1e12
-        peak = PEAK_TFLOPS[gemm_dtype]
-        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+        achieved = rate(dom) / 1e12
+        peak = PEAK_TFLOPS[gemm_dtype] if kind == "mfma" else PEAK_VALU_TFLOPS[vec_dtype]
+        roof = {"bound": kind, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": None}
     roof["kernel"] = dom
+    roof["avg_launch_ms"] = round(stages[dom][0] / stages[dom][1], 4)
+    roof["traffic"] = measured_traffic(dom, prec, tuning)     # HBM bytes per launch, counters
+    if dom == "plane":
+        # the plane pass's own HBM bytes for the bands of one launch: z-sticks
+        # in and out, V(r) once
+        inf, nbl = infos[0], (tuning or {}).get("band_chunk") or cell.nbands
+        sz = 16 if prec == 0 else 8
+        roof["hbm_bytes_algorithmic_per_launch"] = float(nbl * 2 * inf["nsticks"] * inf["n"] * sz
+                                                          + inf["n"] ** 3 * sz // 2)
     stage_out = {}
     for k, (ms, n) in sorted(stages.items(), key=lambda kv: -kv[1][0]):
-        kind_k, amt = models[0].get(k, ("-", 0.0))
-        avg = ms / n
-        ent = {"avg_ms": round(avg, 4), "launches": n, "share": round(ms / sum(v[0] for v in stages.values()), 3)}
+        kind_k = models[0].get(k, ("-", 0.0))[0]
+        ent = {"avg_ms": round(ms / n, 4), "launches": n, "share": round(ms / sum(v[0] for v in stages.values()), 3)}
         if kind_k == "hbm":
-            ent["GB/s"] = round(float(np.mean([m[k][1] for m in models])) / (avg * 1e-3) / 1e9, 1)
-        elif kind_k == "mfma":
-            ent["TFLOP/s"] = round(float(np.mean([m[k][1] for m in models])) / (avg * 1e-3) / 1e12, 2)
+            ent["GB/s"] = round(rate(k) / 1e9, 1)
+        elif kind_k in ("mfma", "alu"):
+            ent["TFLOP/s"] = round(rate(k) / 1e12, 2)
         stage_out[k] = ent
 
     out = {
@@ -316,6 +403,7 @@ def main():
             "precision_form": args.precision,
             "npw": [inf["npw"] for inf in infos],
             "nsticks": [inf["nsticks"] for inf in infos],
+            "launch_choices_kpoint0": tuning,
         },
         "roofline": roof,
         "stages": stage_out,
@@ -323,7 +411,8 @@ def main():
     }
     dav = None if args.no_davidson else davidson_section(args.davidson_reps)
     if not args.no_batched:
-        out["batched_ragged_cells"] = batched_section(args.batched_cells, max(3, args.steps // 2))
+        out["batched_ragged_cells"] = batched_section(args.batched_cells, max(3, args.steps // 2),
+                                                      autotune=not args.no_autotune)
     if not args.no_learned:
         out["learned_preconditioner"] = learned_section()
     if not args.no_cpu_baseline:

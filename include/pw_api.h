@@ -269,15 +269,20 @@ pw_status pw_batch_launch(pw_batch *b, void *stream);
 
 /*
  * Autotuner: times pw_hpsi on nbands scratch bands (reps timed calls per
- * shape) over the bands per plane workgroup, the bands per FFT sweep and the
- * split-K factor of the projection GEMM, keeps the fastest in the handle and
- * returns its time (ms per call, may be NULL).  Allocates and frees its own
- * scratch bands; synchronises the stream.
+ * shape) over the plane kernel and the bands per plane workgroup, then the
+ * bands per FFT sweep, then the split-K factor of the projection GEMM, keeps
+ * the fastest in the handle and returns its time (ms per call, may be NULL).
+ * Allocates and frees its own scratch bands; synchronises the stream.
+ * pw_problem_tuning reports the handle's current choices (any output may be
+ * NULL); plane_kernel is one of PW_PLANE_*.
  */
+#define PW_PLANE_REGISTER 0 /* line FFTs in registers (even compile-time grid sizes) */
+#define PW_PLANE_WAVE 1     /* wave-local LDS passes                                 */
+#define PW_PLANE_LDS 2      /* workgroup LDS Stockham passes                         */
 pw_status pw_problem_autotune(pw_problem *p, int64_t nbands, int32_t reps, void *stream,
                               double *best_ms);
 pw_status pw_problem_tuning(const pw_problem *p, int32_t *plane_group, int64_t *band_chunk,
-                            int32_t *ksplit);
+                            int32_t *ksplit, int32_t *plane_kernel);
 
 /*
  * Learned diagonal preconditioner (FP32 network 4 -> 64 -> 64 -> 1, SiLU,

@@ -22,6 +22,7 @@ PW_NOT_CONVERGED = 1
 PW_FP64, PW_MIXED_FP32, PW_MIXED_BF16 = 0, 1, 2
 PW_TERM_KINETIC, PW_TERM_LOCAL, PW_TERM_NONLOCAL, PW_TERM_ALL = 1, 2, 4, 7
 PW_PRECOND_NONE, PW_PRECOND_TPA, PW_PRECOND_MLP = 0, 1, 2
+PW_PLANE_REGISTER, PW_PLANE_WAVE, PW_PLANE_LDS = 0, 1, 2
 STATUS_NAMES = {0: "PW_OK", 1: "PW_NOT_CONVERGED", -1: "PW_ERR_INVALID", -2: "PW_ERR_SHAPE",
                 -3: "PW_ERR_NOMEM", -4: "PW_ERR_HIP", -5: "PW_ERR_NOT_FINITE",
                 -6: "PW_ERR_NUMERIC"}
@@ -101,7 +102,7 @@ def _load():
         "pw_batch_capture": (i32, [vp, vp]),
         "pw_batch_launch": (i32, [vp, vp]),
         "pw_problem_autotune": (i32, [vp, i64, i32, vp, C.POINTER(f64)]),
-        "pw_problem_tuning": (i32, [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32)]),
+        "pw_problem_tuning": (i32, [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32), C.POINTER(i32)]),
         "pw_eigh_workspace": (i32, [i32, C.POINTER(C.c_size_t)]),
         "pw_eigh": (i32, [vp, i64, i32, vp, vp, i64, vp, C.c_size_t, vp]),
         "pw_profile_enable": (i32, [vp, i32]),
@@ -600,9 +601,9 @@ def pw_problem_autotune(prob: Problem, nbands: int, reps: int = 3, stream=None) 
 
 
 def pw_problem_tuning(prob: Problem) -> dict:
-    g, c, k = C.c_int32(), C.c_int64(), C.c_int32()
-    _check(LIB.pw_problem_tuning(prob.handle, C.byref(g), C.byref(c), C.byref(k)))
-    return dict(plane_group=g.value, band_chunk=c.value, ksplit=k.value)
+    g, c, k, pk = C.c_int32(), C.c_int64(), C.c_int32(), C.c_int32()
+    _check(LIB.pw_problem_tuning(prob.handle, C.byref(g), C.byref(c), C.byref(k), C.byref(pk)))
+    return dict(plane_group=g.value, band_chunk=c.value, ksplit=k.value, plane_kernel=pk.value)
 
 
 def pw_eigh(A, stream=None):

@@ -104,6 +104,12 @@ static int build_stick_map(pw_problem *p, const int32_t *miller, int ts) {
       if (hasx[x]) sm.xlist.push_back(x);
   }
   sm.nx = (int)sm.xlist.size();
+  sm.ls = n1 | 1;
+  sm.xslot.assign(n0, sm.nx);
+  for (int i = 0; i < sm.nx; ++i) sm.xslot[sm.xlist[i]] = i;
+  sm.stick_cpos.resize(sm.nst);
+  for (int s = 0; s < sm.nst; ++s)
+    sm.stick_cpos[s] = sm.xslot[sm.stick_xy[s] / n1] * sm.ls + sm.stick_xy[s] % n1;
   // entries grouped by tile, then stick, then z
   std::vector<int64_t> key(npw);
   std::vector<int32_t> order(npw);
@@ -210,6 +216,7 @@ static void free_problem(pw_problem *p) {
   if (!p) return;
   p->prof.release();
   void *bufs[] = {p->d_gidx,   p->d_gpos,    p->d_tile_ptr, p->d_stick_xy, p->d_xlist,
+                  p->d_xslot,  p->d_stick_cpos,
                   p->d_kin,    p->d_tw,      p->d_vplanes,  p->d_beta,     p->d_beta_lp,
                   p->d_dij,    p->d_pj_atom, p->d_proj_off, p->d_dij_off,  p->d_sticks,
                   p->d_P,      p->d_Q,       p->d_part,     p->d_tn};
@@ -342,6 +349,8 @@ pw_status pw_problem_create(const pw_problem_desc *d, int64_t max_bands, void *s
   if ((rc = upload(&p->d_tile_ptr, sm.tile_ptr)) != PW_OK) return fail(rc);
   if ((rc = upload(&p->d_stick_xy, sm.stick_xy)) != PW_OK) return fail(rc);
   if ((rc = upload(&p->d_xlist, sm.xlist)) != PW_OK) return fail(rc);
+  if ((rc = upload(&p->d_xslot, sm.xslot)) != PW_OK) return fail(rc);
+  if ((rc = upload(&p->d_stick_cpos, sm.stick_cpos)) != PW_OK) return fail(rc);
 
   // twiddles (x, y, z back to back) in the FFT precision
   std::vector<unsigned char> tw;
@@ -426,7 +435,7 @@ pw_status pw_problem_create(const pw_problem_desc *d, int64_t max_bands, void *s
   if (chunk <= 0) chunk = std::max<int64_t>(1, std::min<int64_t>(max_bands, ((size_t)1 << 30) / per_band));
   chunk = std::min(chunk, max_bands);
   p->band_chunk = chunk;
-  p->plane_group = std::max(1, env_int("PW_PLANE_GROUP", 8));
+  p->plane_group = env_int("PW_PLANE_GROUP", 0);  // <= 0: chosen for the plane kernel below
   if (hipMalloc(&p->d_sticks, per_band * chunk) != hipSuccess) return fail(PW_ERR_NOMEM);
   if (hipMalloc(&p->d_tn, (size_t)max_bands * sizeof(double)) != hipSuccess) return fail(PW_ERR_NOMEM);
 
@@ -449,11 +458,15 @@ pw_status pw_problem_create(const pw_problem_desc *d, int64_t max_bands, void *s
   f.tile_ptr = p->d_tile_ptr;
   f.stick_xy = p->d_stick_xy;
   f.xlist = p->d_xlist;
+  f.xslot = p->d_xslot;
+  f.stick_cpos = p->d_stick_cpos;
   f.tw0 = static_cast<unsigned char *>(p->d_tw) + off[0];
   f.tw1 = static_cast<unsigned char *>(p->d_tw) + off[1];
   f.tw2 = static_cast<unsigned char *>(p->d_tw) + off[2];
   f.vplanes = p->d_vplanes;
   f.kin = p->d_kin;
+  p->plane_kernel = plane_kernel_default();
+  if (p->plane_group <= 0) p->plane_group = plane_default_group(f, d->precision, p->plane_kernel);
   if (hipStreamSynchronize(s) != hipSuccess) {
     set_error("pw_problem_create: stream synchronisation failed");
     return fail(PW_ERR_HIP);
@@ -516,7 +529,7 @@ pw_status pw_hpsi(pw_problem *p, const void *psi, int64_t ld_psi, void *hpsi, in
       }
       if (rc == PW_OK) {
         ProfScope ps_(&p->prof, PW_STAGE_PLANE, s);
-        rc = launch_plane(p->fft, p->precision, p->d_sticks, nb, p->plane_group, s);
+        rc = launch_plane(p->fft, p->precision, p->d_sticks, nb, p->plane_group, p->plane_kernel, s);
       }
       if (rc == PW_OK) {
         ProfScope ps_(&p->prof, PW_STAGE_ZFFT_FWD, s);

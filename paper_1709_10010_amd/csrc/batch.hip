@@ -8,9 +8,9 @@
 // pw_hpsi allocates, synchronises or clears memory with a memset, so the
 // recorded graph is the same sequence of kernels an eager sweep enqueues.
 //
-// The autotuner times pw_hpsi on scratch bands for a few launch shapes
-// (bands per plane workgroup, bands per FFT sweep, split-K of the
-// projection GEMM) and keeps the fastest for the handle.
+// The autotuner times pw_hpsi on scratch bands for a few launch choices
+// (plane kernel and bands per plane workgroup, bands per FFT sweep, split-K
+// of the projection GEMM) and keeps the fastest for the handle.
 #include <algorithm>
 #include <vector>
 
@@ -133,8 +133,11 @@ pw_status pw_problem_autotune(pw_problem *p, int64_t nbands, int32_t reps, void 
   const int groups[] = {1, 2, 4, 8, 16};
   const int64_t chunks[] = {chunk0, 128, 64, 32};
   const int splits[] = {0, 4, 8, 16, 32};
+  // the register plane kernel only where it has an instance for the grid
+  std::vector<int> kernels{PW_PLANE_LDS};
+  if (plane_register_ok(p->fft, p->precision)) kernels.insert(kernels.begin(), PW_PLANE_REGISTER);
   double best = 1e30;
-  int bg = p->plane_group, bs = p->ksplit;
+  int bg = p->plane_group, bs = p->ksplit, bk = p->plane_kernel;
   int64_t bc = chunk0;
   auto time_it = [&](double *ms) -> int {
     int rc = pw_hpsi(p, x, ld, y, ld, nbands, PW_TERM_ALL, stream);  // warm-up
@@ -150,16 +153,22 @@ pw_status pw_problem_autotune(pw_problem *p, int64_t nbands, int32_t reps, void 
     return PW_OK;
   };
   int rc = PW_OK;
-  // coordinate search: plane group, then sweep height, then split-K
-  for (int g : groups) {
-    p->plane_group = g;
-    double ms;
-    if ((rc = time_it(&ms)) != PW_OK) break;
-    if (ms < best) {
-      best = ms;
-      bg = g;
+  // coordinate search: plane kernel x plane group, then sweep height, then split-K
+  for (int k : kernels) {
+    for (int g : groups) {
+      if (rc != PW_OK) break;
+      p->plane_kernel = k;
+      p->plane_group = g;
+      double ms;
+      if ((rc = time_it(&ms)) != PW_OK) break;
+      if (ms < best) {
+        best = ms;
+        bg = g;
+        bk = k;
+      }
     }
   }
+  p->plane_kernel = bk;
   p->plane_group = bg;
   for (int64_t c : chunks) {
     if (rc != PW_OK || c > chunk0 || c < 1) continue;
@@ -197,8 +206,9 @@ pw_status pw_problem_autotune(pw_problem *p, int64_t nbands, int32_t reps, void 
 }
 
 pw_status pw_problem_tuning(const pw_problem *p, int32_t *plane_group, int64_t *band_chunk,
-                            int32_t *ksplit) {
+                            int32_t *ksplit, int32_t *plane_kernel) {
   PW_CHECK_ARG(p, PW_ERR_INVALID, "pw_problem_tuning: null handle");
+  if (plane_kernel) *plane_kernel = p->plane_kernel;
   if (plane_group) *plane_group = p->plane_group;
   if (band_chunk) *band_chunk = p->band_chunk;
   if (ksplit) *ksplit = p->ksplit;

@@ -58,6 +58,12 @@ struct StickMap {
   std::vector<int32_t> tile_ptr; // [ntile+1]
   std::vector<int32_t> stick_xy; // [nst] x * N1 + y
   std::vector<int32_t> xlist;    // [nx] rows holding sticks
+  // compact plane layout of the register plane pass: x -> slot (0..nx-1,
+  // nx for an x without sticks, a column kept zero) and each stick's
+  // position slot * ls + y, with slot stride ls = N1 | 1
+  int ls = 0;
+  std::vector<int32_t> xslot;      // [N0]
+  std::vector<int32_t> stick_cpos; // [nst]
 };
 
 // Device-side view passed to the FFT launchers.
@@ -66,6 +72,7 @@ struct FFTDev {
   int nst, ts, ntile, nst_pad, nx;
   AxisPlan px, py, pz;
   const int32_t *gidx, *gpos, *tile_ptr, *stick_xy, *xlist;
+  const int32_t *xslot, *stick_cpos;  // compact plane layout (see StickMap)
   const void *tw0, *tw1, *tw2;  // twiddle tables in the FFT precision
   const void *vplanes;          // [N2][N0][N1] V / (N0 N1 N2) in the FFT precision
   const double *kin;            // [npw]
@@ -117,12 +124,14 @@ struct pw_problem {
   double vavg = 0;          // mean of V_LOC over the grid (a feature of the learned preconditioner)
   int64_t band_chunk = 0;   // bands per FFT sweep (stick-buffer height)
   int plane_group = 8;      // bands per plane-pass workgroup
+  int plane_kernel = 0;     // PW_PLANE_REGISTER / _WAVE / _LDS
   int ksplit = 0;           // split-K factor for projections (0 = auto)
   pw::StickMap map;
   pw::FFTDev fft{};
   // device buffers owned by the handle
   int32_t *d_gidx = nullptr, *d_gpos = nullptr, *d_tile_ptr = nullptr;
   int32_t *d_stick_xy = nullptr, *d_xlist = nullptr;
+  int32_t *d_xslot = nullptr, *d_stick_cpos = nullptr;
   double *d_kin = nullptr;
   void *d_tw = nullptr;        // three twiddle tables back to back
   void *d_vplanes = nullptr;
@@ -145,7 +154,12 @@ namespace pw {
 // FFT launchers (fft.hip)
 int launch_zfft_inv(const FFTDev &f, int prec, const void *psi, int64_t ld, void *sticks,
                     int nb, hipStream_t s);
-int launch_plane(const FFTDev &f, int prec, void *sticks, int nb, int group, hipStream_t s);
+int launch_plane(const FFTDev &f, int prec, void *sticks, int nb, int group, int kernel,
+                 hipStream_t s);
+// plane kernel a new problem starts with, and whether the register plane
+// kernel has an instance for the grid (fft.hip)
+int plane_kernel_default();
+bool plane_register_ok(const FFTDev &f, int prec);
 int launch_zfft_fwd(const FFTDev &f, int prec, const void *sticks, const void *psi, int64_t ld,
                     void *hpsi, int64_t ldh, int nb, bool kinetic, hipStream_t s);
 int launch_kinetic_only(const double *kin, const void *psi, int64_t ld, void *hpsi, int64_t ldh,
@@ -175,6 +189,8 @@ int launch_apply_d(const double *dij, const int32_t *pj_atom, const int32_t *pro
 // Diagonal preconditioner (nonlocal.hip): t = K r, K per PW_PRECOND_TPA / _NONE.
 int launch_tpa(const double *kin, const void *x, const void *r, void *t, int64_t ld, int64_t npw,
                int nb, int kind, double *tn_work, hipStream_t s);
+// Bands per plane-pass workgroup that suits a plane kernel on the grid (fft.hip).
+int plane_default_group(const FFTDev &f, int prec, int kernel);
 // tn[n] = <x_n|t|x_n> / <x_n|x_n> for nb bands (nonlocal.hip).
 int band_kinetic(const double *kin, const void *x, int64_t ld, int64_t npw, int nb, double *tn,
                  hipStream_t s);

@@ -338,6 +338,124 @@ __device__ __forceinline__ void fft_axis(V *buf, int nlines, int lstride, int es
     fft_lines<V, INV, LINE_FAST, INDIRECT>(buf, nlines, lstride, estride, lbase, pl, tw, tid, nthr);
 }
 
+// ---------------------------------------------------------------- register FFTs
+// One thread transforms one line of compile-time length N held in its own
+// registers: every index and every twiddle is a compile-time constant, so
+// a line costs its butterflies and nothing else, and no barrier is needed
+// inside a transform.
+namespace rf {
+struct CS {
+  double c, s;
+};
+// cos and sin of 0 <= x <= pi/4: Taylor series, terms summed from the smallest
+constexpr CS sincos_small(double x) {
+  double tc[14] = {}, ts[14] = {};
+  const double x2 = x * x;
+  double a = 1.0, b = x;
+  for (int k = 0; k < 14; ++k) {
+    tc[k] = a;
+    ts[k] = b;
+    a *= -x2 / ((2.0 * k + 1.0) * (2.0 * k + 2.0));
+    b *= -x2 / ((2.0 * k + 2.0) * (2.0 * k + 3.0));
+  }
+  double c = 0.0, s = 0.0;
+  for (int k = 13; k >= 0; --k) {
+    c += tc[k];
+    s += ts[k];
+  }
+  return CS{c, s};
+}
+// e^{-2 pi i m / n}: the angle is reduced in integers to q quarter turns plus
+// at most an eighth of a turn, so the series only sees |x| <= pi/4
+constexpr CS twiddle(int m, int n) {
+  m %= n;
+  if (m < 0) m += n;
+  const int q = (4 * m) / n, r = 4 * m - q * n;  // angle = (pi/2) (q + r/n)
+  constexpr double kHalfPi = 1.57079632679489661923132169163975;
+  CS e{0.0, 0.0};
+  if (2 * r <= n) {
+    e = sincos_small(kHalfPi * r / n);
+  } else {
+    const CS t = sincos_small(kHalfPi * (n - r) / n);
+    e = CS{t.s, t.c};
+  }
+  for (int i = 0; i < q; ++i) e = CS{-e.s, e.c};
+  return CS{e.c, -e.s};
+}
+
+// x[r] *= w^(r M) (forward) or its conjugate, r = 1 .. R-1; exact quarter
+// turns become swaps and sign changes.  Other twiddles are compile-time
+// constants, or with a table (tw[m * TS] = w_N^m, TS > 0) read from it at the
+// point of use, which keeps them out of the registers between uses.
+template <typename V, int N, int M, bool INV, int R, int TS, int r = 1>
+__device__ __forceinline__ void tw_mul(V *x, const V *tw) {
+  if constexpr (r < R) {
+    constexpr int m = (r * M) % N;
+    if constexpr (m != 0) {
+      if constexpr ((4 * m) % N == 0) {
+        constexpr int q = (4 * m) / N;
+        if constexpr (q == 2) {
+          x[r] = V{-x[r].x, -x[r].y};
+        } else {
+          x[r] = c_rot<INV>(x[r]);
+          if constexpr (q == 3) x[r] = V{-x[r].x, -x[r].y};
+        }
+      } else {
+        V wv;
+        if constexpr (TS > 0) {
+          wv = tw[m * TS];
+        } else {
+          using S = decltype(x[0].x);
+          constexpr CS w = twiddle(m, N);
+          wv = V{S(w.c), S(w.s)};
+        }
+        x[r] = INV ? c_mulconj(x[r], wv) : c_mul(x[r], wv);
+      }
+    }
+    tw_mul<V, N, M, INV, R, TS, r + 1>(x, tw);
+  }
+}
+
+// butterflies J, J+1, ... of one Stockham pass (radix R, NS = product of the
+// radices before it), reading a and writing b
+template <typename V, int N, int NS, int R, bool INV, int TS, int J>
+__device__ __forceinline__ void pass_bf(const V *a, V *b, const V *tw) {
+  if constexpr (J < N / R) {
+    constexpr int NBF = N / R;
+    constexpr int K = J % NS;
+    V x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = a[J + r * NBF];
+    if constexpr (NS > 1) tw_mul<V, N, K * (N / (NS * R)), INV, R, TS>(x, tw);
+    Dft<R, INV, V>::run(x);
+#pragma unroll
+    for (int r = 0; r < R; ++r) b[(J - K) * R + K + r * NS] = x[r];
+    pass_bf<V, N, NS, R, INV, TS, J + 1>(a, b, tw);
+  }
+}
+
+template <typename V, int N, int P, int NS, bool INV, int TS>
+__device__ __forceinline__ void passes(V *a, V *b, const V *tw) {
+  if constexpr (P < ct_npass(N)) {
+    constexpr int R = ct_radix(N, P);
+    pass_bf<V, N, NS, R, INV, TS, 0>(a, b, tw);
+    passes<V, N, P + 1, NS * R, INV, TS>(b, a, tw);
+  }
+}
+}  // namespace rf
+
+// v <- DFT_N(v) (unnormalised; forward e^{-2 pi i jk/N}, inverse e^{+...}),
+// natural order in and out; twiddles from tw[m * TS] = w_N^m when TS > 0
+template <typename V, int N, bool INV, int TS = 0>
+__device__ __forceinline__ void reg_fft(V *v, const V *tw = nullptr) {
+  V t[N];
+  rf::passes<V, N, 0, 1, INV, TS>(v, t, tw);
+  if constexpr (ct_npass(N) % 2 == 1) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = t[i];
+  }
+}
+
 // ---------------------------------------------------------------- wave-local FFTs
 // One wavefront transforms lines it owns alone, so the read and write halves
 // of a Stockham pass need no workgroup barrier: the wave's LDS operations
@@ -572,6 +690,195 @@ __global__ __launch_bounds__(NTHR) void k_plane_w(FFTDev f, cpx_t<T> *__restrict
   }
 }
 
+// ---------------------------------------------------------------- lane-group FFTs
+// A line of length N = L M (L = 2 or 4) is shared by L consecutive lanes,
+// which run in lockstep: each holds M values and transforms them as an
+// M-point line in registers, and log2(L) radix-2 levels join the lanes
+// through cross-lane moves (DPP quad permutations: [1,0,3,2] swaps lanes
+// differing in bit 0, [2,3,0,1] lanes differing in bit 1).
+template <int B> __device__ __forceinline__ int lane_xchg(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, B == 0 ? 0xB1 : 0x4E, 0xF, 0xF, false);
+}
+template <int B> __device__ __forceinline__ double lane_xchg(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = lane_xchg<B>((int)b);
+  const int hi = lane_xchg<B>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int B> __device__ __forceinline__ float lane_xchg(float v) {
+  return __int_as_float(lane_xchg<B>(__float_as_int(v)));
+}
+
+// One radix-2 level over lanes q and q ^ 2^B for sub-transforms of length
+// NB: lanes with bit B set multiply e[k] by w_NB^(lo M + k), lo being bit LO
+// of q (LO < 0: lo = 0), before (decimation in time) or after (decimation
+// in frequency) the join, where the bit-clear lane takes own + partner's and
+// the other partner's - own.  Twiddles come from the table tw[m] = w_N^m;
+// the other lanes read its entry 0 (= 1).
+template <typename V, int N, int M, int B, int NB, int LO, bool INV>
+__device__ __forceinline__ void level_twiddle(V *e, int q, const V *tw) {
+  constexpr int ST = N / NB;
+  const bool hi = (q >> B) & 1;
+  const int lo = LO >= 0 ? (q >> (LO < 0 ? 0 : LO)) & 1 : 0;
+  const V *t = tw + (hi ? lo * M * ST : 0);
+  const int step = hi ? ST : 0;
+#pragma unroll
+  for (int k = (LO < 0 ? 1 : 0); k < M; ++k) {
+    const V w = t[k * step];
+    e[k] = INV ? c_mulconj(e[k], w) : c_mul(e[k], w);
+  }
+}
+template <typename V, int M, int B>
+__device__ __forceinline__ void level_join(V *e, int q) {
+  using S = decltype(e[0].x);
+  const S sg = ((q >> B) & 1) ? S(-1) : S(1);  // partner's + sg * own
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const V o{lane_xchg<B>(e[k].x), lane_xchg<B>(e[k].y)};
+    e[k] = V{fma(sg, e[k].x, o.x), fma(sg, e[k].y, o.y)};
+  }
+}
+
+// rev reverses the log2(L) bits of a lane index
+template <int L> __device__ __forceinline__ int rev_lane(int q) {
+  return L == 4 ? ((q & 1) << 1) | (q >> 1) : q;
+}
+
+// decimation in time: lane q holds x[L j + q] and ends with
+// X[rev(q) M + k].  With four lanes, lanes q and q ^ 2 hold the even and
+// odd halves of one stride-2 subsequence, so bit 1 is joined first.
+template <typename V, int L, int N, bool INV>
+__device__ __forceinline__ void group_fft_dit(V *e, int q, const V *tw) {
+  constexpr int M = N / L;
+  reg_fft<V, M, INV, L>(e, tw);
+  if constexpr (L == 4) {
+    level_twiddle<V, N, M, 1, 2 * M, -1, INV>(e, q, tw);
+    level_join<V, M, 1>(e, q);
+    level_twiddle<V, N, M, 0, 4 * M, 1, INV>(e, q, tw);
+    level_join<V, M, 0>(e, q);
+  } else {
+    level_twiddle<V, N, M, 0, 2 * M, -1, INV>(e, q, tw);
+    level_join<V, M, 0>(e, q);
+  }
+}
+// decimation in frequency: lane q holds x[rev(q) M + j] (the layout the
+// decimation-in-time transform leaves) and ends with X[L k + q]
+template <typename V, int L, int N, bool INV>
+__device__ __forceinline__ void group_fft_dif(V *e, int q, const V *tw) {
+  constexpr int M = N / L;
+  if constexpr (L == 4) {
+    level_join<V, M, 0>(e, q);
+    level_twiddle<V, N, M, 0, 4 * M, 1, INV>(e, q, tw);
+    level_join<V, M, 1>(e, q);
+    level_twiddle<V, N, M, 1, 2 * M, -1, INV>(e, q, tw);
+  } else {
+    level_join<V, M, 0>(e, q);
+    level_twiddle<V, N, M, 0, 2 * M, -1, INV>(e, q, tw);
+  }
+  reg_fft<V, M, INV, L>(e, tw);
+}
+
+// hides the values from the optimiser: twiddle reads and lane-dependent
+// twiddle addresses derived from them stay inside the loop body that uses
+// them instead of being hoisted and held in registers across the loop
+__device__ __forceinline__ void opaque(int &a, int &b) { asm volatile("" : "+v"(a), "+v"(b)); }
+
+
+// Plane pass with register FFTs.  LDS holds the twiddle table w_N^m, only
+// the nx columns that carry sticks, compact [slot][y] with slot stride
+// LS = N | 1 (odd, so that lanes reading down different columns are free of
+// bank conflicts), one column kept zero for the x without sticks, and the
+// x -> slot table.
+// Per band-plane: clear, scatter the sticks, inverse y transform of each
+// column, then per row the inverse x transform, the V(r) product and the
+// forward x transform back to back, forward y transform of each column,
+// gather.  Every line is held by a group of L lanes.  Cubic grids of
+// compile-time size N (a multiple of L) only.  Workgroups of four waves
+// and a register budget of three (FP64) or four (FP32) waves per SIMD let
+// two or more workgroups share a CU and hide each other's latencies.
+template <typename T, int N, int L, int NTHR>
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 4)))
+void k_plane_r(FFTDev f, cpx_t<T> *__restrict__ sticks, int nb, int group) {
+  using V = cpx_t<T>;
+  static_assert(N % L == 0 && NTHR % (4 * L) == 0, "lane-group plane pass: whole lane groups");
+  constexpr int M = N / L, LS = N | 1, NL = NTHR / L;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nx = f.nx;
+  const int nel = (nx + 1) * LS;
+  V *tw = reinterpret_cast<V *>(smem);
+  V *pl = tw + N;
+  int *xs = reinterpret_cast<int *>(pl + nel);
+  const int z = blockIdx.x % N;
+  const int g = blockIdx.x / N;
+  const int tid = threadIdx.x;
+  const int line = tid / L;
+  const int q = tid % L;
+  const int rq = rev_lane<L>(q);
+  for (int i = tid; i < N; i += NTHR) {
+    xs[i] = f.xslot[i];
+    tw[i] = static_cast<const V *>(f.tw0)[i];
+  }
+  const T *vp = static_cast<const T *>(f.vplanes) + (int64_t)z * N * N;
+  for (int bb = 0; bb < group; ++bb) {
+    const int b = g * group + bb;
+    if (b >= nb) break;
+    for (int i = tid; i < nel; i += NTHR) pl[i] = V{0, 0};
+    __syncthreads();
+    V *col = sticks + (int64_t)b * N * f.nst_pad + (int64_t)z * f.nst_pad;
+    for (int s = tid; s < f.nst; s += NTHR) pl[f.stick_cpos[s]] = col[s];
+    __syncthreads();
+    for (int c = line; c < nx; c += NL) {
+      V e[M];
+      V *p = pl + c * LS;
+      int zero = 0, qo = q;
+      opaque(zero, qo);
+#pragma unroll
+      for (int j = 0; j < M; ++j) e[j] = p[L * j + q];
+      group_fft_dit<V, L, N, true>(e, qo, tw + zero);
+#pragma unroll
+      for (int k = 0; k < M; ++k) p[rq * M + k] = e[k];
+    }
+    __syncthreads();
+    for (int y = line; y < N; y += NL) {
+      V e[M];
+      int zero = 0, qo = q;
+      opaque(zero, qo);
+#pragma unroll
+      for (int j = 0; j < M; ++j) e[j] = pl[xs[L * j + q] * LS + y];
+      group_fft_dit<V, L, N, true>(e, qo, tw + zero);
+      // V and the output slots are read only now (their offsets are opaque
+      // past the transform), not held in registers across it
+      int vo = rq * M * N + y, xo = q;
+      opaque(vo, xo);
+      const T *vr = vp + vo;
+#pragma unroll
+      for (int k = 0; k < M; ++k) e[k] = c_scale(e[k], vr[k * N]);
+      group_fft_dif<V, L, N, false>(e, qo, tw + zero);
+      opaque(xo, zero);
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const int sl = xs[L * k + xo];
+        if (sl < nx) pl[sl * LS + y] = e[k];
+      }
+    }
+    __syncthreads();
+    for (int c = line; c < nx; c += NL) {
+      V e[M];
+      V *p = pl + c * LS;
+      int zero = 0, qo = q;
+      opaque(zero, qo);
+#pragma unroll
+      for (int j = 0; j < M; ++j) e[j] = p[rq * M + j];
+      group_fft_dif<V, L, N, false>(e, qo, tw + zero);
+#pragma unroll
+      for (int k = 0; k < M; ++k) p[L * k + q] = e[k];
+    }
+    __syncthreads();
+    for (int s = tid; s < f.nst; s += NTHR) col[s] = pl[f.stick_cpos[s]];
+    __syncthreads();
+  }
+}
+
 template <typename T, int NTHR, int NC>
 __global__ __launch_bounds__(NTHR) void k_zfft_fwd(FFTDev f, const cpx_t<T> *__restrict__ sticks,
                                                    const double2 *__restrict__ psi, int64_t ld,
@@ -682,6 +989,8 @@ static inline int nb_pad8(int nb) { return (nb + 7) / 8 * 8; }
 
 // cubic grids of the workloads run compile-time-planned kernels
 #define PW_CT_SIZES(X) X(24) X(36) X(40) X(45) X(48) X(50) X(54) X(60) X(64) X(72) X(81) X(90)
+// the register plane pass needs an even length (a line is shared by a lane pair)
+#define PW_CT_EVEN_SIZES(X) X(24) X(36) X(40) X(48) X(50) X(54) X(60) X(64) X(72) X(90)
 
 static int ct_size(const FFTDev &f, int prec) {
   static int off = -1;
@@ -725,13 +1034,34 @@ static int zinv_t(const FFTDev &f, const void *psi, int64_t ld, void *sticks, in
   }
 }
 
-static int plane_impl() {
+// Plane kernels: PW_PLANE_REGISTER (register FFTs where the grid has an
+// even compile-time size, else the LDS Stockham pass), PW_PLANE_WAVE
+// (wave-local lines), PW_PLANE_LDS (LDS Stockham passes).  A problem
+// starts with PW_PLANE_IMPL from the environment, else PW_PLANE_REGISTER.
+int plane_kernel_default() {
   static int v = -1;
   if (v < 0) {
     const char *e = std::getenv("PW_PLANE_IMPL");
-    v = (e && *e) ? std::atoi(e) : 0;
+    v = (e && *e) ? std::atoi(e) : PW_PLANE_REGISTER;
+    if (v < PW_PLANE_REGISTER || v > PW_PLANE_LDS) v = PW_PLANE_REGISTER;
   }
   return v;
+}
+
+// lanes per line: four where N allows (register pressure), else two
+#ifndef PW_PLANE_R_THREADS
+#define PW_PLANE_R_THREADS 256
+#endif
+template <typename T, int N>
+static int plane_r(const FFTDev &f, void *sticks, int nb, int group, int blocks, hipStream_t s) {
+  using V = cpx_t<T>;
+  constexpr int L = (N % 4 == 0) ? 4 : 2;
+  constexpr int NT = PW_PLANE_R_THREADS;
+  const size_t lds = sizeof(V) * ((size_t)(f.nx + 1) * (N | 1) + N) + sizeof(int) * N;
+  auto k = k_plane_r<T, N, L, NT>;
+  if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(NT), lds, s, f, static_cast<V *>(sticks), nb, group);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
 
 template <typename T, int NT>
@@ -762,17 +1092,38 @@ static int plane_c(const FFTDev &f, void *sticks, int nb, int group, size_t lds,
   return plane_n<T, 1024, NC>(f, sticks, nb, group, lds, blocks, s);
 }
 
+bool plane_register_ok(const FFTDev &f, int prec) {
+  switch (ct_size(f, prec)) {
+#define PW_CASE(n) case n: return true;
+    PW_CT_EVEN_SIZES(PW_CASE)
+#undef PW_CASE
+    default: return false;
+  }
+}
+
+int plane_default_group(const FFTDev &f, int prec, int kernel) {
+  return (kernel == PW_PLANE_REGISTER && plane_register_ok(f, prec)) ? 2 : 8;
+}
+
 template <typename T>
-static int plane_t(const FFTDev &f, void *sticks, int nb, int group, hipStream_t s) {
+static int plane_t(const FFTDev &f, void *sticks, int nb, int group, int kernel, hipStream_t s) {
   using V = cpx_t<T>;
   const int npl = f.n0 * f.n1;
   const size_t lds = sizeof(V) * (size_t)(f.n0 + f.n1 + npl) + sizeof(int) * (size_t)f.nx;
   const int groups = (nb + group - 1) / group;
   const int blocks = f.n2 * groups;
-  if (plane_impl() == 1) {
+  if (kernel == PW_PLANE_WAVE) {
     if (npl <= 2048) return plane_w_n<T, 256>(f, sticks, nb, group, lds, blocks, s);
     if (npl <= 4096) return plane_w_n<T, 512>(f, sticks, nb, group, lds, blocks, s);
     return plane_w_n<T, 1024>(f, sticks, nb, group, lds, blocks, s);
+  }
+  if (kernel == PW_PLANE_REGISTER) {
+    switch (ct_size(f, sizeof(T) == 8 ? PW_FP64 : PW_MIXED_FP32)) {
+#define PW_CASE(n) case n: return plane_r<T, n>(f, sticks, nb, group, blocks, s);
+      PW_CT_EVEN_SIZES(PW_CASE)
+#undef PW_CASE
+      default: break;
+    }
   }
   switch (ct_size(f, sizeof(T) == 8 ? PW_FP64 : PW_MIXED_FP32)) {
 #define PW_CASE(n) case n: return plane_c<T, n>(f, sticks, nb, group, lds, blocks, s);
@@ -820,10 +1171,11 @@ int launch_zfft_inv(const FFTDev &f, int prec, const void *psi, int64_t ld, void
                          : zinv_t<float>(f, psi, ld, sticks, nb, s);
 }
 
-int launch_plane(const FFTDev &f, int prec, void *sticks, int nb, int group, hipStream_t s) {
+int launch_plane(const FFTDev &f, int prec, void *sticks, int nb, int group, int kernel,
+                 hipStream_t s) {
   if (nb <= 0) return PW_OK;
-  return prec == PW_FP64 ? plane_t<double>(f, sticks, nb, group, s)
-                         : plane_t<float>(f, sticks, nb, group, s);
+  return prec == PW_FP64 ? plane_t<double>(f, sticks, nb, group, kernel, s)
+                         : plane_t<float>(f, sticks, nb, group, kernel, s);
 }
 
 int launch_zfft_fwd(const FFTDev &f, int prec, const void *sticks, const void *psi, int64_t ld,
