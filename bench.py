@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--batched-cells", type=int, default=64)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--davidson-reps", type=int, default=3)
+    ap.add_argument("--no-davidson-medium", action="store_true")
+    ap.add_argument("--davidson-medium-kpoints", type=int, default=5)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch choices")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference "
@@ -162,6 +164,56 @@ def davidson_section(reps: int):
         if "iterations_first" in r:
             out[name]["iterations_reduced_precision"] = r["iterations_first"]
         out[name]["_theta"] = r["theta"]
+    return out
+
+
+def davidson_medium_section(nk: int):
+    """Config-2 time-to-solution, every k-point in turn (256 bands each): plain
+    FP64 to 1e-8 Ry; the FP32 form to 1e-6 Ry alone; the FP32 form to 1e-5 Ha
+    followed by FP64 iterations to 1e-8 Ry from the same subspace."""
+    import torch
+    import synth
+    from paper_1709_10010_amd import _lib
+    from paper_1709_10010_amd.problems import band_block, build_problem
+
+    cell = synth.make_cell(2)
+    nb = cell.nbands
+    nk = max(1, min(nk, len(cell.kpts)))
+    out = {"workload": f"a=20 bohr, 30 Ry, 72^3, 64 atoms s+p+d (576 proj), {nb} bands, {nk} k-points "
+                       f"solved one after another; residual 2-norm of every band"}
+    forms = {"fp64_1e-8Ry": dict(tol=5e-9), "fp32_1e-6Ry": dict(tol=5e-7, mixed=True),
+             "fp32_then_fp64_1e-8Ry": dict(tol=1e-5, mixed=True, refine=True)}
+    res = {k: {"seconds": 0.0, "iterations": 0, "n_hpsi": 0, "converged": True, "max_residual_Ha": 0.0,
+               "theta": []} for k in forms}
+    for ik in range(nk):
+        p64, miller = build_problem(cell, ik, precision=_lib.PW_FP64, max_bands=nb)
+        p32, _ = build_problem(cell, ik, precision=_lib.PW_MIXED_FP32, max_bands=nb, miller=miller)
+        npw = p64.npw
+        x0 = band_block(nb, npw)
+        x0[:, :npw] = torch.from_numpy(synth.psi_start(cell.seed, nb, npw, ik)).cuda()
+        for name, kw in forms.items():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = _lib.davidson_solve(p32 if kw.get("mixed") else p64, x0, tol=kw["tol"],
+                                    refine=p64 if kw.get("refine") else None, refine_tol=5e-9)
+            torch.cuda.synchronize()
+            o = res[name]
+            o["seconds"] += time.perf_counter() - t0
+            o["iterations"] += r["iterations"]
+            o["n_hpsi"] += r["n_hpsi"]
+            o["converged"] &= bool(r["converged"])
+            o["max_residual_Ha"] = max(o["max_residual_Ha"], float(r["rho"].max()))
+            o["theta"].append(r["theta"])
+        p64.close()
+        p32.close()
+    ref = np.concatenate(res["fp64_1e-8Ry"]["theta"])
+    for name, o in res.items():
+        th = np.concatenate(o.pop("theta"))
+        o["seconds"] = round(o["seconds"], 3)
+        o["max_abs_theta_minus_fp64_Ry"] = float(2.0 * np.abs(th - ref).max())
+        out[name] = o
+    base = res["fp64_1e-8Ry"]["seconds"]
+    out["speedup_over_fp64_at_1e-8Ry"] = round(base / res["fp32_then_fp64_1e-8Ry"]["seconds"], 3)
     return out
 
 
@@ -383,6 +435,29 @@ def main():
             ent["TFLOP/s"] = round(rate(k) / 1e12, 2)
         stage_out[k] = ent
 
+    # the three FFT stages together against both roofs: compulsory HBM bytes of
+    # the stick/plane scheme (sphere in and out, the stick buffer written and
+    # read in each direction, V once) and the nominal 5 m log2 m FFT flops
+    fft_pipe = None
+    if all(k in stages for k in ("zfft_inv", "plane", "zfft_fwd")):
+        sz = 16 if prec == 0 else 8
+        t_fft = sum(stages[k][0] for k in ("zfft_inv", "plane", "zfft_fwd")) * 1e-3
+        b_fft = f_fft = 0.0
+        for inf in infos:
+            n = inf["n"]
+            b_fft += cell.nbands * (32 * inf["npw"] + 4 * inf["nsticks"] * n * sz) + n ** 3 * sz / 2
+            f_fft += cell.nbands * (n * (2 * inf["nx"] + 2 * n) * 5.0 * n * np.log2(n)
+                                    + 2 * inf["nsticks"] * 5.0 * n * np.log2(n) + 2.0 * n ** 3)
+        b_fft *= args.steps
+        f_fft *= args.steps
+        vpk = PEAK_VALU_TFLOPS["f64" if prec == 0 else "f32"]
+        fft_pipe = {"ms_per_kpoint": round(t_fft / (args.steps * len(infos)) * 1e3, 4),
+                    "hbm_GB/s_algorithmic": round(b_fft / t_fft / 1e9, 1),
+                    "hbm_frac": round(b_fft / t_fft / 1e9 / PEAK_HBM_GBS, 4),
+                    "TFLOP/s": round(f_fft / t_fft / 1e12, 2),
+                    "valu_frac": round(f_fft / t_fft / 1e12 / vpk, 4),
+                    "flop_per_byte": round(f_fft / b_fft, 2)}
+
     out = {
         "metric": "band-H*psi/s (plane-wave Hamiltonian applied to a band block)",
         "value": round(value, 1),
@@ -407,6 +482,7 @@ def main():
         },
         "roofline": roof,
         "stages": stage_out,
+        "fft_pipeline": fft_pipe,
         "ms_per_step_profiled": round(dt_prof / args.steps * 1e3, 4),
     }
     dav = None if args.no_davidson else davidson_section(args.davidson_reps)
@@ -424,6 +500,8 @@ def main():
         for k in ("fp64", "fp32_then_fp64"):
             dav[k].pop("_theta", None)
         out["davidson_time_to_1e-8Ry"] = dav
+        if not args.no_davidson_medium:
+            out["davidson_medium_time_to_solution"] = davidson_medium_section(args.davidson_medium_kpoints)
     print(json.dumps(out), flush=True)
 
 

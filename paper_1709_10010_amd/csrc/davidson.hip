@@ -22,10 +22,12 @@
 
 namespace pw {
 int eig_herm(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz, void *rot_ws,
-             double *acc_ws, int *sweeps, int coop_blocks, hipStream_t s);
+             double *acc_ws, int *sweeps, int coop_blocks, hipStream_t s, double off_abs);
+bool eig_transforms_in_place(int m);
 int coop_jacobi_blocks();
 int eig_select(const double *w, int m, int nsel, double *wsel, int *idx, const double2 *Z, int64_t ldz,
-               double2 *Y, int64_t ldy, hipStream_t s);
+               double2 *Y, int64_t ldy, hipStream_t s, const double2 *A, int64_t lda, double2 *H,
+               int64_t ldh);
 int cholesky(const double2 *S, int64_t lds, int n, double2 *L, int64_t ldl, double rel, int *flag,
              hipStream_t s);
 int trinv_h(const double2 *L, int64_t ldl, int n, double2 *X, int64_t ldx, double2 *B, int64_t ldb,
@@ -79,6 +81,7 @@ struct pw_davidson {
   std::vector<int> stall;
   std::vector<uint8_t> tpa_only;
   int *h_bad = nullptr;
+  double off_target = 0.0;  // eigensolver stop level (Frobenius norm of the off-diagonal part)
 };
 
 namespace {
@@ -161,7 +164,7 @@ int ortho_block(pw_davidson *d, int m, double2 *T, int n, double2 *dst, int *n_o
         ProfScope ps(&d->p->prof, PW_STAGE_EIG, s);
         DV_RC(copy_mat(d->S, n, d->Ae, d->lde, n, n, s));
         DV_RC(eig_herm(d->Ae, d->lde, n, d->lam, d->Ze, d->lde, d->rot_ws, d->acc_ws, d->sweeps,
-                       d->coop, s));
+                       d->coop, s, 0.0));
       }
       PW_HIP(hipMemcpyAsync(d->h_lam, d->lam, n * sizeof(double), hipMemcpyDeviceToHost, s));
       PW_HIP(hipStreamSynchronize(s));
@@ -269,6 +272,7 @@ pw_status pw_davidson_init(pw_davidson *d, const void *psi0, int64_t ld, void *s
   d->iter = 0;
   d->n_hpsi = d->nb;
   d->prev_rho.assign(d->nb, INFINITY);
+  d->off_target = 0.0;
   d->stall.assign(d->nb, 0);
   d->tpa_only.assign(d->nb, 0);
   d->inited = true;
@@ -287,13 +291,21 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   const bool set_error_if_empty = true;
   const char *where = "pw_davidson_step: launch failed";
   const int nb = d->nb;
-  // 1. Rayleigh-Ritz: H_s = Z diag(w) Z^H, eigenpairs sorted ascending
+  // 1. Rayleigh-Ritz: Z^H H_s Z = diag(w) + E, eigenpairs sorted ascending.
+  //    Where the eigensolver transforms H_s in place, it stops once the
+  //    off-diagonal part E is below off_target (tied to the residuals of
+  //    the previous step) and Z^H H_s Z, E included, becomes the next H_s,
+  //    so nothing is dropped and the next step continues the diagonalisation.
+  //    The residual test below sees E: R_n has an in-subspace part of norm
+  //    |E e_n|, so convergence still means every Ritz pair is accurate.
+  const bool carry = eig_transforms_in_place(d->m);
   {
     ProfScope ps(&d->p->prof, PW_STAGE_EIG, s);
     DV_RC(copy_mat(d->Hs, d->lde, d->Ae, d->lde, d->m, d->m, s));
     DV_RC(eig_herm(d->Ae, d->lde, d->m, d->w_all, d->Ze, d->lde, d->rot_ws, d->acc_ws, d->sweeps,
-                   d->coop, s));
-    DV_RC(eig_select(d->w_all, d->m, d->m, d->w_sorted, d->idx_all, d->Ze, d->lde, d->Ae, d->lde, s));
+                   d->coop, s, carry ? d->off_target : 0.0));
+    DV_RC(eig_select(d->w_all, d->m, d->m, d->w_sorted, d->idx_all, d->Ze, d->lde, d->Ae, d->lde, s,
+                     carry ? d->Ae : nullptr, d->lde, d->Hs, d->lde));
   }
   // 2. rotate the whole space into the Ritz basis (V <- V Z, W <- W Z): the
   //    first nb columns are the Ritz vectors, H_s becomes diag(w), and the
@@ -302,7 +314,7 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   DV_RC(nn(d, d->m, d->m, 1.0, d->W, d->Ae, d->lde, 0.0, d->Wt, s));
   std::swap(d->V, d->Vt);
   std::swap(d->W, d->Wt);
-  DV_RC(set_diag(d->Hs, d->lde, d->m, d->w_sorted, s));
+  if (!carry) DV_RC(set_diag(d->Hs, d->lde, d->m, d->w_sorted, s));
   PW_HIP(hipMemcpyAsync(d->theta, d->w_sorted, nb * sizeof(double), hipMemcpyDeviceToDevice, s));
   PW_HIP(hipMemcpyAsync(d->X, d->V, (size_t)nb * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
   PW_HIP(hipMemcpyAsync(d->HX, d->W, (size_t)nb * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
@@ -321,13 +333,20 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
       return PW_ERR_NOT_FINITE;
     }
   int nu = 0;
+  double rho_min = INFINITY;
   for (int n = 0; n < nb; ++n) {
-    if (d->h_rho[n] >= d->tol) d->h_U[nu++] = n;
+    if (d->h_rho[n] >= d->tol) {
+      d->h_U[nu++] = n;
+      rho_min = std::min(rho_min, d->h_rho[n]);
+    }
     d->stall[n] = (d->h_rho[n] >= d->prev_rho[n]) ? d->stall[n] + 1 : 0;
     if (d->stall[n] >= 2) d->tpa_only[n] = 1;
     d->prev_rho[n] = d->h_rho[n];
   }
   d->converged = (nu == 0);
+  // next step's eigensolver target: a tenth of the smallest residual still
+  // to converge (never below a tenth of the tolerance)
+  d->off_target = 0.1 * std::max(d->tol, nu ? rho_min : d->tol);
   if (converged) *converged = d->converged ? 1 : 0;
   if (d->converged) return PW_OK;
   PW_HIP(hipMemcpyAsync(d->dU, d->h_U, nu * sizeof(int), hipMemcpyHostToDevice, s));

@@ -73,6 +73,36 @@ __device__ __forceinline__ Rot make_rot(double alpha, double gamma, double2 beta
   return r;
 }
 
+// The same rotation from the hardware reciprocal and reciprocal square root,
+// each refined by one Newton step (a few ulps instead of correct rounding):
+// a shorter dependency chain for solves that stop at a target well above
+// the rounding level.  The threshold test is done on squares.
+__device__ __forceinline__ double rsq_nr(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  return y * fma(-0.5 * x * y, y, 1.5);
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  return y * fma(-x, y, 2.0);
+}
+__device__ __forceinline__ Rot make_rot_fast(double alpha, double gamma, double2 beta) {
+  Rot r{1.0, 0.0, 1.0, 0.0};
+  const double ab2 = beta.x * beta.x + beta.y * beta.y;
+  if (!(ab2 > 1e-300) || ab2 <= 1e-32 * fabs(alpha * gamma)) return r;
+  const double rab = rsq_nr(ab2);
+  const double tau = 0.5 * (gamma - alpha) * rab;
+  const double at = fabs(tau);
+  // |tau| + sqrt(1 + tau^2), without overflow for huge |tau|
+  const double den = at < 1e150 ? at + (1.0 + tau * tau) * rsq_nr(1.0 + tau * tau) : 2.0 * at;
+  const double t = (tau >= 0.0 ? 1.0 : -1.0) * rcp_nr(den);
+  const double c = rsq_nr(1.0 + t * t);
+  r.c = c;
+  r.s = t * c;
+  r.er = beta.x * rab;
+  r.ei = -beta.y * rab;
+  return r;
+}
+
 // J entries: j11 = c, j12 = s, j21 = -s e, j22 = c e.
 __device__ __forceinline__ void rot_entries(const Rot &r, double2 &j11, double2 &j12, double2 &j21,
                                             double2 &j22) {
@@ -319,17 +349,41 @@ __device__ __forceinline__ int bj_global(int p, int r, int nblk, int i) {
   return i < kBJ ? bj_index(I, i) : bj_index(J, i - kBJ);
 }
 
-__global__ __launch_bounds__(256) void k_bj_inner(const double2 *__restrict__ A, int64_t lda, int nblk,
-                                                  int r, double2 *__restrict__ U, int max_sweeps) {
+// Sum over the 1024 threads of a block (16 waves): wave reduction, then the
+// partial sums through LDS; every thread gets the total.
+__device__ __forceinline__ double block_sum1024(double v, double *part) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) t += part[w];
+  __syncthreads();
+  return t;
+}
+
+// One pair of blocks: the 2kBJ x 2kBJ Hermitian sub-matrix diagonalised in
+// LDS by round-robin sweeps, 1024 threads.  A round has two phases: the 16
+// rotations (one lane each), then the 256 2x2 block updates (threads
+// 0..255) beside the 512 row updates of the accumulated rotation (threads
+// 256..767), each item owned by one thread.
+// A pair whose off-diagonal mass is at most skip2 (or at the rounding level)
+// is left alone: rotated[p] = 0 and its U is not written; k_bj_apply then
+// skips every block whose transforms are all identities.
+static_assert(kSub == 32, "the thread layout of k_bj_inner assumes 16 x 16 blocks of 2 x 2");
+template <bool FAST>
+__global__ __launch_bounds__(1024) void k_bj_inner(const double2 *__restrict__ A, int64_t lda, int nblk,
+                                                   int r, double2 *__restrict__ U, int max_sweeps,
+                                                   double skip2, int *__restrict__ rotated) {
   __shared__ double2 S[kSub][kSub + 1];
   __shared__ double2 Q[kSub][kSub + 1];
   __shared__ Rot rot[kSub / 2];
-  __shared__ double red[256];
-  __shared__ int done;
+  __shared__ double part[16];
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
-  for (int e = tid; e < kSub * kSub; e += 256) {
-    const int i = e % kSub, j = e / kSub;
+  {
+    const int i = tid % kSub, j = tid / kSub;
     S[i][j] = A[bj_global(p, r, nblk, i) + (int64_t)bj_global(p, r, nblk, j) * lda];
     Q[i][j] = double2{i == j ? 1.0 : 0.0, 0.0};
   }
@@ -337,38 +391,31 @@ __global__ __launch_bounds__(256) void k_bj_inner(const double2 *__restrict__ A,
   constexpr int np = kSub / 2;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     double off = 0.0, tot = 0.0;
-    for (int e = tid; e < kSub * kSub; e += 256) {
-      const int i = e % kSub, j = e / kSub;
-      const double v = S[i][j].x * S[i][j].x + S[i][j].y * S[i][j].y;
-      tot += v;
-      if (i != j) off += v;
+    {
+      const int i = tid % kSub, j = tid / kSub;
+      const double2 v = S[i][j];
+      const double v2 = v.x * v.x + v.y * v.y;
+      tot = v2;
+      off = (i != j) ? v2 : 0.0;
     }
-    red[tid] = off;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
+    off = block_sum1024(off, part);
+    tot = block_sum1024(tot, part);
+    const bool conv = off <= kOffRel * (double)kSub * tot;
+    if (sweep == 0) {
+      const bool skip = conv || off <= skip2;
+      if (tid == 0) rotated[p] = skip ? 0 : 1;
+      if (skip) return;  // identity: U is not needed
     }
-    const double offs = red[0];
-    __syncthreads();
-    red[tid] = tot;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    if (tid == 0) done = (offs <= kOffRel * (double)kSub * red[0]) ? 1 : 0;
-    __syncthreads();
-    if (done) break;
+    if (conv) break;
     for (int rr = 0; rr < kSub - 1; ++rr) {
       if (tid < np) {
         int a, b;
         pair_of(tid, rr, kSub, &a, &b);
-        rot[tid] = make_rot(S[a][a].x, S[b][b].x, S[a][b]);
+        rot[tid] = FAST ? make_rot_fast(S[a][a].x, S[b][b].x, S[a][b]) : make_rot(S[a][a].x, S[b][b].x, S[a][b]);
       }
       __syncthreads();
-      for (int e = tid; e < np * np; e += 256) {
-        const int ka = e % np, kb = e / np;
+      if (tid < np * np) {
+        const int ka = tid % np, kb = tid / np;
         int pa, qa, pb, qb;
         pair_of(ka, rr, kSub, &pa, &qa);
         pair_of(kb, rr, kSub, &pb, &qb);
@@ -378,8 +425,8 @@ __global__ __launch_bounds__(256) void k_bj_inner(const double2 *__restrict__ A,
         S[pa][qb] = b;
         S[qa][pb] = c;
         S[qa][qb] = d;
-      }
-      for (int e = tid; e < kSub * np; e += 256) {
+      } else if (tid < np * np + kSub * np) {
+        const int e = tid - np * np;
         const int i = e % kSub, kb = e / kSub;
         int pb, qb;
         pair_of(kb, rr, kSub, &pb, &qb);
@@ -389,8 +436,8 @@ __global__ __launch_bounds__(256) void k_bj_inner(const double2 *__restrict__ A,
     }
   }
   double2 *Up = U + (int64_t)p * kSub * kSub;
-  for (int e = tid; e < kSub * kSub; e += 256) {
-    const int i = e % kSub, j = e / kSub;
+  {
+    const int i = tid % kSub, j = tid / kSub;
     Up[i + j * kSub] = Q[i][j];
   }
 }
@@ -399,19 +446,24 @@ __global__ __launch_bounds__(256) void k_bj_inner(const double2 *__restrict__ A,
 // 2kBJ*P .. +2kBJ, columns of pair Q)
 __global__ __launch_bounds__(256) void k_bj_apply(double2 *__restrict__ A, int64_t lda,
                                                   double2 *__restrict__ Z, int64_t ldz, int nblk, int r,
-                                                  const double2 *__restrict__ U) {
+                                                  const double2 *__restrict__ U,
+                                                  const int *__restrict__ rotated) {
   __shared__ double2 X[kSub][kSub + 1];
   __shared__ double2 UQ[kSub][kSub + 1];
   __shared__ double2 UP[kSub][kSub + 1];
   const int P = blockIdx.x, Qp = blockIdx.y;
   const bool isZ = blockIdx.z == 1;
+  // identity transforms leave the block as it is
+  if (isZ ? !rotated[Qp] : (!rotated[Qp] && !rotated[P])) return;
   const int tid = threadIdx.x;
   const double2 *uq = U + (int64_t)Qp * kSub * kSub;
   const double2 *up = U + (int64_t)P * kSub * kSub;
+  const bool rq = rotated[Qp], rp = rotated[P];
   for (int e = tid; e < kSub * kSub; e += 256) {
     const int i = e % kSub, j = e / kSub;
-    UQ[i][j] = uq[i + j * kSub];
-    if (!isZ) UP[i][j] = up[i + j * kSub];
+    const double2 id = double2{i == j ? 1.0 : 0.0, 0.0};
+    UQ[i][j] = rq ? uq[i + j * kSub] : id;
+    if (!isZ) UP[i][j] = rp ? up[i + j * kSub] : id;
     const int col = bj_global(Qp, r, nblk, j);
     const int64_t row = isZ ? (int64_t)P * kSub + i : bj_global(P, r, nblk, i);
     X[i][j] = isZ ? Z[row + (int64_t)col * ldz] : A[row + (int64_t)col * lda];
@@ -532,6 +584,18 @@ __global__ void k_gather_cols(const double2 *__restrict__ Z, int64_t ldz, const 
   }
 }
 
+// H[r + r' ldh] = A[idx[r] + idx[r'] lda] for r, r' < m: the transformed
+// matrix in the order of the selected eigenvalues.
+__global__ void k_perm_sym(const double2 *__restrict__ A, int64_t lda, const int *__restrict__ idx, int m,
+                           double2 *__restrict__ H, int64_t ldh) {
+  const int64_t tot = (int64_t)m * m;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % m), c = (int)(e / m);
+    H[r + c * ldh] = A[idx[r] + (int64_t)idx[c] * lda];
+  }
+}
+
 // ---------------------------------------------------------------- Cholesky
 // S (lds) Hermitian positive n x n -> L lower (ldl, upper part zeroed).
 // flag[0] = first column whose pivot fell to <= rel * S_jj (or was not
@@ -577,6 +641,163 @@ __global__ __launch_bounds__(1024) void k_cholesky(const double2 *__restrict__ S
     __syncthreads();
   }
   if (tid == 0) *flag = bad;
+}
+
+// Blocked Cholesky in one workgroup (n <= kCholMaxN): right-looking over
+// panels of kCholPB columns.  The panel (all rows below its top) is factored
+// in LDS column by column; the trailing lower triangle is then updated from
+// global memory with the panel's outer product.  Breakdown rule as in
+// k_cholesky (pivot <= rel * S_jj or not finite: flag = column + 1, pivot 1).
+constexpr int kCholPB = 16;
+constexpr int kCholMaxN = 512;
+__global__ __launch_bounds__(1024) void k_cholesky_blk(const double2 *__restrict__ S, int64_t lds, int n,
+                                                       double2 *__restrict__ L, int64_t ldl, double rel,
+                                                       int *__restrict__ flag) {
+  extern __shared__ __align__(16) unsigned char smem_c[];
+  double2 *P = reinterpret_cast<double2 *>(smem_c);  // [n][kCholPB + 1]
+  constexpr int PS = kCholPB + 1;
+  __shared__ double inv_piv;
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int64_t e = tid; e < (int64_t)n * n; e += 1024) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    L[i + j * ldl] = (i >= j) ? S[i + j * lds] : double2{0.0, 0.0};
+  }
+  __syncthreads();
+  for (int j0 = 0; j0 < n; j0 += kCholPB) {
+    const int jb = min(kCholPB, n - j0), nr = n - j0;
+    for (int e = tid; e < nr * jb; e += 1024) {
+      const int r = e % nr, c = e / nr;
+      P[r * PS + c] = L[(j0 + r) + (int64_t)(j0 + c) * ldl];
+    }
+    __syncthreads();
+    for (int c = 0; c < jb; ++c) {
+      if (tid == 0) {
+        double d = P[c * PS + c].x;
+        const double s0 = S[(j0 + c) + (int64_t)(j0 + c) * lds].x;
+        if (!(d > rel * s0) || !isfinite(d)) {
+          if (!bad) bad = j0 + c + 1;
+          d = 1.0;
+        }
+        const double piv = sqrt(d);
+        P[c * PS + c] = double2{piv, 0.0};
+        inv_piv = 1.0 / piv;
+      }
+      __syncthreads();
+      const double iv = inv_piv;
+      for (int r = c + 1 + tid; r < nr; r += 1024) {
+        const double2 v = P[r * PS + c];
+        P[r * PS + c] = double2{v.x * iv, v.y * iv};
+      }
+      __syncthreads();
+      const int w = jb - c - 1;
+      if (w > 0) {
+        const int rows = nr - c - 1;
+        for (int e = tid; e < rows * w; e += 1024) {
+          const int r = c + 1 + e % rows, c2 = c + 1 + e / rows;
+          if (r < c2) continue;
+          const double2 a = P[r * PS + c], b = P[c2 * PS + c];  // a * conj(b)
+          double2 t = P[r * PS + c2];
+          t.x -= a.x * b.x + a.y * b.y;
+          t.y -= a.y * b.x - a.x * b.y;
+          P[r * PS + c2] = t;
+        }
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < nr * jb; e += 1024) {
+      const int r = e % nr, c = e / nr;
+      L[(j0 + r) + (int64_t)(j0 + c) * ldl] = (r >= c) ? P[r * PS + c] : double2{0.0, 0.0};
+    }
+    const int nt = nr - jb;
+    for (int64_t e = tid; e < (int64_t)nt * nt; e += 1024) {
+      const int i = (int)(e % nt), k = (int)(e / nt);
+      if (i < k) continue;
+      double2 acc = L[(j0 + jb + i) + (int64_t)(j0 + jb + k) * ldl];
+      const double2 *pi = P + (jb + i) * PS, *pk = P + (jb + k) * PS;
+      for (int c = 0; c < jb; ++c) {
+        const double2 a = pi[c], b = pk[c];
+        acc.x -= a.x * b.x + a.y * b.y;
+        acc.y -= a.y * b.x - a.x * b.y;
+      }
+      L[(j0 + jb + i) + (int64_t)(j0 + jb + k) * ldl] = acc;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *flag = bad;
+}
+
+// Blocked inverse of a lower-triangular L in one workgroup, then
+// B = (L^{-1})^H.  X = L^{-1} by blocks of kTriBS: diagonal blocks by
+// forward substitution (one thread per column), then block diagonals
+// d = 1, 2, ...: X_IJ = -X_II sum_{K=J..I-1} L_IK X_KJ, with the pairs of
+// one diagonal independent (four at a time, one thread per element).
+constexpr int kTriBS = 16;
+__global__ __launch_bounds__(1024) void k_trinv_blk(const double2 *__restrict__ L, int64_t ldl, int n,
+                                                    double2 *__restrict__ X, int64_t ldx,
+                                                    double2 *__restrict__ B, int64_t ldb) {
+  constexpr int BS = kTriBS;
+  __shared__ double2 T[4][BS][BS + 1];
+  const int tid = threadIdx.x;
+  const int nbk = (n + BS - 1) / BS;
+  for (int64_t e = tid; e < (int64_t)n * n; e += 1024) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    if (i < j) X[i + (int64_t)j * ldx] = double2{0.0, 0.0};
+  }
+  // diagonal blocks
+  for (int t = tid; t < nbk * BS; t += 1024) {
+    const int I = t / BS, c = I * BS + t % BS;
+    if (c >= n) continue;
+    const int hi = min(n, (I + 1) * BS);
+    for (int i = c; i < hi; ++i) {
+      double2 acc = double2{i == c ? 1.0 : 0.0, 0.0};
+      for (int k = c; k < i; ++k) {
+        const double2 a = L[i + (int64_t)k * ldl], x = X[k + (int64_t)c * ldx];
+        acc.x -= a.x * x.x - a.y * x.y;
+        acc.y -= a.x * x.y + a.y * x.x;
+      }
+      const double dinv = 1.0 / L[i + (int64_t)i * ldl].x;
+      X[i + (int64_t)c * ldx] = double2{acc.x * dinv, acc.y * dinv};
+    }
+  }
+  __syncthreads();
+  const int g = tid >> 8, el = tid & 255, ei = el % BS, ej = el / BS;
+  for (int d = 1; d < nbk; ++d) {
+    const int npair = nbk - d;
+    for (int p0 = 0; p0 < npair; p0 += 4) {
+      const int J = p0 + g, I = J + d;
+      const bool act = (p0 + g) < npair;
+      const int i = I * BS + ei, j = J * BS + ej;
+      if (act) {
+        double2 acc = double2{0.0, 0.0};
+        if (i < n && j < n) {
+          for (int k = J * BS; k < I * BS; ++k) {
+            const double2 a = L[i + (int64_t)k * ldl], x = X[k + (int64_t)j * ldx];
+            acc.x += a.x * x.x - a.y * x.y;
+            acc.y += a.x * x.y + a.y * x.x;
+          }
+        }
+        T[g][ei][ej] = acc;
+      }
+      __syncthreads();
+      if (act && i < n && j < n) {
+        double2 acc = double2{0.0, 0.0};
+        for (int k = 0; k <= ei; ++k) {
+          const double2 a = X[(I * BS + ei) + (int64_t)(I * BS + k) * ldx], t = T[g][k][ej];
+          acc.x -= a.x * t.x - a.y * t.y;
+          acc.y -= a.x * t.y + a.y * t.x;
+        }
+        X[i + (int64_t)j * ldx] = acc;
+      }
+      __syncthreads();
+    }
+  }
+  for (int64_t e = tid; e < (int64_t)n * n; e += 1024) {
+    const int i = (int)(e % n), c = (int)(e / n);
+    const double2 x = X[i + (int64_t)c * ldx];
+    B[c + (int64_t)i * ldb] = (i >= c) ? double2{x.x, -x.y} : double2{0.0, 0.0};
+  }
 }
 
 // B = (L^{-1})^H (upper triangular, ldb): column c of X = L^{-1} e_c by
@@ -728,7 +949,7 @@ static int eig_impl() {
 // per-pair unitaries (mpb/kBJ/2 * (2 kBJ)^2 complex); acc >= 2 doubles.  One
 // host sync per sweep reads the off-diagonal mass.
 static int eig_block(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz, void *uws,
-                     double *acc, hipStream_t s) {
+                     double *acc, hipStream_t s, double off_abs) {
   const int mpb = (m + kSub - 1) / kSub * kSub;
   const int nblk = mpb / kBJ;
   const int npair = nblk / 2;
@@ -736,6 +957,9 @@ static int eig_block(double2 *A, int64_t lda, int m, double *w, double2 *Z, int6
   if (!h_acc && hipHostMalloc((void **)&h_acc, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return PW_ERR_NOMEM;
   double2 *U = static_cast<double2 *>(uws);
+  int *rotated = reinterpret_cast<int *>(U + (int64_t)npair * kSub * kSub);
+  // a pair below this mass is skipped: all of them together stay below the target
+  const double skip2 = off_abs * off_abs / (double)std::max(1, nblk * (nblk - 1) / 2);
   // inner sweeps per pair solve: the outer iteration converges with partial
   // inner diagonalisation, and a pair problem is the cost of a round
   static int inner = -1;
@@ -752,10 +976,18 @@ static int eig_block(double2 *A, int64_t lda, int m, double *w, double2 *Z, int6
     if (hipMemcpyAsync(h_acc, acc, 2 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return PW_ERR_HIP;
-    if (!(h_acc[0] > kOffRel * (double)mpb * h_acc[1])) break;  // converged (or NaN)
+    // converged to the rounding level, or to the caller's target (or NaN)
+    if (!(h_acc[0] > std::max(kOffRel * (double)mpb * h_acc[1], off_abs * off_abs))) break;
     for (int r = 0; r < nblk - 1; ++r) {
-      hipLaunchKernelGGL(k_bj_inner, dim3(npair), dim3(256), 0, s, A, lda, nblk, r, U, inner);
-      hipLaunchKernelGGL(k_bj_apply, dim3(npair, npair, 2), dim3(256), 0, s, A, lda, Z, ldz, nblk, r, U);
+      // a target far above the rounding level allows the short-chain rotations
+      if (off_abs > 0.0)
+        hipLaunchKernelGGL(k_bj_inner<true>, dim3(npair), dim3(1024), 0, s, A, lda, nblk, r, U, inner,
+                           skip2, rotated);
+      else
+        hipLaunchKernelGGL(k_bj_inner<false>, dim3(npair), dim3(1024), 0, s, A, lda, nblk, r, U, inner,
+                           skip2, rotated);
+      hipLaunchKernelGGL(k_bj_apply, dim3(npair, npair, 2), dim3(256), 0, s, A, lda, Z, ldz, nblk, r, U,
+                         rotated);
     }
     if (hipGetLastError() != hipSuccess) return PW_ERR_HIP;
   }
@@ -764,15 +996,17 @@ static int eig_block(double2 *A, int64_t lda, int m, double *w, double2 *Z, int6
 }
 
 // rot_ws: second matrix buffer of the same shape as A (lda x lda).
+bool eig_transforms_in_place(int m) { return ((m + 1) & ~1) > 64 && eig_impl() == 0; }
+
 int eig_herm(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz, void *rot_ws,
-             double *acc_ws, int *sweeps, int coop_blocks, hipStream_t s) {
+             double *acc_ws, int *sweeps, int coop_blocks, hipStream_t s, double off_abs) {
   if (m <= 0) return PW_OK;
   const int mp = (m + 1) & ~1;
   if (mp <= 64) {
     hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(256), 0, s, A, lda, m, w, Z, ldz, sweeps);
     return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
   }
-  if (eig_impl() == 0) return eig_block(A, lda, m, w, Z, ldz, rot_ws, acc_ws, s);
+  if (eig_impl() == 0) return eig_block(A, lda, m, w, Z, ldz, rot_ws, acc_ws, s, off_abs);
   double2 *B = static_cast<double2 *>(rot_ws);
   void *args[] = {&A, &B, &lda, &m, &w, &Z, &ldz, &acc_ws, &sweeps};
   // about 8 block updates per thread: fewer workgroups make each grid barrier cheaper
@@ -803,23 +1037,56 @@ int coop_jacobi_blocks() {
 }
 
 int eig_select(const double *w, int m, int nsel, double *wsel, int *idx, const double2 *Z, int64_t ldz,
-               double2 *Y, int64_t ldy, hipStream_t s) {
+               double2 *Y, int64_t ldy, hipStream_t s, const double2 *A, int64_t lda, double2 *H,
+               int64_t ldh) {
   hipLaunchKernelGGL(k_eig_rank, dim3((m + 255) / 256), dim3(256), 0, s, w, m, nsel, wsel, idx);
   if (hipGetLastError() != hipSuccess) return PW_ERR_HIP;
+  if (A && nsel == m) {
+    hipLaunchKernelGGL(k_perm_sym, dim3(grid_for((int64_t)m * m)), dim3(256), 0, s, A, lda, idx, m, H, ldh);
+    if (hipGetLastError() != hipSuccess) return PW_ERR_HIP;
+  }
   hipLaunchKernelGGL(k_gather_cols, dim3(grid_for((int64_t)m * nsel)), dim3(256), 0, s, Z, ldz, idx, m,
                      nsel, Y, ldy);
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
 
+// PW_CHOL_IMPL=1 keeps the unblocked kernels (reference for the blocked ones)
+static int chol_impl() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = std::getenv("PW_CHOL_IMPL");
+    v = (e && *e) ? std::atoi(e) : 0;
+  }
+  return v;
+}
+
 int cholesky(const double2 *S, int64_t lds, int n, double2 *L, int64_t ldl, double rel, int *flag,
              hipStream_t s) {
-  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, S, lds, n, L, ldl, rel, flag);
+  if (n <= 0) return PW_OK;
+  if (chol_impl() == 0 && n <= kCholMaxN) {
+    const size_t lds_bytes = sizeof(double2) * (size_t)n * (kCholPB + 1);
+    static bool attr = false;
+    if (!attr) {
+      if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_cholesky_blk),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(double2) * kCholMaxN * (kCholPB + 1))) != hipSuccess)
+        return PW_ERR_HIP;
+      attr = true;
+    }
+    hipLaunchKernelGGL(k_cholesky_blk, dim3(1), dim3(1024), lds_bytes, s, S, lds, n, L, ldl, rel, flag);
+  } else {
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, S, lds, n, L, ldl, rel, flag);
+  }
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
 
 int trinv_h(const double2 *L, int64_t ldl, int n, double2 *X, int64_t ldx, double2 *B, int64_t ldb,
             hipStream_t s) {
-  hipLaunchKernelGGL(k_trinv_h, dim3((n + 63) / 64), dim3(64), 0, s, L, ldl, n, X, ldx, B, ldb);
+  if (n <= 0) return PW_OK;
+  if (chol_impl() == 0)
+    hipLaunchKernelGGL(k_trinv_blk, dim3(1), dim3(1024), 0, s, L, ldl, n, X, ldx, B, ldb);
+  else
+    hipLaunchKernelGGL(k_trinv_h, dim3((n + 63) / 64), dim3(64), 0, s, L, ldl, n, X, ldx, B, ldb);
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
 
@@ -891,9 +1158,9 @@ pw_status pw_eigh(const void *A, int64_t lda, int32_t m, double *w, void *Z, int
   double *acc = wu + mp;
   int *idx = reinterpret_cast<int *>(acc + 2 * kMaxSweeps + 2);
   int rc = copy_mat(static_cast<const double2 *>(A), lda, Ac, mp, m, m, s);
-  if (rc == PW_OK) rc = eig_herm(Ac, mp, m, wu, Zw, mp, Bw, acc, nullptr, coop, s);
+  if (rc == PW_OK) rc = eig_herm(Ac, mp, m, wu, Zw, mp, Bw, acc, nullptr, coop, s, 0.0);
   if (rc == PW_OK)
-    rc = eig_select(wu, m, m, w, idx, Zw, mp, static_cast<double2 *>(Z), ldz, s);
+    rc = eig_select(wu, m, m, w, idx, Zw, mp, static_cast<double2 *>(Z), ldz, s, nullptr, 0, nullptr, 0);
   if (rc != PW_OK) set_error("pw_eigh: launch failed");
   return rc;
 }
