@@ -132,7 +132,7 @@ pw_status pw_problem_autotune(pw_problem *p, int64_t nbands, int32_t reps, void 
   const int64_t chunk0 = p->band_chunk;
   const int groups[] = {1, 2, 4, 8, 16};
   const int64_t chunks[] = {chunk0, 128, 64, 32};
-  const int splits[] = {0, 4, 8, 16, 32};
+  const int splits[] = {0, 4, 8, 12, 14, 16, 24, 28, 32};
   // the register plane kernel only where it has an instance for the grid
   std::vector<int> kernels{PW_PLANE_LDS};
   if (plane_register_ok(p->fft, p->precision)) kernels.insert(kernels.begin(), PW_PLANE_REGISTER);

@@ -60,58 +60,69 @@ template <typename S2> __device__ __forceinline__ S2 cvt2(float2 v);
 template <> __device__ __forceinline__ float2 cvt2<float2>(float2 v) { return v; }
 template <> __device__ __forceinline__ double2 cvt2<double2>(float2 v) { return double2{v.x, v.y}; }
 
+// LDS tiles are [k][mn] with a padded row: with 16-byte elements a stride
+// of 2 (mod 8) elements, with 8-byte elements 4 (mod 16), spreads the rows a
+// group of lanes touches at once over distinct banks, for the stores below
+// (consecutive lanes: consecutive k of one column, then the next column)
+// and for the MFMA operand reads (consecutive lanes: consecutive mn).
+template <typename S2> struct Lds {
+  static constexpr int stride = GB_M + (sizeof(S2) == 16 ? 2 : 4);
+};
+template <typename S2> using LdsTile = S2[GB_K][Lds<S2>::stride];
+
 // Load a 16(k) x 64(mn) tile of a K-contiguous column-major matrix
 // (element (k, c) at P[c * ld + k]) into registers: thread t covers column
-// t/4 and k = 4*(t%4) .. +3.
+// t/4 and k = t%4 + 4u, u = 0..3 (the four lanes of a column read 16
+// consecutive k together).
 template <typename T, typename S2>
 __device__ __forceinline__ void load_kcontig(const T *__restrict__ P, int64_t ld, int64_t k0,
                                              int64_t c0, int64_t K, int64_t C, S2 r[4]) {
   const int t = threadIdx.x;
   const int64_t c = c0 + (t >> 2);
-  const int64_t k = k0 + ((t & 3) << 2);
+  const int64_t k = k0 + (t & 3);
   if (c < C) {
     const T *p = P + c * ld + k;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) r[u] = (k + u < K) ? cvt2<S2>(p[u]) : S2{0, 0};
+    for (int u = 0; u < 4; ++u) r[u] = (k + 4 * u < K) ? cvt2<S2>(p[4 * u]) : S2{0, 0};
   } else {
 #pragma unroll
     for (int u = 0; u < 4; ++u) r[u] = S2{0, 0};
   }
 }
 template <typename S2>
-__device__ __forceinline__ void store_kcontig(S2 (*S)[GB_M + 1], const S2 r[4]) {
+__device__ __forceinline__ void store_kcontig(LdsTile<S2> &S, const S2 r[4]) {
   const int t = threadIdx.x;
   const int c = t >> 2;
-  const int k = (t & 3) << 2;
+  const int k = t & 3;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) S[k + u][c] = r[u];
+  for (int u = 0; u < 4; ++u) S[k + 4 * u][c] = r[u];
 }
 
 // Load a 64(m) x 16(k) tile of an M-contiguous column-major matrix
 // (element (m, k) at P[k * ld + m]): thread t covers k = t/16 and
-// m = 4*(t%16) .. +3.
+// m = t%16 + 16u, u = 0..3.
 template <typename T, typename S2>
 __device__ __forceinline__ void load_mcontig(const T *__restrict__ P, int64_t ld, int64_t m0,
                                              int64_t k0, int64_t M, int64_t K, S2 r[4]) {
   const int t = threadIdx.x;
   const int64_t k = k0 + (t >> 4);
-  const int64_t m = m0 + ((t & 15) << 2);
+  const int64_t m = m0 + (t & 15);
   if (k < K) {
     const T *p = P + k * ld + m;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) r[u] = (m + u < M) ? cvt2<S2>(p[u]) : S2{0, 0};
+    for (int u = 0; u < 4; ++u) r[u] = (m + 16 * u < M) ? cvt2<S2>(p[16 * u]) : S2{0, 0};
   } else {
 #pragma unroll
     for (int u = 0; u < 4; ++u) r[u] = S2{0, 0};
   }
 }
 template <typename S2>
-__device__ __forceinline__ void store_mcontig(S2 (*S)[GB_M + 1], const S2 r[4]) {
+__device__ __forceinline__ void store_mcontig(LdsTile<S2> &S, const S2 r[4]) {
   const int t = threadIdx.x;
   const int k = t >> 4;
-  const int m = (t & 15) << 2;
+  const int m = t & 15;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) S[k][m + u] = r[u];
+  for (int u = 0; u < 4; ++u) S[k][m + 16 * u] = r[u];
 }
 
 template <typename MF> struct Acc {
@@ -120,9 +131,9 @@ template <typename MF> struct Acc {
 
 // One LDS stage: As[k][m], Bs[k][n], 16 complex k.
 template <typename MF>
-__device__ __forceinline__ void mma_stage(const typename MF::S2 (*As)[GB_M + 1],
-                                          const typename MF::S2 (*Bs)[GB_M + 1], Acc<MF> &acc,
-                                          int wm, int wn) {
+__device__ __forceinline__ void mma_stage(const LdsTile<typename MF::S2> &As,
+                                          const LdsTile<typename MF::S2> &Bs, Acc<MF> &acc, int wm,
+                                          int wn) {
   const int lane = threadIdx.x & 63;
   const int lr = lane & 15;
   const int lk = lane >> 4;
@@ -184,8 +195,8 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_cn(int64_t M, int64_t N, int
                                                        double2 *__restrict__ C, int64_t ldc,
                                                        int64_t kchunk, int direct) {
   using S2 = typename MF::S2;
-  __shared__ S2 As[GB_K][GB_M + 1];
-  __shared__ S2 Bs[GB_K][GB_M + 1];
+  __shared__ LdsTile<S2> As;
+  __shared__ LdsTile<S2> Bs;
   const int64_t m0 = (int64_t)blockIdx.x * GB_M;
   const int64_t n0 = (int64_t)blockIdx.y * GB_N;
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
@@ -242,8 +253,8 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_nn(int64_t M, int64_t N, int
                                                        double beta, double2 *__restrict__ C,
                                                        int64_t ldc) {
   using S2 = typename MF::S2;
-  __shared__ S2 As[GB_K][GB_M + 1];
-  __shared__ S2 Bs[GB_K][GB_M + 1];
+  __shared__ LdsTile<S2> As;
+  __shared__ LdsTile<S2> Bs;
   const int64_t m0 = (int64_t)blockIdx.x * GB_M;
   const int64_t n0 = (int64_t)blockIdx.y * GB_N;
   const int wave = threadIdx.x >> 6;
@@ -534,8 +545,9 @@ int convert_beta(const void *src, void *dst, int64_t n, int prec, hipStream_t s)
 
 int choose_splits(int64_t M, int64_t N, int64_t K) {
   const int64_t tiles = ((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N);
-  // aim for >= 2 workgroups per CU on 256 CUs, each with >= 32 K stages
-  int64_t s = (512 + tiles - 1) / tiles;
+  // fill the 2 x 256 workgroup slots once, without a nearly empty second
+  // round (rounding down), each workgroup with >= 32 K stages
+  int64_t s = 512 / tiles;
   const int64_t maxs = (K + 32 * GB_K - 1) / (32 * GB_K);
   if (s > maxs) s = maxs;
   if (s > 64) s = 64;
