@@ -283,6 +283,15 @@ pw_status pw_problem_autotune(pw_problem *p, int64_t nbands, int32_t reps, void 
                               double *best_ms);
 pw_status pw_problem_tuning(const pw_problem *p, int32_t *plane_group, int64_t *band_chunk,
                             int32_t *ksplit, int32_t *plane_kernel);
+/*
+ * Sets the launch choices (e.g. saved from an earlier autotune):
+ * plane_group >= 1; 1 <= band_chunk <= the sweep height chosen at create
+ * (the stick buffer's size); 0 <= ksplit <= 64 (0: automatic); plane_kernel
+ * one of PW_PLANE_* (PW_PLANE_REGISTER falls back to PW_PLANE_LDS on grids
+ * without a register instance).  PW_ERR_INVALID leaves the handle unchanged.
+ */
+pw_status pw_problem_set_tuning(pw_problem *p, int32_t plane_group, int64_t band_chunk, int32_t ksplit,
+                                int32_t plane_kernel);
 
 /*
  * Learned diagonal preconditioner (FP32 network 4 -> 64 -> 64 -> 1, SiLU,

@@ -103,6 +103,7 @@ def _load():
         "pw_batch_launch": (i32, [vp, vp]),
         "pw_problem_autotune": (i32, [vp, i64, i32, vp, C.POINTER(f64)]),
         "pw_problem_tuning": (i32, [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32), C.POINTER(i32)]),
+        "pw_problem_set_tuning": (i32, [vp, i32, i64, i32, i32]),
         "pw_eigh_workspace": (i32, [i32, C.POINTER(C.c_size_t)]),
         "pw_eigh": (i32, [vp, i64, i32, vp, vp, i64, vp, C.c_size_t, vp]),
         "pw_profile_enable": (i32, [vp, i32]),
@@ -598,6 +599,12 @@ def pw_problem_autotune(prob: Problem, nbands: int, reps: int = 3, stream=None) 
     ms = C.c_double(0.0)
     _check(LIB.pw_problem_autotune(prob.handle, int(nbands), int(reps), _stream(stream), C.byref(ms)))
     return ms.value
+
+
+def pw_problem_set_tuning(prob: Problem, plane_group: int, band_chunk: int, ksplit: int,
+                          plane_kernel: int) -> None:
+    _check(LIB.pw_problem_set_tuning(prob.handle, int(plane_group), int(band_chunk), int(ksplit),
+                                     int(plane_kernel)))
 
 
 def pw_problem_tuning(prob: Problem) -> dict:

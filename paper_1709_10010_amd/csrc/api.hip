@@ -435,6 +435,7 @@ pw_status pw_problem_create(const pw_problem_desc *d, int64_t max_bands, void *s
   if (chunk <= 0) chunk = std::max<int64_t>(1, std::min<int64_t>(max_bands, ((size_t)1 << 30) / per_band));
   chunk = std::min(chunk, max_bands);
   p->band_chunk = chunk;
+  p->band_chunk_max = chunk;
   p->plane_group = env_int("PW_PLANE_GROUP", 0);  // <= 0: chosen for the plane kernel below
   if (hipMalloc(&p->d_sticks, per_band * chunk) != hipSuccess) return fail(PW_ERR_NOMEM);
   if (hipMalloc(&p->d_tn, (size_t)max_bands * sizeof(double)) != hipSuccess) return fail(PW_ERR_NOMEM);

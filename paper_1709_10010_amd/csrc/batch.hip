@@ -205,6 +205,19 @@ pw_status pw_problem_autotune(pw_problem *p, int64_t nbands, int32_t reps, void 
   return PW_OK;
 }
 
+pw_status pw_problem_set_tuning(pw_problem *p, int32_t plane_group, int64_t band_chunk, int32_t ksplit,
+                                int32_t plane_kernel) {
+  PW_CHECK_ARG(p, PW_ERR_INVALID, "pw_problem_set_tuning: null handle");
+  PW_CHECK_ARG(plane_group >= 1 && band_chunk >= 1 && band_chunk <= p->band_chunk_max && ksplit >= 0 &&
+                   ksplit <= 64 && plane_kernel >= PW_PLANE_REGISTER && plane_kernel <= PW_PLANE_LDS,
+               PW_ERR_INVALID, "pw_problem_set_tuning: choice out of range");
+  p->plane_group = plane_group;
+  p->band_chunk = band_chunk;
+  p->ksplit = ksplit;
+  p->plane_kernel = plane_kernel;
+  return PW_OK;
+}
+
 pw_status pw_problem_tuning(const pw_problem *p, int32_t *plane_group, int64_t *band_chunk,
                             int32_t *ksplit, int32_t *plane_kernel) {
   PW_CHECK_ARG(p, PW_ERR_INVALID, "pw_problem_tuning: null handle");

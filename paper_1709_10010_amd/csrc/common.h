@@ -123,6 +123,7 @@ struct pw_problem {
   int natom = 0;
   double vavg = 0;          // mean of V_LOC over the grid (a feature of the learned preconditioner)
   int64_t band_chunk = 0;   // bands per FFT sweep (stick-buffer height)
+  int64_t band_chunk_max = 0;  // sweep height the stick buffer was sized for
   int plane_group = 8;      // bands per plane-pass workgroup
   int plane_kernel = 0;     // PW_PLANE_REGISTER / _WAVE / _LDS
   int ksplit = 0;           // split-K factor for projections (0 = auto)

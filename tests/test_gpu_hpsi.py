@@ -164,3 +164,40 @@ def test_sphere_outside_grid_is_shape_error(lib):
     with pytest.raises(lib.PwError) as e:
         lib.pw_problem_create(po.A, po.kfrac, c.ecut_ha, (8, 8, 8), po.miller, v, None, None, None)
     assert e.value.status == -2
+
+
+# every cubic grid size with compile-time FFT plans (odd ones have no
+# register plane instance and fall back to the LDS kernel)
+PLANE_SIZES = [24, 36, 40, 45, 48, 50, 54, 60, 64, 72, 81, 90]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("n", PLANE_SIZES)
+def test_hpsi_every_plane_kernel_and_size(lib, n, prec):
+    """The tiny cell on an n^3 grid through each plane kernel (register,
+    wave-local, LDS), one and four bands per plane workgroup, and sweeps of
+    four bands (nine bands: ragged groups and a ragged last sweep).  FP64
+    against the oracle at 1e-12; the complex64-FFT form at 5e-6 (the
+    precision-form bound)."""
+    c = synth.make_cell(0, seed=31)
+    c.nr = (n, n, n)
+    log("plane kernels n", n, "prec", prec)
+    po, pl = problems(c, precision=prec, max_bands=9)
+    psi = start_block(c, 9, po.npw)
+    ref = ham.hpsi(po, psi)
+    tol = TOL if prec == 0 else 5e-6
+    for kernel in (lib.PW_PLANE_REGISTER, lib.PW_PLANE_WAVE, lib.PW_PLANE_LDS):
+        for group, chunk in ((1, 9), (4, 4)):
+            lib.pw_problem_set_tuning(pl, group, chunk, 0, kernel)
+            err = rel_err(_run(lib, pl, psi), ref)
+            assert err < tol, (kernel, group, chunk, err)
+
+
+def test_set_tuning_rejects_out_of_range(lib):
+    c = synth.make_cell(0)
+    po, pl = problems(c, max_bands=8)
+    before = lib.pw_problem_tuning(pl)
+    for bad in ((0, 8, 0, 0), (2, 9, 0, 0), (2, 8, 65, 0), (2, 8, 0, 3), (2, 0, 0, 0)):
+        with pytest.raises(lib.PwError):
+            lib.pw_problem_set_tuning(pl, *bad)
+    assert lib.pw_problem_tuning(pl) == before
