@@ -1,0 +1,56 @@
+#!/usr/bin/env python3
+"""Writes the stored expected values under tests/golden/ from the FP64 oracle
+alone (dense diagonalisation of the discrete Hamiltonian of eq. pauli_ks on
+the sphere basis; sphere sizes from the cutoff inequality).
+
+    python tests/golden/make_golden.py
+
+Regression fixtures: tests/test_golden.py recomputes them with the oracle,
+and the GPU tests compare the library against them.
+"""
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import numpy as np  # noqa: E402
+
+import synth  # noqa: E402
+from oracle import gsphere  # noqa: E402
+from oracle import hamiltonian as ham  # noqa: E402
+
+
+def eig_fixture(cfg, nlow):
+    c = synth.make_cell(cfg)
+    po = ham.problem_from_cell(c)
+    w, _ = ham.eigh_lowest(po, nlow)
+    return c, po, w
+
+
+def sphere_rows():
+    rows = []
+    for cfg, idx in ((0, 0), (1, 0), (2, 0), (5, -1)):
+        c = synth.make_cell(cfg, idx)
+        for ik in range(len(c.kpts)):
+            m = gsphere.gsphere(c.A, c.kpts[ik], c.ecut_ha)
+            rows.append((c.name, ik, len(m)))
+    return rows
+
+
+def main():
+    for cfg, nlow, fname in ((0, 8, "tiny_cell_lowest8_Ha.txt"), (1, 16, "config1_lowest16_Ha.txt")):
+        c, po, w = eig_fixture(cfg, nlow)
+        with open(os.path.join(HERE, fname), "w") as f:
+            f.write(f"# {c.name}: lowest {nlow} eigenvalues (Ha) of the dense FP64 Hamiltonian, npw {po.npw},"
+                    f" grid {c.nr[0]}^3; written by make_golden.py (oracle only)\n")
+            for v in w:
+                f.write(f"{v:.17e}\n")
+    with open(os.path.join(HERE, "sphere_sizes.txt"), "w") as f:
+        f.write("# cell  k-point  npw: |k+G|^2/2 < ecut (strict, FP64); written by make_golden.py (oracle only)\n")
+        for name, ik, n in sphere_rows():
+            f.write(f"{name} {ik} {n}\n")
+
+
+if __name__ == "__main__":
+    main()

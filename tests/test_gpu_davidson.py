@@ -6,6 +6,8 @@ the oracle's dense H to the 1e-8 Ry target (5e-9 Ha) and within each band's
 residual norm (Weyl / Bauer-Fike); Ritz vectors orthonormal; and the residual
 ||H x - theta x|| recomputed by the oracle's own H*psi below the tolerance.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -63,6 +65,10 @@ def test_davidson_config1(lib):
     po, res, X = _solve(lib, c, 16)
     log("iterations", res["iterations"], "n_hpsi", res["n_hpsi"])
     _check_against_eigh(po, res, X, 16)
+    # and against the stored dense eigenvalues (tests/golden/, written by the oracle)
+    gold = np.loadtxt(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                   "config1_lowest16_Ha.txt"), comments="#")
+    assert np.abs(res["theta"] - gold).max() < 5e-9
 
 
 def test_davidson_cooperative_jacobi_path(lib):
