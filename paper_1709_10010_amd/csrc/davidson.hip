@@ -82,6 +82,9 @@ struct pw_davidson {
   std::vector<uint8_t> tpa_only;
   int *h_bad = nullptr;
   double off_target = 0.0;  // eigensolver stop level (Frobenius norm of the off-diagonal part)
+  // locked prefix: bands 0 .. nl-1 have converged (all of them), their
+  // vectors stay fixed in V and W, and Rayleigh-Ritz runs on the rest
+  int nl = 0;
 };
 
 namespace {
@@ -273,6 +276,7 @@ pw_status pw_davidson_init(pw_davidson *d, const void *psi0, int64_t ld, void *s
   d->n_hpsi = d->nb;
   d->prev_rho.assign(d->nb, INFINITY);
   d->off_target = 0.0;
+  d->nl = 0;
   d->stall.assign(d->nb, 0);
   d->tpa_only.assign(d->nb, 0);
   d->inited = true;
@@ -298,24 +302,36 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   //    so nothing is dropped and the next step continues the diagonalisation.
   //    The residual test below sees E: R_n has an in-subspace part of norm
   //    |E e_n|, so convergence still means every Ritz pair is accurate.
-  const bool carry = eig_transforms_in_place(d->m);
+  //    Only the active block (indices nl .. m-1) takes part: the locked
+  //    prefix is fixed, and its couplings to the active part, of the order
+  //    of its residuals (below the tolerance), are left out.
+  const int nl = d->nl, ma = d->m - nl;
+  const size_t hoff = (size_t)nl * d->lde + nl;
+  const bool carry = eig_transforms_in_place(ma);
   {
     ProfScope ps(&d->p->prof, PW_STAGE_EIG, s);
-    DV_RC(copy_mat(d->Hs, d->lde, d->Ae, d->lde, d->m, d->m, s));
-    DV_RC(eig_herm(d->Ae, d->lde, d->m, d->w_all, d->Ze, d->lde, d->rot_ws, d->acc_ws, d->sweeps,
+    DV_RC(copy_mat(d->Hs + hoff, d->lde, d->Ae, d->lde, ma, ma, s));
+    DV_RC(eig_herm(d->Ae, d->lde, ma, d->w_all, d->Ze, d->lde, d->rot_ws, d->acc_ws, d->sweeps,
                    d->coop, s, carry ? d->off_target : 0.0));
-    DV_RC(eig_select(d->w_all, d->m, d->m, d->w_sorted, d->idx_all, d->Ze, d->lde, d->Ae, d->lde, s,
-                     carry ? d->Ae : nullptr, d->lde, d->Hs, d->lde));
+    DV_RC(eig_select(d->w_all, ma, ma, d->w_sorted, d->idx_all, d->Ze, d->lde, d->Ae, d->lde, s,
+                     carry ? d->Ae : nullptr, d->lde, d->Hs + hoff, d->lde));
   }
-  // 2. rotate the whole space into the Ritz basis (V <- V Z, W <- W Z): the
-  //    first nb columns are the Ritz vectors, H_s becomes diag(w), and the
-  //    next bordered H_s is nearly diagonal, so its Jacobi solve is short
-  DV_RC(nn(d, d->m, d->m, 1.0, d->V, d->Ae, d->lde, 0.0, d->Vt, s));
-  DV_RC(nn(d, d->m, d->m, 1.0, d->W, d->Ae, d->lde, 0.0, d->Wt, s));
+  // 2. rotate the active space into the Ritz basis (V <- V Z, W <- W Z): the
+  //    first nb columns are the Ritz vectors, the active H_s becomes diag(w),
+  //    and the next bordered H_s is nearly diagonal, so its Jacobi solve is
+  //    short.  The locked columns are carried over unchanged.
+  const size_t lcol = (size_t)nl * d->ld;
+  DV_RC(nn(d, ma, ma, 1.0, d->V + lcol, d->Ae, d->lde, 0.0, d->Vt + lcol, s));
+  DV_RC(nn(d, ma, ma, 1.0, d->W + lcol, d->Ae, d->lde, 0.0, d->Wt + lcol, s));
+  if (nl > 0) {
+    PW_HIP(hipMemcpyAsync(d->Vt, d->V, lcol * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    PW_HIP(hipMemcpyAsync(d->Wt, d->W, lcol * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  }
   std::swap(d->V, d->Vt);
   std::swap(d->W, d->Wt);
-  if (!carry) DV_RC(set_diag(d->Hs, d->lde, d->m, d->w_sorted, s));
-  PW_HIP(hipMemcpyAsync(d->theta, d->w_sorted, nb * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (!carry) DV_RC(set_diag(d->Hs + hoff, d->lde, ma, d->w_sorted, s));
+  if (nb > nl)
+    PW_HIP(hipMemcpyAsync(d->theta + nl, d->w_sorted, (nb - nl) * sizeof(double), hipMemcpyDeviceToDevice, s));
   PW_HIP(hipMemcpyAsync(d->X, d->V, (size_t)nb * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
   PW_HIP(hipMemcpyAsync(d->HX, d->W, (size_t)nb * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
   // 3. residuals
@@ -347,6 +363,21 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   // next step's eigensolver target: a tenth of the smallest residual still
   // to converge (never below a tenth of the tolerance)
   d->off_target = 0.1 * std::max(d->tol, nu ? rho_min : d->tol);
+  // lock the converged prefix.  An active Ritz value below the largest
+  // locked one means the locked bands are not the lowest after all: the
+  // locking is dropped and H_s rebuilt over the whole space.
+  if (!d->converged) {
+    if (nl > 0 && nl < nb && d->h_theta[nl] < d->h_theta[nl - 1] - d->tol) {
+      d->nl = 0;
+      DV_RC(cn(d, d->m, d->m, d->V, d->W, d->Hs, d->lde, s));
+      DV_RC(hermitize(d->Hs, d->lde, 0, d->m, s));
+      d->off_target = 0.0;
+    } else {
+      int l = nl;
+      while (l < nb && d->h_rho[l] < d->tol) ++l;
+      d->nl = l;
+    }
+  }
   if (converged) *converged = d->converged ? 1 : 0;
   if (d->converged) return PW_OK;
   PW_HIP(hipMemcpyAsync(d->dU, d->h_U, nu * sizeof(int), hipMemcpyHostToDevice, s));
@@ -402,6 +433,9 @@ pw_status pw_davidson_set_problem(pw_davidson *d, pw_problem *p, void *stream) {
   d->n_hpsi += d->m;
   DV_RC(cn(d, d->m, d->m, d->V, d->W, d->Hs, d->lde, s));
   DV_RC(hermitize(d->Hs, d->lde, 0, d->m, s));
+  // a new operator: every band is checked again, nothing stays locked
+  d->nl = 0;
+  d->off_target = 0.0;
   return PW_OK;
 }
 
