@@ -86,20 +86,24 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return y * fma(-x, y, 2.0);
 }
 __device__ __forceinline__ Rot make_rot_fast(double alpha, double gamma, double2 beta) {
-  Rot r{1.0, 0.0, 1.0, 0.0};
   const double ab2 = beta.x * beta.x + beta.y * beta.y;
-  if (!(ab2 > 1e-300) || ab2 <= 1e-32 * fabs(alpha * gamma)) return r;
-  const double rab = rsq_nr(ab2);
-  const double tau = 0.5 * (gamma - alpha) * rab;
-  const double at = fabs(tau);
-  // |tau| + sqrt(1 + tau^2), without overflow for huge |tau|
-  const double den = at < 1e150 ? at + (1.0 + tau * tau) * rsq_nr(1.0 + tau * tau) : 2.0 * at;
-  const double t = (tau >= 0.0 ? 1.0 : -1.0) * rcp_nr(den);
-  const double c = rsq_nr(1.0 + t * t);
-  r.c = c;
-  r.s = t * c;
-  r.er = beta.x * rab;
-  r.ei = -beta.y * rab;
+  // branch-free: the identity is selected at the end (the inputs of every
+  // rotation can then be read together)
+  const bool id = !(ab2 > 1e-300) || ab2 <= 1e-32 * fabs(alpha * gamma);
+  const double ab2s = id ? 1.0 : ab2;
+  // with d = gamma - alpha and rho = sqrt(d^2 + 4 |beta|^2): cos 2theta =
+  // |d| / rho, c = sqrt((1 + cos 2theta) / 2), s = sign(d) |beta| / (rho c)
+  // -- the angle of t = tan theta above, with no cancellation
+  const double d = id ? 0.0 : gamma - alpha;
+  const double rab = rsq_nr(ab2s);
+  const double rrho = rsq_nr(fma(d, d, 4.0 * ab2s));
+  const double h = fma(0.5 * fabs(d), rrho, 0.5);
+  const double rh = rsq_nr(h);
+  Rot r;
+  r.c = id ? 1.0 : h * rh;
+  r.s = id ? 0.0 : (d >= 0.0 ? 1.0 : -1.0) * (ab2s * rab) * rrho * rh;
+  r.er = id ? 1.0 : beta.x * rab;
+  r.ei = id ? 0.0 : -beta.y * rab;
   return r;
 }
 
@@ -115,12 +119,14 @@ __device__ __forceinline__ void rot_entries(const Rot &r, double2 &j11, double2 
 // Indices of pair k in round r for m' (even) indices.
 __device__ __forceinline__ void pair_of(int k, int r, int mp, int *p, int *q) {
   const int n1 = mp - 1;
+  // 0 <= r < n1 and 0 <= k < mp / 2, so each sum needs at most one wrap
   if (k == 0) {
     *p = 0;
-    *q = 1 + (r % n1);
+    *q = 1 + r;
   } else {
-    *p = 1 + ((k + r) % n1);
-    *q = 1 + ((mp - 1 - k + r) % n1);
+    const int a = k + r;
+    *p = 1 + (a >= n1 ? a - n1 : a);
+    *q = 1 + (r >= k ? r - k : n1 - k + r);
   }
 }
 
@@ -327,185 +333,298 @@ __global__ __launch_bounds__(256) void k_jacobi_coop(double2 *__restrict__ A, do
 }
 
 // ---------------------------------------------------------------- block Jacobi
-// Indices are grouped into blocks of kBJ; a round pairs the 2k blocks by the
-// circle schedule, and
-//   k_bj_inner  (one workgroup per block pair) diagonalises the pair's
-//               2kBJ x 2kBJ sub-matrix completely in LDS with the scalar
-//               Jacobi rotations above and stores its unitary U_P;
-//   k_bj_apply  replaces every 2kBJ x 2kBJ block A_PQ by U_P^H A_PQ U_Q and
-//               every row chunk of Z[:, Q] by Z[:, Q] U_Q (each block owned by
-//               one workgroup, so the update is in place).
-// A sweep is 2k-1 rounds, i.e. 2m/kBJ global steps instead of m for the
-// element-wise schedule, and the inner solves run at workgroup-barrier cost.
+// Indices are grouped into blocks of kBJ.  A sweep is one intra round, which
+// pairs blocks 2P and 2P+1 and diagonalises each pair's 2kBJ x 2kBJ
+// sub-matrix with one full sweep of scalar rotations (every index pair
+// inside a block is rotated there), followed by 2k-1 cross rounds, which
+// pair the 2k blocks by the circle schedule and rotate only index pairs
+// (i in I, j in J), kBJ steps of kBJ disjoint rotations.  Together every
+// off-diagonal index pair is rotated once per sweep, as in a cyclic scalar
+// sweep, at half the steps of diagonalising every pair problem in full.
+//   k_bj_inner  (one workgroup per block pair) runs the steps in LDS and
+//               stores the pair's accumulated unitary U_P;
+//   k_bj_apply  replaces every 2kBJ x 2kBJ block A_PQ (P <= Q) by
+//               U_P^H A_PQ U_Q, mirrors it into A_QP, and every row chunk of
+//               Z[:, Q] by Z[:, Q] U_Q (each block owned by one workgroup, so
+//               the update is in place).
 constexpr int kBJ = 16;
 constexpr int kSub = 2 * kBJ;
 
-__device__ __forceinline__ int bj_index(int blk, int i) { return blk * kBJ + i; }
-
-// rows / columns of pair p in round r of 2k blocks: local i < kBJ -> block I, else block J
-__device__ __forceinline__ int bj_global(int p, int r, int nblk, int i) {
-  int I, J;
-  pair_of(p, r, nblk, &I, &J);
-  return i < kBJ ? bj_index(I, i) : bj_index(J, i - kBJ);
+// Blocks (I, J) of pair p in round r: r < 0 is the intra round (2p, 2p+1),
+// otherwise the circle schedule over the nblk blocks.
+__device__ __forceinline__ void bj_pair(int p, int r, int nblk, int *I, int *J) {
+  if (r < 0) {
+    *I = 2 * p;
+    *J = 2 * p + 1;
+  } else {
+    pair_of(p, r, nblk, I, J);
+  }
 }
 
-// Sum over the 1024 threads of a block (16 waves): wave reduction, then the
-// partial sums through LDS; every thread gets the total.
-__device__ __forceinline__ double block_sum1024(double v, double *part) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double t = 0.0;
-#pragma unroll
-  for (int w = 0; w < 16; ++w) t += part[w];
-  __syncthreads();
-  return t;
+// global index of local index i (< kBJ: block I, else block J)
+__device__ __forceinline__ int bj_row(int I, int J, int i) { return i < kBJ ? I * kBJ + i : J * kBJ + i - kBJ; }
+
+// Rotation k at step st of a pair solve.  CROSS: index k of block I with
+// index (k + st) mod kBJ of block J; otherwise the circle schedule over all
+// 2kBJ indices.
+template <bool CROSS>
+__device__ __forceinline__ void step_pair(int k, int st, int *p, int *q) {
+  if (CROSS) {
+    *p = k;
+    *q = kBJ + ((k + st) & (kBJ - 1));
+  } else {
+    pair_of(k, st, kSub, p, q);
+  }
 }
 
-// One pair of blocks: the 2kBJ x 2kBJ Hermitian sub-matrix diagonalised in
-// LDS by round-robin sweeps, 1024 threads.  A round has two phases: the 16
-// rotations (one lane each), then the 256 2x2 block updates (threads
-// 0..255) beside the 512 row updates of the accumulated rotation (threads
-// 256..767), each item owned by one thread.
-// A pair whose off-diagonal mass is at most skip2 (or at the rounding level)
-// is left alone: rotated[p] = 0 and its U is not written; k_bj_apply then
-// skips every block whose transforms are all identities.
-static_assert(kSub == 32, "the thread layout of k_bj_inner assumes 16 x 16 blocks of 2 x 2");
-template <bool FAST>
-__global__ __launch_bounds__(1024) void k_bj_inner(const double2 *__restrict__ A, int64_t lda, int nblk,
-                                                   int r, double2 *__restrict__ U, int max_sweeps,
-                                                   double skip2, int *__restrict__ rotated) {
-  __shared__ double2 S[kSub][kSub + 1];
+// X <- J_a^H X J_b for the 2x2 block X = [a b; c d] (rows p_a, q_a; columns
+// p_b, q_b).  J = diag(1, e) R with R = [[c, s], [-s, c]] real, so the phase
+// scales row q_a by conj(e_a) and column q_b by e_b, then the real rotations
+// mix the rows and the columns.
+__device__ __forceinline__ void rotate_block(double2 &a, double2 &b, double2 &c, double2 &d, const Rot &ra,
+                                             const Rot &rb) {
+  const double2 eb{rb.er, rb.ei}, eac{ra.er, -ra.ei};
+  b = cm(b, eb);
+  d = cm(eac, cm(d, eb));
+  c = cm(eac, c);
+  // columns: (x, y) -> (c x - s y, s x + c y)
+  const double2 a1{rb.c * a.x - rb.s * b.x, rb.c * a.y - rb.s * b.y};
+  const double2 b1{rb.s * a.x + rb.c * b.x, rb.s * a.y + rb.c * b.y};
+  const double2 c1{rb.c * c.x - rb.s * d.x, rb.c * c.y - rb.s * d.y};
+  const double2 d1{rb.s * c.x + rb.c * d.x, rb.s * c.y + rb.c * d.y};
+  // rows: (u, v) -> (c u - s v, s u + c v)
+  a = double2{ra.c * a1.x - ra.s * c1.x, ra.c * a1.y - ra.s * c1.y};
+  c = double2{ra.s * a1.x + ra.c * c1.x, ra.s * a1.y + ra.c * c1.y};
+  b = double2{ra.c * b1.x - ra.s * d1.x, ra.c * b1.y - ra.s * d1.y};
+  d = double2{ra.s * b1.x + ra.c * d1.x, ra.s * b1.y + ra.c * d1.y};
+}
+
+// (z_p, z_q) <- (z_p, z_q) J for one row of the accumulated unitary
+__device__ __forceinline__ void rotate_cols(double2 &zp, double2 &zq, const Rot &r) {
+  const double2 y = cm(zq, double2{r.er, r.ei});
+  const double2 x = zp;
+  zp = double2{r.c * x.x - r.s * y.x, r.c * x.y - r.s * y.y};
+  zq = double2{r.s * x.x + r.c * y.x, r.s * x.y + r.c * y.y};
+}
+
+// Sum over the 256 threads of a block (4 waves) of two values.
+__device__ __forceinline__ void block_sum256x2(double &u, double &v, double (*part)[4]) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    u += __shfl_xor(u, o, 64);
+    v += __shfl_xor(v, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    part[0][threadIdx.x >> 6] = u;
+    part[1][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  u = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+  v = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+}
+
+// One block pair: the 2kBJ x 2kBJ sub-matrix S of A in LDS, 256 threads.
+// Thread (ka, kb) = (tid / kBJ, tid % kBJ) owns, at each step, the 2x2 block
+// of S at rotations (ka, kb) and the rows ka, ka + kBJ of the accumulated
+// unitary at rotation kb; it recomputes the two rotations it needs from the
+// current S (every thread gets the same bits), reads S from one LDS buffer
+// and writes the other, so a step costs one barrier.
+// A pair whose off-diagonal mass (CROSS: of the block A_IJ) is at most
+// skip2, or at the rounding level, is left alone: rotated[p] = 0 and its U
+// is not written; k_bj_apply then skips every block whose transforms are
+// all identities.
+static_assert(kSub == 32 && kBJ * kBJ == 256, "k_bj_inner maps one thread to each rotation pair");
+template <bool CROSS, bool FAST>
+__global__ __launch_bounds__(256) void k_bj_inner(const double2 *__restrict__ A, int64_t lda, int nblk,
+                                                  int r, double2 *__restrict__ U, double skip2,
+                                                  int *__restrict__ rotated) {
+  __shared__ double2 S[2][kSub][kSub + 1];
   __shared__ double2 Q[kSub][kSub + 1];
-  __shared__ Rot rot[kSub / 2];
-  __shared__ double part[16];
+  __shared__ double part[2][4];
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
-  {
-    const int i = tid % kSub, j = tid / kSub;
-    S[i][j] = A[bj_global(p, r, nblk, i) + (int64_t)bj_global(p, r, nblk, j) * lda];
+  int I, J;
+  bj_pair(p, r, nblk, &I, &J);
+  double off = 0.0, tot = 0.0;
+#pragma unroll
+  for (int q = 0; q < kSub * kSub / 256; ++q) {
+    const int e = tid + 256 * q;
+    const int i = e % kSub, j = e / kSub;
+    const double2 v = A[bj_row(I, J, i) + (int64_t)bj_row(I, J, j) * lda];
+    S[0][i][j] = v;
     Q[i][j] = double2{i == j ? 1.0 : 0.0, 0.0};
+    const double v2 = v.x * v.x + v.y * v.y;
+    tot += v2;
+    if (CROSS ? ((i < kBJ) != (j < kBJ)) : (i != j)) off += v2;
   }
-  __syncthreads();
-  constexpr int np = kSub / 2;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    {
-      const int i = tid % kSub, j = tid / kSub;
-      const double2 v = S[i][j];
-      const double v2 = v.x * v.x + v.y * v.y;
-      tot = v2;
-      off = (i != j) ? v2 : 0.0;
-    }
-    off = block_sum1024(off, part);
-    tot = block_sum1024(tot, part);
-    const bool conv = off <= kOffRel * (double)kSub * tot;
-    if (sweep == 0) {
-      const bool skip = conv || off <= skip2;
-      if (tid == 0) rotated[p] = skip ? 0 : 1;
-      if (skip) return;  // identity: U is not needed
-    }
-    if (conv) break;
-    for (int rr = 0; rr < kSub - 1; ++rr) {
-      if (tid < np) {
-        int a, b;
-        pair_of(tid, rr, kSub, &a, &b);
-        rot[tid] = FAST ? make_rot_fast(S[a][a].x, S[b][b].x, S[a][b]) : make_rot(S[a][a].x, S[b][b].x, S[a][b]);
-      }
-      __syncthreads();
-      if (tid < np * np) {
-        const int ka = tid % np, kb = tid / np;
-        int pa, qa, pb, qb;
-        pair_of(ka, rr, kSub, &pa, &qa);
-        pair_of(kb, rr, kSub, &pb, &qb);
-        double2 a = S[pa][pb], b = S[pa][qb], c = S[qa][pb], d = S[qa][qb];
-        update_block(a, b, c, d, rot[ka], rot[kb]);
-        S[pa][pb] = a;
-        S[pa][qb] = b;
-        S[qa][pb] = c;
-        S[qa][qb] = d;
-      } else if (tid < np * np + kSub * np) {
-        const int e = tid - np * np;
-        const int i = e % kSub, kb = e / kSub;
-        int pb, qb;
-        pair_of(kb, rr, kSub, &pb, &qb);
-        update_zrow(Q[i][pb], Q[i][qb], rot[kb]);
-      }
-      __syncthreads();
-    }
+  block_sum256x2(off, tot, part);
+  const bool skip = off <= kOffRel * (double)kSub * tot || off <= skip2;
+  if (skip) {
+    if (tid == 0) rotated[p] = 0;
+    return;  // identity: U is not needed
+  }
+  if (tid == 0) rotated[p] = 1;
+  constexpr int nsteps = CROSS ? kBJ : kSub - 1;
+  const int ka = tid / kBJ, kb = tid % kBJ;
+  int cur = 0;
+  for (int st = 0; st < nsteps; ++st) {
+    int pa, qa, pb, qb;
+    step_pair<CROSS>(ka, st, &pa, &qa);
+    step_pair<CROSS>(kb, st, &pb, &qb);
+    const double2 (*Sc)[kSub + 1] = S[cur];
+    double2 (*Sn)[kSub + 1] = S[cur ^ 1];
+    // every LDS read of the step is issued before any arithmetic
+    const double2 ba = Sc[pa][qa], bb = Sc[pb][qb];
+    const double aa = Sc[pa][pa].x, ga = Sc[qa][qa].x, ab = Sc[pb][pb].x, gb = Sc[qb][qb].x;
+    double2 a = Sc[pa][pb], b = Sc[pa][qb], c = Sc[qa][pb], d = Sc[qa][qb];
+    double2 z0 = Q[ka][pb], z1 = Q[ka][qb], z2 = Q[ka + kBJ][pb], z3 = Q[ka + kBJ][qb];
+    const Rot ra = FAST ? make_rot_fast(aa, ga, ba) : make_rot(aa, ga, ba);
+    const Rot rb = FAST ? make_rot_fast(ab, gb, bb) : make_rot(ab, gb, bb);
+    rotate_block(a, b, c, d, ra, rb);
+    rotate_cols(z0, z1, rb);
+    rotate_cols(z2, z3, rb);
+    Sn[pa][pb] = a;
+    Sn[pa][qb] = b;
+    Sn[qa][pb] = c;
+    Sn[qa][qb] = d;
+    Q[ka][pb] = z0;
+    Q[ka][qb] = z1;
+    Q[ka + kBJ][pb] = z2;
+    Q[ka + kBJ][qb] = z3;
+    __syncthreads();
+    cur ^= 1;
   }
   double2 *Up = U + (int64_t)p * kSub * kSub;
-  {
-    const int i = tid % kSub, j = tid / kSub;
-    Up[i + j * kSub] = Q[i][j];
+#pragma unroll
+  for (int q = 0; q < kSub * kSub / 256; ++q) {
+    const int e = tid + 256 * q;
+    Up[e] = Q[e % kSub][e / kSub];
   }
 }
 
-// grid (npair, npair, 2): z = 0 updates A block (P, Q), z = 1 the Z chunk (rows
-// 2kBJ*P .. +2kBJ, columns of pair Q)
+// Workgroups 0 .. nA-1 (nA = npair (npair + 1) / 2) update the A blocks
+// (P, Q), P <= Q, in row-major order; the next npair^2 update the Z row
+// chunks (rows 2kBJ P .. +2kBJ, columns of pair Q).  Each thread computes a
+// 2 x 2 tile of the 2kBJ x 2kBJ products from LDS; results leave through LDS
+// so that every global store is along a column.
 __global__ __launch_bounds__(256) void k_bj_apply(double2 *__restrict__ A, int64_t lda,
                                                   double2 *__restrict__ Z, int64_t ldz, int nblk, int r,
                                                   const double2 *__restrict__ U,
                                                   const int *__restrict__ rotated) {
-  __shared__ double2 X[kSub][kSub + 1];
-  __shared__ double2 UQ[kSub][kSub + 1];
-  __shared__ double2 UP[kSub][kSub + 1];
-  const int P = blockIdx.x, Qp = blockIdx.y;
-  const bool isZ = blockIdx.z == 1;
+  __shared__ double2 X[kSub][kSub + 1];   // X[col][row]: the block, then T, then the result
+  __shared__ double2 UQ[kSub][kSub + 1];  // UQ[k][j] = U_Q(k, j)
+  __shared__ double2 UP[kSub][kSub + 1];  // UP[k][i] = U_P(k, i)
+  const int npair = nblk / 2;
+  const int nA = npair * (npair + 1) / 2;
+  int b = blockIdx.x;
+  const bool isZ = b >= nA;
+  int P, Qp;
+  if (isZ) {
+    b -= nA;
+    P = b % npair;
+    Qp = b / npair;
+  } else {
+    P = 0;
+    while (b >= npair - P) {
+      b -= npair - P;
+      ++P;
+    }
+    Qp = P + b;
+  }
+  const bool rq = rotated[Qp] != 0;
+  const bool rp = !isZ && rotated[P] != 0;
   // identity transforms leave the block as it is
-  if (isZ ? !rotated[Qp] : (!rotated[Qp] && !rotated[P])) return;
+  if (!rq && !rp) return;
+  int QI, QJ, PI = 0, PJ = 0;
+  bj_pair(Qp, r, nblk, &QI, &QJ);
+  if (!isZ) bj_pair(P, r, nblk, &PI, &PJ);
   const int tid = threadIdx.x;
   const double2 *uq = U + (int64_t)Qp * kSub * kSub;
   const double2 *up = U + (int64_t)P * kSub * kSub;
-  const bool rq = rotated[Qp], rp = rotated[P];
-  for (int e = tid; e < kSub * kSub; e += 256) {
-    const int i = e % kSub, j = e / kSub;
-    const double2 id = double2{i == j ? 1.0 : 0.0, 0.0};
-    UQ[i][j] = rq ? uq[i + j * kSub] : id;
-    if (!isZ) UP[i][j] = rp ? up[i + j * kSub] : id;
-    const int col = bj_global(Qp, r, nblk, j);
-    const int64_t row = isZ ? (int64_t)P * kSub + i : bj_global(P, r, nblk, i);
-    X[i][j] = isZ ? Z[row + (int64_t)col * ldz] : A[row + (int64_t)col * lda];
-  }
-  __syncthreads();
-  // T = X U_Q  (each thread: 4 entries)
-  double2 t[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < kSub * kSub / 256; ++q) {
     const int e = tid + 256 * q;
     const int i = e % kSub, j = e / kSub;
-    double2 acc = double2{0.0, 0.0};
-    for (int k = 0; k < kSub; ++k) acc = cadd(acc, cm(X[i][k], UQ[k][j]));
-    t[q] = acc;
+    if (rq) UQ[i][j] = uq[e];
+    if (rp) UP[i][j] = up[e];
+    const int col = bj_row(QI, QJ, j);
+    X[j][i] = isZ ? Z[(int64_t)P * kSub + i + (int64_t)col * ldz] : A[bj_row(PI, PJ, i) + (int64_t)col * lda];
   }
   __syncthreads();
+  const int i0 = 2 * (tid % kBJ), j0 = 2 * (tid / kBJ);
+  double2 t00, t01, t10, t11;
+  if (rq) {
+    // T = X U_Q
+    t00 = t01 = t10 = t11 = double2{0.0, 0.0};
+    // operands of 8 k at a time are read before they are used
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = tid + 256 * q;
-    X[e % kSub][e / kSub] = t[q];
-  }
-  __syncthreads();
-  if (!isZ) {
-    // out = U_P^H T
+    for (int k0 = 0; k0 < kSub; k0 += 8) {
+      double2 x0[8], x1[8], u0[8], u1[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      const int i = e % kSub, j = e / kSub;
-      double2 acc = double2{0.0, 0.0};
-      for (int k = 0; k < kSub; ++k) acc = cadd(acc, cmc(UP[k][i], X[k][j]));
-      t[q] = acc;
+      for (int k = 0; k < 8; ++k) {
+        x0[k] = X[k0 + k][i0];
+        x1[k] = X[k0 + k][i0 + 1];
+        u0[k] = UQ[k0 + k][j0];
+        u1[k] = UQ[k0 + k][j0 + 1];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        t00 = cadd(t00, cm(x0[k], u0[k]));
+        t01 = cadd(t01, cm(x0[k], u1[k]));
+        t10 = cadd(t10, cm(x1[k], u0[k]));
+        t11 = cadd(t11, cm(x1[k], u1[k]));
+      }
     }
+    __syncthreads();
+    X[j0][i0] = t00;
+    X[j0 + 1][i0] = t01;
+    X[j0][i0 + 1] = t10;
+    X[j0 + 1][i0 + 1] = t11;
+    __syncthreads();
+  }
+  if (rp) {
+    // out = U_P^H T
+    t00 = t01 = t10 = t11 = double2{0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < kSub; k0 += 8) {
+      double2 u0[8], u1[8], x0[8], x1[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        u0[k] = UP[k0 + k][i0];
+        u1[k] = UP[k0 + k][i0 + 1];
+        x0[k] = X[j0][k0 + k];
+        x1[k] = X[j0 + 1][k0 + k];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        t00 = cadd(t00, cmc(u0[k], x0[k]));
+        t01 = cadd(t01, cmc(u0[k], x1[k]));
+        t10 = cadd(t10, cmc(u1[k], x0[k]));
+        t11 = cadd(t11, cmc(u1[k], x1[k]));
+      }
+    }
+    __syncthreads();
+    X[j0][i0] = t00;
+    X[j0 + 1][i0] = t01;
+    X[j0][i0 + 1] = t10;
+    X[j0 + 1][i0 + 1] = t11;
+    __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < kSub * kSub / 256; ++q) {
     const int e = tid + 256 * q;
     const int i = e % kSub, j = e / kSub;
-    const int col = bj_global(Qp, r, nblk, j);
-    if (isZ)
-      Z[(int64_t)P * kSub + i + (int64_t)col * ldz] = t[q];
-    else
-      A[bj_global(P, r, nblk, i) + (int64_t)col * lda] = t[q];
+    const int col = bj_row(QI, QJ, j);
+    if (isZ) {
+      Z[(int64_t)P * kSub + i + (int64_t)col * ldz] = X[j][i];
+    } else {
+      A[bj_row(PI, PJ, i) + (int64_t)col * lda] = X[j][i];
+      // mirror: A_QP(i, j) = conj(A_PQ(j, i))
+      if (P != Qp) {
+        const double2 v = X[i][j];
+        A[bj_row(QI, QJ, i) + (int64_t)bj_row(PI, PJ, j) * lda] = double2{v.x, -v.y};
+      }
+    }
   }
 }
 
@@ -946,8 +1065,32 @@ static int eig_impl() {
 
 // Block Jacobi driver: A (lda >= mpb, mpb = m rounded up to 2 kBJ) is
 // overwritten; Z (ldz >= mpb) receives the eigenvectors; uws holds the
-// per-pair unitaries (mpb/kBJ/2 * (2 kBJ)^2 complex); acc >= 2 doubles.  One
-// host sync per sweep reads the off-diagonal mass.
+// per-pair unitaries (mpb/kBJ/2 * (2 kBJ)^2 complex) and flags; acc >= 2
+// doubles.  One host sync per sweep reads the off-diagonal mass.
+// PW_BJ_CROSS=0 replaces the intra + cross rounds by 2k-1 rounds of full
+// pair solves (every pair problem diagonalised by one scalar sweep).
+static int bj_cross() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = std::getenv("PW_BJ_CROSS");
+    v = (e && *e) ? std::atoi(e) : 1;
+  }
+  return v;
+}
+
+template <bool FAST>
+static void bj_round(bool cross, int npair, int nblk, int r, double2 *A, int64_t lda, double2 *Z, int64_t ldz,
+                     double2 *U, double skip2, int *rotated, hipStream_t s) {
+  if (cross)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_bj_inner<true, FAST>), dim3(npair), dim3(256), 0, s, A, lda, nblk, r, U,
+                       skip2, rotated);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_bj_inner<false, FAST>), dim3(npair), dim3(256), 0, s, A, lda, nblk, r,
+                       U, skip2, rotated);
+  const int nA = npair * (npair + 1) / 2;
+  hipLaunchKernelGGL(k_bj_apply, dim3(nA + npair * npair), dim3(256), 0, s, A, lda, Z, ldz, nblk, r, U, rotated);
+}
+
 static int eig_block(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz, void *uws,
                      double *acc, hipStream_t s, double off_abs) {
   const int mpb = (m + kSub - 1) / kSub * kSub;
@@ -958,15 +1101,14 @@ static int eig_block(double2 *A, int64_t lda, int m, double *w, double2 *Z, int6
     return PW_ERR_NOMEM;
   double2 *U = static_cast<double2 *>(uws);
   int *rotated = reinterpret_cast<int *>(U + (int64_t)npair * kSub * kSub);
-  // a pair below this mass is skipped: all of them together stay below the target
-  const double skip2 = off_abs * off_abs / (double)std::max(1, nblk * (nblk - 1) / 2);
-  // inner sweeps per pair solve: the outer iteration converges with partial
-  // inner diagonalisation, and a pair problem is the cost of a round
-  static int inner = -1;
-  if (inner < 0) {
-    const char *e = std::getenv("PW_BJ_INNER");
-    inner = (e && *e) ? std::max(1, std::atoi(e)) : 1;
-  }
+  const bool cross = bj_cross() != 0;
+  // a pair below this mass is skipped: the pair problems of one sweep
+  // (npair intra + nblk (nblk - 1) / 2 cross, or the latter alone) together
+  // stay below the target
+  const int nprob = cross ? npair + nblk * (nblk - 1) / 2 : nblk * (nblk - 1) / 2;
+  const double skip2 = off_abs * off_abs / (double)std::max(1, nprob);
+  // a target far above the rounding level allows the short-chain rotations
+  const bool fast = off_abs > 0.0;
   hipLaunchKernelGGL(k_bj_init, dim3(grid_for((int64_t)mpb * mpb)), dim3(256), 0, s, A, lda, m, mpb, Z, ldz);
   if (hipGetLastError() != hipSuccess) return PW_ERR_HIP;
   for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
@@ -978,16 +1120,14 @@ static int eig_block(double2 *A, int64_t lda, int m, double *w, double2 *Z, int6
       return PW_ERR_HIP;
     // converged to the rounding level, or to the caller's target (or NaN)
     if (!(h_acc[0] > std::max(kOffRel * (double)mpb * h_acc[1], off_abs * off_abs))) break;
-    for (int r = 0; r < nblk - 1; ++r) {
-      // a target far above the rounding level allows the short-chain rotations
-      if (off_abs > 0.0)
-        hipLaunchKernelGGL(k_bj_inner<true>, dim3(npair), dim3(1024), 0, s, A, lda, nblk, r, U, inner,
-                           skip2, rotated);
+    // the intra round (r = -1) runs full pair solves; the circle rounds then
+    // rotate the cross pairs only
+    for (int r = cross ? -1 : 0; r < nblk - 1; ++r) {
+      const bool c = cross && r >= 0;
+      if (fast)
+        bj_round<true>(c, npair, nblk, r, A, lda, Z, ldz, U, skip2, rotated, s);
       else
-        hipLaunchKernelGGL(k_bj_inner<false>, dim3(npair), dim3(1024), 0, s, A, lda, nblk, r, U, inner,
-                           skip2, rotated);
-      hipLaunchKernelGGL(k_bj_apply, dim3(npair, npair, 2), dim3(256), 0, s, A, lda, Z, ldz, nblk, r, U,
-                         rotated);
+        bj_round<false>(c, npair, nblk, r, A, lda, Z, ldz, U, skip2, rotated, s);
     }
     if (hipGetLastError() != hipSuccess) return PW_ERR_HIP;
   }
