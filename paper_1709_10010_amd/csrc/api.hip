@@ -131,6 +131,8 @@ static int build_stick_map(pw_problem *p, const int32_t *miller, int ts) {
     sm.tile_ptr[tile + 1]++;
   }
   for (int t = 0; t < sm.ntile; ++t) sm.tile_ptr[t + 1] += sm.tile_ptr[t];
+  sm.g_linear = true;
+  for (int64_t e = 0; e < npw && sm.g_linear; ++e) sm.g_linear = sm.gidx[e] == (int32_t)e;
   return PW_OK;
 }
 
@@ -455,6 +457,7 @@ pw_status pw_problem_create(const pw_problem_desc *d, int64_t max_bands, void *s
     return fail(PW_ERR_SHAPE);
   }
   f.gidx = p->d_gidx;
+  f.g_linear = sm.g_linear ? 1 : 0;
   f.gpos = p->d_gpos;
   f.tile_ptr = p->d_tile_ptr;
   f.stick_xy = p->d_stick_xy;

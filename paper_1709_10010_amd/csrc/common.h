@@ -54,6 +54,7 @@ struct StickMap {
   int nst_pad = 0;    // ntile * ts
   int nx = 0;         // distinct x rows holding sticks
   std::vector<int32_t> gidx;     // [npw] caller G index, grouped by tile
+  bool g_linear = false;         // gidx[e] == e: the caller lists G by stick, then z
   std::vector<int32_t> gpos;     // [npw] z * ts + (stick - tile*ts)
   std::vector<int32_t> tile_ptr; // [ntile+1]
   std::vector<int32_t> stick_xy; // [nst] x * N1 + y
@@ -72,6 +73,7 @@ struct FFTDev {
   int nst, ts, ntile, nst_pad, nx;
   AxisPlan px, py, pz;
   const int32_t *gidx, *gpos, *tile_ptr, *stick_xy, *xlist;
+  int g_linear;  // gidx is the identity (the z passes then read and write G in order)
   const int32_t *xslot, *stick_cpos;  // compact plane layout (see StickMap)
   const void *tw0, *tw1, *tw2;  // twiddle tables in the FFT precision
   const void *vplanes;          // [N2][N0][N1] V / (N0 N1 N2) in the FFT precision

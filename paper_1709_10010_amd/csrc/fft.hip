@@ -21,7 +21,10 @@
 //   k_zfft_fwd  per (tile, band): forward FFT along z, gather the sphere,
 //               add the kinetic term t(G) psi(G), write H psi.
 // Only the grid columns that hold sphere points (the z-sticks) ever travel
-// through HBM; the pruned y passes skip rows without sticks.
+// through HBM; the pruned y passes skip rows without sticks.  The G order
+// is the caller's: listed by stick (x, then y, then z on the grid) the z
+// passes read psi and write H psi in order, any other order costs a
+// gather / scatter through the stick map.
 //
 // FFTs are in-place Stockham passes in LDS: in each radix-R pass every
 // thread loads its butterflies' R inputs into registers, applies the
@@ -569,7 +572,7 @@ __global__ __launch_bounds__(NTHR) void k_zfft_inv(FFTDev f, const double2 *__re
   const int e0 = f.tile_ptr[tile], e1 = f.tile_ptr[tile + 1];
   const double2 *src = psi + (int64_t)b * ld;
   for (int e = e0 + tid; e < e1; e += NTHR) {
-    const double2 v = src[f.gidx[e]];
+    const double2 v = src[f.g_linear ? e : f.gidx[e]];
     buf[f.gpos[e]] = V{(T)v.x, (T)v.y};
   }
   __syncthreads();
@@ -907,7 +910,7 @@ __global__ __launch_bounds__(NTHR) void k_zfft_fwd(FFTDev f, const cpx_t<T> *__r
   const double2 *src = psi + (int64_t)b * ld;
   double2 *dst = hpsi + (int64_t)b * ldh;
   for (int e = e0 + tid; e < e1; e += NTHR) {
-    const int gi = f.gidx[e];
+    const int gi = f.g_linear ? e : f.gidx[e];
     const V v = buf[f.gpos[e]];
     double2 o = double2{(double)v.x, (double)v.y};
     if (kinetic) {

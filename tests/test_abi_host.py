@@ -91,3 +91,17 @@ def test_problem_create_rejects_bad_grid_before_device_work():
     h = ctypes.c_void_p()
     st = L.LIB.pw_problem_create(ctypes.byref(d), 4, None, ctypes.byref(h))
     assert st == -2 and b"grid" in L.LIB.pw_last_error()
+
+
+def test_stick_order_is_a_permutation_listed_by_stick():
+    """The front end's G order: the sphere's set unchanged, listed by
+    (h mod N0, k mod N1) and then l mod N2 ascending, so each z-stick's
+    points are consecutive."""
+    from paper_1709_10010_amd.problems import stick_order
+    c = synth.make_cell(1)
+    m0 = gs.gsphere(c.A, c.kpts[0], c.ecut_ha)
+    m = stick_order(m0, c.nr)
+    assert sorted(map(tuple, m.tolist())) == sorted(map(tuple, np.asarray(m0).tolist()))
+    key = [((h % c.nr[0]) * c.nr[1] + k % c.nr[1], l % c.nr[2]) for h, k, l in m.tolist()]
+    assert key == sorted(key)
+    assert len(set(key)) == len(key)

@@ -141,6 +141,27 @@ def test_hpsi_config2_full_block_sampled(lib):
     assert np.abs(a - a.conj().T).max() <= 1e-12 * np.abs(a).max()
 
 
+def _by_stick(miller, nr):
+    """The Miller list re-listed by z-stick: (h mod N0, k mod N1), then l mod N2."""
+    m = np.asarray(miller)
+    return m[np.lexsort((m[:, 2] % nr[2], m[:, 1] % nr[1], m[:, 0] % nr[0]))]
+
+
+@pytest.mark.parametrize("cfg,ik,nb,prec", [(1, 0, 16, 0), (1, 0, 16, 1), (2, 1, 24, 0)])
+def test_hpsi_stick_ordered_sphere(lib, cfg, ik, nb, prec):
+    """G listed by stick: the z passes then read psi and write H psi in order
+    (no gather).  Same check as above on that order; the FP32-FFT form at the
+    precision-form bound."""
+    c = synth.make_cell(cfg)
+    log("hpsi stick order cfg", cfg, "k", ik, "prec", prec)
+    m = _by_stick(ham.problem_from_cell(c, ik).miller, c.nr)
+    po, pl = problems(c, ik=ik, precision=prec, max_bands=nb, miller=m)
+    psi = start_block(c, nb, po.npw, ik=ik)
+    got = _run(lib, pl, psi)
+    ref = ham.hpsi(po, psi)
+    assert rel_err(got, ref) < (TOL if prec == 0 else 5e-6)
+
+
 def test_precond_tpa_matches_oracle(lib):
     import torch
     c = synth.make_cell(1)
