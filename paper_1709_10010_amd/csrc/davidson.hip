@@ -16,6 +16,7 @@
 // changes how H is applied.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "common.h"
@@ -193,6 +194,26 @@ int ortho_block(pw_davidson *d, int m, double2 *T, int n, double2 *dst, int *n_o
 }
 
 }  // namespace
+
+// Active-space cap of the restart (step 5); PW_DAV_ACT_MUL=0 turns it off.
+struct RestartCap {
+  int mul = 3, min = 64, keep = 3;
+};
+static const RestartCap &restart_cap() {
+  static RestartCap c;
+  static bool init = false;
+  if (!init) {
+    auto get = [](const char *n, int dflt) {
+      const char *e = std::getenv(n);
+      return (e && *e) ? std::max(0, std::atoi(e)) : dflt;
+    };
+    c.mul = get("PW_DAV_ACT_MUL", c.mul);
+    c.min = get("PW_DAV_ACT_MIN", c.min);
+    c.keep = get("PW_DAV_ACT_KEEP", c.keep);
+    init = true;
+  }
+  return c;
+}
 
 extern "C" {
 
@@ -397,7 +418,20 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   }
   // 5. restart with the Ritz vectors when the space is full (they already
   //    are the first nb columns of V, with H_s = diag(theta) there)
-  if (d->m + nu > d->mmax) d->m = nb;
+  //    The active part is also capped at act_mul times the bands still to
+  //    converge (at least act_min): late in a solve nearly all of it is
+  //    upper Ritz vectors, which carry almost all of the next subspace
+  //    matrix's off-diagonal mass and none of the wanted pairs.  That
+  //    restart keeps act_keep times as many upper Ritz vectors as bands
+  //    left to converge.
+  if (d->m + nu > d->mmax) {
+    d->m = nb;
+  } else {
+    const int nact = nb - d->nl;
+    const RestartCap &rc = restart_cap();
+    if (rc.mul > 0 && d->m - d->nl + nu > std::max(rc.min, rc.mul * nact))
+      d->m = std::min(d->m, nb + rc.keep * nact);
+  }
   // 6. orthonormalise against the space
   int nk = 0;
   double2 *Vn = d->V + (size_t)d->m * d->ld;
