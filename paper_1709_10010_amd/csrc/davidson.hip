@@ -195,6 +195,17 @@ int ortho_block(pw_davidson *d, int m, double2 *T, int n, double2 *dst, int *n_o
 
 }  // namespace
 
+// Eigensolver stop level relative to the smallest open residual
+// (PW_DAV_OFF_FACTOR).
+static double off_factor() {
+  static double v = -1.0;
+  if (v < 0.0) {
+    const char *e = std::getenv("PW_DAV_OFF_FACTOR");
+    v = (e && *e) ? std::max(1e-6, std::atof(e)) : 3.0;
+  }
+  return v;
+}
+
 // Active-space cap of the restart (step 5); PW_DAV_ACT_MUL=0 turns it off.
 struct RestartCap {
   int mul = 3, min = 64, keep = 3;
@@ -381,9 +392,11 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
     d->prev_rho[n] = d->h_rho[n];
   }
   d->converged = (nu == 0);
-  // next step's eigensolver target: a tenth of the smallest residual still
-  // to converge (never below a tenth of the tolerance)
-  d->off_target = 0.1 * std::max(d->tol, nu ? rho_min : d->tol);
+  // next step's eigensolver target: off_factor (3) times the smallest
+  // residual still to converge, never below that times the tolerance.  The
+  // off-diagonal rest is carried in H_s and counted in every residual, so a
+  // band converges only once its column of it is below the tolerance.
+  d->off_target = off_factor() * std::max(d->tol, nu ? rho_min : d->tol);
   // lock the converged prefix.  An active Ritz value below the largest
   // locked one means the locked bands are not the lowest after all: the
   // locking is dropped and H_s rebuilt over the whole space.

@@ -158,12 +158,15 @@ __device__ __forceinline__ void update_zrow(double2 &zp, double2 &zq, const Rot 
 }
 
 // ---------------------------------------------------------------- LDS Jacobi
-// A: m x m (lda), Hermitian; on exit w[i] = eigenvalue i (unsorted) and
-// Z (ldz) the eigenvectors (column i).  mp = m rounded up to even <= 64.
-__global__ __launch_bounds__(256) void k_jacobi_lds(const double2 *__restrict__ Ain, int64_t lda,
+// A: m x m (lda), Hermitian; on exit w[i] = eigenvalue i (unsorted), Z (ldz)
+// the eigenvectors (column i) and A overwritten by Z^H A Z.  mp = m rounded
+// up to even <= 64.  Sweeps stop at the rounding level or once the
+// off-diagonal mass is at most off_abs^2 (off_abs > 0 also selects the
+// short-chain rotations).
+__global__ __launch_bounds__(256) void k_jacobi_lds(double2 *__restrict__ Ain, int64_t lda,
                                                     int m, double *__restrict__ w,
                                                     double2 *__restrict__ Z, int64_t ldz,
-                                                    int *__restrict__ sweeps_out) {
+                                                    int *__restrict__ sweeps_out, double off_abs) {
   constexpr int MP = 64;
   __shared__ double2 A[MP][MP + 1];
   __shared__ double2 Zs[MP][MP + 1];
@@ -203,14 +206,15 @@ __global__ __launch_bounds__(256) void k_jacobi_lds(const double2 *__restrict__ 
       if (tid < s) red[tid] += red[tid + s];
       __syncthreads();
     }
-    if (tid == 0) done = (offs <= kOffRel * (double)mp * red[0]) ? 1 : 0;
+    if (tid == 0) done = (offs <= fmax(kOffRel * (double)mp * red[0], off_abs * off_abs)) ? 1 : 0;
     __syncthreads();
     if (done) break;
     for (int r = 0; r < mp - 1; ++r) {
       if (tid < np) {
         int p, q;
         pair_of(tid, r, mp, &p, &q);
-        rot[tid] = make_rot(A[p][p].x, A[q][q].x, A[p][q]);
+        rot[tid] = off_abs > 0.0 ? make_rot_fast(A[p][p].x, A[q][q].x, A[p][q])
+                                 : make_rot(A[p][p].x, A[q][q].x, A[p][q]);
       }
       __syncthreads();
       for (int e = tid; e < np * np; e += 256) {
@@ -238,6 +242,7 @@ __global__ __launch_bounds__(256) void k_jacobi_lds(const double2 *__restrict__ 
   for (int e = tid; e < m * m; e += 256) {
     const int i = e % m, j = e / m;
     Z[i + j * ldz] = Zs[i][j];
+    Ain[i + j * lda] = A[i][j];
   }
   if (tid == 0 && sweeps_out) *sweeps_out = sweep;
 }
@@ -1136,14 +1141,14 @@ static int eig_block(double2 *A, int64_t lda, int m, double *w, double2 *Z, int6
 }
 
 // rot_ws: second matrix buffer of the same shape as A (lda x lda).
-bool eig_transforms_in_place(int m) { return ((m + 1) & ~1) > 64 && eig_impl() == 0; }
+bool eig_transforms_in_place(int m) { return ((m + 1) & ~1) <= 64 || eig_impl() == 0; }
 
 int eig_herm(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz, void *rot_ws,
              double *acc_ws, int *sweeps, int coop_blocks, hipStream_t s, double off_abs) {
   if (m <= 0) return PW_OK;
   const int mp = (m + 1) & ~1;
   if (mp <= 64) {
-    hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(256), 0, s, A, lda, m, w, Z, ldz, sweeps);
+    hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(256), 0, s, A, lda, m, w, Z, ldz, sweeps, off_abs);
     return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
   }
   if (eig_impl() == 0) return eig_block(A, lda, m, w, Z, ldz, rot_ws, acc_ws, s, off_abs);
