@@ -31,6 +31,28 @@ constexpr int GB_N = 64;
 constexpr int GB_K = 16;
 constexpr int G_THR = 256;
 
+// Workgroups are dealt to the 8 XCDs round-robin, each XCD with its own L2.
+// A 1-D grid of 8 * ceil(T / 8) blocks is mapped so that XCD x takes tiles
+// x * P .. x * P + P - 1 (P = ceil(T / 8)) in order: tiles next to each other
+// in the tile order (the N tiles of one M tile, the tiles of one K chunk)
+// then run together under one L2, which fetches their shared operand panels
+// from HBM once.  Returns false for the padding blocks.
+__device__ __forceinline__ bool xcd_tile(int64_t ntiles, int64_t *t) {
+  const int64_t per = (ntiles + 7) / 8;
+  const int64_t b = blockIdx.x;
+  *t = (b & 7) * per + (b >> 3);
+  return *t < ntiles;
+}
+static inline dim3 xcd_grid(int64_t ntiles) { return dim3((unsigned)(8 * ((ntiles + 7) / 8))); }
+// tile t -> (M tile, N tile, K chunk) with N fastest, then M, then K
+__device__ __forceinline__ void tile_mnz(int64_t t, int64_t M, int64_t N, int64_t *m0, int64_t *n0, int64_t *z) {
+  const int64_t tn = (N + GB_N - 1) / GB_N, tm = (M + GB_M - 1) / GB_M;
+  const int64_t r = t % (tm * tn);
+  *z = t / (tm * tn);
+  *m0 = (r / tn) * GB_M;
+  *n0 = (r % tn) * GB_N;
+}
+
 // MFMA flavours with K = 4 per instruction: operand lanes hold A[i = l%16][k = l/16]
 // and B[k = l/16][j = l%16].  The accumulator's row for register r of lane l
 // differs: l/16 + 4r for the f64 instruction, 4(l/16) + r for the f32 one.
@@ -186,20 +208,22 @@ template <typename MF> __device__ __forceinline__ void zero_acc(Acc<MF> &acc) {
     for (int j = 0; j < 2; ++j) acc.rr[i][j] = acc.ii[i][j] = acc.ri[i][j] = acc.ir[i][j] = z;
 }
 
-// CN: grid (tilesM, tilesN, splits).  out = C (splits == 1) or part[split] (M x N, ld M).
+// CN: tiles (M, N, K chunk) over an XCD-mapped 1-D grid.  out = C (one chunk) or
+// part[chunk] (M x N, ld M).
 // A in storage type TA (double2 or float2), B complex128 rounded to MF::S on load.
 template <typename MF, typename TA>
 __global__ __launch_bounds__(G_THR, 2) void k_zgemm_cn(int64_t M, int64_t N, int64_t K,
                                                        const TA *__restrict__ A, int64_t lda,
                                                        const double2 *__restrict__ B, int64_t ldb,
                                                        double2 *__restrict__ C, int64_t ldc,
-                                                       int64_t kchunk, int direct) {
+                                                       int64_t kchunk, int direct, int64_t nsplit) {
   using S2 = typename MF::S2;
   __shared__ LdsTile<S2> As;
   __shared__ LdsTile<S2> Bs;
-  const int64_t m0 = (int64_t)blockIdx.x * GB_M;
-  const int64_t n0 = (int64_t)blockIdx.y * GB_N;
-  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  int64_t t, m0, n0, kz;
+  if (!xcd_tile(((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N) * nsplit, &t)) return;
+  tile_mnz(t, M, N, &m0, &n0, &kz);
+  const int64_t kb = kz * kchunk;
   const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
   const int wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -221,7 +245,7 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_cn(int64_t M, int64_t N, int
     mma_stage<MF>(As, Bs, acc, wm, wn);
     __syncthreads();
   }
-  double2 *out = direct ? C : C + (int64_t)blockIdx.z * M * N;
+  double2 *out = direct ? C : C + kz * M * N;
   const int64_t ldo = direct ? ldc : M;
   for_each_out<MF, true>(acc, wm, wn, [&](int mi, int ni, double re, double im) {
     const int64_t m = m0 + mi, n = n0 + ni;
@@ -245,7 +269,8 @@ __global__ void k_splitk_reduce(int64_t M, int64_t N, int splits, const double2 
   }
 }
 
-// NN: grid (tilesM, tilesN).  C = alpha A B + beta C (C complex128, combined in FP64).
+// NN: tiles (M, N) over an XCD-mapped 1-D grid.  C = alpha A B + beta C (C complex128,
+// combined in FP64).
 template <typename MF, typename TA>
 __global__ __launch_bounds__(G_THR, 2) void k_zgemm_nn(int64_t M, int64_t N, int64_t K, double alpha,
                                                        const TA *__restrict__ A, int64_t lda,
@@ -255,8 +280,9 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_nn(int64_t M, int64_t N, int
   using S2 = typename MF::S2;
   __shared__ LdsTile<S2> As;
   __shared__ LdsTile<S2> Bs;
-  const int64_t m0 = (int64_t)blockIdx.x * GB_M;
-  const int64_t n0 = (int64_t)blockIdx.y * GB_N;
+  int64_t t, m0, n0, kz;
+  if (!xcd_tile(((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N), &t)) return;
+  tile_mnz(t, M, N, &m0, &n0, &kz);
   const int wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   Acc<MF> acc;
@@ -437,11 +463,12 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_cn_bf16(int64_t M, int64_t N
                                                             const ushort2 *__restrict__ A, int64_t lda,
                                                             const double2 *__restrict__ B, int64_t ldb,
                                                             double2 *__restrict__ C, int64_t ldc,
-                                                            int64_t kchunk, int direct) {
+                                                            int64_t kchunk, int direct, int64_t nsplit) {
   __shared__ BfTile At, Bt;
-  const int64_t m0 = (int64_t)blockIdx.x * GB_M;
-  const int64_t n0 = (int64_t)blockIdx.y * GB_N;
-  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  int64_t t, m0, n0, kz;
+  if (!xcd_tile(((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N) * nsplit, &t)) return;
+  tile_mnz(t, M, N, &m0, &n0, &kz);
+  const int64_t kb = kz * kchunk;
   const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
   const int wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -467,7 +494,7 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_cn_bf16(int64_t M, int64_t N
     bf_stage(At, Bt, acc, wm, wn);
     __syncthreads();
   }
-  double2 *out = direct ? C : C + (int64_t)blockIdx.z * M * N;
+  double2 *out = direct ? C : C + kz * M * N;
   const int64_t ldo = direct ? ldc : M;
   bf_out<true>(acc, wm, wn, [&](int mi, int ni, double re, double im) {
     const int64_t m = m0 + mi, n = n0 + ni;
@@ -481,8 +508,9 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_nn_bf16(int64_t M, int64_t N
                                                             int64_t ldb, double beta,
                                                             double2 *__restrict__ C, int64_t ldc) {
   __shared__ BfTile At, Bt;
-  const int64_t m0 = (int64_t)blockIdx.x * GB_M;
-  const int64_t n0 = (int64_t)blockIdx.y * GB_N;
+  int64_t t, m0, n0, kz;
+  if (!xcd_tile(((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N), &t)) return;
+  tile_mnz(t, M, N, &m0, &n0, &kz);
   const int wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   AccF acc;
@@ -573,18 +601,19 @@ int zgemm_cn_p(int prec, int64_t M, int64_t N, int64_t K, const void *A, int64_t
   if (kchunk <= 0) kchunk = kq;
   const int direct = (splits == 1) ? 1 : 0;
   void *out = direct ? C : part;
-  dim3 grid((unsigned)((M + GB_M - 1) / GB_M), (unsigned)((N + GB_N - 1) / GB_N), (unsigned)splits);
+  const int64_t ns = splits;
+  const dim3 grid = xcd_grid(((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N) * ns);
   const double2 *Bd = static_cast<const double2 *>(B);
   double2 *O = static_cast<double2 *>(out);
   if (prec == PW_FP64)
     hipLaunchKernelGGL((k_zgemm_cn<MF64, double2>), grid, dim3(G_THR), 0, s, M, N, K,
-                       static_cast<const double2 *>(A), lda, Bd, ldb, O, ldc, kchunk, direct);
+                       static_cast<const double2 *>(A), lda, Bd, ldb, O, ldc, kchunk, direct, ns);
   else if (prec == PW_MIXED_FP32)
     hipLaunchKernelGGL((k_zgemm_cn<MF32, float2>), grid, dim3(G_THR), 0, s, M, N, K,
-                       static_cast<const float2 *>(A), lda, Bd, ldb, O, ldc, kchunk, direct);
+                       static_cast<const float2 *>(A), lda, Bd, ldb, O, ldc, kchunk, direct, ns);
   else
     hipLaunchKernelGGL(k_zgemm_cn_bf16, grid, dim3(G_THR), 0, s, M, N, K,
-                       static_cast<const ushort2 *>(A), lda, Bd, ldb, O, ldc, kchunk, direct);
+                       static_cast<const ushort2 *>(A), lda, Bd, ldb, O, ldc, kchunk, direct, ns);
   if (hipGetLastError() != hipSuccess) return PW_ERR_HIP;
   return direct ? PW_OK : launch_reduce(M, N, splits, part, C, ldc, s);
 }
@@ -592,7 +621,7 @@ int zgemm_cn_p(int prec, int64_t M, int64_t N, int64_t K, const void *A, int64_t
 int zgemm_nn_p(int prec, int64_t M, int64_t N, int64_t K, double alpha, const void *A, int64_t lda,
                const void *B, int64_t ldb, double beta, void *C, int64_t ldc, hipStream_t s) {
   if (M <= 0 || N <= 0) return PW_OK;
-  dim3 grid((unsigned)((M + GB_M - 1) / GB_M), (unsigned)((N + GB_N - 1) / GB_N));
+  const dim3 grid = xcd_grid(((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N));
   const double2 *Bd = static_cast<const double2 *>(B);
   double2 *Cd = static_cast<double2 *>(C);
   if (prec == PW_FP64)
