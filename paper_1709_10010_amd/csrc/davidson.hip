@@ -143,8 +143,11 @@ int ortho_block(pw_davidson *d, int m, double2 *T, int n, double2 *dst, int *n_o
   const char *where = "pw_davidson: orthonormalisation failed";
   double2 *src = T, *out = dst;
   for (int round = 0; round < 2 && n > 0; ++round) {
+    // two Gram-Schmidt passes against V in the first round; in the second
+    // the block is already orthogonal to V to ~eps kappa and one pass
+    // takes it to the rounding level
     if (m > 0) {
-      for (int c = 0; c < 2; ++c) {
+      for (int c = 0; c < (round == 0 ? 2 : 1); ++c) {
         DV_RC(cn(d, m, n, d->V, src, d->C, d->lde, s));
         DV_RC(nn(d, n, m, -1.0, d->V, d->C, d->lde, 1.0, src, s));
       }
