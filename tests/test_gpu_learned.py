@@ -7,8 +7,8 @@ start from the same block; the converged eigenvalues must agree to 1e-6 Ry,
 and on a held-out cell of the training family (15 Ry, 256 bands) the network
 must need fewer Davidson iterations than TPA (the validated gain).  On the
 30 Ry evaluation cell the network is only required to converge to TPA's
-eigenvalues: there it takes fewer iterations but more H*psi than TPA, and the
-recorded ratios say so.
+eigenvalues: there it needs more iterations and more H*psi than TPA, and the
+logged counts say so.
 """
 import json
 import os
