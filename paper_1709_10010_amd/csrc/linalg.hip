@@ -924,6 +924,67 @@ __global__ __launch_bounds__(1024) void k_trinv_blk(const double2 *__restrict__ 
   }
 }
 
+// X = L^{-1} and B = X^H by block columns, one workgroup per block column
+// J of kTriBS columns (they are independent): forward substitution over the
+// block rows, X_JJ = L_JJ^{-1} and X_IJ = -L_II^{-1} sum_{K=J..I-1} L_IK X_KJ
+// for I > J, with the block column held in LDS (dynamic, n x kTriBS) and
+// each diagonal solve by one thread per column.  Block rows above J are
+// zero.
+__global__ __launch_bounds__(256) void k_trinv_cols(const double2 *__restrict__ L, int64_t ldl, int n,
+                                                    double2 *__restrict__ X, int64_t ldx,
+                                                    double2 *__restrict__ B, int64_t ldb) {
+  constexpr int BS = kTriBS;
+  extern __shared__ __align__(16) unsigned char smem_t[];
+  double2 *Xc = reinterpret_cast<double2 *>(smem_t);  // [n][BS + 1], row i = global row i
+  constexpr int XS = BS + 1;
+  __shared__ double2 T[BS][BS + 1];
+  const int J = blockIdx.x;
+  const int nbk = (n + BS - 1) / BS;
+  const int tid = threadIdx.x;
+  const int r = tid / BS, c = tid % BS;  // element (r, c) of a BS x BS block
+  const int j0 = J * BS;
+  const int jc = j0 + c;                  // global column of this thread's element
+  for (int I = J; I < nbk; ++I) {
+    const int i0 = I * BS;
+    // T = delta_IJ I - sum_{K=J..I-1} L_IK X_KJ (element (r, c))
+    double2 acc = double2{(I == J && r == c) ? 1.0 : 0.0, 0.0};
+    const int gi = i0 + r;
+    if (gi < n && jc < n) {
+      for (int k = j0; k < i0; ++k) {
+        const double2 a = L[gi + (int64_t)k * ldl], x = Xc[k * XS + c];
+        acc.x -= a.x * x.x - a.y * x.y;
+        acc.y -= a.x * x.y + a.y * x.x;
+      }
+    }
+    T[r][c] = acc;
+    __syncthreads();
+    // X_IJ = L_II^{-1} T: thread c < BS solves column c down the block rows
+    if (tid < BS) {
+      for (int rr = 0; rr < BS && i0 + rr < n; ++rr) {
+        const int g = i0 + rr;
+        double2 v = T[rr][tid];
+        for (int k = 0; k < rr; ++k) {
+          const double2 a = L[g + (int64_t)(i0 + k) * ldl], x = Xc[(i0 + k) * XS + tid];
+          v.x -= a.x * x.x - a.y * x.y;
+          v.y -= a.x * x.y + a.y * x.x;
+        }
+        const double dinv = 1.0 / L[g + (int64_t)g * ldl].x;
+        Xc[g * XS + tid] = double2{v.x * dinv, v.y * dinv};
+      }
+    }
+    __syncthreads();
+  }
+  // X[:, J] (zero above the diagonal block) and B = X^H (rows J of B)
+  for (int e = tid; e < n * BS; e += 256) {
+    const int i = e % n, cc = e / n, col = j0 + cc;
+    if (col >= n) continue;
+    const double2 x = i >= j0 ? Xc[i * XS + cc] : double2{0.0, 0.0};
+    const double2 xv = i >= col ? x : double2{0.0, 0.0};
+    X[i + (int64_t)col * ldx] = xv;
+    B[col + (int64_t)i * ldb] = double2{xv.x, -xv.y};
+  }
+}
+
 // B = (L^{-1})^H (upper triangular, ldb): column c of X = L^{-1} e_c by
 // forward substitution, one thread per column; B[c][i] = conj(X[i][c]).
 __global__ void k_trinv_h(const double2 *__restrict__ L, int64_t ldl, int n, double2 *__restrict__ X,
@@ -1228,9 +1289,21 @@ int cholesky(const double2 *S, int64_t lds, int n, double2 *L, int64_t ldl, doub
 int trinv_h(const double2 *L, int64_t ldl, int n, double2 *X, int64_t ldx, double2 *B, int64_t ldb,
             hipStream_t s) {
   if (n <= 0) return PW_OK;
-  if (chol_impl() == 0)
+  if (chol_impl() == 0 && n <= kCholMaxN) {
+    const size_t lds = sizeof(double2) * (size_t)n * (kTriBS + 1);
+    static bool attr = false;
+    if (!attr) {
+      if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_trinv_cols),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(double2) * kCholMaxN * (kTriBS + 1))) != hipSuccess)
+        return PW_ERR_HIP;
+      attr = true;
+    }
+    hipLaunchKernelGGL(k_trinv_cols, dim3((n + kTriBS - 1) / kTriBS), dim3(256), lds, s, L, ldl, n, X, ldx, B,
+                       ldb);
+  } else if (chol_impl() == 2) {
     hipLaunchKernelGGL(k_trinv_blk, dim3(1), dim3(1024), 0, s, L, ldl, n, X, ldx, B, ldb);
-  else
+  } else
     hipLaunchKernelGGL(k_trinv_h, dim3((n + 63) / 64), dim3(64), 0, s, L, ldl, n, X, ldx, B, ldb);
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
