@@ -354,21 +354,22 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   // 2. rotate the active space into the Ritz basis (V <- V Z, W <- W Z): the
   //    first nb columns are the Ritz vectors, the active H_s becomes diag(w),
   //    and the next bordered H_s is nearly diagonal, so its Jacobi solve is
-  //    short.  The locked columns are carried over unchanged.
+  //    short.  The locked columns are carried over unchanged.  The Ritz
+  //    vectors are rotated first; the upper columns only once step 5 has
+  //    decided how many of them the space keeps.
   const size_t lcol = (size_t)nl * d->ld;
-  DV_RC(nn(d, ma, ma, 1.0, d->V + lcol, d->Ae, d->lde, 0.0, d->Vt + lcol, s));
-  DV_RC(nn(d, ma, ma, 1.0, d->W + lcol, d->Ae, d->lde, 0.0, d->Wt + lcol, s));
+  const int nw = nb - nl;
+  DV_RC(nn(d, nw, ma, 1.0, d->V + lcol, d->Ae, d->lde, 0.0, d->Vt + lcol, s));
+  DV_RC(nn(d, nw, ma, 1.0, d->W + lcol, d->Ae, d->lde, 0.0, d->Wt + lcol, s));
   if (nl > 0) {
     PW_HIP(hipMemcpyAsync(d->Vt, d->V, lcol * sizeof(double2), hipMemcpyDeviceToDevice, s));
     PW_HIP(hipMemcpyAsync(d->Wt, d->W, lcol * sizeof(double2), hipMemcpyDeviceToDevice, s));
   }
-  std::swap(d->V, d->Vt);
-  std::swap(d->W, d->Wt);
   if (!carry) DV_RC(set_diag(d->Hs + hoff, d->lde, ma, d->w_sorted, s));
   if (nb > nl)
     PW_HIP(hipMemcpyAsync(d->theta + nl, d->w_sorted, (nb - nl) * sizeof(double), hipMemcpyDeviceToDevice, s));
-  PW_HIP(hipMemcpyAsync(d->X, d->V, (size_t)nb * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
-  PW_HIP(hipMemcpyAsync(d->HX, d->W, (size_t)nb * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  PW_HIP(hipMemcpyAsync(d->X, d->Vt, (size_t)nb * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  PW_HIP(hipMemcpyAsync(d->HX, d->Wt, (size_t)nb * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
   // 3. residuals
   {
     ProfScope ps(&d->p->prof, PW_STAGE_VEC, s);
@@ -403,17 +404,50 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   // lock the converged prefix.  An active Ritz value below the largest
   // locked one means the locked bands are not the lowest after all: the
   // locking is dropped and H_s rebuilt over the whole space.
+  bool lock_drop = false;
   if (!d->converged) {
     if (nl > 0 && nl < nb && d->h_theta[nl] < d->h_theta[nl - 1] - d->tol) {
       d->nl = 0;
-      DV_RC(cn(d, d->m, d->m, d->V, d->W, d->Hs, d->lde, s));
-      DV_RC(hermitize(d->Hs, d->lde, 0, d->m, s));
-      d->off_target = 0.0;
+      lock_drop = true;
     } else {
       int l = nl;
       while (l < nb && d->h_rho[l] < d->tol) ++l;
       d->nl = l;
     }
+  }
+  // 5. restart with the Ritz vectors when the space is full (they are the
+  //    first nb columns of the rotated V, with H_s = diag(theta) there)
+  //    The active part is also capped at act_mul times the bands still to
+  //    converge (at least act_min): late in a solve nearly all of it is
+  //    upper Ritz vectors, which carry almost all of the next subspace
+  //    matrix's off-diagonal mass and none of the wanted pairs.  That
+  //    restart keeps act_keep times as many upper Ritz vectors as bands
+  //    left to converge.  A converged solve keeps the whole space.
+  int keep = d->m;
+  if (!d->converged) {
+    if (d->m + nu > d->mmax) {
+      keep = nb;
+    } else {
+      const int nact = nb - d->nl;
+      const RestartCap &rc = restart_cap();
+      if (rc.mul > 0 && d->m - d->nl + nu > std::max(rc.min, rc.mul * nact))
+        keep = std::min(d->m, nb + rc.keep * nact);
+    }
+  }
+  // the upper columns that stay: nb .. keep-1
+  if (keep > nb) {
+    const size_t ucol = (size_t)nb * d->ld;
+    const double2 *Zu = d->Ae + (size_t)nw * d->lde;
+    DV_RC(nn(d, keep - nb, ma, 1.0, d->V + lcol, Zu, d->lde, 0.0, d->Vt + ucol, s));
+    DV_RC(nn(d, keep - nb, ma, 1.0, d->W + lcol, Zu, d->lde, 0.0, d->Wt + ucol, s));
+  }
+  std::swap(d->V, d->Vt);
+  std::swap(d->W, d->Wt);
+  d->m = keep;
+  if (lock_drop) {
+    DV_RC(cn(d, d->m, d->m, d->V, d->W, d->Hs, d->lde, s));
+    DV_RC(hermitize(d->Hs, d->lde, 0, d->m, s));
+    d->off_target = 0.0;
   }
   if (converged) *converged = d->converged ? 1 : 0;
   if (d->converged) return PW_OK;
@@ -431,22 +465,6 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
       DV_RC(precond_idx(d->p->d_kin, d->tn, d->dU, d->R, d->ld, d->T, d->ld, d->npw, nu,
                         precond_kind, s));
     }
-  }
-  // 5. restart with the Ritz vectors when the space is full (they already
-  //    are the first nb columns of V, with H_s = diag(theta) there)
-  //    The active part is also capped at act_mul times the bands still to
-  //    converge (at least act_min): late in a solve nearly all of it is
-  //    upper Ritz vectors, which carry almost all of the next subspace
-  //    matrix's off-diagonal mass and none of the wanted pairs.  That
-  //    restart keeps act_keep times as many upper Ritz vectors as bands
-  //    left to converge.
-  if (d->m + nu > d->mmax) {
-    d->m = nb;
-  } else {
-    const int nact = nb - d->nl;
-    const RestartCap &rc = restart_cap();
-    if (rc.mul > 0 && d->m - d->nl + nu > std::max(rc.min, rc.mul * nact))
-      d->m = std::min(d->m, nb + rc.keep * nact);
   }
   // 6. orthonormalise against the space
   int nk = 0;
