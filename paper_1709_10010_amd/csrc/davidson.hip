@@ -23,7 +23,7 @@
 
 namespace pw {
 int eig_herm(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz, void *rot_ws,
-             double *acc_ws, int *sweeps, int coop_blocks, hipStream_t s, double off_abs);
+             double *acc_ws, int *sweeps, int coop_blocks, hipStream_t s, double off_abs, int nwant);
 bool eig_transforms_in_place(int m);
 int coop_jacobi_blocks();
 int eig_select(const double *w, int m, int nsel, double *wsel, int *idx, const double2 *Z, int64_t ldz,
@@ -171,7 +171,7 @@ int ortho_block(pw_davidson *d, int m, double2 *T, int n, double2 *dst, int *n_o
         ProfScope ps(&d->p->prof, PW_STAGE_EIG, s);
         DV_RC(copy_mat(d->S, n, d->Ae, d->lde, n, n, s));
         DV_RC(eig_herm(d->Ae, d->lde, n, d->lam, d->Ze, d->lde, d->rot_ws, d->acc_ws, d->sweeps,
-                       d->coop, s, 0.0));
+                       d->coop, s, 0.0, 0));
       }
       PW_HIP(hipMemcpyAsync(d->h_lam, d->lam, n * sizeof(double), hipMemcpyDeviceToHost, s));
       PW_HIP(hipStreamSynchronize(s));
@@ -207,6 +207,19 @@ static double off_factor() {
     v = (e && *e) ? std::max(1e-6, std::atof(e)) : 3.0;
   }
   return v;
+}
+
+// The eigensolver's stop test counts only pairs that touch the nb - nl
+// lowest diagonal entries (PW_EIG_WANTED=0 counts every pair): the residual
+// of an active band sees its own column of the carried rest, and the rest
+// among upper directions is carried and rotated on in later steps.
+static bool eig_wanted() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = std::getenv("PW_EIG_WANTED");
+    v = (e && *e) ? std::atoi(e) : 1;
+  }
+  return v != 0;
 }
 
 // Active-space cap of the restart (step 5); PW_DAV_ACT_MUL=0 turns it off.
@@ -347,7 +360,7 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
     ProfScope ps(&d->p->prof, PW_STAGE_EIG, s);
     DV_RC(copy_mat(d->Hs + hoff, d->lde, d->Ae, d->lde, ma, ma, s));
     DV_RC(eig_herm(d->Ae, d->lde, ma, d->w_all, d->Ze, d->lde, d->rot_ws, d->acc_ws, d->sweeps,
-                   d->coop, s, carry ? d->off_target : 0.0));
+                   d->coop, s, carry ? d->off_target : 0.0, carry && eig_wanted() ? nb - nl : 0));
     DV_RC(eig_select(d->w_all, ma, ma, d->w_sorted, d->idx_all, d->Ze, d->lde, d->Ae, d->lde, s,
                      carry ? d->Ae : nullptr, d->lde, d->Hs + hoff, d->lde));
   }

@@ -30,7 +30,9 @@
 #include <hip/hip_cooperative_groups.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
+#include <vector>
 
 #include "common.h"
 
@@ -634,8 +636,9 @@ __global__ __launch_bounds__(256) void k_bj_apply(double2 *__restrict__ A, int64
 }
 
 // off-diagonal and total mass of the mpb x mpb matrix -> acc[0..1] (acc zeroed by caller)
+// (only pairs (i, j) with min(a_ii, a_jj) <= thr count as off-diagonal)
 __global__ __launch_bounds__(256) void k_offnorm(const double2 *__restrict__ A, int64_t lda, int n,
-                                                 double *__restrict__ acc) {
+                                                 double *__restrict__ acc, double thr) {
   __shared__ double red[2][256];
   double off = 0.0, tot = 0.0;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)n * n;
@@ -644,7 +647,7 @@ __global__ __launch_bounds__(256) void k_offnorm(const double2 *__restrict__ A, 
     const double2 v = A[i + (int64_t)j * lda];
     const double a2 = v.x * v.x + v.y * v.y;
     tot += a2;
-    if (i != j) off += a2;
+    if (i != j && fmin(A[i + (int64_t)i * lda].x, A[j + (int64_t)j * lda].x) <= thr) off += a2;
   }
   red[0][threadIdx.x] = off;
   red[1][threadIdx.x] = tot;
@@ -1158,7 +1161,8 @@ static void bj_round(bool cross, int npair, int nblk, int r, double2 *A, int64_t
 }
 
 static int eig_block(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz, void *uws,
-                     double *acc, hipStream_t s, double off_abs) {
+                     double *acc, hipStream_t s, double off_abs, int nwant) {
+  std::vector<double> h_diag(nwant > 0 ? m : 0);
   const int mpb = (m + kSub - 1) / kSub * kSub;
   const int nblk = mpb / kBJ;
   const int npair = nblk / 2;
@@ -1179,8 +1183,19 @@ static int eig_block(double2 *A, int64_t lda, int m, double *w, double2 *Z, int6
   if (hipGetLastError() != hipSuccess) return PW_ERR_HIP;
   for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
     if (hipMemsetAsync(acc, 0, 2 * sizeof(double), s) != hipSuccess) return PW_ERR_HIP;
+    double thr = INFINITY;
+    if (nwant > 0 && nwant < m) {
+      // the nwant-th smallest diagonal entry: pairs above it on both sides
+      // are not counted
+      hipLaunchKernelGGL(k_diag_out, dim3((m + 255) / 256), dim3(256), 0, s, A, lda, m, w);
+      if (hipMemcpyAsync(h_diag.data(), w, m * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return PW_ERR_HIP;
+      std::nth_element(h_diag.begin(), h_diag.begin() + (nwant - 1), h_diag.begin() + m);
+      thr = h_diag[nwant - 1];
+    }
     hipLaunchKernelGGL(k_offnorm, dim3(grid_for((int64_t)mpb * mpb, 256, 256)), dim3(256), 0, s, A, lda,
-                       mpb, acc);
+                       mpb, acc, thr);
     if (hipMemcpyAsync(h_acc, acc, 2 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return PW_ERR_HIP;
@@ -1205,14 +1220,14 @@ static int eig_block(double2 *A, int64_t lda, int m, double *w, double2 *Z, int6
 bool eig_transforms_in_place(int m) { return ((m + 1) & ~1) <= 64 || eig_impl() == 0; }
 
 int eig_herm(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz, void *rot_ws,
-             double *acc_ws, int *sweeps, int coop_blocks, hipStream_t s, double off_abs) {
+             double *acc_ws, int *sweeps, int coop_blocks, hipStream_t s, double off_abs, int nwant) {
   if (m <= 0) return PW_OK;
   const int mp = (m + 1) & ~1;
   if (mp <= 64) {
     hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(256), 0, s, A, lda, m, w, Z, ldz, sweeps, off_abs);
     return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
   }
-  if (eig_impl() == 0) return eig_block(A, lda, m, w, Z, ldz, rot_ws, acc_ws, s, off_abs);
+  if (eig_impl() == 0) return eig_block(A, lda, m, w, Z, ldz, rot_ws, acc_ws, s, off_abs, nwant);
   double2 *B = static_cast<double2 *>(rot_ws);
   void *args[] = {&A, &B, &lda, &m, &w, &Z, &ldz, &acc_ws, &sweeps};
   // about 8 block updates per thread: fewer workgroups make each grid barrier cheaper
@@ -1376,7 +1391,7 @@ pw_status pw_eigh(const void *A, int64_t lda, int32_t m, double *w, void *Z, int
   double *acc = wu + mp;
   int *idx = reinterpret_cast<int *>(acc + 2 * kMaxSweeps + 2);
   int rc = copy_mat(static_cast<const double2 *>(A), lda, Ac, mp, m, m, s);
-  if (rc == PW_OK) rc = eig_herm(Ac, mp, m, wu, Zw, mp, Bw, acc, nullptr, coop, s, 0.0);
+  if (rc == PW_OK) rc = eig_herm(Ac, mp, m, wu, Zw, mp, Bw, acc, nullptr, coop, s, 0.0, 0);
   if (rc == PW_OK)
     rc = eig_select(wu, m, m, w, idx, Zw, mp, static_cast<double2 *>(Z), ldz, s, nullptr, 0, nullptr, 0);
   if (rc != PW_OK) set_error("pw_eigh: launch failed");
