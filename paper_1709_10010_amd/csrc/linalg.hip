@@ -159,6 +159,36 @@ __device__ __forceinline__ void update_zrow(double2 &zp, double2 &zq, const Rot 
   zq = nq;
 }
 
+// X <- J_a^H X J_b for the 2x2 block X = [a b; c d] (rows p_a, q_a; columns
+// p_b, q_b).  J = diag(1, e) R with R = [[c, s], [-s, c]] real, so the phase
+// scales row q_a by conj(e_a) and column q_b by e_b, then the real rotations
+// mix the rows and the columns.
+__device__ __forceinline__ void rotate_block(double2 &a, double2 &b, double2 &c, double2 &d, const Rot &ra,
+                                             const Rot &rb) {
+  const double2 eb{rb.er, rb.ei}, eac{ra.er, -ra.ei};
+  b = cm(b, eb);
+  d = cm(eac, cm(d, eb));
+  c = cm(eac, c);
+  // columns: (x, y) -> (c x - s y, s x + c y)
+  const double2 a1{rb.c * a.x - rb.s * b.x, rb.c * a.y - rb.s * b.y};
+  const double2 b1{rb.s * a.x + rb.c * b.x, rb.s * a.y + rb.c * b.y};
+  const double2 c1{rb.c * c.x - rb.s * d.x, rb.c * c.y - rb.s * d.y};
+  const double2 d1{rb.s * c.x + rb.c * d.x, rb.s * c.y + rb.c * d.y};
+  // rows: (u, v) -> (c u - s v, s u + c v)
+  a = double2{ra.c * a1.x - ra.s * c1.x, ra.c * a1.y - ra.s * c1.y};
+  c = double2{ra.s * a1.x + ra.c * c1.x, ra.s * a1.y + ra.c * c1.y};
+  b = double2{ra.c * b1.x - ra.s * d1.x, ra.c * b1.y - ra.s * d1.y};
+  d = double2{ra.s * b1.x + ra.c * d1.x, ra.s * b1.y + ra.c * d1.y};
+}
+
+// (z_p, z_q) <- (z_p, z_q) J for one row of the accumulated unitary
+__device__ __forceinline__ void rotate_cols(double2 &zp, double2 &zq, const Rot &r) {
+  const double2 y = cm(zq, double2{r.er, r.ei});
+  const double2 x = zp;
+  zp = double2{r.c * x.x - r.s * y.x, r.c * x.y - r.s * y.y};
+  zq = double2{r.s * x.x + r.c * y.x, r.s * x.y + r.c * y.y};
+}
+
 // ---------------------------------------------------------------- LDS Jacobi
 // A: m x m (lda), Hermitian; on exit w[i] = eigenvalue i (unsorted), Z (ldz)
 // the eigenvectors (column i) and A overwritten by Z^H A Z.  mp = m rounded
@@ -225,7 +255,7 @@ __global__ __launch_bounds__(256) void k_jacobi_lds(double2 *__restrict__ Ain, i
         pair_of(ka, r, mp, &pa, &qa);
         pair_of(kb, r, mp, &pb, &qb);
         double2 a = A[pa][pb], b = A[pa][qb], c = A[qa][pb], d = A[qa][qb];
-        update_block(a, b, c, d, rot[ka], rot[kb]);
+        rotate_block(a, b, c, d, rot[ka], rot[kb]);
         A[pa][pb] = a;
         A[pa][qb] = b;
         A[qa][pb] = c;
@@ -235,7 +265,7 @@ __global__ __launch_bounds__(256) void k_jacobi_lds(double2 *__restrict__ Ain, i
         const int i = e % mp, kb = e / mp;
         int pb, qb;
         pair_of(kb, r, mp, &pb, &qb);
-        update_zrow(Zs[i][pb], Zs[i][qb], rot[kb]);
+        rotate_cols(Zs[i][pb], Zs[i][qb], rot[kb]);
       }
       __syncthreads();
     }
@@ -382,36 +412,6 @@ __device__ __forceinline__ void step_pair(int k, int st, int *p, int *q) {
   } else {
     pair_of(k, st, kSub, p, q);
   }
-}
-
-// X <- J_a^H X J_b for the 2x2 block X = [a b; c d] (rows p_a, q_a; columns
-// p_b, q_b).  J = diag(1, e) R with R = [[c, s], [-s, c]] real, so the phase
-// scales row q_a by conj(e_a) and column q_b by e_b, then the real rotations
-// mix the rows and the columns.
-__device__ __forceinline__ void rotate_block(double2 &a, double2 &b, double2 &c, double2 &d, const Rot &ra,
-                                             const Rot &rb) {
-  const double2 eb{rb.er, rb.ei}, eac{ra.er, -ra.ei};
-  b = cm(b, eb);
-  d = cm(eac, cm(d, eb));
-  c = cm(eac, c);
-  // columns: (x, y) -> (c x - s y, s x + c y)
-  const double2 a1{rb.c * a.x - rb.s * b.x, rb.c * a.y - rb.s * b.y};
-  const double2 b1{rb.s * a.x + rb.c * b.x, rb.s * a.y + rb.c * b.y};
-  const double2 c1{rb.c * c.x - rb.s * d.x, rb.c * c.y - rb.s * d.y};
-  const double2 d1{rb.s * c.x + rb.c * d.x, rb.s * c.y + rb.c * d.y};
-  // rows: (u, v) -> (c u - s v, s u + c v)
-  a = double2{ra.c * a1.x - ra.s * c1.x, ra.c * a1.y - ra.s * c1.y};
-  c = double2{ra.s * a1.x + ra.c * c1.x, ra.s * a1.y + ra.c * c1.y};
-  b = double2{ra.c * b1.x - ra.s * d1.x, ra.c * b1.y - ra.s * d1.y};
-  d = double2{ra.s * b1.x + ra.c * d1.x, ra.s * b1.y + ra.c * d1.y};
-}
-
-// (z_p, z_q) <- (z_p, z_q) J for one row of the accumulated unitary
-__device__ __forceinline__ void rotate_cols(double2 &zp, double2 &zq, const Rot &r) {
-  const double2 y = cm(zq, double2{r.er, r.ei});
-  const double2 x = zp;
-  zp = double2{r.c * x.x - r.s * y.x, r.c * x.y - r.s * y.y};
-  zq = double2{r.s * x.x + r.c * y.x, r.s * x.y + r.c * y.y};
 }
 
 // Sum over the 256 threads of a block (4 waves) of two values.
