@@ -137,17 +137,30 @@ int nn(pw_davidson *d, int64_t N, int64_t K, double alpha, const double2 *A, con
     }                         \
   } while (0)
 
+// Gram-Schmidt passes against V in the first orthonormalisation round
+// (PW_DAV_GS_FIRST, 1 or 2; default 1).
+static int gs_first() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = std::getenv("PW_DAV_GS_FIRST");
+    v = (e && *e && std::atoi(e) == 2) ? 2 : 1;
+  }
+  return v;
+}
+
 // Orthonormalise n columns at T against V[0:m] into dst; *n_out columns kept.
 int ortho_block(pw_davidson *d, int m, double2 *T, int n, double2 *dst, int *n_out, hipStream_t s) {
   const bool set_error_if_empty = true;
   const char *where = "pw_davidson: orthonormalisation failed";
   double2 *src = T, *out = dst;
   for (int round = 0; round < 2 && n > 0; ++round) {
-    // two Gram-Schmidt passes against V in the first round; in the second
-    // the block is already orthogonal to V to ~eps kappa and one pass
-    // takes it to the rounding level
+    // one Gram-Schmidt pass against V per round: the Cholesky-QR between
+    // the two passes normalises what the first left, and the second pass
+    // takes the V components that normalisation amplified to the rounding
+    // level (twice is enough); a block numerically inside span(V) goes to
+    // the rank-revealing path below
     if (m > 0) {
-      for (int c = 0; c < (round == 0 ? 2 : 1); ++c) {
+      for (int c = 0; c < (round == 0 ? gs_first() : 1); ++c) {
         DV_RC(cn(d, m, n, d->V, src, d->C, d->lde, s));
         DV_RC(nn(d, n, m, -1.0, d->V, d->C, d->lde, 1.0, src, s));
       }
