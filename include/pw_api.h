@@ -202,8 +202,9 @@ pw_status pw_davidson_init(pw_davidson *d, const void *psi0, int64_t ld, void *s
  * part (the columns past the converged prefix) exceeds max(64, 3 x the bands
  * left to converge) -- that restart keeps the lowest Ritz vectors plus three
  * upper ones per band left (PW_DAV_ACT_MUL / _MIN / _KEEP override; MUL=0
- * disables it) --, two rounds of
- * classical Gram-Schmidt + Cholesky-QR, H on the new vectors and the
+ * disables it) --, classical Gram-Schmidt + Cholesky-QR (a second round
+ * unless the first kept at least 1 % of every column's norm), H on the new
+ * vectors and the
  * bordered subspace matrix.  Reads the residual norms back (one host sync)
  * and sets *converged.  Returns PW_ERR_NOT_FINITE on a non-finite norm.
  */

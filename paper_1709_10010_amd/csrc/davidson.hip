@@ -47,6 +47,7 @@ int mlp_precond_idx(const pw_mlp *net, pw_problem *p, const double *theta, const
                     const double *tn, hipStream_t s);
 int mlp_fallback(const int *bad, pw_problem *p, const double *tn, const int *idx, const double2 *R,
                  int64_t ld, double2 *T, int nu, hipStream_t s);
+int col_norms2(const double2 *T, int64_t ld, int64_t npw, int n, double *nrm2, hipStream_t s);
 }  // namespace pw
 
 using namespace pw;
@@ -75,6 +76,9 @@ struct pw_davidson {
   // pinned host mirrors
   double *h_theta = nullptr, *h_rho = nullptr, *h_lam = nullptr;
   int *h_U = nullptr, *h_flag = nullptr, *h_keep = nullptr;
+  // orthonormalisation: column norms^2 before it, the Cholesky diagonal
+  double *cnorm = nullptr, *h_cnorm = nullptr;
+  double2 *h_ldiag = nullptr;
   // learned-preconditioner fallback: residual of the previous step and the
   // number of consecutive non-decreasing steps, per band; bands that stall
   // for two steps use TPA for the rest of the solve
@@ -95,10 +99,11 @@ void free_dav(pw_davidson *d) {
   void *dev[] = {d->V,  d->W,  d->X,  d->HX,    d->R,     d->T,    d->Hs,    d->Ae,  d->Ze,
                  d->Y,  d->C,  d->S,  d->L,     d->Xi,    d->Bi,   d->w_all, d->theta, d->rho,
                  d->tn, d->lam, d->idx_sel, d->dU, d->keep, d->flag, d->sweeps, d->rot_ws,
-                 d->acc_ws, d->part, d->bad, d->Vt, d->Wt, d->w_sorted, d->idx_all};
+                 d->acc_ws, d->part, d->bad, d->Vt, d->Wt, d->w_sorted, d->idx_all, d->cnorm};
   for (void *b : dev)
     if (b) (void)hipFree(b);
-  void *host[] = {d->h_theta, d->h_rho, d->h_lam, d->h_U, d->h_flag, d->h_keep, d->h_bad};
+  void *host[] = {d->h_theta, d->h_rho, d->h_lam, d->h_U, d->h_flag, d->h_keep, d->h_bad, d->h_cnorm,
+                  d->h_ldiag};
   for (void *b : host)
     if (b) (void)hipHostFree(b);
   delete d;
@@ -137,6 +142,16 @@ int nn(pw_davidson *d, int64_t N, int64_t K, double alpha, const double2 *A, con
     }                         \
   } while (0)
 
+// PW_DAV_ORTHO_SKIP=0 always runs the second orthonormalisation round.
+static bool ortho_skip() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = std::getenv("PW_DAV_ORTHO_SKIP");
+    v = (e && *e) ? std::atoi(e) : 1;
+  }
+  return v != 0;
+}
+
 // Gram-Schmidt passes against V in the first orthonormalisation round
 // (PW_DAV_GS_FIRST, 1 or 2; default 1).
 static int gs_first() {
@@ -153,6 +168,12 @@ int ortho_block(pw_davidson *d, int m, double2 *T, int n, double2 *dst, int *n_o
   const bool set_error_if_empty = true;
   const char *where = "pw_davidson: orthonormalisation failed";
   double2 *src = T, *out = dst;
+  // column norms before any projection, for the second round's test below
+  const bool may_skip = ortho_skip() && n > 0;
+  if (may_skip) {
+    DV_RC(col_norms2(T, d->ld, d->npw, n, d->cnorm, s));
+    PW_HIP(hipMemcpyAsync(d->h_cnorm, d->cnorm, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
   for (int round = 0; round < 2 && n > 0; ++round) {
     // one Gram-Schmidt pass against V per round: the Cholesky-QR between
     // the two passes normalises what the first left, and the second pass
@@ -171,6 +192,9 @@ int ortho_block(pw_davidson *d, int m, double2 *T, int n, double2 *dst, int *n_o
       DV_RC(cholesky(d->S, n, n, d->L, n, 1e-12, d->flag, s));
     }
     PW_HIP(hipMemcpyAsync(d->h_flag, d->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (may_skip && round == 0)
+      PW_HIP(hipMemcpy2DAsync(d->h_ldiag, sizeof(double2), d->L, (size_t)(n + 1) * sizeof(double2),
+                              sizeof(double2), n, hipMemcpyDeviceToHost, s));
     PW_HIP(hipStreamSynchronize(s));
     if (*d->h_flag == 0) {
       {
@@ -178,6 +202,24 @@ int ortho_block(pw_davidson *d, int m, double2 *T, int n, double2 *dst, int *n_o
         DV_RC(trinv_h(d->L, n, n, d->Xi, n, d->Bi, n, s));
       }
       DV_RC(nn(d, n, n, 1.0, src, d->Bi, n, 0.0, out, s));
+      // L_jj^2 is what column j kept of its squared norm through the
+      // projection and against the columns before it.  If every column
+      // kept at least kKeep^2 of it, the normalisation amplified what the
+      // first pass left by at most 1/kKeep, Cholesky-QR's loss of
+      // orthogonality is at most about eps / kKeep^2, and a second round
+      // would change the block at the 1e-12 level: it is skipped.
+      if (may_skip && round == 0) {
+        constexpr double kKeep2 = 1e-4;  // kKeep = 1e-2
+        bool keep_all = true;
+        for (int j = 0; j < n && keep_all; ++j) {
+          const double l = d->h_ldiag[j].x;
+          keep_all = std::isfinite(l) && l * l > kKeep2 * d->h_cnorm[j];
+        }
+        if (keep_all) {
+          std::swap(src, out);
+          break;
+        }
+      }
     } else {
       // rank-revealing path: S = U diag(lam) U^H, keep lam > 1e-12 max
       {
@@ -202,7 +244,7 @@ int ortho_block(pw_davidson *d, int m, double2 *T, int n, double2 *dst, int *n_o
     }
     std::swap(src, out);
   }
-  // after two rounds the result sits in T (src after the final swap)
+  // the result sits in src after the last swap (dst after one round, T after two)
   if (src != dst && n > 0)
     PW_HIP(hipMemcpyAsync(dst, src, (size_t)n * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
   *n_out = n;
@@ -290,7 +332,8 @@ pw_status pw_davidson_create(pw_problem *p, int64_t nbands, int64_t max_subspace
             dalloc(&d->sweeps, 1) && dalloc(&d->bad, nb) && dalloc((double2 **)&d->rot_ws, lde * lde) &&
             dalloc(&d->acc_ws, 128) && halloc(&d->h_theta, nb) && halloc(&d->h_rho, nb) &&
             halloc(&d->h_lam, lde) && halloc(&d->h_U, nb) && halloc(&d->h_flag, 1) &&
-            halloc(&d->h_keep, nb) && halloc(&d->h_bad, nb);
+            halloc(&d->h_keep, nb) && halloc(&d->h_bad, nb) && dalloc(&d->cnorm, nb) &&
+            halloc(&d->h_cnorm, nb) && halloc(&d->h_ldiag, nb);
   d->part_bytes = (size_t)32 * lde * nb * sizeof(double2);
   ok = ok && dalloc((char **)&d->part, d->part_bytes);
   if (!ok) {

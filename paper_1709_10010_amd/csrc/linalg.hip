@@ -1037,6 +1037,25 @@ __global__ __launch_bounds__(256) void k_residual(const double2 *__restrict__ X,
   if (threadIdx.x == 0) rho[b] = sqrt(red[0]);
 }
 
+// nrm2[b] = sum_g |T[b][g]|^2, one workgroup per column
+__global__ __launch_bounds__(256) void k_colnorm2(const double2 *__restrict__ T, int64_t ld, int64_t npw,
+                                                  double *__restrict__ nrm2) {
+  __shared__ double red[256];
+  const int b = blockIdx.x;
+  double s = 0.0;
+  for (int64_t g = threadIdx.x; g < npw; g += 256) {
+    const double2 x = T[b * ld + g];
+    s += x.x * x.x + x.y * x.y;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) nrm2[b] = red[0];
+}
+
 // Hermitise the new columns [m0, m1) of H (ldh): mirror the off-diagonal
 // rectangle into rows, average the new diagonal block with its adjoint.
 __global__ void k_hermitize(double2 *__restrict__ H, int64_t ldh, int m0, int m1) {
@@ -1320,6 +1339,12 @@ int trinv_h(const double2 *L, int64_t ldl, int n, double2 *X, int64_t ldx, doubl
     hipLaunchKernelGGL(k_trinv_blk, dim3(1), dim3(1024), 0, s, L, ldl, n, X, ldx, B, ldb);
   } else
     hipLaunchKernelGGL(k_trinv_h, dim3((n + 63) / 64), dim3(64), 0, s, L, ldl, n, X, ldx, B, ldb);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
+int col_norms2(const double2 *T, int64_t ld, int64_t npw, int n, double *nrm2, hipStream_t s) {
+  if (n <= 0) return PW_OK;
+  hipLaunchKernelGGL(k_colnorm2, dim3(n), dim3(256), 0, s, T, ld, npw, nrm2);
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
 
