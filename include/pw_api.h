@@ -204,9 +204,10 @@ pw_status pw_davidson_init(pw_davidson *d, const void *psi0, int64_t ld, void *s
  * upper ones per band left (PW_DAV_ACT_MUL / _MIN / _KEEP override; MUL=0
  * disables it) --, classical Gram-Schmidt + Cholesky-QR (a second round
  * unless the first kept at least 1 % of every column's norm), H on the new
- * vectors and the
- * bordered subspace matrix.  Reads the residual norms back (one host sync)
- * and sets *converged.  Returns PW_ERR_NOT_FINITE on a non-finite norm.
+ * vectors and the bordered subspace matrix.  Synchronises the stream to
+ * read back the residual norms, the Cholesky checks and the eigensolver's
+ * convergence per sweep; sets *converged.  Returns PW_ERR_NOT_FINITE on a
+ * non-finite norm.
  */
 pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *net,
                            void *stream, int32_t *converged);
