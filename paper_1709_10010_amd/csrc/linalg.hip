@@ -15,14 +15,20 @@
 //           becomes J_a^H A_ab J_b) and accumulates  Z <- Z J.
 // A sweep is m'-1 rounds (m' = m rounded up to even; a padding index has a
 // zero row so its rotations are the identity).  Sweeps repeat until the
-// off-diagonal mass is at the rounding level (4 m eps^2 of the total), at
-// most kMaxSweeps; elements below eps sqrt(|a_pp a_qq|) are not rotated.
+// off-diagonal mass is at the rounding level (4 m eps^2 of the total) or
+// below a caller's absolute target, at most kMaxSweeps; elements below
+// eps sqrt(|a_pp a_qq|) are not rotated.  The block variant can also count
+// only the pairs that touch the lowest few diagonal entries, which is all a
+// Davidson step needs of the subspace problem.
 //
-// Small matrices (m' <= 64) run in one workgroup with A and Z in LDS; larger
-// ones run as a cooperative grid in which each thread recomputes the two
-// rotations of its block from the previous round's matrix and writes into
-// a second buffer, so a round costs one grid-wide barrier.  Both are
-// bounded: every wave leaves after at most kMaxSweeps sweeps.
+// Small matrices (m' <= 64) run in one workgroup with A and Z in LDS.
+// Larger ones run by blocks of 16 indices: each block pair's 32 x 32
+// sub-problem is solved in LDS by one workgroup, and the pair unitaries are
+// then applied to the whole matrix and to Z (see the block-Jacobi section).
+// An element-wise variant on a cooperative grid (each thread recomputes the
+// two rotations of its block from the previous round's matrix and writes
+// into a second buffer, one grid-wide barrier per round) stays selectable.
+// All are bounded: every wave leaves after at most kMaxSweeps sweeps.
 //
 // Also here: eigenvalue sort / Ritz-vector selection, Cholesky of a small
 // Hermitian positive matrix with breakdown detection, the inverse of its
