@@ -781,6 +781,94 @@ __device__ __forceinline__ void group_fft_dif(V *e, int q, const V *tw) {
   reg_fft<V, M, INV, L>(e, tw);
 }
 
+// Exchange of halves (M = N / 4 even).  The four lanes of a line are
+// l + 16 q (q = 0..3), so the two lane levels pair lanes 16 apart (rows of a
+// wave, v_permlane16_swap) and 32 apart (halves of a wave,
+// v_permlane32_swap).  One such move swaps a register x of one lane with a
+// register y of its partner: afterwards the lane with the bit clear holds
+// (x, x of the partner) and the partner (y of the first lane, y).  Applied to
+// the element pairs (e[k], e[k + M/2]) it leaves in each lane the two inputs
+// of M/2 radix-2 butterflies, so a level costs each lane M/2 twiddle
+// products and half the exchange traffic of a join over all M values.
+template <int B> __device__ __forceinline__ void row_swap(unsigned &x, unsigned &y) {
+  if constexpr (B == 0) {
+    const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+    x = r[0];
+    y = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+    x = r[0];
+    y = r[1];
+  }
+}
+template <int B> __device__ __forceinline__ void row_swap(double &x, double &y) {
+  const unsigned long long a = __double_as_longlong(x), b = __double_as_longlong(y);
+  unsigned al = (unsigned)a, ah = (unsigned)(a >> 32), bl = (unsigned)b, bh = (unsigned)(b >> 32);
+  row_swap<B>(al, bl);
+  row_swap<B>(ah, bh);
+  x = __longlong_as_double((long long)(((unsigned long long)ah << 32) | al));
+  y = __longlong_as_double((long long)(((unsigned long long)bh << 32) | bl));
+}
+template <int B> __device__ __forceinline__ void row_swap(float &x, float &y) {
+  unsigned a = __float_as_uint(x), b = __float_as_uint(y);
+  row_swap<B>(a, b);
+  x = __uint_as_float(a);
+  y = __uint_as_float(b);
+}
+template <int B, typename V> __device__ __forceinline__ void row_swap_c(V &x, V &y) {
+  row_swap<B>(x.x, y.x);
+  row_swap<B>(x.y, y.y);
+}
+
+// One lane level by exchange of halves over lane bit 4 + B, twiddles
+// t[ST k] (conjugated for INV), k < M/2.  Decimation in time: swap, then
+// (X, Y) <- (X + t Y, X - t Y); decimation in frequency: (X, Y) <-
+// (X + Y, (X - Y) t), then swap.
+template <typename V, int M, int B, int ST, bool INV, bool DIT>
+__device__ __forceinline__ void level_halves(V *e, const V *t) {
+  constexpr int H = M / 2;
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    V x = e[k], y = e[k + H];
+    const V w = t[ST * k];
+    if constexpr (DIT) {
+      row_swap_c<B>(x, y);
+      const V u = INV ? c_mulconj(y, w) : c_mul(y, w);
+      e[k] = c_add(x, u);
+      e[k + H] = c_sub(x, u);
+    } else {
+      const V d = c_sub(x, y);
+      x = c_add(x, y);
+      y = INV ? c_mulconj(d, w) : c_mul(d, w);
+      row_swap_c<B>(x, y);
+      e[k] = x;
+      e[k + H] = y;
+    }
+  }
+}
+
+// Lane q of a line holds, between the two transforms, X[c_q + k] in e[k] and
+// X[c_q + 2M + k] in e[k + M/2] (k < M/2), c_q = (q >> 1) M/2 + (q & 1) M.
+template <int M> __device__ __forceinline__ int halves_base(int q) { return (q >> 1) * (M / 2) + (q & 1) * M; }
+template <int M> constexpr int halves_off(int k) { return k < M / 2 ? k : k + 3 * (M / 2); }
+
+// decimation in time: lane q holds x[4 j + q], ends in the layout above
+template <typename V, int N, bool INV>
+__device__ __forceinline__ void group_fft_dit_h(V *e, int q, const V *tw) {
+  constexpr int M = N / 4;
+  reg_fft<V, M, INV, 4>(e, tw);
+  level_halves<V, M, 1, 2, INV, true>(e, tw + (q >> 1) * M);
+  level_halves<V, M, 0, 1, INV, true>(e, tw + halves_base<M>(q));
+}
+// decimation in frequency: from the layout above to X[4 k + q]
+template <typename V, int N, bool INV>
+__device__ __forceinline__ void group_fft_dif_h(V *e, int q, const V *tw) {
+  constexpr int M = N / 4;
+  level_halves<V, M, 0, 1, INV, false>(e, tw + halves_base<M>(q));
+  level_halves<V, M, 1, 2, INV, false>(e, tw + (q >> 1) * M);
+  reg_fft<V, M, INV, 4>(e, tw);
+}
+
 // hides the values from the optimiser: twiddle reads and lane-dependent
 // twiddle addresses derived from them stay inside the loop body that uses
 // them instead of being hoisted and held in registers across the loop
@@ -795,15 +883,18 @@ __device__ __forceinline__ void opaque(int &a, int &b) { asm volatile("" : "+v"(
 // Per band-plane: clear, scatter the sticks, inverse y transform of each
 // column, then per row the inverse x transform, the V(r) product and the
 // forward x transform back to back, forward y transform of each column,
-// gather.  Every line is held by a group of L lanes.  Cubic grids of
-// compile-time size N (a multiple of L) only.  Workgroups of four waves
+// gather.  Every line is held by a group of L lanes: L consecutive lanes
+// joined by quad permutations, or with XH (L = 4, N / 4 even) lanes
+// l + 16 q joined by exchange of halves.  Cubic grids of compile-time size
+// N (a multiple of L) only.  Workgroups of four waves
 // and a register budget of three (FP64) or four (FP32) waves per SIMD let
 // two or more workgroups share a CU and hide each other's latencies.
-template <typename T, int N, int L, int NTHR>
+template <typename T, int N, int L, int NTHR, bool XH>
 __global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 4)))
 void k_plane_r(FFTDev f, cpx_t<T> *__restrict__ sticks, int nb, int group) {
   using V = cpx_t<T>;
   static_assert(N % L == 0 && NTHR % (4 * L) == 0, "lane-group plane pass: whole lane groups");
+  static_assert(!XH || (L == 4 && (N / 4) % 2 == 0 && NTHR % 64 == 0), "exchange of halves: L = 4, N / 4 even");
   constexpr int M = N / L, LS = N | 1, NL = NTHR / L;
   extern __shared__ __align__(16) unsigned char smem[];
   const int nx = f.nx;
@@ -814,9 +905,10 @@ void k_plane_r(FFTDev f, cpx_t<T> *__restrict__ sticks, int nb, int group) {
   const int z = blockIdx.x % N;
   const int g = blockIdx.x / N;
   const int tid = threadIdx.x;
-  const int line = tid / L;
-  const int q = tid % L;
-  const int rq = rev_lane<L>(q);
+  const int line = XH ? (tid >> 6) * 16 + (tid & 15) : tid / L;
+  const int q = XH ? (tid >> 4) & 3 : tid % L;
+  // first x of the lane's run between the transforms (XH: c_q, else rev(q) M)
+  const int xq = XH ? halves_base<M>(q) : rev_lane<L>(q) * M;
   for (int i = tid; i < N; i += NTHR) {
     xs[i] = f.xslot[i];
     tw[i] = static_cast<const V *>(f.tw0)[i];
@@ -837,9 +929,12 @@ void k_plane_r(FFTDev f, cpx_t<T> *__restrict__ sticks, int nb, int group) {
       opaque(zero, qo);
 #pragma unroll
       for (int j = 0; j < M; ++j) e[j] = p[L * j + q];
-      group_fft_dit<V, L, N, true>(e, qo, tw + zero);
+      if constexpr (XH)
+        group_fft_dit_h<V, N, true>(e, qo, tw + zero);
+      else
+        group_fft_dit<V, L, N, true>(e, qo, tw + zero);
 #pragma unroll
-      for (int k = 0; k < M; ++k) p[rq * M + k] = e[k];
+      for (int k = 0; k < M; ++k) p[xq + (XH ? halves_off<M>(k) : k)] = e[k];
     }
     __syncthreads();
     for (int y = line; y < N; y += NL) {
@@ -848,15 +943,21 @@ void k_plane_r(FFTDev f, cpx_t<T> *__restrict__ sticks, int nb, int group) {
       opaque(zero, qo);
 #pragma unroll
       for (int j = 0; j < M; ++j) e[j] = pl[xs[L * j + q] * LS + y];
-      group_fft_dit<V, L, N, true>(e, qo, tw + zero);
+      if constexpr (XH)
+        group_fft_dit_h<V, N, true>(e, qo, tw + zero);
+      else
+        group_fft_dit<V, L, N, true>(e, qo, tw + zero);
       // V and the output slots are read only now (their offsets are opaque
       // past the transform), not held in registers across it
-      int vo = rq * M * N + y, xo = q;
+      int vo = xq * N + y, xo = q;
       opaque(vo, xo);
       const T *vr = vp + vo;
 #pragma unroll
-      for (int k = 0; k < M; ++k) e[k] = c_scale(e[k], vr[k * N]);
-      group_fft_dif<V, L, N, false>(e, qo, tw + zero);
+      for (int k = 0; k < M; ++k) e[k] = c_scale(e[k], vr[(XH ? halves_off<M>(k) : k) * N]);
+      if constexpr (XH)
+        group_fft_dif_h<V, N, false>(e, qo, tw + zero);
+      else
+        group_fft_dif<V, L, N, false>(e, qo, tw + zero);
       opaque(xo, zero);
 #pragma unroll
       for (int k = 0; k < M; ++k) {
@@ -871,8 +972,11 @@ void k_plane_r(FFTDev f, cpx_t<T> *__restrict__ sticks, int nb, int group) {
       int zero = 0, qo = q;
       opaque(zero, qo);
 #pragma unroll
-      for (int j = 0; j < M; ++j) e[j] = p[rq * M + j];
-      group_fft_dif<V, L, N, false>(e, qo, tw + zero);
+      for (int j = 0; j < M; ++j) e[j] = p[xq + (XH ? halves_off<M>(j) : j)];
+      if constexpr (XH)
+        group_fft_dif_h<V, N, false>(e, qo, tw + zero);
+      else
+        group_fft_dif<V, L, N, false>(e, qo, tw + zero);
 #pragma unroll
       for (int k = 0; k < M; ++k) p[L * k + q] = e[k];
     }
@@ -1051,7 +1155,17 @@ int plane_kernel_default() {
   return v;
 }
 
-// lanes per line: four where N allows (register pressure), else two
+// lanes per line: four where N allows (register pressure), else two.  With
+// four lanes and N / 4 even the lane levels exchange halves; PW_PLANE_HALVES=0
+// keeps the quad-permutation joins.
+static bool plane_halves() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = std::getenv("PW_PLANE_HALVES");
+    v = (e && *e) ? std::atoi(e) : 1;
+  }
+  return v != 0;
+}
 #ifndef PW_PLANE_R_THREADS
 #define PW_PLANE_R_THREADS 256
 #endif
@@ -1060,8 +1174,9 @@ static int plane_r(const FFTDev &f, void *sticks, int nb, int group, int blocks,
   using V = cpx_t<T>;
   constexpr int L = (N % 4 == 0) ? 4 : 2;
   constexpr int NT = PW_PLANE_R_THREADS;
+  constexpr bool xh_ok = L == 4 && (N / 4) % 2 == 0;
   const size_t lds = sizeof(V) * ((size_t)(f.nx + 1) * (N | 1) + N) + sizeof(int) * N;
-  auto k = k_plane_r<T, N, L, NT>;
+  auto k = (xh_ok && plane_halves()) ? k_plane_r<T, N, L, NT, xh_ok> : k_plane_r<T, N, L, NT, false>;
   if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
   hipLaunchKernelGGL(k, dim3(blocks), dim3(NT), lds, s, f, static_cast<V *>(sticks), nb, group);
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
