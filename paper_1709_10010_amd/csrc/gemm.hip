@@ -12,9 +12,14 @@
 // All matrices are column-major complex128 (band-major blocks).
 //
 // A 256-thread workgroup owns a 64 x 64 complex tile; its four waves each
-// own 32 x 32 = 2 x 2 MFMA blocks.  A complex product takes four real MFMAs
-// (re*re, im*im, re*im, im*re) into four accumulators, combined at the end
-// (with the sign pattern of conj(A) for CN).  K advances 16 complex per
+// own 32 x 32 = 2 x 2 MFMA blocks.  In FP64 a complex product takes three
+// real MFMAs (the three-multiplication form of a complex product, known as
+// 3M): re*re, im*im and (re(A) +- im(A)) (re(B) + im(B)), the sign minus for
+// conj(A), combined at the end into re = rr -+ ii, im = s - rr -+ ii.  That
+// is a quarter fewer MFMAs for two VALU adds per operand pair; the error of
+// the imaginary part is bounded by (|re A| + |im A|)(|re B| + |im B|) terms
+// instead of |re A||im B| + |im A||re B|.  The FP32 flavour keeps four
+// products (re*re, im*im, re*im, im*re).  K advances 16 complex per
 // LDS stage; the next stage's global loads are issued before the current
 // stage's MFMAs.  The MFMA operands are fed "transposed" (the N-side tile
 // as the first operand) so that each lane's output column runs along M,
@@ -60,15 +65,20 @@ struct MF64 {
   using S = double;
   using S2 = double2;
   using acc_t = d4_t;
+  static constexpr bool three = false;  // four real products per complex one
   static __device__ __forceinline__ acc_t mfma(S a, S b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
+struct MF64x3 : MF64 {
+  static constexpr bool three = true;  // three real products per complex one
+};
 struct MF32 {
   using S = float;
   using S2 = float2;
   using acc_t = f4_t;
+  static constexpr bool three = false;
   static __device__ __forceinline__ acc_t mfma(S a, S b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -147,12 +157,15 @@ __device__ __forceinline__ void store_mcontig(LdsTile<S2> &S, const S2 r[4]) {
   for (int u = 0; u < 4; ++u) S[k][m + 16 * u] = r[u];
 }
 
+// Sums of real products: rr = re A re B, ii = im A im B; with three
+// products ri holds (re A +- im A)(re B + im B) and ir is unused, else
+// ri = re A im B and ir = im A re B.
 template <typename MF> struct Acc {
   typename MF::acc_t rr[2][2], ii[2][2], ri[2][2], ir[2][2];
 };
 
 // One LDS stage: As[k][m], Bs[k][n], 16 complex k.
-template <typename MF>
+template <typename MF, bool CONJ_A>
 __device__ __forceinline__ void mma_stage(const LdsTile<typename MF::S2> &As,
                                           const LdsTile<typename MF::S2> &Bs, Acc<MF> &acc, int wm,
                                           int wn) {
@@ -166,15 +179,32 @@ __device__ __forceinline__ void mma_stage(const LdsTile<typename MF::S2> &As,
     for (int i = 0; i < 2; ++i) a[i] = As[kk + lk][wm * 32 + i * 16 + lr];
 #pragma unroll
     for (int j = 0; j < 2; ++j) b[j] = Bs[kk + lk][wn * 32 + j * 16 + lr];
+    if constexpr (MF::three) {
+      typename MF::S sa[2], sb[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < 2; ++i) sa[i] = CONJ_A ? a[i].x - a[i].y : a[i].x + a[i].y;
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        // first operand: N side (rows of the accumulator), second: M side
-        acc.rr[i][j] = MF::mfma(b[j].x, a[i].x, acc.rr[i][j]);
-        acc.ii[i][j] = MF::mfma(b[j].y, a[i].y, acc.ii[i][j]);
-        acc.ri[i][j] = MF::mfma(b[j].y, a[i].x, acc.ri[i][j]);  // re(A) im(B)
-        acc.ir[i][j] = MF::mfma(b[j].x, a[i].y, acc.ir[i][j]);  // im(A) re(B)
+      for (int j = 0; j < 2; ++j) sb[j] = b[j].x + b[j].y;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          // first operand: N side (rows of the accumulator), second: M side
+          acc.rr[i][j] = MF::mfma(b[j].x, a[i].x, acc.rr[i][j]);
+          acc.ii[i][j] = MF::mfma(b[j].y, a[i].y, acc.ii[i][j]);
+          acc.ri[i][j] = MF::mfma(sb[j], sa[i], acc.ri[i][j]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc.rr[i][j] = MF::mfma(b[j].x, a[i].x, acc.rr[i][j]);
+          acc.ii[i][j] = MF::mfma(b[j].y, a[i].y, acc.ii[i][j]);
+          acc.ri[i][j] = MF::mfma(b[j].y, a[i].x, acc.ri[i][j]);  // re(A) im(B)
+          acc.ir[i][j] = MF::mfma(b[j].x, a[i].y, acc.ir[i][j]);  // im(A) re(B)
+        }
       }
     }
   }
@@ -193,9 +223,15 @@ __device__ __forceinline__ void for_each_out(const Acc<MF> &acc, int wm, int wn,
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const double rr = acc.rr[i][j][r], ii = acc.ii[i][j][r];
-        const double ri = acc.ri[i][j][r], ir = acc.ir[i][j][r];
         const double re = CONJ_A ? rr + ii : rr - ii;
-        const double im = CONJ_A ? ri - ir : ri + ir;
+        double im;
+        if constexpr (MF::three) {
+          const double sp = acc.ri[i][j][r];
+          im = CONJ_A ? sp - rr + ii : sp - rr - ii;
+        } else {
+          const double ri = acc.ri[i][j][r], ir = acc.ir[i][j][r];
+          im = CONJ_A ? ri - ir : ri + ir;
+        }
         f(wm * 32 + i * 16 + lm, wn * 32 + j * 16 + MF::row(lane, r), re, im);
       }
 }
@@ -205,7 +241,10 @@ template <typename MF> __device__ __forceinline__ void zero_acc(Acc<MF> &acc) {
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc.rr[i][j] = acc.ii[i][j] = acc.ri[i][j] = acc.ir[i][j] = z;
+    for (int j = 0; j < 2; ++j) {
+      acc.rr[i][j] = acc.ii[i][j] = acc.ri[i][j] = z;
+      if constexpr (!MF::three) acc.ir[i][j] = z;
+    }
 }
 
 // CN: tiles (M, N, K chunk) over an XCD-mapped 1-D grid.  out = C (one chunk) or
@@ -242,7 +281,7 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_cn(int64_t M, int64_t N, int
       load_kcontig(A, lda, k0 + GB_K, m0, ke, M, ra);
       load_kcontig(B, ldb, k0 + GB_K, n0, ke, N, rb);
     }
-    mma_stage<MF>(As, Bs, acc, wm, wn);
+    mma_stage<MF, true>(As, Bs, acc, wm, wn);
     __syncthreads();
   }
   double2 *out = direct ? C : C + kz * M * N;
@@ -300,7 +339,7 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_nn(int64_t M, int64_t N, int
       load_mcontig(A, lda, m0, k0 + GB_K, M, K, ra);
       load_kcontig(B, ldb, k0 + GB_K, n0, K, N, rb);
     }
-    mma_stage<MF>(As, Bs, acc, wm, wn);
+    mma_stage<MF, false>(As, Bs, acc, wm, wn);
     __syncthreads();
   }
   for_each_out<MF, false>(acc, wm, wn, [&](int mi, int ni, double re, double im) {
@@ -571,6 +610,16 @@ int convert_beta(const void *src, void *dst, int64_t n, int prec, hipStream_t s)
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
 
+// FP64 products in the three-multiplication form unless PW_GEMM_3M=0
+static bool gemm_3m() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = std::getenv("PW_GEMM_3M");
+    v = (e && *e) ? std::atoi(e) : 1;
+  }
+  return v != 0;
+}
+
 int choose_splits(int64_t M, int64_t N, int64_t K) {
   const int64_t tiles = ((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N);
   // fill the 2 x 256 workgroup slots once, without a nearly empty second
@@ -605,7 +654,10 @@ int zgemm_cn_p(int prec, int64_t M, int64_t N, int64_t K, const void *A, int64_t
   const dim3 grid = xcd_grid(((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N) * ns);
   const double2 *Bd = static_cast<const double2 *>(B);
   double2 *O = static_cast<double2 *>(out);
-  if (prec == PW_FP64)
+  if (prec == PW_FP64 && gemm_3m())
+    hipLaunchKernelGGL((k_zgemm_cn<MF64x3, double2>), grid, dim3(G_THR), 0, s, M, N, K,
+                       static_cast<const double2 *>(A), lda, Bd, ldb, O, ldc, kchunk, direct, ns);
+  else if (prec == PW_FP64)
     hipLaunchKernelGGL((k_zgemm_cn<MF64, double2>), grid, dim3(G_THR), 0, s, M, N, K,
                        static_cast<const double2 *>(A), lda, Bd, ldb, O, ldc, kchunk, direct, ns);
   else if (prec == PW_MIXED_FP32)
@@ -624,7 +676,10 @@ int zgemm_nn_p(int prec, int64_t M, int64_t N, int64_t K, double alpha, const vo
   const dim3 grid = xcd_grid(((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N));
   const double2 *Bd = static_cast<const double2 *>(B);
   double2 *Cd = static_cast<double2 *>(C);
-  if (prec == PW_FP64)
+  if (prec == PW_FP64 && gemm_3m())
+    hipLaunchKernelGGL((k_zgemm_nn<MF64x3, double2>), grid, dim3(G_THR), 0, s, M, N, K, alpha,
+                       static_cast<const double2 *>(A), lda, Bd, ldb, beta, Cd, ldc);
+  else if (prec == PW_FP64)
     hipLaunchKernelGGL((k_zgemm_nn<MF64, double2>), grid, dim3(G_THR), 0, s, M, N, K, alpha,
                        static_cast<const double2 *>(A), lda, Bd, ldb, beta, Cd, ldc);
   else if (prec == PW_MIXED_FP32)
