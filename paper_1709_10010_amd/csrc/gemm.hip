@@ -105,56 +105,57 @@ template <typename S2> using LdsTile = S2[GB_K][Lds<S2>::stride];
 // Load a 16(k) x 64(mn) tile of a K-contiguous column-major matrix
 // (element (k, c) at P[c * ld + k]) into registers: thread t covers column
 // t/4 and k = t%4 + 4u, u = 0..3 (the four lanes of a column read 16
-// consecutive k together).
-template <typename T, typename S2>
+// consecutive k together).  Values stay in the source type until the LDS
+// store, so a conversion does not wait for the loads of the next stage.
+template <typename T>
 __device__ __forceinline__ void load_kcontig(const T *__restrict__ P, int64_t ld, int64_t k0,
-                                             int64_t c0, int64_t K, int64_t C, S2 r[4]) {
+                                             int64_t c0, int64_t K, int64_t C, T r[4]) {
   const int t = threadIdx.x;
   const int64_t c = c0 + (t >> 2);
   const int64_t k = k0 + (t & 3);
   if (c < C) {
     const T *p = P + c * ld + k;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) r[u] = (k + 4 * u < K) ? cvt2<S2>(p[4 * u]) : S2{0, 0};
+    for (int u = 0; u < 4; ++u) r[u] = (k + 4 * u < K) ? p[4 * u] : T{0, 0};
   } else {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) r[u] = S2{0, 0};
+    for (int u = 0; u < 4; ++u) r[u] = T{0, 0};
   }
 }
-template <typename S2>
-__device__ __forceinline__ void store_kcontig(LdsTile<S2> &S, const S2 r[4]) {
+template <typename S2, typename T>
+__device__ __forceinline__ void store_kcontig(LdsTile<S2> &S, const T r[4]) {
   const int t = threadIdx.x;
   const int c = t >> 2;
   const int k = t & 3;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) S[k + 4 * u][c] = r[u];
+  for (int u = 0; u < 4; ++u) S[k + 4 * u][c] = cvt2<S2>(r[u]);
 }
 
 // Load a 64(m) x 16(k) tile of an M-contiguous column-major matrix
 // (element (m, k) at P[k * ld + m]): thread t covers k = t/16 and
 // m = t%16 + 16u, u = 0..3.
-template <typename T, typename S2>
+template <typename T>
 __device__ __forceinline__ void load_mcontig(const T *__restrict__ P, int64_t ld, int64_t m0,
-                                             int64_t k0, int64_t M, int64_t K, S2 r[4]) {
+                                             int64_t k0, int64_t M, int64_t K, T r[4]) {
   const int t = threadIdx.x;
   const int64_t k = k0 + (t >> 4);
   const int64_t m = m0 + (t & 15);
   if (k < K) {
     const T *p = P + k * ld + m;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) r[u] = (m + 16 * u < M) ? cvt2<S2>(p[16 * u]) : S2{0, 0};
+    for (int u = 0; u < 4; ++u) r[u] = (m + 16 * u < M) ? p[16 * u] : T{0, 0};
   } else {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) r[u] = S2{0, 0};
+    for (int u = 0; u < 4; ++u) r[u] = T{0, 0};
   }
 }
-template <typename S2>
-__device__ __forceinline__ void store_mcontig(LdsTile<S2> &S, const S2 r[4]) {
+template <typename S2, typename T>
+__device__ __forceinline__ void store_mcontig(LdsTile<S2> &S, const T r[4]) {
   const int t = threadIdx.x;
   const int k = t >> 4;
   const int m = t & 15;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) S[k][m + 16 * u] = r[u];
+  for (int u = 0; u < 4; ++u) S[k][m + 16 * u] = cvt2<S2>(r[u]);
 }
 
 // Sums of real products: rr = re A re B, ii = im A im B; with three
@@ -268,7 +269,8 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_cn(int64_t M, int64_t N, int
   const int wm = wave & 1, wn = wave >> 1;
   Acc<MF> acc;
   zero_acc(acc);
-  S2 ra[4], rb[4];
+  TA ra[4];
+  double2 rb[4];
   if (kb < ke) {
     load_kcontig(A, lda, kb, m0, ke, M, ra);
     load_kcontig(B, ldb, kb, n0, ke, N, rb);
@@ -326,7 +328,8 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_nn(int64_t M, int64_t N, int
   const int wm = wave & 1, wn = wave >> 1;
   Acc<MF> acc;
   zero_acc(acc);
-  S2 ra[4], rb[4];
+  TA ra[4];
+  double2 rb[4];
   if (K > 0) {
     load_mcontig(A, lda, m0, 0, M, K, ra);
     load_kcontig(B, ldb, 0, n0, K, N, rb);
@@ -371,82 +374,111 @@ __device__ __forceinline__ unsigned short bf16_rne(float f) {
 }
 __device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
 
+// Rows of 40 bf16 (80 bytes): each group of 8 k starts 16-byte aligned, so
+// a thread stores its 8 values of a row in one write, and the 16 rows a
+// fragment read touches fall on distinct banks.
+constexpr int BB_KP = BB_K + 8;
 struct BfTile {
-  unsigned short re[GB_M][BB_K + 4];
-  unsigned short im[GB_M][BB_K + 4];
+  unsigned short re[GB_M][BB_KP];
+  unsigned short im[GB_M][BB_KP];
 };
+__device__ __forceinline__ uint4 bf_pack8(const unsigned short v[8]) {
+  return uint4{v[0] | ((unsigned)v[1] << 16), v[2] | ((unsigned)v[3] << 16), v[4] | ((unsigned)v[5] << 16),
+               v[6] | ((unsigned)v[7] << 16)};
+}
 
-// K-contiguous source of complex128 (convert) or bf16 pairs: 64 columns x 32 k.
-// Thread t: column t/4, k = 8*(t%4) .. +7.
+// A thread's 8 values of a stage, kept in the source format between the
+// global loads and the LDS store (so the loads of the next stage overlap the
+// MFMAs of this one): complex128, or bf16 (re, im) pairs packed re-low.
+struct BfRawD {
+  double2 v[8];
+};
+struct BfRawH {
+  unsigned w[8];
+};
+__device__ __forceinline__ void bf_split(const BfRawD &r, unsigned short re[8], unsigned short im[8]) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    re[u] = bf16_rne((float)r.v[u].x);
+    im[u] = bf16_rne((float)r.v[u].y);
+  }
+}
+__device__ __forceinline__ void bf_split(const BfRawH &r, unsigned short re[8], unsigned short im[8]) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    re[u] = (unsigned short)(r.w[u] & 0xFFFFu);
+    im[u] = (unsigned short)(r.w[u] >> 16);
+  }
+}
+
+// K-contiguous source, 64 columns x 32 k: thread t: column t/4, k = 8*(t%4) .. +7.
 __device__ __forceinline__ void bf_load_kc(const double2 *__restrict__ P, int64_t ld, int64_t k0,
-                                           int64_t c0, int64_t K, int64_t C, unsigned short re[8],
-                                           unsigned short im[8]) {
+                                           int64_t c0, int64_t K, int64_t C, BfRawD &r) {
   const int t = threadIdx.x;
   const int64_t c = c0 + (t >> 2);
   const int64_t k = k0 + ((t & 3) << 3);
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    double2 v = double2{0.0, 0.0};
-    if (c < C && k + u < K) v = P[c * ld + k + u];
-    re[u] = bf16_rne((float)v.x);
-    im[u] = bf16_rne((float)v.y);
-  }
+  for (int u = 0; u < 8; ++u) r.v[u] = (c < C && k + u < K) ? P[c * ld + k + u] : double2{0.0, 0.0};
 }
 __device__ __forceinline__ void bf_load_kc(const ushort2 *__restrict__ P, int64_t ld, int64_t k0,
-                                           int64_t c0, int64_t K, int64_t C, unsigned short re[8],
-                                           unsigned short im[8]) {
+                                           int64_t c0, int64_t K, int64_t C, BfRawH &r) {
   const int t = threadIdx.x;
   const int64_t c = c0 + (t >> 2);
   const int64_t k = k0 + ((t & 3) << 3);
+  const ushort2 *q = P + c * ld + k;
+  if (c < C && k + 7 < K && (reinterpret_cast<uintptr_t>(q) & 15) == 0) {
+    // 8 (re, im) pairs, 32 bytes: two 16-byte loads
+    const uint4 v0 = reinterpret_cast<const uint4 *>(q)[0], v1 = reinterpret_cast<const uint4 *>(q)[1];
+    const unsigned w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) r.w[u] = w[u];
+    return;
+  }
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     ushort2 v = ushort2{0, 0};
     if (c < C && k + u < K) v = P[c * ld + k + u];
-    re[u] = v.x;
-    im[u] = v.y;
+    r.w[u] = (unsigned)v.x | ((unsigned)v.y << 16);
   }
 }
-__device__ __forceinline__ void bf_store_kc(BfTile &T, const unsigned short re[8], const unsigned short im[8]) {
+template <typename R> __device__ __forceinline__ void bf_store_kc(BfTile &T, const R &r) {
   const int t = threadIdx.x;
   const int c = t >> 2;
   const int k = (t & 3) << 3;
-#pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    T.re[c][k + u] = re[u];
-    T.im[c][k + u] = im[u];
-  }
+  unsigned short re[8], im[8];
+  bf_split(r, re, im);
+  *reinterpret_cast<uint4 *>(&T.re[c][k]) = bf_pack8(re);
+  *reinterpret_cast<uint4 *>(&T.im[c][k]) = bf_pack8(im);
 }
-// M-contiguous bf16 source, 64 m x 32 k: thread t: k = t/8, m = 8*(t%8) .. +7.
+// M-contiguous bf16 source, 64 m x 32 k: thread t: m = t%64, k = 8*(t/64) .. +7
+// (each load instruction reads 64 consecutive m of one k across the wave).
 __device__ __forceinline__ void bf_load_mc(const ushort2 *__restrict__ P, int64_t ld, int64_t m0,
-                                           int64_t k0, int64_t M, int64_t K, unsigned short re[8],
-                                           unsigned short im[8]) {
+                                           int64_t k0, int64_t M, int64_t K, BfRawH &r) {
   const int t = threadIdx.x;
-  const int64_t k = k0 + (t >> 3);
-  const int64_t m = m0 + ((t & 7) << 3);
+  const int64_t m = m0 + (t & 63);
+  const int64_t k = k0 + ((t >> 6) << 3);
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     ushort2 v = ushort2{0, 0};
-    if (k < K && m + u < M) v = P[k * ld + m + u];
-    re[u] = v.x;
-    im[u] = v.y;
+    if (m < M && k + u < K) v = P[(k + u) * ld + m];
+    r.w[u] = (unsigned)v.x | ((unsigned)v.y << 16);
   }
 }
-__device__ __forceinline__ void bf_store_mc(BfTile &T, const unsigned short re[8], const unsigned short im[8]) {
+__device__ __forceinline__ void bf_store_mc(BfTile &T, const BfRawH &r) {
   const int t = threadIdx.x;
-  const int k = t >> 3;
-  const int m = (t & 7) << 3;
-#pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    T.re[m + u][k] = re[u];
-    T.im[m + u][k] = im[u];
-  }
+  const int m = t & 63;
+  const int k = (t >> 6) << 3;
+  unsigned short re[8], im[8];
+  bf_split(r, re, im);
+  *reinterpret_cast<uint4 *>(&T.re[m][k]) = bf_pack8(re);
+  *reinterpret_cast<uint4 *>(&T.im[m][k]) = bf_pack8(im);
 }
 
 struct AccF {
   f4_t rr[2][2], ii[2][2], ri[2][2], ir[2][2];
 };
 
-__device__ __forceinline__ s4_t bf_frag(const unsigned short (*S)[BB_K + 4], int row, int k) {
+__device__ __forceinline__ s4_t bf_frag(const unsigned short (*S)[BB_KP], int row, int k) {
   const unsigned short *p = &S[row][k];
   return s4_t{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
 }
@@ -503,7 +535,7 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_cn_bf16(int64_t M, int64_t N
                                                             const double2 *__restrict__ B, int64_t ldb,
                                                             double2 *__restrict__ C, int64_t ldc,
                                                             int64_t kchunk, int direct, int64_t nsplit) {
-  __shared__ BfTile At, Bt;
+  __shared__ __align__(16) BfTile At, Bt;
   int64_t t, m0, n0, kz;
   if (!xcd_tile(((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N) * nsplit, &t)) return;
   tile_mnz(t, M, N, &m0, &n0, &kz);
@@ -517,18 +549,19 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_cn_bf16(int64_t M, int64_t N
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc.rr[i][j] = acc.ii[i][j] = acc.ri[i][j] = acc.ir[i][j] = z;
-  unsigned short ar[8], ai[8], br[8], bi[8];
+  BfRawH ra;
+  BfRawD rb;
   if (kb < ke) {
-    bf_load_kc(A, lda, kb, m0, ke, M, ar, ai);
-    bf_load_kc(B, ldb, kb, n0, ke, N, br, bi);
+    bf_load_kc(A, lda, kb, m0, ke, M, ra);
+    bf_load_kc(B, ldb, kb, n0, ke, N, rb);
   }
   for (int64_t k0 = kb; k0 < ke; k0 += BB_K) {
-    bf_store_kc(At, ar, ai);
-    bf_store_kc(Bt, br, bi);
+    bf_store_kc(At, ra);
+    bf_store_kc(Bt, rb);
     __syncthreads();
     if (k0 + BB_K < ke) {
-      bf_load_kc(A, lda, k0 + BB_K, m0, ke, M, ar, ai);
-      bf_load_kc(B, ldb, k0 + BB_K, n0, ke, N, br, bi);
+      bf_load_kc(A, lda, k0 + BB_K, m0, ke, M, ra);
+      bf_load_kc(B, ldb, k0 + BB_K, n0, ke, N, rb);
     }
     bf_stage(At, Bt, acc, wm, wn);
     __syncthreads();
@@ -546,7 +579,7 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_nn_bf16(int64_t M, int64_t N
                                                             int64_t lda, const double2 *__restrict__ B,
                                                             int64_t ldb, double beta,
                                                             double2 *__restrict__ C, int64_t ldc) {
-  __shared__ BfTile At, Bt;
+  __shared__ __align__(16) BfTile At, Bt;
   int64_t t, m0, n0, kz;
   if (!xcd_tile(((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N), &t)) return;
   tile_mnz(t, M, N, &m0, &n0, &kz);
@@ -558,18 +591,19 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_nn_bf16(int64_t M, int64_t N
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc.rr[i][j] = acc.ii[i][j] = acc.ri[i][j] = acc.ir[i][j] = z;
-  unsigned short ar[8], ai[8], br[8], bi[8];
+  BfRawH ra;
+  BfRawD rb;
   if (K > 0) {
-    bf_load_mc(A, lda, m0, 0, M, K, ar, ai);
-    bf_load_kc(B, ldb, 0, n0, K, N, br, bi);
+    bf_load_mc(A, lda, m0, 0, M, K, ra);
+    bf_load_kc(B, ldb, 0, n0, K, N, rb);
   }
   for (int64_t k0 = 0; k0 < K; k0 += BB_K) {
-    bf_store_mc(At, ar, ai);
-    bf_store_kc(Bt, br, bi);
+    bf_store_mc(At, ra);
+    bf_store_kc(Bt, rb);
     __syncthreads();
     if (k0 + BB_K < K) {
-      bf_load_mc(A, lda, m0, k0 + BB_K, M, K, ar, ai);
-      bf_load_kc(B, ldb, k0 + BB_K, n0, K, N, br, bi);
+      bf_load_mc(A, lda, m0, k0 + BB_K, M, K, ra);
+      bf_load_kc(B, ldb, k0 + BB_K, n0, K, N, rb);
     }
     bf_stage(At, Bt, acc, wm, wn);
     __syncthreads();
