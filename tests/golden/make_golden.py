@@ -1,9 +1,11 @@
 #!/usr/bin/env python3
 """Writes the stored expected values under tests/golden/ from the FP64 oracle
 alone (dense diagonalisation of the discrete Hamiltonian of eq. pauli_ks on
-the sphere basis; sphere sizes from the cutoff inequality).
+the sphere basis; sphere sizes from the cutoff inequality; the oracle's
+block Davidson at the medium workload's full size).
 
-    python tests/golden/make_golden.py
+    python tests/golden/make_golden.py               # everything (~10 min)
+    python tests/golden/make_golden.py --quick       # without the medium-size Davidson
 
 Regression fixtures: tests/test_golden.py recomputes them with the oracle,
 and the GPU tests compare the library against them.
@@ -38,7 +40,29 @@ def sphere_rows():
     return rows
 
 
+def davidson_config2(ik):
+    """Oracle block Davidson (TPA, soft locking, m_max = 3 nb) on the medium
+    workload at k-point ik, all 256 bands, to a residual 2-norm of 5e-9 Ha
+    (1e-8 Ry) on every band."""
+    from oracle import davidson as odv
+    c = synth.make_cell(2)
+    po = ham.problem_from_cell(c, ik)
+    r = odv.davidson(po, synth.psi_start(c.seed, c.nbands, po.npw, ik), c.nbands, 5e-9)
+    assert r["converged"], "oracle Davidson did not converge"
+    fname = f"config2_k{ik}_davidson256_Ha.txt"
+    with open(os.path.join(HERE, fname), "w") as f:
+        f.write(f"# {c.name} k-point {ik} (crystal {np.round(c.kpts[ik], 6).tolist()}): npw {po.npw}, grid "
+                f"{c.nr[0]}^3, {c.nbands} bands; oracle block Davidson to |Hx - theta x| < 5e-9 Ha "
+                f"({r['iterations']} iterations); columns: theta (Ha), residual 2-norm (Ha); "
+                f"written by make_golden.py (oracle only)\n")
+        for t, rho in zip(r["theta"], r["rho"]):
+            f.write(f"{t:.17e} {rho:.3e}\n")
+
+
 def main():
+    if "--quick" not in sys.argv:
+        for ik in (0, 1):
+            davidson_config2(ik)
     for cfg, nlow, fname in ((0, 8, "tiny_cell_lowest8_Ha.txt"), (1, 16, "config1_lowest16_Ha.txt")):
         c, po, w = eig_fixture(cfg, nlow)
         with open(os.path.join(HERE, fname), "w") as f:

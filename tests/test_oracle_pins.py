@@ -275,6 +275,34 @@ def test_tpa_closed_form_properties():
     assert np.allclose(dv.tpa_k(big) * 2 * big, 1.0, rtol=2e-3)
 
 
+def test_tpa_exact_rational_values():
+    # K(x) = (27+18x+12x^2+8x^3) / (27+18x+12x^2+8x^3+16x^4) at small rationals,
+    # worked by hand: the interior coefficients each change one of these
+    for x, num, den in ((1.0, 65, 81), (2.0, 175, 431), (0.5, 40, 41), (3.0, 405, 1701)):
+        assert abs(dv.tpa_k(x) - num / den) <= 2e-16, (x, dv.tpa_k(x), num / den)
+
+
+def test_tpa_apply_by_hand():
+    # a band that is one plane wave G0 has T_n = t(G0), so x = t(G)/t(G0);
+    # a 0.6/0.8 two-wave band has T_n = 0.36 t1 + 0.64 t2, whatever the
+    # band's overall scale (T_n is a Rayleigh quotient); the residual enters
+    # linearly and the iterate does not
+    t = np.array([0.5, 1.0, 2.0, 4.0, 8.0])
+    X = np.zeros((5, 2), dtype=complex)
+    X[1, 0] = 3.0j                      # not normalised on purpose
+    X[[2, 4], 1] = [0.6, 0.8]
+    R = np.array([[1.0 + 1.0j, 2.0], [0.5j, -1.0], [2.0, 0.25], [-1.0, 1.0j], [0.0, 3.0]])
+    T = dv.tpa_apply(t, X, R)
+    tn1 = 0.36 * 2.0 + 0.64 * 8.0
+    for g in range(5):
+        assert abs(T[g, 0] - dv.tpa_k(t[g] / 1.0) * R[g, 0]) <= 1e-15 * abs(R[g, 0])
+        assert abs(T[g, 1] - dv.tpa_k(t[g] / tn1) * R[g, 1]) <= 1e-15 * abs(R[g, 1])
+    # at G0 the argument is exactly 1: K = 65/81
+    assert abs(T[1, 0] - 65 / 81 * R[1, 0]) <= 1e-15
+    # where t(G) = 2 T_n the factor is 175/431 (the one-wave band at G = 2)
+    assert abs(T[2, 0] - 175 / 431 * R[2, 0]) <= 1e-15 * abs(R[2, 0])
+
+
 # ---------------------------------------------------------------- MLP
 def test_mlp_gradient_central_differences():
     rng = np.random.default_rng(21)
