@@ -30,10 +30,19 @@
  *     nor written.
  *   - "device" pointers are HIP device memory on the current device;
  *     "host" pointers are ordinary host memory.  The caller owns every
- *     pointer it passes.  The library never frees caller memory; it owns
- *     only what it allocates inside a handle (maps, twiddles, a reordered
- *     copy of V_LOC, reduced-precision copies of beta, work buffers), all
- *     released by the matching destroy call.
+ *     pointer it passes, workspaces included, and never loses memory to
+ *     the library: the paper's own library interface runs its routines
+ *     inside resources the caller hands to an init routine (section
+ *     "Modular parallelism").  A problem or Davidson handle keeps every
+ *     large buffer (the reordered V_LOC, the copies of beta, the stick
+ *     buffer, projections, split-K partials, the Davidson space and its
+ *     subspace matrices) in a workspace the caller allocates from the size
+ *     query and binds at create; it stays bound until destroy and must not
+ *     be touched meanwhile.  The handle itself owns only small tables
+ *     (stick maps, twiddles, kinetic energies, D blocks, a few pinned host
+ *     words), released by the matching destroy call.  A handle is used by
+ *     one stream at a time: two calls on one handle from different streams
+ *     race on its workspace.
  *   - stream: a hipStream_t passed as void* (NULL = the null stream).  All
  *     device work of a call is enqueued on that stream; calls return
  *     without waiting for it unless stated.  Buffers must stay valid until
@@ -124,17 +133,33 @@ pw_status pw_gsphere(const double cell[9], const double kpt[3], double ecut,
                      int32_t *miller_out, int64_t cap, int64_t *npw_out);
 
 /*
- * Build a problem handle.  Copies everything it needs from desc (host
- * arrays, V_LOC and beta are copied into library-owned device memory, so
- * the caller's buffers may be freed after the stream has passed this call).
- * max_bands bounds nbands of later pw_hpsi calls (work buffers are sized
- * for it here; pw_hpsi then allocates nothing).  Synchronises `stream`.
+ * Device workspace a problem needs (bytes, into *bytes): the reordered and
+ * scaled V_LOC, the padded complex128 copy of beta (and its FP32 / BF16
+ * copy in the mixed forms), the stick buffer of one FFT sweep, the
+ * projections P and D P for max_bands bands, split-K partial sums, and a
+ * few per-band words.  Runs every check pw_problem_create runs on desc and
+ * max_bands (same errors), on the host only; desc->vloc and desc->beta are
+ * not read.  The size depends on PW_STICK_TILE and PW_BAND_CHUNK when set.
+ */
+pw_status pw_workspace_size(const pw_problem_desc *desc, int64_t max_bands, size_t *bytes);
+
+/*
+ * Build a problem handle.  Host arrays of desc are copied; V_LOC and beta
+ * (device) are copied into the workspace, so the caller's V_LOC and beta
+ * may be freed after the stream has passed this call.  max_bands bounds
+ * nbands of later pw_hpsi calls.  workspace: device memory, 256-byte
+ * aligned, of at least pw_workspace_size(desc, max_bands) bytes
+ * (ws_bytes), owned by the caller and bound to the handle until
+ * pw_problem_destroy; a null, misaligned or smaller workspace is
+ * PW_ERR_INVALID before any device work.  Allocates only the small tables
+ * (stick maps, twiddles, kinetic energies, D blocks); pw_hpsi then
+ * allocates nothing.  Synchronises `stream`.
  * Errors: PW_ERR_INVALID, PW_ERR_SHAPE (sphere does not fit the grid, grid
  * size not 2^a 3^b 5^c or outside 2..128, plane too large for LDS),
  * PW_ERR_NOMEM, PW_ERR_HIP.
  */
-pw_status pw_problem_create(const pw_problem_desc *desc, int64_t max_bands,
-                            void *stream, pw_problem **out);
+pw_status pw_problem_create(const pw_problem_desc *desc, int64_t max_bands, void *workspace,
+                            size_t ws_bytes, void *stream, pw_problem **out);
 pw_status pw_problem_destroy(pw_problem *p);
 
 /* Realised sizes of a handle: npw, number of z-sticks, nproj. */
@@ -170,14 +195,29 @@ pw_status pw_projections(pw_problem *p, const void *psi, int64_t ld_psi,
  *   PW_PRECOND_MLP : K = s(G, n) K_TPA(G, n), s from the network `net` (see
  *                    pw_mlp_*): a learned per-G scale on top of TPA, with
  *                    per-band fallback to TPA when any s of the band is not
- *                    finite, or (inside pw_davidson_step) once the band's
- *                    residual has not decreased for two consecutive steps.
- * theta: device double [nbands] Ritz values (used by MLP only);
- * x, r, t: device complex128 band-major with leading dimension ld.
+ *                    finite.  The features are those of pw_mlp_features,
+ *                    with |r_n| computed here.  (Inside pw_davidson_step a
+ *                    band also falls back once its residual has not
+ *                    decreased for two consecutive steps; a single call has
+ *                    no such history.)
+ * theta: device double [nbands] Ritz values (MLP only; may be NULL otherwise);
+ * x, r, t: device complex128 band-major with leading dimension ld; t must
+ * not overlap x or r.  Uses the problem's workspace (per-band words).
  */
 pw_status pw_precond(pw_problem *p, int32_t kind, const double *theta,
                      const void *x, const void *r, void *t, int64_t ld,
                      int64_t nbands, const pw_mlp *net, void *stream);
+
+/*
+ * Device workspace of a Davidson state (bytes): the space V, W = H V and
+ * their rotation targets [max_subspace][ld], the Ritz vectors X, H X, the
+ * residuals and corrections [nbands][ld] (ld = npw rounded up to 64), the
+ * subspace matrices and eigensolver work [lde][lde] (lde = max_subspace
+ * rounded up to 32), split-K partials and per-band words.  Same argument
+ * checks as pw_davidson_create (tol excepted); host only.
+ */
+pw_status pw_davidson_workspace_size(pw_problem *p, int64_t nbands, int64_t max_subspace,
+                                     size_t *bytes);
 
 /*
  * Block-Davidson state for the lowest nbands eigenpairs of one problem.
@@ -185,10 +225,14 @@ pw_status pw_precond(pw_problem *p, int32_t kind, const double *theta,
  * the residual 2-norm target in Ha (|H x - theta x| < tol for every band).
  * All subspace work (H_s = V^H H V, Cholesky orthonormalisation, the
  * Hermitian eigensolve, Ritz vectors, residual norms) runs in FP64 on the
- * GPU whatever the problem's precision form.  Allocates its device state.
+ * GPU whatever the problem's precision form.  workspace: device memory,
+ * 256-byte aligned, of at least pw_davidson_workspace_size bytes, owned by
+ * the caller and bound to the state until pw_davidson_destroy (null,
+ * misaligned or too small: PW_ERR_INVALID before any device work).  The
+ * state allocates only a few pinned host words.
  */
-pw_status pw_davidson_create(pw_problem *p, int64_t nbands, int64_t max_subspace,
-                             double tol, void *stream, pw_davidson **out);
+pw_status pw_davidson_create(pw_problem *p, int64_t nbands, int64_t max_subspace, double tol,
+                             void *workspace, size_t ws_bytes, void *stream, pw_davidson **out);
 pw_status pw_davidson_destroy(pw_davidson *d);
 
 /* Load and orthonormalise the start block (device complex128 [nbands][ld]),
@@ -278,15 +322,17 @@ pw_status pw_batch_launch(pw_batch *b, void *stream);
  * shape) over the plane kernel and the bands per plane workgroup, then the
  * bands per FFT sweep, then the split-K factor of the projection GEMM, keeps
  * the fastest in the handle and returns its time (ms per call, may be NULL).
- * Allocates and frees its own scratch bands; synchronises the stream.
+ * scratch: device memory of at least 2 * nbands * ld * 16 bytes
+ * (scratch_bytes; ld = npw rounded up to 64), owned by the caller, for the
+ * input and output bands of the timing runs; synchronises the stream.
  * pw_problem_tuning reports the handle's current choices (any output may be
  * NULL); plane_kernel is one of PW_PLANE_*.
  */
 #define PW_PLANE_REGISTER 0 /* line FFTs in registers (even compile-time grid sizes) */
 #define PW_PLANE_WAVE 1     /* wave-local LDS passes                                 */
 #define PW_PLANE_LDS 2      /* workgroup LDS Stockham passes                         */
-pw_status pw_problem_autotune(pw_problem *p, int64_t nbands, int32_t reps, void *stream,
-                              double *best_ms);
+pw_status pw_problem_autotune(pw_problem *p, int64_t nbands, int32_t reps, void *scratch,
+                              size_t scratch_bytes, void *stream, double *best_ms);
 pw_status pw_problem_tuning(const pw_problem *p, int32_t *plane_group, int64_t *band_chunk,
                             int32_t *ksplit, int32_t *plane_kernel);
 /*
@@ -309,7 +355,8 @@ pw_status pw_problem_set_tuning(pw_problem *p, int32_t plane_group, int64_t band
  * b2 [64], W3 [64], b3 [1] (row-major, y = W x + b).  The scaler holds the
  * feature means mu[4] and inverse standard deviations is[4]; features are
  * standardised as (f - mu) * is.  Features of sample (G, n), float4:
- * (t(G), theta_n, |r_n(G)| sqrt(npw) / ||r_n||, <V_LOC>).
+ * (t(G)/T_n, theta_n, |r_n(G)| sqrt(npw) / ||r_n||, <V_LOC>), with t(G) the
+ * kinetic energy |k+G|^2/2 and T_n = <x_n|t|x_n>/<x_n|x_n> the band's.
  */
 int32_t pw_mlp_num_params(void);
 /* params / scaler: host arrays (NULL: zeros / identity scaling). */

@@ -67,13 +67,15 @@ def _load():
         "pw_last_error": (C.c_char_p, []),
         "pw_version": (C.c_char_p, []),
         "pw_gsphere": (i32, [C.POINTER(f64), C.POINTER(f64), f64, C.POINTER(i32), i64, C.POINTER(i64)]),
-        "pw_problem_create": (i32, [C.POINTER(_Desc), i64, vp, C.POINTER(vp)]),
+        "pw_workspace_size": (i32, [C.POINTER(_Desc), i64, C.POINTER(C.c_size_t)]),
+        "pw_problem_create": (i32, [C.POINTER(_Desc), i64, vp, C.c_size_t, vp, C.POINTER(vp)]),
         "pw_problem_destroy": (i32, [vp]),
         "pw_problem_info": (i32, [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]),
         "pw_hpsi": (i32, [vp, vp, i64, vp, i64, i64, i32, vp]),
         "pw_projections": (i32, [vp, vp, i64, vp, i64, vp]),
         "pw_precond": (i32, [vp, i32, vp, vp, vp, vp, i64, i64, vp, vp]),
-        "pw_davidson_create": (i32, [vp, i64, i64, f64, vp, C.POINTER(vp)]),
+        "pw_davidson_workspace_size": (i32, [vp, i64, i64, C.POINTER(C.c_size_t)]),
+        "pw_davidson_create": (i32, [vp, i64, i64, f64, vp, C.c_size_t, vp, C.POINTER(vp)]),
         "pw_davidson_destroy": (i32, [vp]),
         "pw_davidson_init": (i32, [vp, vp, i64, vp]),
         "pw_davidson_step": (i32, [vp, i32, vp, vp, C.POINTER(i32)]),
@@ -101,7 +103,7 @@ def _load():
         "pw_batch_hpsi": (i32, [vp, vp]),
         "pw_batch_capture": (i32, [vp, vp]),
         "pw_batch_launch": (i32, [vp, vp]),
-        "pw_problem_autotune": (i32, [vp, i64, i32, vp, C.POINTER(f64)]),
+        "pw_problem_autotune": (i32, [vp, i64, i32, vp, C.c_size_t, vp, C.POINTER(f64)]),
         "pw_problem_tuning": (i32, [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32), C.POINTER(i32)]),
         "pw_problem_set_tuning": (i32, [vp, i32, i64, i32, i32]),
         "pw_eigh_workspace": (i32, [i32, C.POINTER(C.c_size_t)]),
@@ -173,15 +175,27 @@ def pw_gsphere(cell, kpt, ecut: float) -> np.ndarray:
     return out
 
 
-class Problem:
-    """Owner of a pw_problem handle (destroyed with the object)."""
+def _workspace(nbytes, device=None):
+    """Caller-owned device workspace of nbytes (torch allocations are 256-byte aligned)."""
+    import torch
+    ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8,
+                     device=device if device is not None else "cuda")
+    if ws.data_ptr() % 256:
+        raise RuntimeError("workspace allocation is not 256-byte aligned")
+    return ws
 
-    def __init__(self, handle, npw, nproj, max_bands, precision):
+
+class Problem:
+    """Owner of a pw_problem handle and of the workspace bound to it (the
+    handle is destroyed before the workspace is released)."""
+
+    def __init__(self, handle, npw, nproj, max_bands, precision, workspace=None):
         self._h = handle
         self.npw = npw
         self.nproj = nproj
         self.max_bands = max_bands
         self.precision = precision
+        self.workspace = workspace
 
     @property
     def handle(self):
@@ -198,6 +212,7 @@ class Problem:
         if self._h:
             LIB.pw_problem_destroy(self._h)
             self._h = None
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -237,10 +252,14 @@ def pw_problem_create(cell, kpt, ecut, nr, miller, vloc, beta, proj_offset, dij,
         d.beta = _dev_ptr(beta, torch.complex128, "beta")
         d.ld_beta = int(beta.stride(0)) if beta.shape[0] > 1 else int(beta.shape[1])
         keep += [po, dj, beta]
+    nbytes = C.c_size_t(0)
+    _check(LIB.pw_workspace_size(C.byref(d), int(max_bands), C.byref(nbytes)))
+    ws = _workspace(nbytes.value, vloc_c.device)
     h = C.c_void_p()
-    _check(LIB.pw_problem_create(C.byref(d), int(max_bands), _stream(stream), C.byref(h)))
+    _check(LIB.pw_problem_create(C.byref(d), int(max_bands), C.c_void_p(ws.data_ptr()), nbytes.value,
+                                 _stream(stream), C.byref(h)))
     del keep
-    return Problem(h, int(d.npw), int(d.nproj), int(max_bands), int(precision))
+    return Problem(h, int(d.npw), int(d.nproj), int(max_bands), int(precision), ws)
 
 
 def pw_hpsi(prob: Problem, psi, hpsi, terms: int = PW_TERM_ALL, stream=None) -> None:
@@ -290,12 +309,17 @@ def pw_profile_read(prob: Problem, reset: bool = True) -> dict:
 
 
 class Davidson:
-    """Owner of a pw_davidson handle."""
+    """Owner of a pw_davidson handle and of its workspace."""
 
     def __init__(self, prob: Problem, nbands: int, max_subspace: int = 0, tol: float = 5e-9,
                  stream=None):
+        nbytes = C.c_size_t(0)
+        _check(LIB.pw_davidson_workspace_size(prob.handle, int(nbands), int(max_subspace),
+                                              C.byref(nbytes)))
+        self.workspace = _workspace(nbytes.value)
         h = C.c_void_p()
         _check(LIB.pw_davidson_create(prob.handle, int(nbands), int(max_subspace), float(tol),
+                                      C.c_void_p(self.workspace.data_ptr()), nbytes.value,
                                       _stream(stream), C.byref(h)))
         self._h = h
         self.prob = prob
@@ -311,6 +335,7 @@ class Davidson:
         if self._h:
             LIB.pw_davidson_destroy(self._h)
             self._h = None
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -596,8 +621,13 @@ def pw_batch_launch(b: Batch, stream=None) -> None:
 
 
 def pw_problem_autotune(prob: Problem, nbands: int, reps: int = 3, stream=None) -> float:
+    ld = (prob.npw + 63) // 64 * 64
+    nbytes = 2 * int(nbands) * ld * 16
+    scratch = _workspace(nbytes)
     ms = C.c_double(0.0)
-    _check(LIB.pw_problem_autotune(prob.handle, int(nbands), int(reps), _stream(stream), C.byref(ms)))
+    _check(LIB.pw_problem_autotune(prob.handle, int(nbands), int(reps), C.c_void_p(scratch.data_ptr()),
+                                   nbytes, _stream(stream), C.byref(ms)))
+    del scratch
     return ms.value
 
 

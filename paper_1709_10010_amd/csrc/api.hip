@@ -14,11 +14,12 @@ namespace pw {
 static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
 
-static int env_int(const char *name, int dflt) {
+int env_switch(const char *name, int dflt) {
   const char *v = std::getenv(name);
   if (!v || !*v) return dflt;
   return std::atoi(v);
 }
+static int env_int(const char *name, int dflt) { return env_switch(name, dflt); }
 
 static void inv3(const double *A, double *Ai) {
   const double a = A[0], b = A[1], c = A[2], d = A[3], e = A[4], f = A[5], g = A[6], h = A[7],
@@ -158,7 +159,6 @@ static int make_vplanes(pw_problem *p, const std::vector<double> &v) {
     for (int y = 0; y < n1; ++y)
       for (int z = 0; z < n2; ++z)
         vp[((size_t)z * n0 + x) * n1 + y] = (T)(v[((size_t)x * n1 + y) * n2 + z] * inv);
-  PW_HIP(hipMalloc(&p->d_vplanes, vp.size() * sizeof(T)));
   PW_HIP(hipMemcpy(p->d_vplanes, vp.data(), vp.size() * sizeof(T), hipMemcpyHostToDevice));
   return PW_OK;
 }
@@ -217,14 +217,94 @@ void Prof::release() {
 static void free_problem(pw_problem *p) {
   if (!p) return;
   p->prof.release();
-  void *bufs[] = {p->d_gidx,   p->d_gpos,    p->d_tile_ptr, p->d_stick_xy, p->d_xlist,
-                  p->d_xslot,  p->d_stick_cpos,
-                  p->d_kin,    p->d_tw,      p->d_vplanes,  p->d_beta,     p->d_beta_lp,
-                  p->d_dij,    p->d_pj_atom, p->d_proj_off, p->d_dij_off,  p->d_sticks,
-                  p->d_P,      p->d_Q,       p->d_part,     p->d_tn};
+  // the workspace regions belong to the caller
+  void *bufs[] = {p->d_gidx,  p->d_gpos,       p->d_tile_ptr, p->d_stick_xy, p->d_xlist,
+                  p->d_xslot, p->d_stick_cpos, p->d_kin,      p->d_tw,       p->d_dij,
+                  p->d_pj_atom, p->d_proj_off, p->d_dij_off};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   delete p;
+}
+
+// Workspace layout of a problem.  pw_workspace_size runs it with a counting
+// Carve; pw_problem_create runs the same take() sequence on the caller's
+// workspace to place the handle's buffers.
+static void carve_problem(pw_problem *p, Carve &c) {
+  const size_t cb = cplx_bytes(p->precision);
+  const size_t n3 = (size_t)p->nr[0] * p->nr[1] * p->nr[2];
+  p->d_vplanes = c.take<char>(n3 * (p->precision == PW_FP64 ? sizeof(double) : sizeof(float)));
+  if (p->nproj > 0) {
+    p->d_beta = c.take<char>((size_t)p->nproj * p->ldb * 16);
+    if (p->precision != PW_FP64)
+      p->d_beta_lp = c.take<char>((size_t)p->nproj * p->ldb * (p->precision == PW_MIXED_FP32 ? 8 : 4));
+    const size_t pq = (size_t)p->max_bands * p->nproj * 16;
+    p->d_P = c.take<char>(pq);
+    p->d_Q = c.take<char>(pq);
+    p->part_bytes = std::min<size_t>(32 * pq, (size_t)512 << 20);
+    p->d_part = c.take<char>(p->part_bytes);
+    if (p->precision == PW_MIXED_BF16) {
+      p->d_psi_lp = c.take<char>((size_t)p->max_bands * p->ldb * 4);
+      p->d_q_lp = c.take<char>((size_t)p->max_bands * p->nproj * 4);
+    }
+  }
+  p->d_sticks = c.take<char>((size_t)p->nr[2] * p->map.nst_pad * cb * p->band_chunk_max);
+  p->d_tn = c.take<double>(p->max_bands);
+  p->d_rnorm = c.take<double>(p->max_bands);
+  p->d_idx = c.take<int>(p->max_bands);
+  p->d_bad = c.take<int>(p->max_bands);
+}
+
+// Argument checks shared by pw_workspace_size and pw_problem_create, then
+// the host-side set-up both need: sizes, reciprocal cell, stick map and the
+// sweep height the stick buffer is sized for.
+static int prepare_problem(const pw_problem_desc *d, int64_t max_bands, pw_problem *p, const char *who) {
+  auto msg = [&](const char *m) { return std::string(who) + ": " + m; };
+  PW_CHECK_ARG(d->npw > 0 && d->npw < (int64_t)1 << 31, PW_ERR_INVALID, msg("npw must be in 1 .. 2^31-1"));
+  PW_CHECK_ARG(d->miller, PW_ERR_INVALID, msg("miller is null"));
+  PW_CHECK_ARG(d->nproj >= 0 && d->natom >= 0, PW_ERR_INVALID, msg("nproj / natom must be >= 0"));
+  PW_CHECK_ARG(d->nproj == 0 || (d->proj_offset && d->dij && d->ld_beta >= d->npw), PW_ERR_INVALID,
+               msg("beta / proj_offset / dij / ld_beta invalid"));
+  PW_CHECK_ARG(max_bands >= 1 && max_bands <= (1 << 20), PW_ERR_INVALID, msg("max_bands must be in 1 .. 2^20"));
+  PW_CHECK_ARG(d->precision >= PW_FP64 && d->precision <= PW_MIXED_BF16, PW_ERR_INVALID,
+               msg("unknown precision"));
+  PW_CHECK_ARG(std::isfinite(d->ecut) && d->ecut > 0, PW_ERR_INVALID, msg("ecut must be > 0"));
+  for (int i = 0; i < 3; ++i)
+    PW_CHECK_ARG(d->nr[i] >= 2 && d->nr[i] <= 128 && smooth235(d->nr[i]), PW_ERR_SHAPE,
+                 msg("grid sizes must be 2^a 3^b 5^c in 2..128"));
+  const size_t cb = cplx_bytes(d->precision);
+  PW_CHECK_ARG((size_t)d->nr[0] * d->nr[1] * cb + (d->nr[0] + d->nr[1]) * cb + 4 * d->nr[0] <= 160 * 1024,
+               PW_ERR_SHAPE, msg("N0*N1 plane does not fit in LDS for this precision"));
+  PW_CHECK_ARG((int64_t)d->nr[0] * d->nr[1] <= 8 * 1024, PW_ERR_SHAPE, msg("plane larger than 8192 points"));
+  if (d->nproj > 0) {
+    PW_CHECK_ARG(d->natom >= 1 && d->proj_offset[0] == 0 && d->proj_offset[d->natom] == d->nproj,
+                 PW_ERR_INVALID, msg("proj_offset must run 0 .. nproj"));
+    for (int a = 0; a < d->natom; ++a)
+      PW_CHECK_ARG(d->proj_offset[a + 1] >= d->proj_offset[a], PW_ERR_INVALID,
+                   msg("proj_offset must be non-decreasing"));
+  }
+  p->precision = d->precision;
+  std::memcpy(p->A, d->cell, sizeof p->A);
+  std::memcpy(p->kpt, d->kpt, sizeof p->kpt);
+  p->ecut = d->ecut;
+  std::memcpy(p->nr, d->nr, sizeof p->nr);
+  p->npw = d->npw;
+  p->nproj = d->nproj;
+  p->natom = d->natom;
+  p->max_bands = max_bands;
+  p->ldb = (d->npw + 63) / 64 * 64;
+  recip(p->A, p->B);
+  const int ts = std::max(1, std::min(64, env_int("PW_STICK_TILE", d->precision == PW_FP64 ? 16 : 32)));
+  PW_CHECK_ARG(ts * d->nr[2] <= 8 * 512, PW_ERR_SHAPE, msg("stick tile too long"));
+  int rc = build_stick_map(p, d->miller, ts);
+  if (rc != PW_OK) return rc;
+  // stick buffer: band_chunk x N2 x nst_pad, at most 1 GiB unless PW_BAND_CHUNK asks
+  const size_t per_band = (size_t)d->nr[2] * p->map.nst_pad * cb;
+  int64_t chunk = env_int("PW_BAND_CHUNK", 0);
+  if (chunk <= 0) chunk = std::max<int64_t>(1, std::min<int64_t>(max_bands, ((size_t)1 << 30) / per_band));
+  chunk = std::min(chunk, max_bands);
+  p->band_chunk = chunk;
+  p->band_chunk_max = chunk;
+  return PW_OK;
 }
 
 }  // namespace pw
@@ -285,39 +365,24 @@ pw_status pw_gsphere(const double cell[9], const double kpt[3], double ecut, int
   return PW_OK;
 }
 
-pw_status pw_problem_create(const pw_problem_desc *d, int64_t max_bands, void *stream,
-                            pw_problem **out) {
+pw_status pw_workspace_size(const pw_problem_desc *d, int64_t max_bands, size_t *bytes) {
+  PW_CHECK_ARG(d && bytes, PW_ERR_INVALID, "pw_workspace_size: null argument");
+  *bytes = 0;
+  pw_problem p;
+  const int rc = prepare_problem(d, max_bands, &p, "pw_workspace_size");
+  if (rc != PW_OK) return rc;
+  Carve c(nullptr);
+  carve_problem(&p, c);
+  *bytes = c.size();
+  return PW_OK;
+}
+
+pw_status pw_problem_create(const pw_problem_desc *d, int64_t max_bands, void *workspace,
+                            size_t ws_bytes, void *stream, pw_problem **out) {
   PW_CHECK_ARG(d && out, PW_ERR_INVALID, "pw_problem_create: null argument");
   *out = nullptr;
-  PW_CHECK_ARG(d->npw > 0 && d->npw < (int64_t)1 << 31, PW_ERR_INVALID,
-               "pw_problem_create: npw must be in 1 .. 2^31-1");
-  PW_CHECK_ARG(d->miller && d->vloc, PW_ERR_INVALID, "pw_problem_create: miller / vloc is null");
-  PW_CHECK_ARG(d->nproj >= 0 && d->natom >= 0, PW_ERR_INVALID,
-               "pw_problem_create: nproj / natom must be >= 0");
-  PW_CHECK_ARG(d->nproj == 0 || (d->beta && d->proj_offset && d->dij && d->ld_beta >= d->npw),
-               PW_ERR_INVALID, "pw_problem_create: beta / proj_offset / dij / ld_beta invalid");
-  PW_CHECK_ARG(max_bands >= 1 && max_bands <= (1 << 20), PW_ERR_INVALID,
-               "pw_problem_create: max_bands must be in 1 .. 2^20");
-  PW_CHECK_ARG(d->precision >= PW_FP64 && d->precision <= PW_MIXED_BF16, PW_ERR_INVALID,
-               "pw_problem_create: unknown precision");
-  PW_CHECK_ARG(std::isfinite(d->ecut) && d->ecut > 0, PW_ERR_INVALID,
-               "pw_problem_create: ecut must be > 0");
-  for (int i = 0; i < 3; ++i)
-    PW_CHECK_ARG(d->nr[i] >= 2 && d->nr[i] <= 128 && smooth235(d->nr[i]), PW_ERR_SHAPE,
-                 "pw_problem_create: grid sizes must be 2^a 3^b 5^c in 2..128");
-  const size_t cb = cplx_bytes(d->precision);
-  PW_CHECK_ARG((size_t)d->nr[0] * d->nr[1] * cb + (d->nr[0] + d->nr[1]) * cb + 4 * d->nr[0] <=
-                   160 * 1024,
-               PW_ERR_SHAPE, "pw_problem_create: N0*N1 plane does not fit in LDS for this precision");
-  PW_CHECK_ARG((int64_t)d->nr[0] * d->nr[1] <= 8 * 1024, PW_ERR_SHAPE,
-               "pw_problem_create: plane larger than 8192 points");
-  if (d->nproj > 0) {
-    PW_CHECK_ARG(d->natom >= 1 && d->proj_offset[0] == 0 && d->proj_offset[d->natom] == d->nproj,
-                 PW_ERR_INVALID, "pw_problem_create: proj_offset must run 0 .. nproj");
-    for (int a = 0; a < d->natom; ++a)
-      PW_CHECK_ARG(d->proj_offset[a + 1] >= d->proj_offset[a], PW_ERR_INVALID,
-                   "pw_problem_create: proj_offset must be non-decreasing");
-  }
+  PW_CHECK_ARG(d->vloc, PW_ERR_INVALID, "pw_problem_create: vloc is null");
+  PW_CHECK_ARG(d->nproj == 0 || d->beta, PW_ERR_INVALID, "pw_problem_create: beta is null");
   hipStream_t s = static_cast<hipStream_t>(stream);
   pw_problem *p = new pw_problem();
   int rc = PW_OK;
@@ -325,21 +390,21 @@ pw_status pw_problem_create(const pw_problem_desc *d, int64_t max_bands, void *s
     free_problem(p);
     return code;
   };
+  if ((rc = prepare_problem(d, max_bands, p, "pw_problem_create")) != PW_OK) return fail(rc);
+  {
+    Carve count(nullptr);
+    carve_problem(p, count);
+    if (!workspace || ws_bytes < count.size() || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0) {
+      set_error("pw_problem_create: workspace must be 256-byte aligned device memory of at least "
+                "pw_workspace_size() = " + std::to_string(count.size()) + " bytes");
+      return fail(PW_ERR_INVALID);
+    }
+    Carve c(workspace);
+    carve_problem(p, c);
+    p->ws = workspace;
+    p->ws_bytes = ws_bytes;
+  }
   (void)hipGetDevice(&p->device);
-  p->precision = d->precision;
-  std::memcpy(p->A, d->cell, sizeof p->A);
-  std::memcpy(p->kpt, d->kpt, sizeof p->kpt);
-  p->ecut = d->ecut;
-  std::memcpy(p->nr, d->nr, sizeof p->nr);
-  p->npw = d->npw;
-  p->nproj = d->nproj;
-  p->natom = d->natom;
-  p->max_bands = max_bands;
-  recip(p->A, p->B);
-
-  const int ts = std::max(1, std::min(64, env_int("PW_STICK_TILE", d->precision == PW_FP64 ? 16 : 32)));
-  PW_CHECK_ARG(ts * d->nr[2] <= 8 * 512, PW_ERR_SHAPE, "pw_problem_create: stick tile too long");
-  if ((rc = build_stick_map(p, d->miller, ts)) != PW_OK) return fail(rc);
   const StickMap &sm = p->map;
 
   // kinetic energies in the caller's G order
@@ -389,8 +454,6 @@ pw_status pw_problem_create(const pw_problem_desc *d, int64_t max_bands, void *s
 
   // nonlocal data
   if (d->nproj > 0) {
-    p->ldb = (d->npw + 63) / 64 * 64;
-    if (hipMalloc(&p->d_beta, (size_t)d->nproj * p->ldb * 16) != hipSuccess) return fail(PW_ERR_NOMEM);
     if (hipMemsetAsync(p->d_beta, 0, (size_t)d->nproj * p->ldb * 16, s) != hipSuccess ||
         hipMemcpy2DAsync(p->d_beta, p->ldb * 16, d->beta, d->ld_beta * 16, d->npw * 16, d->nproj,
                          hipMemcpyDeviceToDevice, s) != hipSuccess) {
@@ -398,8 +461,6 @@ pw_status pw_problem_create(const pw_problem_desc *d, int64_t max_bands, void *s
       return fail(PW_ERR_HIP);
     }
     if (d->precision != PW_FP64) {
-      const size_t eb = d->precision == PW_MIXED_FP32 ? 8 : 4;
-      if (hipMalloc(&p->d_beta_lp, (size_t)d->nproj * p->ldb * eb) != hipSuccess) return fail(PW_ERR_NOMEM);
       if ((rc = convert_beta(p->d_beta, p->d_beta_lp, d->nproj * p->ldb, d->precision, s)) != PW_OK) {
         set_error("pw_problem_create: beta conversion failed");
         return fail(rc);
@@ -424,23 +485,19 @@ pw_status pw_problem_create(const pw_problem_desc *d, int64_t max_bands, void *s
     if ((rc = upload(&p->d_pj_atom, pj)) != PW_OK) return fail(rc);
     if ((rc = upload(&p->d_proj_off, poff)) != PW_OK) return fail(rc);
     if ((rc = upload(&p->d_dij_off, doff)) != PW_OK) return fail(rc);
-    const size_t pq = (size_t)max_bands * d->nproj * 16;
-    if (hipMalloc(&p->d_P, pq) != hipSuccess || hipMalloc(&p->d_Q, pq) != hipSuccess)
-      return fail(PW_ERR_NOMEM);
-    p->part_bytes = std::min<size_t>(32 * pq, (size_t)512 << 20);
-    if (hipMalloc(&p->d_part, p->part_bytes) != hipSuccess) return fail(PW_ERR_NOMEM);
   }
-
-  // stick buffer: band_chunk x N2 x nst_pad
-  const size_t per_band = (size_t)d->nr[2] * sm.nst_pad * cb;
-  int64_t chunk = env_int("PW_BAND_CHUNK", 0);
-  if (chunk <= 0) chunk = std::max<int64_t>(1, std::min<int64_t>(max_bands, ((size_t)1 << 30) / per_band));
-  chunk = std::min(chunk, max_bands);
-  p->band_chunk = chunk;
-  p->band_chunk_max = chunk;
+  {
+    // band indices 0 .. max_bands-1 for the learned preconditioner of pw_precond
+    std::vector<int> iota((size_t)max_bands);
+    std::iota(iota.begin(), iota.end(), 0);
+    if (hipMemcpyAsync(p->d_idx, iota.data(), iota.size() * sizeof(int), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      set_error("pw_problem_create: workspace initialisation failed");
+      return fail(PW_ERR_HIP);
+    }
+  }
   p->plane_group = env_int("PW_PLANE_GROUP", 0);  // <= 0: chosen for the plane kernel below
-  if (hipMalloc(&p->d_sticks, per_band * chunk) != hipSuccess) return fail(PW_ERR_NOMEM);
-  if (hipMalloc(&p->d_tn, (size_t)max_bands * sizeof(double)) != hipSuccess) return fail(PW_ERR_NOMEM);
 
   // device view for the FFT launchers
   FFTDev &f = p->fft;
@@ -501,6 +558,12 @@ static int projections_impl(pw_problem *p, const void *psi, int64_t ld, void *P,
   int splits = p->ksplit > 0 ? p->ksplit : choose_splits(M, N, K);
   while (splits > 1 && (size_t)splits * M * N * 16 > p->part_bytes) --splits;
   const void *A = p->precision == PW_FP64 ? p->d_beta : p->d_beta_lp;
+  if (p->precision == PW_MIXED_BF16) {
+    // psi rounded once here rather than by every M tile of the GEMM
+    const int rc = bf16_round(psi, ld, p->d_psi_lp, p->ldb, K, N, s);
+    if (rc != PW_OK) return rc;
+    return zgemm_cn_p(p->precision, M, N, K, A, p->ldb, p->d_psi_lp, p->ldb, P, M, splits, p->d_part, s);
+  }
   return zgemm_cn_p(p->precision, M, N, K, A, p->ldb, psi, ld, P, M, splits, p->d_part, s);
 }
 
@@ -566,8 +629,14 @@ pw_status pw_hpsi(pw_problem *p, const void *psi, int64_t ld_psi, void *hpsi, in
     if (rc == PW_OK) {
       ProfScope ps_(&p->prof, PW_STAGE_NLUPD, s);
       const void *A = p->precision == PW_FP64 ? p->d_beta : p->d_beta_lp;
-      rc = zgemm_nn_p(p->precision, p->npw, nbands, p->nproj, 1.0, A, p->ldb, p->d_Q, p->nproj, 1.0,
-                      hpsi, ld_hpsi, s);
+      const void *Q = p->d_Q;
+      if (p->precision == PW_MIXED_BF16) {
+        rc = bf16_round(p->d_Q, p->nproj, p->d_q_lp, p->nproj, p->nproj, nbands, s);
+        Q = p->d_q_lp;
+      }
+      if (rc == PW_OK)
+        rc = zgemm_nn_p(p->precision, p->npw, nbands, p->nproj, 1.0, A, p->ldb, Q, p->nproj, 1.0, hpsi,
+                        ld_hpsi, s);
     }
     if (rc != PW_OK) {
       set_error("pw_hpsi: nonlocal launch failed");
@@ -593,18 +662,33 @@ pw_status pw_projections(pw_problem *p, const void *psi, int64_t ld_psi, void *p
 pw_status pw_precond(pw_problem *p, int32_t kind, const double *theta, const void *x,
                      const void *r, void *t, int64_t ld, int64_t nbands, const pw_mlp *net,
                      void *stream) {
-  (void)theta;
-  (void)net;
   PW_CHECK_ARG(p, PW_ERR_INVALID, "pw_precond: null handle");
-  PW_CHECK_ARG(kind == PW_PRECOND_NONE || kind == PW_PRECOND_TPA, PW_ERR_INVALID,
+  PW_CHECK_ARG(kind == PW_PRECOND_NONE || kind == PW_PRECOND_TPA || kind == PW_PRECOND_MLP, PW_ERR_INVALID,
                "pw_precond: unknown preconditioner kind");
   PW_CHECK_ARG(nbands >= 0 && nbands <= p->max_bands, PW_ERR_INVALID,
                "pw_precond: nbands must be in 0 .. max_bands");
+  PW_CHECK_ARG(kind != PW_PRECOND_MLP || (net && theta), PW_ERR_INVALID,
+               "pw_precond: the learned preconditioner needs a network and the Ritz values");
   if (nbands == 0) return PW_OK;
   PW_CHECK_ARG(x && r && t && ld >= p->npw, PW_ERR_INVALID, "pw_precond: null pointer or ld < npw");
-  ProfScope ps_(&p->prof, PW_STAGE_PRECOND, static_cast<hipStream_t>(stream));
-  const int rc = launch_tpa(p->d_kin, x, r, t, ld, p->npw, (int)nbands, kind, p->d_tn,
-                            static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ProfScope ps_(&p->prof, PW_STAGE_PRECOND, s);
+  int rc;
+  if (kind == PW_PRECOND_MLP) {
+    // features need T_n of the iterate and |r_n|; bands whose scales come
+    // out non-finite are redone with TPA
+    const double2 *R = static_cast<const double2 *>(r);
+    double2 *T = static_cast<double2 *>(t);
+    rc = band_kinetic(p->d_kin, x, ld, p->npw, (int)nbands, p->d_tn, s);
+    if (rc == PW_OK) rc = col_norms(R, ld, p->npw, (int)nbands, p->d_rnorm, s);
+    if (rc == PW_OK && hipMemsetAsync(p->d_bad, 0, (size_t)nbands * sizeof(int), s) != hipSuccess)
+      rc = PW_ERR_HIP;
+    if (rc == PW_OK)
+      rc = mlp_precond_idx(net, p, theta, p->d_rnorm, p->d_idx, R, ld, T, (int)nbands, p->d_bad, p->d_tn, s);
+    if (rc == PW_OK) rc = mlp_fallback(p->d_bad, p, p->d_tn, p->d_idx, R, ld, T, (int)nbands, s);
+  } else {
+    rc = launch_tpa(p->d_kin, x, r, t, ld, p->npw, (int)nbands, kind, p->d_tn, s);
+  }
   if (rc != PW_OK) set_error("pw_precond: launch failed");
   return rc;
 }

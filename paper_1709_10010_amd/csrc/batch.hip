@@ -1,5 +1,5 @@
-// Batched H*psi over many independent problems (cells or k-points) and a
-// per-problem autotuner.
+// Batched H*psi and batched Davidson over many independent problems (cells
+// or k-points), and a per-problem autotuner.
 //
 // The paper runs independent units side by side as images and k-point
 // pools; on one GPU the same independence lets the H*psi sweeps of many
@@ -8,10 +8,14 @@
 // pw_hpsi allocates, synchronises or clears memory with a memset, so the
 // recorded graph is the same sequence of kernels an eager sweep enqueues.
 //
-// The autotuner times pw_hpsi on scratch bands for a few launch choices
+// The autotuner times pw_hpsi on the caller's scratch bands for a few launch choices
 // (plane kernel and bands per plane workgroup, bands per FFT sweep, split-K
 // of the projection GEMM) and keeps the fastest for the handle.
 #include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -25,7 +29,47 @@ struct pw_batch {
   std::vector<int64_t> ld_psi, ld_hpsi, nb;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // side streams of the sweep (pw_batch_set_streams): problems placed on
+  // them longest first, forked from and joined to the call's stream
+  std::vector<hipStream_t> side;
+  std::vector<std::vector<int>> placed;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
 };
+
+namespace {
+
+// Work of one H*psi sweep of a problem (FFT lines and projector GEMMs), the
+// unit the batch balances its streams by.
+double hpsi_cost(const pw_problem *p, int64_t nb) {
+  return (double)p->npw * (double)nb * (std::log2((double)p->nr[0]) + (double)p->nproj / 64.0);
+}
+
+// Longest-processing-time placement of items with the given costs on k bins.
+std::vector<std::vector<int>> lpt(const std::vector<double> &cost, int k) {
+  std::vector<int> order(cost.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<std::vector<int>> bins(k);
+  std::vector<double> load(k, 0.0);
+  for (int i : order) {
+    const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    bins[j].push_back(i);
+    load[j] += cost[i];
+  }
+  return bins;
+}
+
+void release_streams(pw_batch *b) {
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+  b->fork = nullptr;
+  b->join.clear();
+  b->side.clear();
+  b->placed.clear();
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -57,17 +101,55 @@ pw_status pw_batch_destroy(pw_batch *b) {
   if (!b) return PW_OK;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  release_streams(b);
   delete b;
   return PW_OK;
 }
 
-// Eager sweep: pw_hpsi on every problem of the batch, in order, on `stream`.
+pw_status pw_batch_set_streams(pw_batch *b, void *const *streams, int32_t nstreams) {
+  PW_CHECK_ARG(b && nstreams >= 0 && nstreams <= 64 && (nstreams == 0 || streams), PW_ERR_INVALID,
+               "pw_batch_set_streams: bad argument");
+  for (int k = 0; k < nstreams; ++k)
+    PW_CHECK_ARG(streams[k], PW_ERR_INVALID, "pw_batch_set_streams: side streams must be non-null streams");
+  release_streams(b);
+  if (nstreams == 0) return PW_OK;
+  std::vector<double> cost(b->probs.size());
+  for (size_t i = 0; i < cost.size(); ++i) cost[i] = hpsi_cost(b->probs[i], b->nb[i]);
+  b->placed = lpt(cost, nstreams);
+  for (int k = 0; k < nstreams; ++k) b->side.push_back(static_cast<hipStream_t>(streams[k]));
+  PW_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+  b->join.assign(nstreams, nullptr);
+  for (int k = 0; k < nstreams; ++k) PW_HIP(hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming));
+  return PW_OK;
+}
+
+// Sweep: pw_hpsi on every problem of the batch.  Without side streams, in
+// order on `stream`; with them, each side stream runs its problems after
+// `stream` has reached the call (fork event), and `stream` continues only
+// once every side stream is done (join events), so the problems of
+// different side streams overlap on the GPU.
 pw_status pw_batch_hpsi(pw_batch *b, void *stream) {
   PW_CHECK_ARG(b, PW_ERR_INVALID, "pw_batch_hpsi: null batch");
-  for (size_t i = 0; i < b->probs.size(); ++i) {
-    const int rc = pw_hpsi(b->probs[i], b->psi[i], b->ld_psi[i], b->hpsi[i], b->ld_hpsi[i], b->nb[i],
-                           PW_TERM_ALL, stream);
-    if (rc != PW_OK) return rc;
+  if (b->side.empty()) {
+    for (size_t i = 0; i < b->probs.size(); ++i) {
+      const int rc = pw_hpsi(b->probs[i], b->psi[i], b->ld_psi[i], b->hpsi[i], b->ld_hpsi[i], b->nb[i],
+                             PW_TERM_ALL, stream);
+      if (rc != PW_OK) return rc;
+    }
+    return PW_OK;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PW_HIP(hipEventRecord(b->fork, s));
+  for (size_t k = 0; k < b->side.size(); ++k) {
+    hipStream_t sk = b->side[k];
+    PW_HIP(hipStreamWaitEvent(sk, b->fork, 0));
+    for (int i : b->placed[k]) {
+      const int rc = pw_hpsi(b->probs[i], b->psi[i], b->ld_psi[i], b->hpsi[i], b->ld_hpsi[i], b->nb[i],
+                             PW_TERM_ALL, sk);
+      if (rc != PW_OK) return rc;
+    }
+    PW_HIP(hipEventRecord(b->join[k], sk));
+    PW_HIP(hipStreamWaitEvent(s, b->join[k], 0));
   }
   return PW_OK;
 }
@@ -112,19 +194,174 @@ pw_status pw_batch_launch(pw_batch *b, void *stream) {
   return PW_OK;
 }
 
-pw_status pw_problem_autotune(pw_problem *p, int64_t nbands, int32_t reps, void *stream,
-                              double *best_ms) {
+}  // extern "C"
+
+// ---------------------------------------------------------------- batched Davidson
+// Independent solves (cells or k-points) advanced side by side, one host
+// worker thread per caller stream: each worker issues its solves' kernels
+// on its own stream and waits on its own host syncs, so the kernels of
+// different solves overlap on the GPU and one solve's syncs do not stall
+// the others.  This is the paper's images and k-point pools on one GPU.
+struct pw_batch_dav {
+  std::vector<pw_davidson *> dav;
+  std::vector<hipStream_t> streams;
+  std::vector<int> order;               // solves, most work first
+  std::vector<std::vector<int>> owned;  // static placement of init / step
+  std::vector<int32_t> conv, iters;
+  int device = 0;
+};
+
+namespace {
+
+double solve_cost(const pw_davidson *d) {
+  const pw_problem *p = dav_problem(d);
+  const double mm = dav_max_subspace(d);
+  return hpsi_cost(p, dav_nbands(d)) + (double)p->npw * mm * mm / 8.0;
+}
+
+// fn(k) on one host thread per stream, with the batch's device current;
+// the first failure's status and message come back to the calling thread.
+template <typename F>
+int run_workers(pw_batch_dav *b, F &&fn) {
+  const int nw = (int)b->streams.size();
+  std::vector<int> rc(nw, PW_OK);
+  std::vector<std::string> msg(nw);
+  std::vector<std::thread> th;
+  th.reserve(nw);
+  for (int k = 0; k < nw; ++k)
+    th.emplace_back([&, k] {
+      if (hipSetDevice(b->device) != hipSuccess) {
+        rc[k] = PW_ERR_HIP;
+        msg[k] = "batched Davidson: hipSetDevice failed in a worker";
+        return;
+      }
+      rc[k] = fn(k);
+      if (rc[k] < 0) msg[k] = pw_last_error();
+    });
+  for (std::thread &t : th) t.join();
+  for (int k = 0; k < nw; ++k)
+    if (rc[k] < 0) {
+      set_error(msg[k]);
+      return rc[k];
+    }
+  return PW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pw_status pw_batch_davidson_create(pw_davidson *const *solvers, int32_t n, void *const *streams,
+                                   int32_t nstreams, pw_batch_dav **out) {
+  PW_CHECK_ARG(out && solvers && streams && n >= 1 && nstreams >= 1 && nstreams <= 64, PW_ERR_INVALID,
+               "pw_batch_davidson_create: bad argument");
+  *out = nullptr;
+  int dev = 0;
+  PW_HIP(hipGetDevice(&dev));
+  for (int i = 0; i < n; ++i) {
+    PW_CHECK_ARG(solvers[i], PW_ERR_INVALID, "pw_batch_davidson_create: null solver");
+    PW_CHECK_ARG(dav_problem(solvers[i])->device == dev, PW_ERR_INVALID,
+                 "pw_batch_davidson_create: every solve must live on the current device");
+    for (int j = 0; j < i; ++j)
+      PW_CHECK_ARG(solvers[j] != solvers[i] && dav_problem(solvers[j]) != dav_problem(solvers[i]),
+                   PW_ERR_INVALID,
+                   "pw_batch_davidson_create: solves must be distinct and must not share a problem");
+  }
+  for (int k = 0; k < nstreams; ++k)
+    PW_CHECK_ARG(streams[k], PW_ERR_INVALID, "pw_batch_davidson_create: streams must be non-null streams");
+  pw_batch_dav *b = new pw_batch_dav();
+  b->device = dev;
+  b->dav.assign(solvers, solvers + n);
+  for (int k = 0; k < nstreams; ++k) b->streams.push_back(static_cast<hipStream_t>(streams[k]));
+  std::vector<double> cost(n);
+  for (int i = 0; i < n; ++i) cost[i] = solve_cost(solvers[i]);
+  b->owned = lpt(cost, nstreams);
+  b->order.resize(n);
+  for (int i = 0; i < n; ++i) b->order[i] = i;
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  b->conv.assign(n, 0);
+  b->iters.assign(n, 0);
+  *out = b;
+  return PW_OK;
+}
+
+pw_status pw_batch_davidson_destroy(pw_batch_dav *b) {
+  delete b;
+  return PW_OK;
+}
+
+pw_status pw_batch_davidson_init(pw_batch_dav *b, const void *const *psi0, const int64_t *ld) {
+  PW_CHECK_ARG(b && psi0 && ld, PW_ERR_INVALID, "pw_batch_davidson_init: bad argument");
+  const int rc = run_workers(b, [&](int k) {
+    for (int i : b->owned[k]) {
+      const int r = pw_davidson_init(b->dav[i], psi0[i], ld[i], b->streams[k]);
+      if (r != PW_OK) return r;
+      b->conv[i] = 0;
+    }
+    return (int)PW_OK;
+  });
+  return rc;
+}
+
+pw_status pw_batch_davidson_step(pw_batch_dav *b, int32_t precond_kind, const pw_mlp *net, int32_t *nconverged) {
+  PW_CHECK_ARG(b, PW_ERR_INVALID, "pw_batch_davidson_step: null batch");
+  for (pw_davidson *d : b->dav)
+    PW_CHECK_ARG(dav_inited(d), PW_ERR_INVALID, "pw_batch_davidson_step: initialise every solve first");
+  const int rc = run_workers(b, [&](int k) {
+    for (int i : b->owned[k]) {
+      if (b->conv[i]) continue;
+      int32_t c = 0;
+      const int r = pw_davidson_step(b->dav[i], precond_kind, net, b->streams[k], &c);
+      if (r != PW_OK) return r;
+      b->conv[i] = c;
+    }
+    return (int)PW_OK;
+  });
+  if (nconverged) {
+    int32_t nc = 0;
+    for (int32_t c : b->conv) nc += c ? 1 : 0;
+    *nconverged = nc;
+  }
+  return rc;
+}
+
+pw_status pw_batch_davidson_run(pw_batch_dav *b, const void *const *psi0, const int64_t *ld, int32_t max_iter,
+                                int32_t precond_kind, const pw_mlp *net, int32_t *converged) {
+  PW_CHECK_ARG(b && psi0 && ld && max_iter >= 1, PW_ERR_INVALID, "pw_batch_davidson_run: bad argument");
+  std::atomic<int> next{0};
+  const int n = (int)b->dav.size();
+  const int rc = run_workers(b, [&](int k) {
+    for (int t = next.fetch_add(1); t < n; t = next.fetch_add(1)) {
+      const int i = b->order[t];
+      int r = pw_davidson_init(b->dav[i], psi0[i], ld[i], b->streams[k]);
+      if (r != PW_OK) return r;
+      int32_t c = 0;
+      r = pw_davidson_run(b->dav[i], max_iter, precond_kind, net, b->streams[k], &c);
+      if (r < 0) return r;
+      b->conv[i] = c;
+    }
+    return (int)PW_OK;
+  });
+  if (rc != PW_OK) return rc;
+  bool all = true;
+  for (int i = 0; i < n; ++i) {
+    if (converged) converged[i] = b->conv[i];
+    all = all && b->conv[i];
+  }
+  return all ? PW_OK : PW_NOT_CONVERGED;
+}
+
+pw_status pw_problem_autotune(pw_problem *p, int64_t nbands, int32_t reps, void *scratch,
+                              size_t scratch_bytes, void *stream, double *best_ms) {
   PW_CHECK_ARG(p && nbands >= 1 && nbands <= p->max_bands && reps >= 1, PW_ERR_INVALID,
                "pw_problem_autotune: bad argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t ld = (p->npw + 63) / 64 * 64;
   const size_t bytes = (size_t)nbands * ld * sizeof(double2);
-  void *x = nullptr, *y = nullptr;
-  if (hipMalloc(&x, bytes) != hipSuccess || hipMalloc(&y, bytes) != hipSuccess) {
-    if (x) (void)hipFree(x);
-    set_error("pw_problem_autotune: scratch allocation failed");
-    return PW_ERR_NOMEM;
-  }
+  PW_CHECK_ARG(scratch && scratch_bytes >= 2 * bytes, PW_ERR_INVALID,
+               "pw_problem_autotune: scratch must hold 2 * nbands * ld * 16 bytes (ld = npw rounded up to 64)");
+  void *x = scratch;
+  void *y = static_cast<char *>(scratch) + bytes;
   PW_HIP(hipMemsetAsync(x, 0, bytes, s));
   hipEvent_t e0, e1;
   PW_HIP(hipEventCreate(&e0));
@@ -195,8 +432,6 @@ pw_status pw_problem_autotune(pw_problem *p, int64_t nbands, int32_t reps, void 
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(s);
-  (void)hipFree(x);
-  (void)hipFree(y);
   if (rc != PW_OK) {
     set_error("pw_problem_autotune: timing run failed");
     return rc;

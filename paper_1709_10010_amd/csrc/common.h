@@ -14,6 +14,11 @@ namespace pw {
 // ----------------------------------------------------------------- errors
 void set_error(const std::string &msg);
 
+// Integer value of an environment switch (dflt when unset or empty).  The
+// library reads each switch once per process, into a function-local static
+// whose initialisation C++ makes thread-safe.
+int env_switch(const char *name, int dflt);
+
 #define PW_CHECK_ARG(cond, code, msg)            \
   do {                                           \
     if (!(cond)) {                               \
@@ -30,6 +35,24 @@ void set_error(const std::string &msg);
       return PW_ERR_HIP;                                                    \
     }                                                                       \
   } while (0)
+
+// ----------------------------------------------------------------- workspace
+// Hands out 256-byte aligned pieces of a caller's workspace in order.  With
+// a null base it only counts: the same sequence of take() calls then gives
+// the workspace size a later call with the real base needs.
+struct Carve {
+  char *base;
+  size_t off = 0;
+  explicit Carve(void *b) : base(static_cast<char *>(b)) {}
+  template <typename T>
+  T *take(size_t n) {
+    off = (off + 255) & ~(size_t)255;
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += (n > 0 ? n : 1) * sizeof(T);
+    return p;
+  }
+  size_t size() const { return (off + 255) & ~(size_t)255; }
+};
 
 // ----------------------------------------------------------------- complex
 template <typename T> struct cpx;
@@ -131,26 +154,37 @@ struct pw_problem {
   int ksplit = 0;           // split-K factor for projections (0 = auto)
   pw::StickMap map;
   pw::FFTDev fft{};
-  // device buffers owned by the handle
+  // small device tables owned by the handle (maps, twiddles, kinetic
+  // energies, D blocks and their offsets)
   int32_t *d_gidx = nullptr, *d_gpos = nullptr, *d_tile_ptr = nullptr;
   int32_t *d_stick_xy = nullptr, *d_xlist = nullptr;
   int32_t *d_xslot = nullptr, *d_stick_cpos = nullptr;
   double *d_kin = nullptr;
   void *d_tw = nullptr;        // three twiddle tables back to back
-  void *d_vplanes = nullptr;
-  void *d_beta = nullptr;      // complex128 [nproj][ldb]
-  void *d_beta_lp = nullptr;   // reduced-precision copy (mixed forms)
-  int64_t ldb = 0;
   double *d_dij = nullptr;     // concatenated blocks
   int32_t *d_pj_atom = nullptr;  // [nproj] atom of each projector
   int32_t *d_proj_off = nullptr; // [natom+1]
   int32_t *d_dij_off = nullptr;  // [natom] offset of the atom's block in d_dij
+  // the caller's workspace (pw_workspace_size bytes), bound to the handle
+  // for its lifetime; everything below points into it
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  void *d_vplanes = nullptr;   // [N2][N0][N1] V / N^3 in the FFT precision
+  void *d_beta = nullptr;      // complex128 [nproj][ldb]
+  void *d_beta_lp = nullptr;   // reduced-precision copy (mixed forms)
+  int64_t ldb = 0;
   void *d_sticks = nullptr;    // [band_chunk][N2][nst_pad] complex (FFT precision)
   void *d_P = nullptr;         // [max_bands][nproj] complex128
   void *d_Q = nullptr;         // [max_bands][nproj] complex128
+  void *d_psi_lp = nullptr;    // BF16 form: psi rounded to bf16 pairs [max_bands][ldb]
+  void *d_q_lp = nullptr;      // BF16 form: D P rounded to bf16 pairs [max_bands][nproj]
   void *d_part = nullptr;      // split-K partial sums
   size_t part_bytes = 0;
   double *d_tn = nullptr;      // [max_bands] band kinetic energies (preconditioner)
+  float *d_mlp_s = nullptr;    // [max_bands * npw] learned scales (pw_precond with the MLP kind)
+  double *d_rnorm = nullptr;   // [max_bands] residual norms (same)
+  int *d_idx = nullptr;        // [max_bands] band indices 0 .. n-1 (same)
+  int *d_bad = nullptr;        // [max_bands] per-band fallback flags (same)
 };
 
 namespace pw {
@@ -178,12 +212,15 @@ int zgemm_nn(int64_t M, int64_t N, int64_t K, double alpha, const void *A, int64
              const void *B, int64_t ldb, double beta, void *C, int64_t ldc, hipStream_t s);
 int choose_splits(int64_t M, int64_t N, int64_t K);
 // Same shapes in a precision form: A in the form's storage (complex128,
-// float2 or bf16 pairs), B and C complex128, accumulation FP64 / FP32 / FP32.
+// float2 or bf16 pairs), B complex128 (bf16 pairs in the BF16 form, made by
+// bf16_round), C complex128, accumulation FP64 / FP32 / FP32.
 int zgemm_cn_p(int prec, int64_t M, int64_t N, int64_t K, const void *A, int64_t lda, const void *B,
                int64_t ldb, void *C, int64_t ldc, int splits, void *part, hipStream_t s);
 int zgemm_nn_p(int prec, int64_t M, int64_t N, int64_t K, double alpha, const void *A, int64_t lda,
                const void *B, int64_t ldb, double beta, void *C, int64_t ldc, hipStream_t s);
 int convert_beta(const void *src, void *dst, int64_t n, int prec, hipStream_t s);
+// dst[c][r] = src[c][r] rounded to bf16 pairs (nearest even), r < rows, c < cols
+int bf16_round(const void *src, int64_t lds, void *dst, int64_t ldd, int64_t rows, int64_t cols, hipStream_t s);
 
 // Nonlocal D application (nonlocal.hip): Q[n][j] = sum_j' D_a(j,j') P[n][j'].
 int launch_apply_d(const double *dij, const int32_t *pj_atom, const int32_t *proj_off,
@@ -194,6 +231,36 @@ int launch_tpa(const double *kin, const void *x, const void *r, void *t, int64_t
                int nb, int kind, double *tn_work, hipStream_t s);
 // Bands per plane-pass workgroup that suits a plane kernel on the grid (fft.hip).
 int plane_default_group(const FFTDev &f, int prec, int kernel);
+// Hermitian eigensolver behind pw_eigh (linalg.hip) on a workspace of
+// eigh_ws_bytes(m): the padded matrix, the pair unitaries and the
+// eigenvectors (3 mp^2 complex, mp = m rounded up to kEighPad), the
+// eigenvalues, the sweep accumulators and the sort permutation.  Every
+// region is written before it is read, so earlier contents do not matter.
+constexpr int kEighPad = 32;
+constexpr int kEighMaxSweeps = 40;
+constexpr size_t eigh_ws_bytes(int m) {
+  return 3 * (size_t)((m + kEighPad - 1) / kEighPad * kEighPad) * ((m + kEighPad - 1) / kEighPad * kEighPad) *
+             sizeof(double2) +
+         ((size_t)((m + kEighPad - 1) / kEighPad * kEighPad) + 2 * kEighMaxSweeps + 2) * sizeof(double) +
+         (size_t)((m + kEighPad - 1) / kEighPad * kEighPad) * sizeof(int);
+}
+int eigh_impl(const void *A, int64_t lda, int m, double *w, void *Z, int64_t ldz, void *work, hipStream_t s);
+// 2-norms of n columns (linalg.hip).
+int col_norms(const double2 *T, int64_t ld, int64_t npw, int n, double *nrm, hipStream_t s);
+// Learned preconditioner of the bands idx[0..nu) (mlp.hip): T_i = s K_TPA R_idx[i];
+// bad[i] is set for a band whose scales are not finite, and mlp_fallback
+// then writes TPA for every flagged band.
+int mlp_precond_idx(const pw_mlp *net, pw_problem *p, const double *theta, const double *rnorm,
+                    const int *idx, const double2 *R, int64_t ld, double2 *T, int nu, int *bad,
+                    const double *tn, hipStream_t s);
+int mlp_fallback(const int *bad, pw_problem *p, const double *tn, const int *idx, const double2 *R,
+                 int64_t ld, double2 *T, int nu, hipStream_t s);
+// Davidson state accessors for the batch scheduler (davidson.hip).
+pw_problem *dav_problem(const pw_davidson *d);
+int dav_nbands(const pw_davidson *d);
+int dav_max_subspace(const pw_davidson *d);
+bool dav_converged(const pw_davidson *d);
+bool dav_inited(const pw_davidson *d);
 // tn[n] = <x_n|t|x_n> / <x_n|x_n> for nb bands (nonlocal.hip).
 int band_kinetic(const double *kin, const void *x, int64_t ld, int64_t npw, int nb, double *tn,
                  hipStream_t s);

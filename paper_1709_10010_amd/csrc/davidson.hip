@@ -23,9 +23,7 @@
 
 namespace pw {
 int eig_herm(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz, void *rot_ws,
-             double *acc_ws, int *sweeps, int coop_blocks, hipStream_t s, double off_abs, int nwant);
-bool eig_transforms_in_place(int m);
-int coop_jacobi_blocks();
+             double *acc_ws, double *h_acc, int *sweeps, hipStream_t s, double off_abs, int nwant);
 int eig_select(const double *w, int m, int nsel, double *wsel, int *idx, const double2 *Z, int64_t ldz,
                double2 *Y, int64_t ldy, hipStream_t s, const double2 *A, int64_t lda, double2 *H,
                int64_t ldh);
@@ -36,17 +34,11 @@ int trinv_h(const double2 *L, int64_t ldl, int n, double2 *X, int64_t ldx, doubl
 int residual(const double2 *X, const double2 *HX, const double *theta, double2 *R, int64_t ld,
              int64_t npw, int nb, double *rho, hipStream_t s);
 int hermitize(double2 *H, int64_t ldh, int m0, int m1, hipStream_t s);
-int set_diag(double2 *H, int64_t ldh, int n, const double *theta, hipStream_t s);
 int copy_mat(const double2 *src, int64_t lds, double2 *dst, int64_t ldd, int m, int n, hipStream_t s);
 int scaled_cols(const double2 *U, int64_t ldu, const double *lam, const int *keep, int n, int nk,
                 double2 *B, int64_t ldb, hipStream_t s);
 int precond_idx(const double *kin, const double *tn, const int *idx, const double2 *R, int64_t ldr,
                 double2 *T, int64_t ldt, int64_t npw, int nu, int kind, hipStream_t s);
-int mlp_precond_idx(const pw_mlp *net, pw_problem *p, const double *theta, const double *rnorm,
-                    const int *idx, const double2 *R, int64_t ld, double2 *T, int nu, int *bad,
-                    const double *tn, hipStream_t s);
-int mlp_fallback(const int *bad, pw_problem *p, const double *tn, const int *idx, const double2 *R,
-                 int64_t ld, double2 *T, int nu, hipStream_t s);
 int col_norms2(const double2 *T, int64_t ld, int64_t npw, int n, double *nrm2, hipStream_t s);
 }  // namespace pw
 
@@ -57,7 +49,7 @@ struct pw_davidson {
   int nb = 0, mmax = 0, lde = 0;
   double tol = 0;
   int64_t ld = 0, npw = 0;
-  int m = 0, iter = 0, coop = 0;
+  int m = 0, iter = 0;
   int64_t n_hpsi = 0;
   bool inited = false, converged = false;
   double2 *V = nullptr, *W = nullptr, *X = nullptr, *HX = nullptr, *R = nullptr, *T = nullptr;
@@ -73,8 +65,12 @@ struct pw_davidson {
   double *acc_ws = nullptr;
   void *part = nullptr;
   size_t part_bytes = 0;
+  // the caller's workspace (pw_davidson_workspace_size bytes); every device
+  // buffer above points into it
+  void *ws = nullptr;
   // pinned host mirrors
   double *h_theta = nullptr, *h_rho = nullptr, *h_lam = nullptr;
+  double *h_acc = nullptr;  // eigensolver's off-diagonal and total mass, read once per sweep
   int *h_U = nullptr, *h_flag = nullptr, *h_keep = nullptr;
   // orthonormalisation: column norms^2 before it, the Cholesky diagonal
   double *cnorm = nullptr, *h_cnorm = nullptr;
@@ -94,25 +90,79 @@ struct pw_davidson {
 
 namespace {
 
+// the device buffers live in the caller's workspace; only the small pinned
+// host mirrors belong to the handle
 void free_dav(pw_davidson *d) {
   if (!d) return;
-  void *dev[] = {d->V,  d->W,  d->X,  d->HX,    d->R,     d->T,    d->Hs,    d->Ae,  d->Ze,
-                 d->Y,  d->C,  d->S,  d->L,     d->Xi,    d->Bi,   d->w_all, d->theta, d->rho,
-                 d->tn, d->lam, d->idx_sel, d->dU, d->keep, d->flag, d->sweeps, d->rot_ws,
-                 d->acc_ws, d->part, d->bad, d->Vt, d->Wt, d->w_sorted, d->idx_all, d->cnorm};
-  for (void *b : dev)
-    if (b) (void)hipFree(b);
   void *host[] = {d->h_theta, d->h_rho, d->h_lam, d->h_U, d->h_flag, d->h_keep, d->h_bad, d->h_cnorm,
-                  d->h_ldiag};
+                  d->h_ldiag, d->h_acc};
   for (void *b : host)
     if (b) (void)hipHostFree(b);
   delete d;
 }
 
-template <typename T>
-bool dalloc(T **p, size_t n) {
-  return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T)) == hipSuccess;
+// Workspace layout of a Davidson state: counted by pw_davidson_workspace_size
+// with a null base, placed by pw_davidson_create with the caller's.
+void carve_dav(pw_davidson *d, Carve &c) {
+  const size_t blk = (size_t)d->ld, nb = d->nb, lde = d->lde;
+  d->V = c.take<double2>(lde * blk);
+  d->W = c.take<double2>(lde * blk);
+  d->Vt = c.take<double2>(lde * blk);
+  d->Wt = c.take<double2>(lde * blk);
+  d->X = c.take<double2>(nb * blk);
+  d->HX = c.take<double2>(nb * blk);
+  d->R = c.take<double2>(nb * blk);
+  d->T = c.take<double2>(nb * blk);
+  d->Hs = c.take<double2>(lde * lde);
+  d->Ae = c.take<double2>(lde * lde);
+  d->Ze = c.take<double2>(lde * lde);
+  d->rot_ws = c.take<double2>(lde * lde);
+  d->Y = c.take<double2>(lde * nb);
+  d->C = c.take<double2>(lde * nb);
+  d->S = c.take<double2>(nb * nb);
+  d->L = c.take<double2>(nb * nb);
+  d->Xi = c.take<double2>(nb * nb);
+  d->Bi = c.take<double2>(nb * nb);
+  d->w_sorted = c.take<double>(lde);
+  d->idx_all = c.take<int>(lde);
+  d->w_all = c.take<double>(lde);
+  d->lam = c.take<double>(lde);
+  d->theta = c.take<double>(nb);
+  d->rho = c.take<double>(nb);
+  d->tn = c.take<double>(nb);
+  d->cnorm = c.take<double>(nb);
+  d->idx_sel = c.take<int>(nb);
+  d->dU = c.take<int>(nb);
+  d->keep = c.take<int>(nb);
+  d->bad = c.take<int>(nb);
+  d->flag = c.take<int>(1);
+  d->sweeps = c.take<int>(1);
+  d->acc_ws = c.take<double>(128);
+  d->part_bytes = (size_t)32 * lde * nb * sizeof(double2);
+  d->part = c.take<char>(d->part_bytes);
 }
+
+// sizes of a Davidson state from its arguments (shared by the size query and create)
+int dav_shape(pw_problem *p, int64_t nbands, int64_t *max_subspace, double tol, const char *who) {
+  auto msg = [&](const char *m) { return std::string(who) + ": " + m; };
+  PW_CHECK_ARG(nbands >= 1 && nbands <= p->max_bands && nbands <= p->npw, PW_ERR_INVALID,
+               msg("nbands must be in 1 .. min(max_bands, npw)"));
+  if (*max_subspace == 0) *max_subspace = 3 * nbands;
+  PW_CHECK_ARG(*max_subspace >= 2 * nbands && *max_subspace <= p->npw && *max_subspace <= 8192, PW_ERR_INVALID,
+               msg("max_subspace must be in 2*nbands .. min(npw, 8192)"));
+  PW_CHECK_ARG(tol > 0 && std::isfinite(tol), PW_ERR_INVALID, msg("tol must be > 0"));
+  return PW_OK;
+}
+
+void dav_dims(pw_davidson *d, pw_problem *p, int64_t nbands, int64_t max_subspace) {
+  d->p = p;
+  d->nb = (int)nbands;
+  d->mmax = (int)max_subspace;
+  d->lde = (d->mmax + 31) / 32 * 32;  // room for the block eigensolver's padding
+  d->npw = p->npw;
+  d->ld = (p->npw + 63) / 64 * 64;
+}
+
 template <typename T>
 bool halloc(T **p, size_t n) {
   return hipHostMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T), hipHostMallocDefault) == hipSuccess;
@@ -144,22 +194,14 @@ int nn(pw_davidson *d, int64_t N, int64_t K, double alpha, const double2 *A, con
 
 // PW_DAV_ORTHO_SKIP=0 always runs the second orthonormalisation round.
 static bool ortho_skip() {
-  static int v = -1;
-  if (v < 0) {
-    const char *e = std::getenv("PW_DAV_ORTHO_SKIP");
-    v = (e && *e) ? std::atoi(e) : 1;
-  }
+  static const int v = env_switch("PW_DAV_ORTHO_SKIP", 1);
   return v != 0;
 }
 
 // Gram-Schmidt passes against V in the first orthonormalisation round
 // (PW_DAV_GS_FIRST, 1 or 2; default 1).
 static int gs_first() {
-  static int v = -1;
-  if (v < 0) {
-    const char *e = std::getenv("PW_DAV_GS_FIRST");
-    v = (e && *e && std::atoi(e) == 2) ? 2 : 1;
-  }
+  static const int v = env_switch("PW_DAV_GS_FIRST", 1) == 2 ? 2 : 1;
   return v;
 }
 
@@ -225,8 +267,8 @@ int ortho_block(pw_davidson *d, int m, double2 *T, int n, double2 *dst, int *n_o
       {
         ProfScope ps(&d->p->prof, PW_STAGE_EIG, s);
         DV_RC(copy_mat(d->S, n, d->Ae, d->lde, n, n, s));
-        DV_RC(eig_herm(d->Ae, d->lde, n, d->lam, d->Ze, d->lde, d->rot_ws, d->acc_ws, d->sweeps,
-                       d->coop, s, 0.0, 0));
+        DV_RC(eig_herm(d->Ae, d->lde, n, d->lam, d->Ze, d->lde, d->rot_ws, d->acc_ws, d->h_acc,
+                       d->sweeps, s, 0.0, 0));
       }
       PW_HIP(hipMemcpyAsync(d->h_lam, d->lam, n * sizeof(double), hipMemcpyDeviceToHost, s));
       PW_HIP(hipStreamSynchronize(s));
@@ -256,11 +298,10 @@ int ortho_block(pw_davidson *d, int m, double2 *T, int n, double2 *dst, int *n_o
 // Eigensolver stop level relative to the smallest open residual
 // (PW_DAV_OFF_FACTOR).
 static double off_factor() {
-  static double v = -1.0;
-  if (v < 0.0) {
+  static const double v = [] {
     const char *e = std::getenv("PW_DAV_OFF_FACTOR");
-    v = (e && *e) ? std::max(1e-6, std::atof(e)) : 3.0;
-  }
+    return (e && *e) ? std::max(1e-6, std::atof(e)) : 3.0;
+  }();
   return v;
 }
 
@@ -269,11 +310,7 @@ static double off_factor() {
 // of an active band sees its own column of the carried rest, and the rest
 // among upper directions is carried and rotated on in later steps.
 static bool eig_wanted() {
-  static int v = -1;
-  if (v < 0) {
-    const char *e = std::getenv("PW_EIG_WANTED");
-    v = (e && *e) ? std::atoi(e) : 1;
-  }
+  static const int v = env_switch("PW_EIG_WANTED", 1);
   return v != 0;
 }
 
@@ -282,70 +319,76 @@ struct RestartCap {
   int mul = 3, min = 64, keep = 3;
 };
 static const RestartCap &restart_cap() {
-  static RestartCap c;
-  static bool init = false;
-  if (!init) {
-    auto get = [](const char *n, int dflt) {
-      const char *e = std::getenv(n);
-      return (e && *e) ? std::max(0, std::atoi(e)) : dflt;
-    };
-    c.mul = get("PW_DAV_ACT_MUL", c.mul);
-    c.min = get("PW_DAV_ACT_MIN", c.min);
-    c.keep = get("PW_DAV_ACT_KEEP", c.keep);
-    init = true;
-  }
+  static const RestartCap c = [] {
+    RestartCap r;
+    r.mul = std::max(0, env_switch("PW_DAV_ACT_MUL", r.mul));
+    r.min = std::max(0, env_switch("PW_DAV_ACT_MIN", r.min));
+    r.keep = std::max(0, env_switch("PW_DAV_ACT_KEEP", r.keep));
+    return r;
+  }();
   return c;
 }
 
+namespace pw {
+// Shape of a Davidson state for the batch scheduler (batch.hip): its
+// problem, bands, subspace bound, and whether its last step converged.
+pw_problem *dav_problem(const pw_davidson *d) { return d->p; }
+int dav_nbands(const pw_davidson *d) { return d->nb; }
+int dav_max_subspace(const pw_davidson *d) { return d->mmax; }
+bool dav_converged(const pw_davidson *d) { return d->inited && d->converged; }
+bool dav_inited(const pw_davidson *d) { return d->inited; }
+}  // namespace pw
+
 extern "C" {
 
+pw_status pw_davidson_workspace_size(pw_problem *p, int64_t nbands, int64_t max_subspace, size_t *bytes) {
+  PW_CHECK_ARG(p && bytes, PW_ERR_INVALID, "pw_davidson_workspace_size: null argument");
+  *bytes = 0;
+  const int rc = dav_shape(p, nbands, &max_subspace, 1.0, "pw_davidson_workspace_size");
+  if (rc != PW_OK) return rc;
+  pw_davidson d;
+  dav_dims(&d, p, nbands, max_subspace);
+  Carve c(nullptr);
+  carve_dav(&d, c);
+  *bytes = c.size();
+  return PW_OK;
+}
+
 pw_status pw_davidson_create(pw_problem *p, int64_t nbands, int64_t max_subspace, double tol,
-                             void *stream, pw_davidson **out) {
+                             void *workspace, size_t ws_bytes, void *stream, pw_davidson **out) {
   PW_CHECK_ARG(p && out, PW_ERR_INVALID, "pw_davidson_create: null argument");
   *out = nullptr;
-  PW_CHECK_ARG(nbands >= 1 && nbands <= p->max_bands && nbands <= p->npw, PW_ERR_INVALID,
-               "pw_davidson_create: nbands must be in 1 .. min(max_bands, npw)");
-  if (max_subspace == 0) max_subspace = 3 * nbands;
-  PW_CHECK_ARG(max_subspace >= 2 * nbands && max_subspace <= p->npw && max_subspace <= 8192,
-               PW_ERR_INVALID, "pw_davidson_create: max_subspace must be in 2*nbands .. min(npw, 8192)");
-  PW_CHECK_ARG(tol > 0 && std::isfinite(tol), PW_ERR_INVALID, "pw_davidson_create: tol must be > 0");
+  int rc = dav_shape(p, nbands, &max_subspace, tol, "pw_davidson_create");
+  if (rc != PW_OK) return rc;
   pw_davidson *d = new pw_davidson();
-  d->p = p;
-  d->nb = (int)nbands;
-  d->mmax = (int)max_subspace;
-  d->lde = (d->mmax + 31) / 32 * 32;  // room for the block eigensolver's padding
+  dav_dims(d, p, nbands, max_subspace);
   d->tol = tol;
-  d->npw = p->npw;
-  d->ld = (p->npw + 63) / 64 * 64;
-  const size_t blk = (size_t)d->ld;
+  {
+    Carve count(nullptr);
+    carve_dav(d, count);
+    if (!workspace || ws_bytes < count.size() || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0) {
+      free_dav(d);
+      set_error("pw_davidson_create: workspace must be 256-byte aligned device memory of at least "
+                "pw_davidson_workspace_size() = " + std::to_string(count.size()) + " bytes");
+      return PW_ERR_INVALID;
+    }
+    Carve c(workspace);
+    carve_dav(d, c);
+    d->ws = workspace;
+  }
   const size_t nb = d->nb, lde = d->lde;
-  bool ok = dalloc(&d->V, lde * blk) && dalloc(&d->W, lde * blk) && dalloc(&d->X, nb * blk) &&
-            dalloc(&d->Vt, lde * blk) && dalloc(&d->Wt, lde * blk) && dalloc(&d->w_sorted, lde) &&
-            dalloc(&d->idx_all, lde) &&
-            dalloc(&d->HX, nb * blk) && dalloc(&d->R, nb * blk) && dalloc(&d->T, nb * blk) &&
-            dalloc(&d->Hs, lde * lde) && dalloc(&d->Ae, lde * lde) && dalloc(&d->Ze, lde * lde) &&
-            dalloc(&d->Y, lde * nb) && dalloc(&d->C, lde * nb) && dalloc(&d->S, nb * nb) &&
-            dalloc(&d->L, nb * nb) && dalloc(&d->Xi, nb * nb) && dalloc(&d->Bi, nb * nb) &&
-            dalloc(&d->w_all, lde) && dalloc(&d->theta, nb) && dalloc(&d->rho, nb) &&
-            dalloc(&d->tn, nb) && dalloc(&d->lam, lde) && dalloc(&d->idx_sel, nb) &&
-            dalloc(&d->dU, nb) && dalloc(&d->keep, nb) && dalloc(&d->flag, 1) &&
-            dalloc(&d->sweeps, 1) && dalloc(&d->bad, nb) && dalloc((double2 **)&d->rot_ws, lde * lde) &&
-            dalloc(&d->acc_ws, 128) && halloc(&d->h_theta, nb) && halloc(&d->h_rho, nb) &&
-            halloc(&d->h_lam, lde) && halloc(&d->h_U, nb) && halloc(&d->h_flag, 1) &&
-            halloc(&d->h_keep, nb) && halloc(&d->h_bad, nb) && dalloc(&d->cnorm, nb) &&
-            halloc(&d->h_cnorm, nb) && halloc(&d->h_ldiag, nb);
-  d->part_bytes = (size_t)32 * lde * nb * sizeof(double2);
-  ok = ok && dalloc((char **)&d->part, d->part_bytes);
+  const bool ok = halloc(&d->h_theta, nb) && halloc(&d->h_rho, nb) && halloc(&d->h_lam, lde) &&
+                  halloc(&d->h_U, nb) && halloc(&d->h_flag, 1) && halloc(&d->h_keep, nb) &&
+                  halloc(&d->h_bad, nb) && halloc(&d->h_cnorm, nb) && halloc(&d->h_ldiag, nb) &&
+                  halloc(&d->h_acc, 2);
   if (!ok) {
     free_dav(d);
-    set_error("pw_davidson_create: device allocation failed");
+    set_error("pw_davidson_create: pinned host allocation failed");
     return PW_ERR_NOMEM;
   }
-  (void)hipMemsetAsync(d->Hs, 0, lde * lde * sizeof(double2), static_cast<hipStream_t>(stream));
-  d->coop = coop_jacobi_blocks();
-  if (d->coop <= 0 && d->lde > 64) {
+  if (hipMemsetAsync(d->Hs, 0, lde * lde * sizeof(double2), static_cast<hipStream_t>(stream)) != hipSuccess) {
     free_dav(d);
-    set_error("pw_davidson_create: cooperative launch not available");
+    set_error("pw_davidson_create: workspace initialisation failed");
     return PW_ERR_HIP;
   }
   *out = d;
@@ -400,7 +443,7 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   const char *where = "pw_davidson_step: launch failed";
   const int nb = d->nb;
   // 1. Rayleigh-Ritz: Z^H H_s Z = diag(w) + E, eigenpairs sorted ascending.
-  //    Where the eigensolver transforms H_s in place, it stops once the
+  //    The eigensolver transforms H_s in place and stops once the
   //    off-diagonal part E is below off_target (tied to the residuals of
   //    the previous step) and Z^H H_s Z, E included, becomes the next H_s,
   //    so nothing is dropped and the next step continues the diagonalisation.
@@ -411,14 +454,13 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   //    of its residuals (below the tolerance), are left out.
   const int nl = d->nl, ma = d->m - nl;
   const size_t hoff = (size_t)nl * d->lde + nl;
-  const bool carry = eig_transforms_in_place(ma);
   {
     ProfScope ps(&d->p->prof, PW_STAGE_EIG, s);
     DV_RC(copy_mat(d->Hs + hoff, d->lde, d->Ae, d->lde, ma, ma, s));
-    DV_RC(eig_herm(d->Ae, d->lde, ma, d->w_all, d->Ze, d->lde, d->rot_ws, d->acc_ws, d->sweeps,
-                   d->coop, s, carry ? d->off_target : 0.0, carry && eig_wanted() ? nb - nl : 0));
+    DV_RC(eig_herm(d->Ae, d->lde, ma, d->w_all, d->Ze, d->lde, d->rot_ws, d->acc_ws, d->h_acc, d->sweeps,
+                   s, d->off_target, eig_wanted() ? nb - nl : 0));
     DV_RC(eig_select(d->w_all, ma, ma, d->w_sorted, d->idx_all, d->Ze, d->lde, d->Ae, d->lde, s,
-                     carry ? d->Ae : nullptr, d->lde, d->Hs + hoff, d->lde));
+                     d->Ae, d->lde, d->Hs + hoff, d->lde));
   }
   // 2. rotate the active space into the Ritz basis (V <- V Z, W <- W Z): the
   //    first nb columns are the Ritz vectors, the active H_s becomes diag(w),
@@ -434,7 +476,6 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
     PW_HIP(hipMemcpyAsync(d->Vt, d->V, lcol * sizeof(double2), hipMemcpyDeviceToDevice, s));
     PW_HIP(hipMemcpyAsync(d->Wt, d->W, lcol * sizeof(double2), hipMemcpyDeviceToDevice, s));
   }
-  if (!carry) DV_RC(set_diag(d->Hs + hoff, d->lde, ma, d->w_sorted, s));
   if (nb > nl)
     PW_HIP(hipMemcpyAsync(d->theta + nl, d->w_sorted, (nb - nl) * sizeof(double), hipMemcpyDeviceToDevice, s));
   PW_HIP(hipMemcpyAsync(d->X, d->Vt, (size_t)nb * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));

@@ -1100,11 +1100,7 @@ static inline int nb_pad8(int nb) { return (nb + 7) / 8 * 8; }
 #define PW_CT_EVEN_SIZES(X) X(24) X(36) X(40) X(48) X(50) X(54) X(60) X(64) X(72) X(90)
 
 static int ct_size(const FFTDev &f, int prec) {
-  static int off = -1;
-  if (off < 0) {
-    const char *e = std::getenv("PW_FFT_GENERIC");
-    off = (e && *e && std::atoi(e)) ? 1 : 0;
-  }
+  static const bool off = env_switch("PW_FFT_GENERIC", 0) != 0;
   if (off || f.n0 != f.n1 || f.n1 != f.n2) return 0;
   if (f.ts != (prec == PW_FP64 ? 16 : 32)) return 0;
   switch (f.n0) {
@@ -1146,12 +1142,10 @@ static int zinv_t(const FFTDev &f, const void *psi, int64_t ld, void *sticks, in
 // (wave-local lines), PW_PLANE_LDS (LDS Stockham passes).  A problem
 // starts with PW_PLANE_IMPL from the environment, else PW_PLANE_REGISTER.
 int plane_kernel_default() {
-  static int v = -1;
-  if (v < 0) {
-    const char *e = std::getenv("PW_PLANE_IMPL");
-    v = (e && *e) ? std::atoi(e) : PW_PLANE_REGISTER;
-    if (v < PW_PLANE_REGISTER || v > PW_PLANE_LDS) v = PW_PLANE_REGISTER;
-  }
+  static const int v = [] {
+    const int x = env_switch("PW_PLANE_IMPL", PW_PLANE_REGISTER);
+    return (x < PW_PLANE_REGISTER || x > PW_PLANE_LDS) ? PW_PLANE_REGISTER : x;
+  }();
   return v;
 }
 
@@ -1159,11 +1153,7 @@ int plane_kernel_default() {
 // four lanes and N / 4 even the lane levels exchange halves; PW_PLANE_HALVES=0
 // keeps the quad-permutation joins.
 static bool plane_halves() {
-  static int v = -1;
-  if (v < 0) {
-    const char *e = std::getenv("PW_PLANE_HALVES");
-    v = (e && *e) ? std::atoi(e) : 1;
-  }
+  static const int v = env_switch("PW_PLANE_HALVES", 1);
   return v != 0;
 }
 #ifndef PW_PLANE_R_THREADS

@@ -360,11 +360,15 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_nn(int64_t M, int64_t N, int
 }
 
 // ---------------------------------------------------------------- BF16 inputs, FP32 accumulation
-// v_mfma_f32_16x16x16_bf16: operand lanes hold 4 consecutive k,
-// A[i = l%16][k = 4(l/16) + v], B[k = 4(l/16) + v][j = l%16]; LDS tiles are
-// [mn][k] (k contiguous) so each lane fetches its 4 values in one read.
-// Complex storage of a bf16 matrix: (re, im) pairs, 4 bytes per element.
-typedef short s4_t __attribute__((ext_vector_type(4)));
+// v_mfma_f32_16x16x32_bf16 (gfx950): operand lanes hold 8 consecutive k,
+// A[i = l%16][k = 8(l/16) + v], B[k = 8(l/16) + v][j = l%16]; the
+// accumulator's row for register r of lane l is 4(l/16) + r.  LDS tiles are
+// [mn][k] (k contiguous) so each lane fetches its 8 values in one 16-byte
+// read.  Complex storage of a bf16 matrix: (re, im) pairs, 4 bytes per
+// element.  Both operands arrive in bf16: beta is converted once at create,
+// psi and D P once per call (bf16_round), so the tiles of every M (or N)
+// block read a quarter of the complex128 bytes and convert nothing.
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 constexpr int BB_K = 32;
 
 __device__ __forceinline__ unsigned short bf16_rne(float f) {
@@ -387,22 +391,12 @@ __device__ __forceinline__ uint4 bf_pack8(const unsigned short v[8]) {
                v[6] | ((unsigned)v[7] << 16)};
 }
 
-// A thread's 8 values of a stage, kept in the source format between the
-// global loads and the LDS store (so the loads of the next stage overlap the
-// MFMAs of this one): complex128, or bf16 (re, im) pairs packed re-low.
-struct BfRawD {
-  double2 v[8];
-};
+// A thread's 8 values of a stage, kept as loaded between the global loads
+// and the LDS store (so the loads of the next stage overlap the MFMAs of
+// this one): bf16 (re, im) pairs packed re-low.
 struct BfRawH {
   unsigned w[8];
 };
-__device__ __forceinline__ void bf_split(const BfRawD &r, unsigned short re[8], unsigned short im[8]) {
-#pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    re[u] = bf16_rne((float)r.v[u].x);
-    im[u] = bf16_rne((float)r.v[u].y);
-  }
-}
 __device__ __forceinline__ void bf_split(const BfRawH &r, unsigned short re[8], unsigned short im[8]) {
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
@@ -412,14 +406,6 @@ __device__ __forceinline__ void bf_split(const BfRawH &r, unsigned short re[8], 
 }
 
 // K-contiguous source, 64 columns x 32 k: thread t: column t/4, k = 8*(t%4) .. +7.
-__device__ __forceinline__ void bf_load_kc(const double2 *__restrict__ P, int64_t ld, int64_t k0,
-                                           int64_t c0, int64_t K, int64_t C, BfRawD &r) {
-  const int t = threadIdx.x;
-  const int64_t c = c0 + (t >> 2);
-  const int64_t k = k0 + ((t & 3) << 3);
-#pragma unroll
-  for (int u = 0; u < 8; ++u) r.v[u] = (c < C && k + u < K) ? P[c * ld + k + u] : double2{0.0, 0.0};
-}
 __device__ __forceinline__ void bf_load_kc(const ushort2 *__restrict__ P, int64_t ld, int64_t k0,
                                            int64_t c0, int64_t K, int64_t C, BfRawH &r) {
   const int t = threadIdx.x;
@@ -478,38 +464,35 @@ struct AccF {
   f4_t rr[2][2], ii[2][2], ri[2][2], ir[2][2];
 };
 
-__device__ __forceinline__ s4_t bf_frag(const unsigned short (*S)[BB_KP], int row, int k) {
-  const unsigned short *p = &S[row][k];
-  return s4_t{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
+// 8 consecutive k of one row (16-byte aligned: rows are 80 bytes, k % 8 == 0)
+__device__ __forceinline__ bf8_t bf_frag(const unsigned short (*S)[BB_KP], int row, int k) {
+  return __builtin_bit_cast(bf8_t, *reinterpret_cast<const uint4 *>(&S[row][k]));
 }
 
 __device__ __forceinline__ void bf_stage(const BfTile &At, const BfTile &Bt, AccF &acc, int wm, int wn) {
   const int lane = threadIdx.x & 63;
   const int lr = lane & 15;
-  const int lk = (lane >> 4) << 2;
+  const int lk = (lane >> 4) << 3;
+  bf8_t ar[2], ai[2], br[2], bi[2];
 #pragma unroll
-  for (int kk = 0; kk < BB_K; kk += 16) {
-    s4_t ar[2], ai[2], br[2], bi[2];
+  for (int i = 0; i < 2; ++i) {
+    ar[i] = bf_frag(At.re, wm * 32 + i * 16 + lr, lk);
+    ai[i] = bf_frag(At.im, wm * 32 + i * 16 + lr, lk);
+  }
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      ar[i] = bf_frag(At.re, wm * 32 + i * 16 + lr, kk + lk);
-      ai[i] = bf_frag(At.im, wm * 32 + i * 16 + lr, kk + lk);
-    }
+  for (int j = 0; j < 2; ++j) {
+    br[j] = bf_frag(Bt.re, wn * 32 + j * 16 + lr, lk);
+    bi[j] = bf_frag(Bt.im, wn * 32 + j * 16 + lr, lk);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      br[j] = bf_frag(Bt.re, wn * 32 + j * 16 + lr, kk + lk);
-      bi[j] = bf_frag(Bt.im, wn * 32 + j * 16 + lr, kk + lk);
+      acc.rr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br[j], ar[i], acc.rr[i][j], 0, 0, 0);
+      acc.ii[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bi[j], ai[i], acc.ii[i][j], 0, 0, 0);
+      acc.ri[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bi[j], ar[i], acc.ri[i][j], 0, 0, 0);
+      acc.ir[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br[j], ai[i], acc.ir[i][j], 0, 0, 0);
     }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        acc.rr[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(br[j], ar[i], acc.rr[i][j], 0, 0, 0);
-        acc.ii[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bi[j], ai[i], acc.ii[i][j], 0, 0, 0);
-        acc.ri[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bi[j], ar[i], acc.ri[i][j], 0, 0, 0);
-        acc.ir[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(br[j], ai[i], acc.ir[i][j], 0, 0, 0);
-      }
-  }
 }
 
 template <bool CONJ_A, typename F>
@@ -532,7 +515,7 @@ __device__ __forceinline__ void bf_out(const AccF &acc, int wm, int wn, F &&f) {
 
 __global__ __launch_bounds__(G_THR, 2) void k_zgemm_cn_bf16(int64_t M, int64_t N, int64_t K,
                                                             const ushort2 *__restrict__ A, int64_t lda,
-                                                            const double2 *__restrict__ B, int64_t ldb,
+                                                            const ushort2 *__restrict__ B, int64_t ldb,
                                                             double2 *__restrict__ C, int64_t ldc,
                                                             int64_t kchunk, int direct, int64_t nsplit) {
   __shared__ __align__(16) BfTile At, Bt;
@@ -549,8 +532,7 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_cn_bf16(int64_t M, int64_t N
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc.rr[i][j] = acc.ii[i][j] = acc.ri[i][j] = acc.ir[i][j] = z;
-  BfRawH ra;
-  BfRawD rb;
+  BfRawH ra, rb;
   if (kb < ke) {
     bf_load_kc(A, lda, kb, m0, ke, M, ra);
     bf_load_kc(B, ldb, kb, n0, ke, N, rb);
@@ -576,7 +558,7 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_cn_bf16(int64_t M, int64_t N
 
 __global__ __launch_bounds__(G_THR, 2) void k_zgemm_nn_bf16(int64_t M, int64_t N, int64_t K,
                                                             double alpha, const ushort2 *__restrict__ A,
-                                                            int64_t lda, const double2 *__restrict__ B,
+                                                            int64_t lda, const ushort2 *__restrict__ B,
                                                             int64_t ldb, double beta,
                                                             double2 *__restrict__ C, int64_t ldc) {
   __shared__ __align__(16) BfTile At, Bt;
@@ -591,8 +573,7 @@ __global__ __launch_bounds__(G_THR, 2) void k_zgemm_nn_bf16(int64_t M, int64_t N
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc.rr[i][j] = acc.ii[i][j] = acc.ri[i][j] = acc.ir[i][j] = z;
-  BfRawH ra;
-  BfRawD rb;
+  BfRawH ra, rb;
   if (K > 0) {
     bf_load_mc(A, lda, m0, 0, M, K, ra);
     bf_load_kc(B, ldb, 0, n0, K, N, rb);
@@ -632,6 +613,26 @@ __global__ void k_cvt_bf16(const double2 *__restrict__ src, ushort2 *__restrict_
     dst[e] = ushort2{bf16_rne((float)src[e].x), bf16_rne((float)src[e].y)};
 }
 
+// [cols][lds] complex128 -> [cols][ldd] bf16 pairs, rows 0..rows-1 of each column
+__global__ void k_cvt_bf16_2d(const double2 *__restrict__ src, int64_t lds, ushort2 *__restrict__ dst,
+                              int64_t ldd, int64_t rows, int64_t cols) {
+  const int64_t tot = rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e / rows, r = e - c * rows;
+    const double2 v = src[c * lds + r];
+    dst[c * ldd + r] = ushort2{bf16_rne((float)v.x), bf16_rne((float)v.y)};
+  }
+}
+
+int bf16_round(const void *src, int64_t lds, void *dst, int64_t ldd, int64_t rows, int64_t cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return PW_OK;
+  int64_t blocks = (rows * cols + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_cvt_bf16_2d, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const double2 *>(src),
+                     lds, static_cast<ushort2 *>(dst), ldd, rows, cols);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
 int convert_beta(const void *src, void *dst, int64_t n, int prec, hipStream_t s) {
   int64_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
@@ -646,11 +647,7 @@ int convert_beta(const void *src, void *dst, int64_t n, int prec, hipStream_t s)
 
 // FP64 products in the three-multiplication form unless PW_GEMM_3M=0
 static bool gemm_3m() {
-  static int v = -1;
-  if (v < 0) {
-    const char *e = std::getenv("PW_GEMM_3M");
-    v = (e && *e) ? std::atoi(e) : 1;
-  }
+  static const int v = env_switch("PW_GEMM_3M", 1);
   return v != 0;
 }
 
@@ -699,7 +696,8 @@ int zgemm_cn_p(int prec, int64_t M, int64_t N, int64_t K, const void *A, int64_t
                        static_cast<const float2 *>(A), lda, Bd, ldb, O, ldc, kchunk, direct, ns);
   else
     hipLaunchKernelGGL(k_zgemm_cn_bf16, grid, dim3(G_THR), 0, s, M, N, K,
-                       static_cast<const ushort2 *>(A), lda, Bd, ldb, O, ldc, kchunk, direct, ns);
+                       static_cast<const ushort2 *>(A), lda, static_cast<const ushort2 *>(B), ldb, O, ldc,
+                       kchunk, direct, ns);
   if (hipGetLastError() != hipSuccess) return PW_ERR_HIP;
   return direct ? PW_OK : launch_reduce(M, N, splits, part, C, ldc, s);
 }
@@ -721,7 +719,8 @@ int zgemm_nn_p(int prec, int64_t M, int64_t N, int64_t K, double alpha, const vo
                        static_cast<const float2 *>(A), lda, Bd, ldb, beta, Cd, ldc);
   else
     hipLaunchKernelGGL(k_zgemm_nn_bf16, grid, dim3(G_THR), 0, s, M, N, K, alpha,
-                       static_cast<const ushort2 *>(A), lda, Bd, ldb, beta, Cd, ldc);
+                       static_cast<const ushort2 *>(A), lda, static_cast<const ushort2 *>(B), ldb, beta, Cd,
+                       ldc);
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
 

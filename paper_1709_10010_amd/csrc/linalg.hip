@@ -25,24 +25,17 @@
 // Larger ones run by blocks of 16 indices: each block pair's 32 x 32
 // sub-problem is solved in LDS by one workgroup, and the pair unitaries are
 // then applied to the whole matrix and to Z (see the block-Jacobi section).
-// An element-wise variant on a cooperative grid (each thread recomputes the
-// two rotations of its block from the previous round's matrix and writes
-// into a second buffer, one grid-wide barrier per round) stays selectable.
-// All are bounded: every wave leaves after at most kMaxSweeps sweeps.
+// Both are bounded: every wave leaves after at most kMaxSweeps sweeps.
 //
 // Also here: eigenvalue sort / Ritz-vector selection, Cholesky of a small
 // Hermitian positive matrix with breakdown detection, the inverse of its
 // triangular factor, and the small elementwise kernels of a Davidson step.
-#include <hip/hip_cooperative_groups.h>
-
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <vector>
 
 #include "common.h"
-
-namespace cg = cooperative_groups;
 
 namespace pw {
 
@@ -285,95 +278,6 @@ __global__ __launch_bounds__(256) void k_jacobi_lds(double2 *__restrict__ Ain, i
   if (tid == 0 && sweeps_out) *sweeps_out = sweep;
 }
 
-// ---------------------------------------------------------------- cooperative Jacobi
-// A (lda) and B (same shape) alternate as input / output of a round, so one
-// grid barrier per round suffices: every thread recomputes, from the input
-// matrix, the two rotations its 2x2 block needs and writes the block to the
-// output; Z (ldz, mp x mp) is updated in place, each (row, pair) by one
-// thread.  acc holds 2*kMaxSweeps doubles (zeroed here).  On exit the
-// eigenvalues are in w; *which = 0 if the final matrix is in A, 1 if in B.
-__device__ __forceinline__ Rot rot_of(const double2 *M, int64_t ld, int p, int q) {
-  return make_rot(M[p + p * ld].x, M[q + q * ld].x, M[p + q * ld]);
-}
-
-__global__ __launch_bounds__(256) void k_jacobi_coop(double2 *__restrict__ A, double2 *__restrict__ B,
-                                                     int64_t lda, int m, double *__restrict__ w,
-                                                     double2 *__restrict__ Z, int64_t ldz,
-                                                     double *__restrict__ acc,
-                                                     int *__restrict__ sweeps_out) {
-  cg::grid_group grid = cg::this_grid();
-  const int mp = (m + 1) & ~1;
-  const int np = mp / 2;
-  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
-  __shared__ double red[2][256];
-  for (int64_t e = gtid; e < (int64_t)mp * mp; e += gsz) {
-    const int i = (int)(e % mp), j = (int)(e / mp);
-    if (i >= m || j >= m) A[i + j * lda] = double2{0.0, 0.0};
-    Z[i + j * ldz] = double2{i == j ? 1.0 : 0.0, 0.0};
-  }
-  for (int64_t e = gtid; e < 2 * kMaxSweeps; e += gsz) acc[e] = 0.0;
-  grid.sync();
-  double2 *cur = A, *nxt = B;
-  int sweep = 0;
-  for (; sweep < kMaxSweeps; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int64_t e = gtid; e < (int64_t)mp * mp; e += gsz) {
-      const int i = (int)(e % mp), j = (int)(e / mp);
-      const double2 v = cur[i + j * lda];
-      const double a2 = v.x * v.x + v.y * v.y;
-      tot += a2;
-      if (i != j) off += a2;
-    }
-    red[0][threadIdx.x] = off;
-    red[1][threadIdx.x] = tot;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) {
-        red[0][threadIdx.x] += red[0][threadIdx.x + s];
-        red[1][threadIdx.x] += red[1][threadIdx.x + s];
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      atomicAdd(&acc[2 * sweep], red[0][0]);
-      atomicAdd(&acc[2 * sweep + 1], red[1][0]);
-    }
-    grid.sync();
-    const double offs = __hip_atomic_load(&acc[2 * sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const double tots = __hip_atomic_load(&acc[2 * sweep + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (offs <= kOffRel * (double)mp * tots) break;  // uniform: all threads read the same totals
-    for (int r = 0; r < mp - 1; ++r) {
-      for (int64_t e = gtid; e < (int64_t)np * np; e += gsz) {
-        const int ka = (int)(e % np), kb = (int)(e / np);
-        int pa, qa, pb, qb;
-        pair_of(ka, r, mp, &pa, &qa);
-        pair_of(kb, r, mp, &pb, &qb);
-        const Rot ra = rot_of(cur, lda, pa, qa);
-        const Rot rb = (ka == kb) ? ra : rot_of(cur, lda, pb, qb);
-        double2 a = cur[pa + pb * lda], b = cur[pa + qb * lda], c = cur[qa + pb * lda], d = cur[qa + qb * lda];
-        update_block(a, b, c, d, ra, rb);
-        nxt[pa + pb * lda] = a;
-        nxt[pa + qb * lda] = b;
-        nxt[qa + pb * lda] = c;
-        nxt[qa + qb * lda] = d;
-      }
-      for (int64_t e = gtid; e < (int64_t)mp * np; e += gsz) {
-        const int i = (int)(e % mp), kb = (int)(e / mp);
-        int pb, qb;
-        pair_of(kb, r, mp, &pb, &qb);
-        const Rot rb = rot_of(cur, lda, pb, qb);
-        update_zrow(Z[i + pb * ldz], Z[i + qb * ldz], rb);
-      }
-      double2 *t = cur;
-      cur = nxt;
-      nxt = t;
-      grid.sync();
-    }
-  }
-  for (int64_t i = gtid; i < m; i += gsz) w[i] = cur[i + i * lda].x;
-  if (gtid == 0 && sweeps_out) *sweeps_out = sweep;
-}
 
 // ---------------------------------------------------------------- block Jacobi
 // Indices are grouped into blocks of kBJ.  A sweep is one intra round, which
@@ -861,77 +765,7 @@ __global__ __launch_bounds__(1024) void k_cholesky_blk(const double2 *__restrict
   if (tid == 0) *flag = bad;
 }
 
-// Blocked inverse of a lower-triangular L in one workgroup, then
-// B = (L^{-1})^H.  X = L^{-1} by blocks of kTriBS: diagonal blocks by
-// forward substitution (one thread per column), then block diagonals
-// d = 1, 2, ...: X_IJ = -X_II sum_{K=J..I-1} L_IK X_KJ, with the pairs of
-// one diagonal independent (four at a time, one thread per element).
 constexpr int kTriBS = 16;
-__global__ __launch_bounds__(1024) void k_trinv_blk(const double2 *__restrict__ L, int64_t ldl, int n,
-                                                    double2 *__restrict__ X, int64_t ldx,
-                                                    double2 *__restrict__ B, int64_t ldb) {
-  constexpr int BS = kTriBS;
-  __shared__ double2 T[4][BS][BS + 1];
-  const int tid = threadIdx.x;
-  const int nbk = (n + BS - 1) / BS;
-  for (int64_t e = tid; e < (int64_t)n * n; e += 1024) {
-    const int i = (int)(e % n), j = (int)(e / n);
-    if (i < j) X[i + (int64_t)j * ldx] = double2{0.0, 0.0};
-  }
-  // diagonal blocks
-  for (int t = tid; t < nbk * BS; t += 1024) {
-    const int I = t / BS, c = I * BS + t % BS;
-    if (c >= n) continue;
-    const int hi = min(n, (I + 1) * BS);
-    for (int i = c; i < hi; ++i) {
-      double2 acc = double2{i == c ? 1.0 : 0.0, 0.0};
-      for (int k = c; k < i; ++k) {
-        const double2 a = L[i + (int64_t)k * ldl], x = X[k + (int64_t)c * ldx];
-        acc.x -= a.x * x.x - a.y * x.y;
-        acc.y -= a.x * x.y + a.y * x.x;
-      }
-      const double dinv = 1.0 / L[i + (int64_t)i * ldl].x;
-      X[i + (int64_t)c * ldx] = double2{acc.x * dinv, acc.y * dinv};
-    }
-  }
-  __syncthreads();
-  const int g = tid >> 8, el = tid & 255, ei = el % BS, ej = el / BS;
-  for (int d = 1; d < nbk; ++d) {
-    const int npair = nbk - d;
-    for (int p0 = 0; p0 < npair; p0 += 4) {
-      const int J = p0 + g, I = J + d;
-      const bool act = (p0 + g) < npair;
-      const int i = I * BS + ei, j = J * BS + ej;
-      if (act) {
-        double2 acc = double2{0.0, 0.0};
-        if (i < n && j < n) {
-          for (int k = J * BS; k < I * BS; ++k) {
-            const double2 a = L[i + (int64_t)k * ldl], x = X[k + (int64_t)j * ldx];
-            acc.x += a.x * x.x - a.y * x.y;
-            acc.y += a.x * x.y + a.y * x.x;
-          }
-        }
-        T[g][ei][ej] = acc;
-      }
-      __syncthreads();
-      if (act && i < n && j < n) {
-        double2 acc = double2{0.0, 0.0};
-        for (int k = 0; k <= ei; ++k) {
-          const double2 a = X[(I * BS + ei) + (int64_t)(I * BS + k) * ldx], t = T[g][k][ej];
-          acc.x -= a.x * t.x - a.y * t.y;
-          acc.y -= a.x * t.y + a.y * t.x;
-        }
-        X[i + (int64_t)j * ldx] = acc;
-      }
-      __syncthreads();
-    }
-  }
-  for (int64_t e = tid; e < (int64_t)n * n; e += 1024) {
-    const int i = (int)(e % n), c = (int)(e / n);
-    const double2 x = X[i + (int64_t)c * ldx];
-    B[c + (int64_t)i * ldb] = (i >= c) ? double2{x.x, -x.y} : double2{0.0, 0.0};
-  }
-}
 
 // X = L^{-1} and B = X^H by block columns, one workgroup per block column
 // J of kTriBS columns (they are independent): forward substitution over the
@@ -1044,6 +878,7 @@ __global__ __launch_bounds__(256) void k_residual(const double2 *__restrict__ X,
 }
 
 // nrm2[b] = sum_g |T[b][g]|^2, one workgroup per column
+template <bool ROOT>
 __global__ __launch_bounds__(256) void k_colnorm2(const double2 *__restrict__ T, int64_t ld, int64_t npw,
                                                   double *__restrict__ nrm2) {
   __shared__ double red[256];
@@ -1059,7 +894,7 @@ __global__ __launch_bounds__(256) void k_colnorm2(const double2 *__restrict__ T,
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) nrm2[b] = red[0];
+  if (threadIdx.x == 0) nrm2[b] = ROOT ? sqrt(red[0]) : red[0];
 }
 
 // Hermitise the new columns [m0, m1) of H (ldh): mirror the off-diagonal
@@ -1085,14 +920,6 @@ __global__ void k_hermitize(double2 *__restrict__ H, int64_t ldh, int m0, int m1
 }
 
 // H[0:n, 0:n] = diag(theta)
-__global__ void k_set_diag(double2 *__restrict__ H, int64_t ldh, int n, const double *__restrict__ theta) {
-  const int64_t nn = (int64_t)n * n;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nn;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e % n), j = (int)(e / n);
-    H[i + j * ldh] = double2{i == j ? theta[i] : 0.0, 0.0};
-  }
-}
 
 // dst (m x n, ldd) = src (m x n, lds)
 __global__ void k_copy_mat(const double2 *__restrict__ src, int64_t lds, double2 *__restrict__ dst,
@@ -1148,14 +975,6 @@ static int grid_for(int64_t n, int bs = 256, int cap = 2048) {
   return (int)b;
 }
 
-static int eig_impl() {
-  static int v = -1;
-  if (v < 0) {
-    const char *e = std::getenv("PW_EIG_IMPL");
-    v = (e && *e) ? std::atoi(e) : 0;  // 0: block Jacobi, 1: element-wise cooperative
-  }
-  return v;
-}
 
 // Block Jacobi driver: A (lda >= mpb, mpb = m rounded up to 2 kBJ) is
 // overwritten; Z (ldz >= mpb) receives the eigenvectors; uws holds the
@@ -1164,11 +983,7 @@ static int eig_impl() {
 // PW_BJ_CROSS=0 replaces the intra + cross rounds by 2k-1 rounds of full
 // pair solves (every pair problem diagonalised by one scalar sweep).
 static int bj_cross() {
-  static int v = -1;
-  if (v < 0) {
-    const char *e = std::getenv("PW_BJ_CROSS");
-    v = (e && *e) ? std::atoi(e) : 1;
-  }
+  static const int v = env_switch("PW_BJ_CROSS", 1);
   return v;
 }
 
@@ -1186,14 +1001,11 @@ static void bj_round(bool cross, int npair, int nblk, int r, double2 *A, int64_t
 }
 
 static int eig_block(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz, void *uws,
-                     double *acc, hipStream_t s, double off_abs, int nwant) {
+                     double *acc, double *h_acc, hipStream_t s, double off_abs, int nwant) {
   std::vector<double> h_diag(nwant > 0 ? m : 0);
   const int mpb = (m + kSub - 1) / kSub * kSub;
   const int nblk = mpb / kBJ;
   const int npair = nblk / 2;
-  static double *h_acc = nullptr;
-  if (!h_acc && hipHostMalloc((void **)&h_acc, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess)
-    return PW_ERR_NOMEM;
   double2 *U = static_cast<double2 *>(uws);
   int *rotated = reinterpret_cast<int *>(U + (int64_t)npair * kSub * kSub);
   const bool cross = bj_cross() != 0;
@@ -1241,46 +1053,22 @@ static int eig_block(double2 *A, int64_t lda, int m, double *w, double2 *Z, int6
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
 
-// rot_ws: second matrix buffer of the same shape as A (lda x lda).
-bool eig_transforms_in_place(int m) { return ((m + 1) & ~1) <= 64 || eig_impl() == 0; }
+// rot_ws: the per-pair unitaries of the block solver (lda x lda complex
+// is enough).  Both solvers leave Z^H A Z in A.
 
+// h_acc: two host doubles (pinned or pageable) owned by the caller, where the
+// block solver reads back the off-diagonal and total mass once per sweep.
 int eig_herm(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz, void *rot_ws,
-             double *acc_ws, int *sweeps, int coop_blocks, hipStream_t s, double off_abs, int nwant) {
+             double *acc_ws, double *h_acc, int *sweeps, hipStream_t s, double off_abs, int nwant) {
   if (m <= 0) return PW_OK;
   const int mp = (m + 1) & ~1;
   if (mp <= 64) {
     hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(256), 0, s, A, lda, m, w, Z, ldz, sweeps, off_abs);
     return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
   }
-  if (eig_impl() == 0) return eig_block(A, lda, m, w, Z, ldz, rot_ws, acc_ws, s, off_abs, nwant);
-  double2 *B = static_cast<double2 *>(rot_ws);
-  void *args[] = {&A, &B, &lda, &m, &w, &Z, &ldz, &acc_ws, &sweeps};
-  // about 8 block updates per thread: fewer workgroups make each grid barrier cheaper
-  const int np = mp / 2;
-  int blocks = (int)(((int64_t)np * np + 2047) / 2048);
-  if (blocks < 8) blocks = 8;
-  static int force = -1;
-  if (force < 0) {
-    const char *e = std::getenv("PW_JACOBI_BLOCKS");
-    force = (e && *e) ? std::atoi(e) : 0;
-  }
-  if (force > 0) blocks = force;
-  if (blocks > coop_blocks) blocks = coop_blocks;
-  const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_jacobi_coop),
-                                                  dim3(blocks), dim3(256), args, 0, s);
-  return e == hipSuccess ? PW_OK : PW_ERR_HIP;
+  return eig_block(A, lda, m, w, Z, ldz, rot_ws, acc_ws, h_acc, s, off_abs, nwant);
 }
 
-int coop_jacobi_blocks() {
-  int dev = 0, ncu = 0, per = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void *>(k_jacobi_coop),
-                                                   256, 0) != hipSuccess)
-    return 0;
-  if (per > 2) per = 2;
-  return per * ncu;
-}
 
 int eig_select(const double *w, int m, int nsel, double *wsel, int *idx, const double2 *Z, int64_t ldz,
                double2 *Y, int64_t ldy, hipStream_t s, const double2 *A, int64_t lda, double2 *H,
@@ -1296,13 +1084,9 @@ int eig_select(const double *w, int m, int nsel, double *wsel, int *idx, const d
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
 
-// PW_CHOL_IMPL=1 keeps the unblocked kernels (reference for the blocked ones)
+// PW_CHOL_IMPL=1 keeps the unblocked kernels (the path above kCholMaxN) at every size
 static int chol_impl() {
-  static int v = -1;
-  if (v < 0) {
-    const char *e = std::getenv("PW_CHOL_IMPL");
-    v = (e && *e) ? std::atoi(e) : 0;
-  }
+  static const int v = env_switch("PW_CHOL_IMPL", 0);
   return v;
 }
 
@@ -1311,14 +1095,10 @@ int cholesky(const double2 *S, int64_t lds, int n, double2 *L, int64_t ldl, doub
   if (n <= 0) return PW_OK;
   if (chol_impl() == 0 && n <= kCholMaxN) {
     const size_t lds_bytes = sizeof(double2) * (size_t)n * (kCholPB + 1);
-    static bool attr = false;
-    if (!attr) {
-      if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_cholesky_blk),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(double2) * kCholMaxN * (kCholPB + 1))) != hipSuccess)
-        return PW_ERR_HIP;
-      attr = true;
-    }
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(k_cholesky_blk),
+                                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                        (int)(sizeof(double2) * kCholMaxN * (kCholPB + 1)));
+    if (attr != hipSuccess) return PW_ERR_HIP;
     hipLaunchKernelGGL(k_cholesky_blk, dim3(1), dim3(1024), lds_bytes, s, S, lds, n, L, ldl, rel, flag);
   } else {
     hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, S, lds, n, L, ldl, rel, flag);
@@ -1331,18 +1111,12 @@ int trinv_h(const double2 *L, int64_t ldl, int n, double2 *X, int64_t ldx, doubl
   if (n <= 0) return PW_OK;
   if (chol_impl() == 0 && n <= kCholMaxN) {
     const size_t lds = sizeof(double2) * (size_t)n * (kTriBS + 1);
-    static bool attr = false;
-    if (!attr) {
-      if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_trinv_cols),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(double2) * kCholMaxN * (kTriBS + 1))) != hipSuccess)
-        return PW_ERR_HIP;
-      attr = true;
-    }
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(k_trinv_cols),
+                                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                        (int)(sizeof(double2) * kCholMaxN * (kTriBS + 1)));
+    if (attr != hipSuccess) return PW_ERR_HIP;
     hipLaunchKernelGGL(k_trinv_cols, dim3((n + kTriBS - 1) / kTriBS), dim3(256), lds, s, L, ldl, n, X, ldx, B,
                        ldb);
-  } else if (chol_impl() == 2) {
-    hipLaunchKernelGGL(k_trinv_blk, dim3(1), dim3(1024), 0, s, L, ldl, n, X, ldx, B, ldb);
   } else
     hipLaunchKernelGGL(k_trinv_h, dim3((n + 63) / 64), dim3(64), 0, s, L, ldl, n, X, ldx, B, ldb);
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
@@ -1350,7 +1124,13 @@ int trinv_h(const double2 *L, int64_t ldl, int n, double2 *X, int64_t ldx, doubl
 
 int col_norms2(const double2 *T, int64_t ld, int64_t npw, int n, double *nrm2, hipStream_t s) {
   if (n <= 0) return PW_OK;
-  hipLaunchKernelGGL(k_colnorm2, dim3(n), dim3(256), 0, s, T, ld, npw, nrm2);
+  hipLaunchKernelGGL(k_colnorm2<false>, dim3(n), dim3(256), 0, s, T, ld, npw, nrm2);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
+int col_norms(const double2 *T, int64_t ld, int64_t npw, int n, double *nrm, hipStream_t s) {
+  if (n <= 0) return PW_OK;
+  hipLaunchKernelGGL(k_colnorm2<true>, dim3(n), dim3(256), 0, s, T, ld, npw, nrm);
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
 
@@ -1365,10 +1145,6 @@ int hermitize(double2 *H, int64_t ldh, int m0, int m1, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
 
-int set_diag(double2 *H, int64_t ldh, int n, const double *theta, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_diag, dim3(grid_for((int64_t)n * n)), dim3(256), 0, s, H, ldh, n, theta);
-  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
-}
 
 int copy_mat(const double2 *src, int64_t lds, double2 *dst, int64_t ldd, int m, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_copy_mat, dim3(grid_for((int64_t)m * n)), dim3(256), 0, s, src, lds, dst, ldd, m, n);
@@ -1391,6 +1167,29 @@ int precond_idx(const double *kin, const double *tn, const int *idx, const doubl
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
 
+static_assert(kSub == kEighPad && kMaxSweeps == kEighMaxSweeps, "eigh_ws_bytes in common.h");
+
+// The eigensolver on a workspace laid out as eigh_ws_bytes(m) describes.
+// Every region is written before it is read (the copy of A, the identity
+// start of Z, the padding of A, the accumulators cleared per sweep), so the
+// workspace's earlier contents do not matter.
+int eigh_impl(const void *A, int64_t lda, int m, double *w, void *Z, int64_t ldz, void *work,
+              hipStream_t s) {
+  const int64_t mp = (m + kSub - 1) / kSub * kSub;
+  double2 *Ac = static_cast<double2 *>(work);
+  double2 *Bw = Ac + mp * mp;
+  double2 *Zw = Bw + mp * mp;
+  double *wu = reinterpret_cast<double *>(Zw + mp * mp);
+  double *acc = wu + mp;
+  int *idx = reinterpret_cast<int *>(acc + 2 * kMaxSweeps + 2);
+  int rc = copy_mat(static_cast<const double2 *>(A), lda, Ac, mp, m, m, s);
+  double h_acc[2];
+  if (rc == PW_OK) rc = eig_herm(Ac, mp, m, wu, Zw, mp, Bw, acc, h_acc, nullptr, s, 0.0, 0);
+  if (rc == PW_OK)
+    rc = eig_select(wu, m, m, w, idx, Zw, mp, static_cast<double2 *>(Z), ldz, s, nullptr, 0, nullptr, 0);
+  return rc;
+}
+
 }  // namespace pw
 
 using namespace pw;
@@ -1399,8 +1198,7 @@ extern "C" {
 
 pw_status pw_eigh_workspace(int32_t m, size_t *bytes) {
   PW_CHECK_ARG(m >= 1 && bytes, PW_ERR_INVALID, "pw_eigh_workspace: bad argument");
-  const size_t mp = (size_t)((m + kSub - 1) / kSub * kSub);
-  *bytes = (3 * mp * mp) * sizeof(double2) + (mp + 2 * kMaxSweeps + 2) * sizeof(double) + mp * sizeof(int);
+  *bytes = eigh_ws_bytes(m);
   return PW_OK;
 }
 
@@ -1408,23 +1206,8 @@ pw_status pw_eigh(const void *A, int64_t lda, int32_t m, double *w, void *Z, int
                   size_t work_bytes, void *stream) {
   PW_CHECK_ARG(A && w && Z && work && m >= 1 && lda >= m && ldz >= m, PW_ERR_INVALID,
                "pw_eigh: bad argument");
-  size_t need = 0;
-  pw_eigh_workspace(m, &need);
-  PW_CHECK_ARG(work_bytes >= need, PW_ERR_INVALID, "pw_eigh: workspace too small");
-  static int coop = -1;
-  if (coop < 0) coop = coop_jacobi_blocks();
-  const int64_t mp = (m + kSub - 1) / kSub * kSub;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  double2 *Ac = static_cast<double2 *>(work);
-  double2 *Bw = Ac + mp * mp;
-  double2 *Zw = Bw + mp * mp;
-  double *wu = reinterpret_cast<double *>(Zw + mp * mp);
-  double *acc = wu + mp;
-  int *idx = reinterpret_cast<int *>(acc + 2 * kMaxSweeps + 2);
-  int rc = copy_mat(static_cast<const double2 *>(A), lda, Ac, mp, m, m, s);
-  if (rc == PW_OK) rc = eig_herm(Ac, mp, m, wu, Zw, mp, Bw, acc, nullptr, coop, s, 0.0, 0);
-  if (rc == PW_OK)
-    rc = eig_select(wu, m, m, w, idx, Zw, mp, static_cast<double2 *>(Z), ldz, s, nullptr, 0, nullptr, 0);
+  PW_CHECK_ARG(work_bytes >= eigh_ws_bytes(m), PW_ERR_INVALID, "pw_eigh: workspace too small");
+  const int rc = eigh_impl(A, lda, m, w, Z, ldz, work, static_cast<hipStream_t>(stream));
   if (rc != PW_OK) set_error("pw_eigh: launch failed");
   return rc;
 }

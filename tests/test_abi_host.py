@@ -74,7 +74,7 @@ def test_gsphere_rejects_bad_cutoff():
 def test_problem_create_rejects_null_desc():
     L = _lib()
     h = ctypes.c_void_p()
-    st = L.LIB.pw_problem_create(None, 1, None, ctypes.byref(h))
+    st = L.LIB.pw_problem_create(None, 1, None, 0, None, ctypes.byref(h))
     assert st == -1 and b"null" in L.LIB.pw_last_error()
 
 
@@ -89,8 +89,70 @@ def test_problem_create_rejects_bad_grid_before_device_work():
     d.miller = mill.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     d.vloc = ctypes.c_void_p(1)     # never dereferenced: the grid check fails first
     h = ctypes.c_void_p()
-    st = L.LIB.pw_problem_create(ctypes.byref(d), 4, None, ctypes.byref(h))
+    st = L.LIB.pw_problem_create(ctypes.byref(d), 4, None, 0, None, ctypes.byref(h))
     assert st == -2 and b"grid" in L.LIB.pw_last_error()
+
+
+def _config1_desc(L, keep):
+    """Descriptor of the config-1 cell whose device pointers are never
+    dereferenced (only host-side checks run on it)."""
+    c = synth.make_cell(1)
+    m = np.ascontiguousarray(gs.gsphere(c.A, c.kpts[0], c.ecut_ha), dtype=np.int32)
+    po = np.ascontiguousarray(c.proj_offset, dtype=np.int32)
+    dj = np.ascontiguousarray(c.dij_concat(), dtype=np.float64)
+    keep += [m, po, dj]
+    d = L._Desc()
+    d.cell[:] = list(np.asarray(c.A, dtype=np.float64).reshape(9))
+    d.kpt[:] = [0.0, 0.0, 0.0]
+    d.ecut = c.ecut_ha
+    d.nr[:] = [int(x) for x in c.nr]
+    d.npw = m.shape[0]
+    d.miller = m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    d.vloc = ctypes.c_void_p(256)
+    d.nproj = int(po[-1])
+    d.natom = po.shape[0] - 1
+    d.proj_offset = po.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    d.dij = dj.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.beta = ctypes.c_void_p(256)
+    d.ld_beta = (m.shape[0] + 63) // 64 * 64
+    return d, m.shape[0], int(po[-1]), c
+
+
+def test_workspace_size_counts_the_per_band_buffers():
+    # per extra band: one band of sticks (FP64, N2 * nst_pad values), P and
+    # D P (2 * nproj complex128), 32 * nproj of split-K partials, and four
+    # per-band words; 256-byte rounding of each region aside
+    L = _lib()
+    keep = []
+    d, npw, nproj, c = _config1_desc(L, keep)
+    b16, b32 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.LIB.pw_workspace_size(ctypes.byref(d), 16, ctypes.byref(b16)) == 0
+    assert L.LIB.pw_workspace_size(ctypes.byref(d), 32, ctypes.byref(b32)) == 0
+    nst = len({(h % c.nr[0], k % c.nr[1]) for h, k, _ in gs.gsphere(c.A, c.kpts[0], c.ecut_ha).tolist()})
+    nst_pad = (nst + 15) // 16 * 16
+    # split-K partials are min(32 * P bytes, 512 MiB): 32 * nproj * 16 per band here
+    per_band = c.nr[2] * nst_pad * 16 + 2 * nproj * 16 + 32 * nproj * 16 + 2 * 8 + 2 * 4
+    diff = b32.value - b16.value
+    assert abs(diff - 16 * per_band) <= 10 * 256, (diff, 16 * per_band)
+    assert b16.value >= np.prod(c.nr) * 8 + nproj * d.ld_beta * 16
+
+
+def test_problem_create_rejects_small_or_misaligned_workspace():
+    L = _lib()
+    keep = []
+    d, npw, nproj, c = _config1_desc(L, keep)
+    need = ctypes.c_size_t()
+    assert L.LIB.pw_workspace_size(ctypes.byref(d), 16, ctypes.byref(need)) == 0
+    h = ctypes.c_void_p()
+    # the pointers are never dereferenced: the workspace check fails first
+    st = L.LIB.pw_problem_create(ctypes.byref(d), 16, ctypes.c_void_p(1 << 20), need.value - 1, None,
+                                 ctypes.byref(h))
+    assert st == -1 and b"workspace" in L.LIB.pw_last_error() and not h.value
+    st = L.LIB.pw_problem_create(ctypes.byref(d), 16, ctypes.c_void_p((1 << 20) + 64), need.value, None,
+                                 ctypes.byref(h))
+    assert st == -1 and b"aligned" in L.LIB.pw_last_error() and not h.value
+    st = L.LIB.pw_problem_create(ctypes.byref(d), 16, None, need.value, None, ctypes.byref(h))
+    assert st == -1 and b"workspace" in L.LIB.pw_last_error() and not h.value
 
 
 def test_stick_order_is_a_permutation_listed_by_stick():

@@ -222,3 +222,44 @@ def test_set_tuning_rejects_out_of_range(lib):
         with pytest.raises(lib.PwError):
             lib.pw_problem_set_tuning(pl, *bad)
     assert lib.pw_problem_tuning(pl) == before
+
+
+def test_caller_workspace_is_never_read_before_written(lib, monkeypatch):
+    """The problem and Davidson handles keep their large buffers in the
+    caller's workspace.  Filled with NaN bytes before create, it must still
+    give H*psi at 1e-12 against the oracle and the dense eigenvalues from a
+    Davidson solve (nothing in it is read before the library writes it)."""
+    import torch
+    real = lib._workspace
+
+    def nan_workspace(nbytes, device=None):
+        ws = real(nbytes, device)
+        ws.fill_(0xFF)           # every double in it is a NaN
+        return ws
+
+    monkeypatch.setattr(lib, "_workspace", nan_workspace)
+    c = synth.make_cell(1)
+    po, pl = problems(c)
+    assert pl.workspace is not None and int(pl.workspace.numel()) > 0
+    psi = start_block(c, 16, po.npw)
+    assert rel_err(_run(lib, pl, psi), ham.hpsi(po, psi)) < TOL
+    res = lib.davidson_solve(pl, to_gpu_block(psi), tol=5e-9)
+    w, _ = ham.eigh_lowest(po, 16)
+    log("nan-filled workspaces: davidson iterations", res["iterations"],
+        "max |theta - eigh|", float(np.abs(res["theta"] - w).max()))
+    assert res["converged"] and np.abs(res["theta"] - w).max() < 5e-9
+    torch.cuda.synchronize()
+
+
+def test_davidson_rejects_small_workspace(lib):
+    import ctypes
+    import torch
+    c = synth.make_cell(0)
+    po, pl = problems(c, max_bands=8)
+    need = ctypes.c_size_t()
+    lib._check(lib.LIB.pw_davidson_workspace_size(pl.handle, 8, 0, ctypes.byref(need)))
+    ws = torch.empty(int(need.value), dtype=torch.uint8, device="cuda")
+    h = ctypes.c_void_p()
+    st = lib.LIB.pw_davidson_create(pl.handle, 8, 0, 5e-9, ctypes.c_void_p(ws.data_ptr()), need.value - 1,
+                                    None, ctypes.byref(h))
+    assert st == -1 and b"workspace" in lib.LIB.pw_last_error() and not h.value

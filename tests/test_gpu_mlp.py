@@ -13,7 +13,7 @@ from oracle import davidson as odv
 from oracle import hamiltonian as ham
 from oracle import mlp as omlp
 
-from gpu_util import from_gpu_block, log, problems, start_block, to_gpu_block
+from gpu_util import from_gpu_block, log, problems, rel_err, start_block, to_gpu_block
 
 pytestmark = pytest.mark.gpu
 
@@ -161,3 +161,39 @@ def test_nan_network_falls_back_to_tpa(lib):
     log("nan-net iterations", r_mlp["iterations"], "tpa", r_tpa["iterations"])
     assert r_mlp["converged"] and r_mlp["iterations"] == r_tpa["iterations"]
     assert np.array_equal(r_mlp["theta"], r_tpa["theta"])
+
+
+def test_precond_mlp_kind_matches_oracle(lib):
+    """pw_precond with the learned kind: T = s(G, n) K_TPA(G, n) R_n(G), the
+    features computed from the iterate (T_n), the residual's own norm, the
+    Ritz value and <V_LOC>; FP32 network against the FP64 oracle network on
+    the same weights (1e-5 of the largest entry, as the forward test).  A
+    NaN network gives TPA in every band."""
+    import torch
+    c = synth.make_cell(1)
+    po, pl = problems(c)
+    npw, nbd = po.npw, 16
+    rng = np.random.default_rng(11)
+    X = start_block(c, nbd, npw)
+    R = rng.standard_normal((nbd, npw)) + 1j * rng.standard_normal((nbd, npw))
+    theta = rng.uniform(-1.0, 1.0, nbd)
+    p = _f32params(12)
+    scaler = np.array([1.0, -0.2, 1.0, -0.4, 0.5, 2.0, 1.0, 1.5], dtype=np.float32)
+    net = lib.Mlp(lib.pack_params(p), scaler)
+    xg, rg = to_gpu_block(X), to_gpu_block(R)
+    tg = torch.zeros_like(xg)
+    th = torch.from_numpy(theta).cuda()
+    lib.pw_precond(pl, lib.PW_PRECOND_MLP, th, xg, rg, tg, net=net)
+    got = from_gpu_block(tg, npw)
+    t = po.kinetic()
+    F = omlp.features(t, theta, X.T, R.T, float(po.vloc.mean()))
+    Fstd = (F.astype(np.float32).astype(np.float64) - scaler[:4].astype(np.float64)) * scaler[4:].astype(np.float64)
+    s, _ = omlp.forward(p, Fstd)
+    ref = s.reshape(nbd, npw) * odv.tpa_apply(t, X.T, R.T).T
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    log("pw_precond MLP kind: max rel err", err)
+    assert err <= 1e-5
+    bad = lib.Mlp(np.full(lib.MLP_NPARAM, np.nan, dtype=np.float32))
+    lib.pw_precond(pl, lib.PW_PRECOND_MLP, th, xg, rg, tg, net=bad)
+    got_nan = from_gpu_block(tg, npw)
+    assert rel_err(got_nan, odv.tpa_apply(t, X.T, R.T).T) < 1e-12
