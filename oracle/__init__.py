@@ -14,9 +14,10 @@ Modules
   hamiltonian  H*psi (FFT path) and the dense H matrix
   davidson     block Davidson with the Teter-Payne-Allan preconditioner
   mlp          the learned preconditioner's network, loss and optimiser
+  lanczos      Lanczos recursion on H and the continued fraction of its resolvent
 
 Parity status: every function is pinned by a test in
 ``tests/test_oracle_pins.py`` except the iteration counts and wall time of
 ``davidson`` ("parity unpinned": the paper prints no such numbers).
 """
-from . import gsphere, grid, hamiltonian, davidson, mlp  # noqa: F401
+from . import gsphere, grid, hamiltonian, davidson, mlp, lanczos  # noqa: F401

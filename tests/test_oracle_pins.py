@@ -399,3 +399,75 @@ def test_mlp_features_by_hand():
     assert np.allclose(f[1, :, 0], t / tn1, rtol=1e-15, atol=0)
     assert np.allclose(f[:, :, 1], [[-0.2], [0.7]]) and np.allclose(f[:, :, 2], 1.0)
     assert np.all(f[:, :, 3] == 0.125)
+
+
+# ---------------------------------------------------------------- Lanczos recursion
+from oracle import lanczos as lz  # noqa: E402
+
+
+def _tiny_dense():
+    c = synth.make_cell(0)
+    po = ham.problem_from_cell(c)
+    return po, ham.dense_h(po)
+
+
+def test_lanczos_moments_match_tridiagonal():
+    # the chain reproduces the moments <v|H^k|v> / |v|^2 = (T_M^k)_11 for
+    # k <= 2M - 1 (the defining property of the first M Lanczos vectors); a
+    # dropped beta_n q_{n-1} term, a wrong alpha or a misplaced beta breaks it
+    po, H = _tiny_dense()
+    rng = np.random.default_rng(61)
+    v = _rand_c(rng, po.npw) * 0.7
+    M = 6
+    a, b = lz.lanczos(po, v, M, apply_h=lambda x: H @ x)
+    T = lz.tridiagonal(a, b)
+    w, U = np.linalg.eigh(H)
+    c2 = np.abs(U.conj().T @ v) ** 2 / np.vdot(v, v).real
+    Tk = np.eye(M)
+    for k in range(2 * M):
+        mom = float(np.sum(c2 * w ** k))
+        scale = float(np.sum(c2 * np.abs(w) ** k))
+        assert abs(Tk[0, 0] - mom) <= 1e-11 * scale, (k, Tk[0, 0], mom)
+        Tk = Tk @ T
+    assert abs(b[0] - np.linalg.norm(v)) <= 1e-15 * np.linalg.norm(v)
+
+
+def test_lanczos_two_eigenvector_start_terminates_with_exact_resolvent():
+    # v in a two-dimensional invariant subspace: beta_3 = 0 and the
+    # fraction equals sum_i |c_i|^2 / (z - lambda_i) exactly
+    po, H = _tiny_dense()
+    w, U = np.linalg.eigh(H)
+    c = np.array([0.6 - 0.3j, 1.1j])
+    v = U[:, 2] * c[0] + U[:, 7] * c[1]
+    a, b = lz.lanczos(po, v, 5, apply_h=lambda x: H @ x)
+    assert b[2] <= 1e-12 * abs(w).max()
+    assert np.all(b[3:] == 0.0) and np.all(a[2:] == 0.0)
+    z = np.array([0.3 + 0.05j, -1.0 + 0.2j, w[2] + 1e-3j, 5.0 - 0.4j])
+    exact = abs(c[0]) ** 2 / (z - w[2]) + abs(c[1]) ** 2 / (z - w[7])
+    assert np.abs(lz.continued_fraction(a, b, z) - exact).max() <= 1e-9 * np.abs(exact).max()
+
+
+def test_lanczos_resolvent_converges_to_dense_solve():
+    # off the real axis the fraction of a long chain approaches
+    # <v|(z - H)^{-1}|v> solved directly; the extreme eigenvalue of T_M
+    # approaches the lowest eigenvalue of H
+    po, H = _tiny_dense()
+    rng = np.random.default_rng(62)
+    v = _rand_c(rng, po.npw)
+    a, b = lz.lanczos(po, v, 120, apply_h=lambda x: H @ x)
+    w = np.linalg.eigvalsh(H)
+    for z in (w[0] - 0.2 + 0.1j, w[10] + 0.3j, 0.5 * (w[0] + w[-1]) + 1.0j):
+        exact = np.vdot(v, np.linalg.solve(z * np.eye(po.npw) - H, v))
+        got = lz.continued_fraction(a, b, z)
+        assert abs(got - exact) <= 1e-8 * abs(exact), (z, got, exact)
+    assert abs(np.linalg.eigvalsh(lz.tridiagonal(a[:40], b[:41]))[0] - w[0]) <= 1e-10
+
+
+def test_lanczos_fft_path_matches_dense_path():
+    # the oracle's default H*psi (FFT path) gives the chain of the dense matrix
+    po, H = _tiny_dense()
+    v = _rand_c(np.random.default_rng(63), po.npw)
+    a1, b1 = lz.lanczos(po, v, 12)
+    a2, b2 = lz.lanczos(po, v, 12, apply_h=lambda x: H @ x)
+    assert np.abs(a1 - a2).max() <= 1e-11 * np.abs(a2).max()
+    assert np.abs(b1 - b2).max() <= 1e-11 * np.abs(b2).max()
