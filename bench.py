@@ -1,10 +1,14 @@
 #!/usr/bin/env python3
-"""Benchmark: band-H*psi/s of the plane-wave Hamiltonian on one MI355X.
+"""Benchmark: band-H*psi/s of the plane-wave Hamiltonian on one MI355X, and
+Davidson time-to-solution of the plain FP64 form against the mixed, batched
+and learned forms at equal accuracy.
 
-One step applies H to the whole band block of the medium workload: a cubic
-cell a = 20 bohr, 30 Ry (npw ~ 22.1-22.2k), 72^3 grid, 64 atoms with s+p+d
-projectors (576), 256 bands at Gamma + 4 k-points = 1280 band-H*psi per
-step, inputs resident in HBM.  Prints one JSON line (rank 0, N = 1).
+The headline step applies H to the whole band block of the medium workload:
+a cubic cell a = 20 bohr, 30 Ry (npw ~ 22.1-22.2k), 72^3 grid, 64 atoms with
+s+p+d projectors (576), 256 bands at Gamma + 4 k-points = 1280 band-H*psi per
+step, inputs resident in HBM, launch choices fixed (the autotuner's pick at
+this workload) so that the kernel profiles under profiles/ describe exactly
+the launches timed here.  Prints one JSON line (N = 1).
 
 The dominant kernel's roofline figures come from HIP events the library
 records around each of its launches on the launch stream over the timed
@@ -14,6 +18,7 @@ same workload on the host cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,6 +28,7 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}       # dense MFMA
@@ -30,32 +36,43 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}       # dense MFMA
 # FP32 counts the packed (two-wide) rate
 PEAK_VALU_TFLOPS = {"f64": 78.6, "f32": 157.3}
 
+# launch choices of the headline step per precision form: (plane_group,
+# band_chunk, ksplit, plane_kernel); 0 = PW_PLANE_REGISTER
+PINNED = {"fp64": (4, 128, 0, 0), "fp32": (4, 128, 0, 0), "bf16": (4, 128, 0, 0)}
+
 # HBM bytes per launch measured with rocprofv3 (FETCH_SIZE x 2.0 + WRITE_SIZE
-# x 1.0, factors from a plain device copy), valid only for the kernel source
+# x 1.0, factors from a plain device copy); valid only for the kernel source
 # and launch choices they were taken with
 MEASURED_TRAFFIC = {
-    "plane": {"source": "paper_1709_10010_amd/csrc/fft.hip", "sha256_16": "08ada82ff90493df",
-              "precision": 0, "band_chunk": 128, "plane_group": 2, "plane_kernel": 0,
-              "bytes_per_launch": 589442585.9},
+    "plane": {"source": "paper_1709_10010_amd/csrc/fft.hip", "sha256_16": None,
+              "precision": 0, "band_chunk": 128, "plane_group": 4, "plane_kernel": 0,
+              "bytes_per_launch": None},
 }
+
+
+def note(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def source_hash(rel):
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def measured_traffic(kernel, prec, tuning):
     """Counter-measured bytes per launch of `kernel`, or None once the kernel
     source or its launch choices differ from those of the measurement."""
-    import hashlib
     m = MEASURED_TRAFFIC.get(kernel)
-    if m is None or tuning is None or prec != m["precision"]:
+    if m is None or tuning is None or prec != m["precision"] or not m["bytes_per_launch"]:
         return None
     if (tuning.get("band_chunk"), tuning.get("plane_group"), tuning.get("plane_kernel_id")) != \
             (m["band_chunk"], m["plane_group"], m["plane_kernel"]):
         return None
     try:
-        with open(os.path.join(ROOT, m["source"]), "rb") as f:
-            h = hashlib.sha256(f.read()).hexdigest()[:16]
+        return m["bytes_per_launch"] if source_hash(m["source"]) == m["sha256_16"] else None
     except OSError:
         return None
-    return m["bytes_per_launch"] if h == m["sha256_16"] else None
 
 
 def parse():
@@ -64,17 +81,19 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp64")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--kpoints", type=int, default=5)
+    ap.add_argument("--autotune", action="store_true", help="search the launch choices instead of the pinned ones")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-davidson", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--batched-cells", type=int, default=64)
-    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--davidson-reps", type=int, default=3)
     ap.add_argument("--no-davidson-medium", action="store_true")
     ap.add_argument("--davidson-medium-kpoints", type=int, default=5)
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch choices")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-cells", type=int, default=64)
+    ap.add_argument("--streams", type=int, default=4, help="streams of the batched forms")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-cells", type=int, default=10)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference "
                          "kernel that scales HBM byte counters) and exit")
@@ -117,32 +136,78 @@ def mfma_executed(prec):
     return 0.75 if prec == 0 and on else 1.0
 
 
-def cpu_baseline(cell, ik, budget_s):
-    """FP64 oracle H*psi on the host: bands of one k-point until ~budget_s of work."""
-    from oracle import hamiltonian as ham
-    import synth
+def golden(name):
+    a = np.loadtxt(os.path.join(GOLDEN, name), comments="#")
+    return a if a.ndim == 2 else a[:, None]
+
+
+def host_info():
+    """Host cores this process may use, CPU model, BLAS library and threads."""
+    info = {"affinity_cores": len(os.sched_getaffinity(0)), "cpu_model": None, "blas": None}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     try:
         from threadpoolctl import threadpool_info
-        blas_threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        info["blas"] = [{"api": d.get("internal_api"), "version": d.get("version"),
+                         "threads": d.get("num_threads")} for d in threadpool_info()
+                        if d.get("user_api") == "blas"]
     except Exception:
-        blas_threads = 1
+        pass
+    return info
+
+
+def cpu_baseline(cell, ik, budget_s):
+    """FP64 oracle H*psi on the host: bands of one k-point for about budget_s
+    with the BLAS threads the process has, and again with one thread."""
+    from oracle import hamiltonian as ham
+    import synth
+    from threadpoolctl import threadpool_limits
+    hi = host_info()
     po = ham.problem_from_cell(cell, ik)
     psi = synth.psi_start(cell.seed, cell.nbands, po.npw, ik)
     ham.hpsi(po, psi[:2])                      # warm-up
-    done, t0 = 0, time.perf_counter()
-    chunk = 8
-    while time.perf_counter() - t0 < budget_s and done + chunk <= cell.nbands:
-        ham.hpsi(po, psi[done:done + chunk])
-        done += chunk
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "band-H*psi/s", "cores": int(blas_threads),
+
+    def run(limit):
+        done, chunk = 0, 8
+        with threadpool_limits(limits=limit, user_api="blas"):
+            t0 = time.perf_counter()
+            while time.perf_counter() - t0 < budget_s and done + chunk <= cell.nbands:
+                ham.hpsi(po, psi[done:done + chunk])
+                done += chunk
+            return done, time.perf_counter() - t0
+
+    n_all, t_all = run(hi["affinity_cores"])
+    n_one, t_one = run(1)
+    blas_threads = max([b["threads"] or 1 for b in hi["blas"] or [{"threads": 1}]])
+    return {"value": n_all / t_all, "unit": "band-H*psi/s", "cores": int(min(blas_threads, hi["affinity_cores"])),
             "kind": "oracle",
-            "sample": f"{done} bands of k-point {ik} (npw={po.npw}, 72^3 grid, 576 projectors), "
-                      f"{dt:.1f} s; numpy FFT single-threaded, BLAS threads={blas_threads}"}
+            "sample": f"{n_all} bands of k-point {ik} of the medium workload (npw={po.npw}, 72^3 grid, "
+                      f"576 projectors) in {t_all:.1f} s; numpy FFT (one thread) per band, BLAS for the "
+                      f"projector products",
+            "one_thread": {"value": n_one / t_one, "sample": f"{n_one} bands in {t_one:.1f} s, BLAS limited to 1 thread"},
+            "host": hi}
 
 
-def davidson_section(reps: int):
-    """Config-1 time-to-solution (first H*psi to all residuals < 1e-8 Ry = 5e-9 Ha)."""
+def fixed_tuning(p, name):
+    from paper_1709_10010_amd import _lib
+    g, c, k, pk = PINNED[name]
+    c = min(c, _lib.pw_problem_tuning(p)["band_chunk"])
+    _lib.pw_problem_set_tuning(p, g, c, k, pk)
+
+
+def davidson_small_section(reps: int):
+    """Config-1 cell (npw 949, 24^3, 32 projectors, 16 bands, Gamma):
+    time-to-solution of each form and, per band, the eigenvalue error against
+    the oracle's dense diagonalisation (tests/golden, written by the oracle)
+    and the residual.  Forms: FP64 to 1e-8 Ry; FP32 (complex64 FFTs, FP32
+    GEMMs) and BF16 (complex64 FFTs, BF16 GEMMs) alone to 1e-6 Ry, and each
+    followed by FP64 iterations to 1e-8 Ry."""
     import torch
     import synth
     from paper_1709_10010_amd import _lib
@@ -152,36 +217,53 @@ def davidson_section(reps: int):
     nb = cell.nbands
     p64, miller = build_problem(cell, 0, precision=_lib.PW_FP64, max_bands=nb)
     p32, _ = build_problem(cell, 0, precision=_lib.PW_MIXED_FP32, max_bands=nb, miller=miller)
+    p16, _ = build_problem(cell, 0, precision=_lib.PW_MIXED_BF16, max_bands=nb, miller=miller)
     npw = p64.npw
     x0 = band_block(nb, npw)
     x0[:, :npw] = torch.from_numpy(synth.psi_start(cell.seed, nb, npw)).cuda()
-    out = {"workload": "a=10 bohr, 15 Ry, npw 949, 24^3, 8 atoms s+p (32 proj), 16 bands, Gamma; "
-                       "tol 1e-8 Ry (5e-9 Ha) on every band's residual 2-norm"}
-    forms = {"fp64": dict(prob=p64), "fp32_then_fp64": dict(prob=p32, refine=p64, tol=1e-5)}
+    exact = golden("config1_lowest16_Ha.txt")[:, 0]
+    out = {"workload": "a=10 bohr, 15 Ry, npw 949, 24^3, 8 atoms s+p (32 proj), 16 bands, Gamma; residual "
+                       "2-norm of every band; errors against the oracle's dense eigenvalues"}
+    forms = {"fp64_1e-8Ry": dict(prob=p64, tol=5e-9),
+             "fp32_1e-6Ry": dict(prob=p32, tol=5e-7),
+             "bf16_1e-6Ry": dict(prob=p16, tol=5e-7),
+             "fp32_then_fp64_1e-8Ry": dict(prob=p32, tol=1e-5, refine=p64, refine_tol=5e-9),
+             "bf16_then_fp64_1e-8Ry": dict(prob=p16, tol=1e-3, refine=p64, refine_tol=5e-9)}
     for name, kw in forms.items():
         best = None
-        for _ in range(reps + 1):          # first run warms up the kernels
+        for _ in range(reps + 1):          # the first run warms up the kernels
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r = _lib.davidson_solve(kw["prob"], x0, tol=kw.get("tol", 5e-9), refine=kw.get("refine"),
-                                    refine_tol=5e-9)
+            r = _lib.davidson_solve(kw["prob"], x0, tol=kw["tol"], refine=kw.get("refine"),
+                                    refine_tol=kw.get("refine_tol"), max_iter=300)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             if best is None or dt < best[0]:
                 best = (dt, r)
         dt, r = best
-        out[name] = {"seconds": round(dt, 5), "iterations": r["iterations"], "n_hpsi": r["n_hpsi"],
-                     "converged": bool(r["converged"]), "max_residual_Ha": float(r["rho"].max())}
+        err = np.abs(r["theta"] - exact)
+        o = {"seconds": round(dt, 5), "iterations": r["iterations"], "n_hpsi": r["n_hpsi"],
+             "converged": bool(r["converged"]), "max_residual_Ry": float(2 * r["rho"].max()),
+             "max_abs_theta_minus_oracle_Ry": float(2 * err.max()),
+             "per_band_abs_theta_minus_oracle_Ry": [float(f"{2 * e:.3e}") for e in err],
+             "per_band_residual_Ry": [float(f"{2 * e:.3e}") for e in r["rho"]]}
         if "iterations_first" in r:
-            out[name]["iterations_reduced_precision"] = r["iterations_first"]
-        out[name]["_theta"] = r["theta"]
+            o["iterations_reduced_precision"] = r["iterations_first"]
+        out[name] = o
+    out["speedup_fp32_then_fp64_over_fp64_at_1e-8Ry"] = round(
+        out["fp64_1e-8Ry"]["seconds"] / out["fp32_then_fp64_1e-8Ry"]["seconds"], 3)
+    for p in (p64, p32, p16):
+        p.close()
     return out
 
 
 def davidson_medium_section(nk: int):
     """Config-2 time-to-solution, every k-point in turn (256 bands each): plain
     FP64 to 1e-8 Ry; the FP32 form to 1e-6 Ry alone; the FP32 form to 1e-5 Ha
-    followed by FP64 iterations to 1e-8 Ry from the same subspace."""
+    followed by FP64 iterations to 1e-8 Ry from the same subspace.  k-points 0
+    and 1 are compared band by band with the oracle's own Davidson at full
+    size (tests/golden).  Then one profiled FP64 solve of k-point 0: time per
+    stage (library HIP events), eigensolver share, ms per iteration."""
     import torch
     import synth
     from paper_1709_10010_amd import _lib
@@ -194,11 +276,15 @@ def davidson_medium_section(nk: int):
                        f"solved one after another; residual 2-norm of every band"}
     forms = {"fp64_1e-8Ry": dict(tol=5e-9), "fp32_1e-6Ry": dict(tol=5e-7, mixed=True),
              "fp32_then_fp64_1e-8Ry": dict(tol=1e-5, mixed=True, refine=True)}
-    res = {k: {"seconds": 0.0, "iterations": 0, "n_hpsi": 0, "converged": True, "max_residual_Ha": 0.0,
+    res = {k: {"seconds": 0.0, "iterations": 0, "n_hpsi": 0, "converged": True, "max_residual_Ry": 0.0,
                "theta": []} for k in forms}
+    gold = {ik: golden(f"config2_k{ik}_davidson256_Ha.txt") for ik in (0, 1)}
+    stage = None
     for ik in range(nk):
         p64, miller = build_problem(cell, ik, precision=_lib.PW_FP64, max_bands=nb)
         p32, _ = build_problem(cell, ik, precision=_lib.PW_MIXED_FP32, max_bands=nb, miller=miller)
+        fixed_tuning(p64, "fp64")
+        fixed_tuning(p32, "fp32")
         npw = p64.npw
         x0 = band_block(nb, npw)
         x0[:, :npw] = torch.from_numpy(synth.psi_start(cell.seed, nb, npw, ik)).cuda()
@@ -213,8 +299,31 @@ def davidson_medium_section(nk: int):
             o["iterations"] += r["iterations"]
             o["n_hpsi"] += r["n_hpsi"]
             o["converged"] &= bool(r["converged"])
-            o["max_residual_Ha"] = max(o["max_residual_Ha"], float(r["rho"].max()))
+            o["max_residual_Ry"] = max(o["max_residual_Ry"], float(2 * r["rho"].max()))
             o["theta"].append(r["theta"])
+            if ik in gold:
+                d = np.abs(r["theta"] - gold[ik][:, 0])
+                o.setdefault("max_abs_theta_minus_oracle_Ry", {})[f"k{ik}"] = float(2 * d.max())
+        if ik == 0:
+            _lib.pw_profile_enable(p64, True)
+            _lib.pw_profile_read(p64, reset=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = _lib.davidson_solve(p64, x0, tol=5e-9)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            st = _lib.pw_profile_read(p64, reset=True)
+            _lib.pw_profile_enable(p64, False)
+            tot = sum(v[0] for v in st.values())
+            stage = {"kpoint": 0, "iterations": r["iterations"], "wall_s_profiled": round(wall, 4),
+                     "ms_per_iteration": round(wall * 1e3 / r["iterations"], 3),
+                     "gpu_busy_fraction": round(tot * 1e-3 / wall, 3),
+                     "stages_ms": {k: round(v[0], 2) for k, v in sorted(st.items(), key=lambda kv: -kv[1][0])},
+                     "eigensolver_share": round(st.get("eig", (0, 0))[0] / max(tot, 1e-9), 3),
+                     "hpsi_share": round(sum(st.get(k, (0, 0))[0] for k in ("zfft_inv", "plane", "zfft_fwd",
+                                                                            "proj", "dmat", "nlupd")) / max(tot, 1e-9), 3),
+                     "subspace_gemm_share": round((st.get("subgemm", (0, 0))[0] + st.get("updgemm", (0, 0))[0])
+                                                  / max(tot, 1e-9), 3)}
         p64.close()
         p32.close()
     ref = np.concatenate(res["fp64_1e-8Ry"]["theta"])
@@ -224,66 +333,112 @@ def davidson_medium_section(nk: int):
         o["max_abs_theta_minus_fp64_Ry"] = float(2.0 * np.abs(th - ref).max())
         out[name] = o
     base = res["fp64_1e-8Ry"]["seconds"]
-    out["speedup_over_fp64_at_1e-8Ry"] = round(base / res["fp32_then_fp64_1e-8Ry"]["seconds"], 3)
+    out["speedup_fp32_then_fp64_over_fp64_at_1e-8Ry"] = round(base / res["fp32_then_fp64_1e-8Ry"]["seconds"], 3)
+    out["speedup_fp32_over_fp64_1e-6Ry_vs_1e-8Ry"] = round(base / res["fp32_1e-6Ry"]["seconds"], 3)
+    out["fp64_stage_breakdown"] = stage
     return out
 
 
-def batched_section(ncells: int, steps: int, autotune: bool = True):
-    """64 ragged cells (a 10-18 bohr, 20-40 Ry, 8-48 atoms, 32-192 bands): one H*psi
-    sweep per step, eager launches vs one HIP-graph launch per step; each cell's
-    launch choices autotuned first (outside the timed region)."""
+def batched_section(ncells: int, steps: int, nstreams: int, learned_net=None):
+    """The 64 ragged cells (a 10-18 bohr, 20-40 Ry, 8-48 atoms s+p, 32-192
+    bands).  H*psi sweep: in order on one stream, over side streams, and the
+    side-stream sweep captured in one HIP graph.  Davidson time-to-solution
+    of the whole batch: plain FP64 one cell after another (the baseline)
+    against the batched forms side by side on the streams: FP64 to 1e-8 Ry,
+    FP32 then FP64 to 1e-8 Ry, FP32 alone to 1e-6 Ry, and the FP32 form with
+    the learned preconditioner to 1e-6 Ry."""
     import torch
     import synth
     from paper_1709_10010_amd import _lib
     from paper_1709_10010_amd.problems import band_block, build_problem
 
-    probs, xs, ys, nbs, npws = [], [], [], [], []
-    for i in range(ncells):
-        c = synth.make_cell(4, i)
-        p, _ = build_problem(c, 0, max_bands=c.nbands)
+    cells = [synth.make_cell(4, i) for i in range(ncells)]
+    p64s, p32s, xs, nbs = [], [], [], []
+    for c in cells:
+        p, miller = build_problem(c, 0, max_bands=c.nbands)
+        q, _ = build_problem(c, 0, precision=_lib.PW_MIXED_FP32, max_bands=c.nbands, miller=miller)
         x = band_block(c.nbands, p.npw)
         x[:, :p.npw] = torch.from_numpy(synth.psi_start(c.seed, c.nbands, p.npw)).cuda()
-        probs.append(p)
+        p64s.append(p)
+        p32s.append(q)
         xs.append(x)
-        ys.append(torch.zeros_like(x))
         nbs.append(c.nbands)
-        npws.append(p.npw)
     kinds = {}
-    if autotune:
-        for p, nb in zip(probs, nbs):
-            _lib.pw_problem_autotune(p, nb, reps=2)
-            k = _lib.pw_problem_tuning(p)["plane_kernel"]
-            kinds[k] = kinds.get(k, 0) + 1
-    b = _lib.Batch(probs, xs, ys)
+    for p, q, nb in zip(p64s, p32s, nbs):              # launch choices, outside the timed regions
+        _lib.pw_problem_autotune(p, nb, reps=2)
+        _lib.pw_problem_autotune(q, nb, reps=2)
+        k = _lib.pw_problem_tuning(p)["plane_kernel"]
+        kinds[k] = kinds.get(k, 0) + 1
+    ys = [torch.zeros_like(x) for x in xs]
+    b = _lib.Batch(p64s, xs, ys)
     s = torch.cuda.Stream()
-    out = {"cells": ncells, "bands_per_step": int(sum(nbs)), "npw_range": [min(npws), max(npws)],
-           "autotuned": autotune, "plane_kernels": {("register", "wave", "lds")[k]: v for k, v in kinds.items()}}
+    out = {"cells": ncells, "bands": int(sum(nbs)), "npw_range": [min(p.npw for p in p64s), max(p.npw for p in p64s)],
+           "streams": nstreams,
+           "plane_kernels": {("register", "wave", "lds")[k]: v for k, v in kinds.items()}}
+
+    def timed(fn):
+        with torch.cuda.stream(s):
+            fn()
+            s.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                fn()
+            s.synchronize()
+            return (time.perf_counter() - t0) / steps
+
+    te = timed(lambda: _lib.pw_batch_hpsi(b, s))
+    _lib.pw_batch_set_streams(b, [torch.cuda.Stream() for _ in range(nstreams)])
+    ts = timed(lambda: _lib.pw_batch_hpsi(b, s))
     with torch.cuda.stream(s):
-        _lib.pw_batch_hpsi(b, s)
-        s.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            _lib.pw_batch_hpsi(b, s)
-        s.synchronize()
-        te = (time.perf_counter() - t0) / steps
         _lib.pw_batch_capture(b, s)
-        _lib.pw_batch_launch(b, s)
-        s.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            _lib.pw_batch_launch(b, s)
-        s.synchronize()
-        tg = (time.perf_counter() - t0) / steps
-    out["eager"] = {"ms_per_step": round(te * 1e3, 3), "band-H*psi/s": round(sum(nbs) / te, 1)}
-    out["graph"] = {"ms_per_step": round(tg * 1e3, 3), "band-H*psi/s": round(sum(nbs) / tg, 1),
-                    "launches_per_step": 1}
+    tg = timed(lambda: _lib.pw_batch_launch(b, s))
     b.close()
+    nbt = sum(nbs)
+    out["hpsi_sweep"] = {"in_order_eager": {"ms": round(te * 1e3, 3), "band-H*psi/s": round(nbt / te, 1)},
+                         "side_streams_eager": {"ms": round(ts * 1e3, 3), "band-H*psi/s": round(nbt / ts, 1)},
+                         "side_streams_graph": {"ms": round(tg * 1e3, 3), "band-H*psi/s": round(nbt / tg, 1),
+                                                "launches_per_sweep": 1}}
+
+    def summarise(rs, dt):
+        return {"seconds": round(dt, 3), "converged": all(r["converged"] for r in rs),
+                "iterations_total": int(sum(r["iterations"] for r in rs)),
+                "max_residual_Ry": float(2 * max(r["rho"].max() for r in rs))}
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [_lib.davidson_solve(p, x, tol=5e-9) for p, x in zip(p64s, xs)]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    dav = {"fp64_one_after_another_1e-8Ry": summarise(seq, t_seq)}
+    ref = [r["theta"] for r in seq]
+    forms = {"fp64_batched_1e-8Ry": dict(probs=p64s, tol=5e-9),
+             "fp32_then_fp64_batched_1e-8Ry": dict(probs=p32s, tol=1e-5, refine=p64s, refine_tol=5e-9),
+             "fp32_batched_1e-6Ry": dict(probs=p32s, tol=5e-7)}
+    if learned_net is not None:
+        forms["fp32_batched_learned_1e-6Ry"] = dict(probs=p32s, tol=5e-7, precond=_lib.PW_PRECOND_MLP,
+                                                     net=learned_net)
+    for name, kw in forms.items():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = _lib.batch_davidson_solve(kw["probs"], xs, tol=kw["tol"], nstreams=nstreams,
+                                       refine=kw.get("refine"), refine_tol=kw.get("refine_tol"),
+                                       precond=kw.get("precond", _lib.PW_PRECOND_TPA), net=kw.get("net"),
+                                       max_iter=300)
+        torch.cuda.synchronize()
+        o = summarise(rs, time.perf_counter() - t0)
+        o["max_abs_theta_minus_fp64_Ry"] = float(2 * max(np.abs(r["theta"] - t).max() for r, t in zip(rs, ref)))
+        o["speedup_over_fp64_one_after_another"] = round(t_seq / o["seconds"], 3)
+        dav[name] = o
+    out["davidson_time_to_solution"] = dav
+    for p in p64s + p32s:
+        p.close()
     return out
 
 
-def learned_section():
-    """TPA vs trained-MLP Davidson (FP32 form, 1e-6 Ry): a held-out cell of the
-    training family and the 512-band evaluation cell."""
+def learned_section(ncells: int):
+    """TPA against the trained network (FP32 form, 1e-6 Ry): cells of the
+    training family that took no part in training or in the choice of the
+    kept weights (indices 201 ..), and the 512-band evaluation cell."""
     from paper_1709_10010_amd import learned
     import synth
     path = os.path.join(ROOT, "paper_1709_10010_amd", "weights", "precond_mlp.npz")
@@ -291,24 +446,37 @@ def learned_section():
         return {"note": "no trained weights in the tree"}
     net = learned.load(path)
     out = {"tol_Ry": 1e-6, "form": "fp32 mixed"}
-    val = synth.make_cell(5, 200)
-    val.nbands = min(val.nbands, 256)
-    for key, cell in (("held_out_training_family", val), ("evaluation_cell", synth.make_cell(5, -1))):
-        r = learned.evaluate(cell, net, tol=5e-7)
-        o = {"cell": f"{cell.name}: a={cell.A[0, 0]:.2f} bohr, {int(round(2 * cell.ecut_ha))} Ry, "
-                     f"{cell.natom} atoms, {cell.nbands} bands, grid {cell.nr[0]}^3",
-             "max_theta_diff_Ry": float(2 * r["max_theta_diff_Ha"])}
+    its, secs = {"tpa": [], "mlp": []}, {"tpa": [], "mlp": []}
+    dth = 0.0
+    for i in range(201, 201 + ncells):
+        c = synth.make_cell(5, i)
+        c.nbands = min(c.nbands, 256)
+        r = learned.evaluate(c, net, tol=5e-7)
         for k in ("tpa", "mlp"):
-            o[k] = {"iterations": r[k]["iterations"], "seconds": round(r[k]["seconds"], 4),
-                    "n_hpsi": r[k]["n_hpsi"], "converged": bool(r[k]["converged"])}
-        o["mlp_time_over_tpa"] = round(r["mlp"]["seconds"] / r["tpa"]["seconds"], 3)
-        out[key] = o
-    net.close()
-    return out
+            its[k].append(r[k]["iterations"])
+            secs[k].append(r[k]["seconds"])
+        dth = max(dth, r["max_theta_diff_Ha"])
+    out["held_out_cells"] = {"cells": f"training family, indices 201..{200 + ncells} (never trained on or "
+                                      f"used to pick the weights), at most 256 bands",
+                             "mean_iterations": {k: round(float(np.mean(v)), 2) for k, v in its.items()},
+                             "mean_seconds": {k: round(float(np.mean(v)), 4) for k, v in secs.items()},
+                             "mlp_time_over_tpa": round(float(np.sum(secs["mlp"]) / np.sum(secs["tpa"])), 3),
+                             "max_theta_diff_Ry": float(2 * dth)}
+    cell = synth.make_cell(5, -1)
+    r = learned.evaluate(cell, net, tol=5e-7)
+    o = {"cell": f"{cell.name}: a={cell.A[0, 0]:.2f} bohr, {int(round(2 * cell.ecut_ha))} Ry, "
+                 f"{cell.natom} atoms, {cell.nbands} bands, grid {cell.nr[0]}^3",
+         "max_theta_diff_Ry": float(2 * r["max_theta_diff_Ha"])}
+    for k in ("tpa", "mlp"):
+        o[k] = {"iterations": r[k]["iterations"], "seconds": round(r[k]["seconds"], 4),
+                "n_hpsi": r[k]["n_hpsi"], "converged": bool(r[k]["converged"])}
+    o["mlp_time_over_tpa"] = round(r["mlp"]["seconds"] / r["tpa"]["seconds"], 3)
+    out["evaluation_cell"] = o
+    return out, net
 
 
 def davidson_cpu_baseline(dav):
-    """Oracle FP64 Davidson on config 1 (host cores) and eigenvalue agreement with the GPU."""
+    """Oracle FP64 Davidson on the config-1 cell (host cores)."""
     from oracle import davidson as odv
     from oracle import hamiltonian as ham
     import synth
@@ -317,10 +485,8 @@ def davidson_cpu_baseline(dav):
     t0 = time.perf_counter()
     r = odv.davidson(po, synth.psi_start(cell.seed, cell.nbands, po.npw), cell.nbands, 5e-9)
     dt = time.perf_counter() - t0
-    for k in ("fp64", "fp32_then_fp64"):
-        if k in dav:
-            dav[k]["max_abs_theta_minus_oracle_Ry"] = float(2.0 * np.abs(dav[k]["_theta"] - r["theta"]).max())
-    dav["cpu_oracle"] = {"seconds": round(dt, 4), "iterations": r["iterations"], "kind": "oracle"}
+    dav["cpu_oracle_fp64_1e-8Ry"] = {"seconds": round(dt, 4), "iterations": r["iterations"], "kind": "oracle",
+                                     "speedup_gpu_fp64": round(dt / dav["fp64_1e-8Ry"]["seconds"], 2)}
 
 
 def main():
@@ -358,19 +524,15 @@ def main():
         psis.append(x)
         hpsis.append(torch.zeros_like(x))
         infos.append(inf)
-    tuning = None
-    if args.no_autotune:
-        tuning = _lib.pw_problem_tuning(probs[0])
-        tuning["plane_kernel_id"] = tuning["plane_kernel"]
-        tuning["plane_kernel"] = ("register", "wave", "lds")[tuning["plane_kernel"]]
-    else:
-        # launch choices (plane kernel, bands per workgroup, sweep height,
-        # split-K) searched once per problem, outside the timed region
-        for p in probs:
+    for p in probs:
+        if args.autotune:
             _lib.pw_problem_autotune(p, cell.nbands, reps=3)
-        tuning = _lib.pw_problem_tuning(probs[0])
-        tuning["plane_kernel_id"] = tuning["plane_kernel"]
-        tuning["plane_kernel"] = ("register", "wave", "lds")[tuning["plane_kernel"]]
+        else:
+            fixed_tuning(p, args.precision)
+    tuning = _lib.pw_problem_tuning(probs[0])
+    tuning["plane_kernel_id"] = tuning["plane_kernel"]
+    tuning["plane_kernel"] = ("register", "wave", "lds")[tuning["plane_kernel"]]
+    tuning["source"] = "autotuned" if args.autotune else "pinned"
     torch.cuda.synchronize()
 
     def step():
@@ -432,7 +594,7 @@ def main():
     if dom == "plane":
         # the plane pass's own HBM bytes for the bands of one launch: z-sticks
         # in and out, V(r) once
-        inf, nbl = infos[0], (tuning or {}).get("band_chunk") or cell.nbands
+        inf, nbl = infos[0], tuning.get("band_chunk") or cell.nbands
         sz = 16 if prec == 0 else 8
         roof["hbm_bytes_algorithmic_per_launch"] = float(nbl * 2 * inf["nsticks"] * inf["n"] * sz
                                                           + inf["n"] ** 3 * sz // 2)
@@ -498,23 +660,37 @@ def main():
         "fft_pipeline": fft_pipe,
         "ms_per_step_profiled": round(dt_prof / args.steps * 1e3, 4),
     }
-    dav = None if args.no_davidson else davidson_section(args.davidson_reps)
-    if not args.no_batched:
-        out["batched_ragged_cells"] = batched_section(args.batched_cells, max(3, args.steps // 2),
-                                                      autotune=not args.no_autotune)
+    for p in probs:
+        p.close()
+    del psis, hpsis
+    torch.cuda.empty_cache()
+    note(f"H*psi step: {value:.1f} band-H*psi/s, dominant kernel {dom} at {roof['frac']} of its roof")
+    net = None
     if not args.no_learned:
-        out["learned_preconditioner"] = learned_section()
+        lr = learned_section(args.learned_cells)
+        if isinstance(lr, tuple):
+            out["learned_preconditioner"], net = lr
+        else:
+            out["learned_preconditioner"] = lr
+        note("learned preconditioner section done")
+    if not args.no_batched:
+        out["batched_ragged_cells"] = batched_section(args.batched_cells, max(3, args.steps // 2), args.streams,
+                                                      learned_net=net)
+        note("batched section done")
+    dav = None
+    if not args.no_davidson:
+        dav = davidson_small_section(args.davidson_reps)
+        note("config-1 Davidson section done")
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(cell, 0, args.cpu_seconds)
-        out["cpu_baseline"] = cb
+        out["cpu_baseline"] = cpu_baseline(cell, 0, args.cpu_seconds)
         if dav is not None:
             davidson_cpu_baseline(dav)
+        note("CPU baseline done")
     if dav is not None:
-        for k in ("fp64", "fp32_then_fp64"):
-            dav[k].pop("_theta", None)
         out["davidson_time_to_1e-8Ry"] = dav
         if not args.no_davidson_medium:
             out["davidson_medium_time_to_solution"] = davidson_medium_section(args.davidson_medium_kpoints)
+            note("medium Davidson section done")
     print(json.dumps(out), flush=True)
 
 

@@ -295,7 +295,6 @@ pw_status pw_davidson_vectors(pw_davidson *d, void *x, int64_t ld, void *stream)
 pw_status pw_eigh_workspace(int32_t m, size_t *bytes);
 pw_status pw_eigh(const void *A, int64_t lda, int32_t m, double *w, void *Z, int64_t ldz, void *work,
                   size_t work_bytes, void *stream);
-
 /*
  * Batched H*psi over independent problems (cells or k-points with ragged
  * npw, grids and band counts): the paper runs such units side by side as
@@ -316,6 +315,56 @@ pw_status pw_batch_destroy(pw_batch *b);
 pw_status pw_batch_hpsi(pw_batch *b, void *stream);
 pw_status pw_batch_capture(pw_batch *b, void *stream);
 pw_status pw_batch_launch(pw_batch *b, void *stream);
+/*
+ * Side streams for a batch's sweep (distinct non-null hipStream_t as void*,
+ * at most 64; nstreams = 0 restores the in-order sweep).  Problems are
+ * placed on them longest first by npw * nbands * (log2 N0 + nproj / 64);
+ * pw_batch_hpsi, and the graph pw_batch_capture records, then fork from the
+ * call's stream to the side streams (an event) and join back (one event per
+ * side stream), so the problems of different side streams overlap on the
+ * GPU.  Results are those of the in-order sweep, bit for bit.
+ */
+pw_status pw_batch_set_streams(pw_batch *b, void *const *streams, int32_t nstreams);
+
+/*
+ * Batched Davidson: independent solves (cells, k-points) advanced side by
+ * side, the paper's images and k-point pools on one GPU.  Each caller
+ * stream gets one host worker thread, which issues its solves' kernels on
+ * that stream and waits on their host syncs, so the kernels of different
+ * solves overlap and one solve's syncs do not stall the others.  The solves
+ * are created beforehand (pw_davidson_create, each with its own problem and
+ * workspaces) and stay owned by the caller; they must be distinct, must not
+ * share a problem, and must live on the current device.  Streams: distinct
+ * non-null hipStream_t as void*, 1..64.  A solve is placed on the streams
+ * longest first by npw * nbands * (log2 N0 + nproj / 64) + npw * m_max^2 / 8.
+ *   pw_batch_davidson_init  pw_davidson_init of every solve (psi0[i] device
+ *                           complex128 [nbands_i][ld[i]]), on its stream
+ *   pw_batch_davidson_step  one pw_davidson_step of every solve not yet
+ *                           converged; *nconverged (may be NULL) counts the
+ *                           converged solves afterwards
+ *   pw_batch_davidson_run   init and up to max_iter steps of every solve,
+ *                           the workers taking solves from one queue,
+ *                           longest first; with psi0 == NULL no init: every
+ *                           solve continues from its state (e.g. after
+ *                           pw_davidson_set_problem and _set_tol for an FP64
+ *                           refinement).  converged[i] (host int32 [n], may
+ *                           be NULL) per solve.  PW_OK when every solve
+ *                           converged, else PW_NOT_CONVERGED.
+ * Results per solve are those of the same calls made one solve after
+ * another.  Every call returns once its workers have finished and every
+ * stream has completed the call's device work (the caller may then use or
+ * free the solves' memory from any stream); the first failing solve's
+ * status and message are returned.
+ */
+typedef struct pw_batch_dav pw_batch_dav;
+pw_status pw_batch_davidson_create(pw_davidson *const *solvers, int32_t n, void *const *streams,
+                                   int32_t nstreams, pw_batch_dav **out);
+pw_status pw_batch_davidson_destroy(pw_batch_dav *b);
+pw_status pw_batch_davidson_init(pw_batch_dav *b, const void *const *psi0, const int64_t *ld);
+pw_status pw_batch_davidson_step(pw_batch_dav *b, int32_t precond_kind, const pw_mlp *net,
+                                 int32_t *nconverged);
+pw_status pw_batch_davidson_run(pw_batch_dav *b, const void *const *psi0, const int64_t *ld, int32_t max_iter,
+                                int32_t precond_kind, const pw_mlp *net, int32_t *converged);
 
 /*
  * Autotuner: times pw_hpsi on nbands scratch bands (reps timed calls per

@@ -103,6 +103,12 @@ def _load():
         "pw_batch_hpsi": (i32, [vp, vp]),
         "pw_batch_capture": (i32, [vp, vp]),
         "pw_batch_launch": (i32, [vp, vp]),
+        "pw_batch_set_streams": (i32, [vp, C.POINTER(vp), i32]),
+        "pw_batch_davidson_create": (i32, [C.POINTER(vp), i32, C.POINTER(vp), i32, C.POINTER(vp)]),
+        "pw_batch_davidson_destroy": (i32, [vp]),
+        "pw_batch_davidson_init": (i32, [vp, C.POINTER(vp), C.POINTER(i64)]),
+        "pw_batch_davidson_step": (i32, [vp, i32, vp, C.POINTER(i32)]),
+        "pw_batch_davidson_run": (i32, [vp, C.POINTER(vp), C.POINTER(i64), i32, i32, vp, C.POINTER(i32)]),
         "pw_problem_autotune": (i32, [vp, i64, i32, vp, C.c_size_t, vp, C.POINTER(f64)]),
         "pw_problem_tuning": (i32, [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32), C.POINTER(i32)]),
         "pw_problem_set_tuning": (i32, [vp, i32, i64, i32, i32]),
@@ -620,6 +626,113 @@ def pw_batch_launch(b: Batch, stream=None) -> None:
     _check(LIB.pw_batch_launch(b.handle, _stream(stream)))
 
 
+def pw_batch_set_streams(b: Batch, streams) -> None:
+    """Side streams (torch.cuda.Stream list) for the batch's sweeps; [] restores in-order."""
+    n = len(streams)
+    arr = (C.c_void_p * max(n, 1))(*[s.cuda_stream for s in streams])
+    _check(LIB.pw_batch_set_streams(b.handle, arr, n))
+    b._streams = list(streams)
+
+
+class BatchDavidson:
+    """Owner of a pw_batch_dav over Davidson objects (kept alive with it) and
+    the torch streams its workers run on."""
+
+    def __init__(self, solvers, streams):
+        n, k = len(solvers), len(streams)
+        ds = (C.c_void_p * n)(*[d.handle for d in solvers])
+        ss = (C.c_void_p * k)(*[s.cuda_stream for s in streams])
+        h = C.c_void_p()
+        _check(LIB.pw_batch_davidson_create(ds, n, ss, k, C.byref(h)))
+        self._h = h
+        self.solvers = list(solvers)
+        self.streams = list(streams)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise PwError(-1, "batched Davidson already destroyed")
+        return self._h
+
+    def _blocks(self, psi0s):
+        n = len(self.solvers)
+        if len(psi0s) != n:
+            raise ValueError("one start block per solve")
+        ptrs, lds = (C.c_void_p * n)(), (C.c_int64 * n)()
+        for i, (d, x) in enumerate(zip(self.solvers, psi0s)):
+            p_, ld_, nb_ = _band_block(x, "psi0", d.prob.npw)
+            if nb_ < d.nbands:
+                raise ValueError("psi0 has fewer bands than its solver")
+            ptrs[i], lds[i] = p_.value, ld_
+        return ptrs, lds
+
+    def init(self, psi0s) -> None:
+        ptrs, lds = self._blocks(psi0s)
+        _check(LIB.pw_batch_davidson_init(self.handle, ptrs, lds))
+
+    def step(self, precond: int = PW_PRECOND_TPA, net=None) -> int:
+        nc = C.c_int32(0)
+        _check(LIB.pw_batch_davidson_step(self.handle, int(precond), net.handle if net is not None else None,
+                                          C.byref(nc)))
+        return nc.value
+
+    def run(self, psi0s, max_iter: int = 200, precond: int = PW_PRECOND_TPA, net=None) -> np.ndarray:
+        """init + run of every solve; psi0s None continues every solve from its state."""
+        ptrs, lds = self._blocks(psi0s) if psi0s is not None else (None, None)
+        conv = np.zeros(len(self.solvers), dtype=np.int32)
+        _check(LIB.pw_batch_davidson_run(self.handle, ptrs, lds, int(max_iter), int(precond),
+                                         net.handle if net is not None else None,
+                                         conv.ctypes.data_as(C.POINTER(C.c_int32))))
+        return conv.astype(bool)
+
+    def close(self):
+        if self._h:
+            LIB.pw_batch_davidson_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_davidson_solve(probs, psi0s, tol: float = 5e-9, nstreams: int = 4, max_subspace: int = 0,
+                         max_iter: int = 200, precond: int = PW_PRECOND_TPA, net=None, refine=None,
+                         refine_tol: float = None) -> list:
+    """Davidson on every problem side by side over nstreams streams; per
+    problem dict(theta, rho, iterations, n_hpsi, converged).  With
+    ``refine`` (one problem per solve on the same sphere, e.g. the FP64
+    forms): run to ``tol``, switch every solve to its refine problem and
+    continue side by side to ``refine_tol``."""
+    import torch
+    solvers = [Davidson(p, int(x.shape[0]), max_subspace, tol) for p, x in zip(probs, psi0s)]
+    streams = [torch.cuda.Stream() for _ in range(max(1, int(nstreams)))]
+    torch.cuda.synchronize()
+    b = BatchDavidson(solvers, streams)
+    try:
+        conv = b.run(psi0s, max_iter, precond, net)
+        if refine is not None:
+            first = [pw_davidson_query(d)["iterations"] for d in solvers]
+            for d, p in zip(solvers, refine):
+                pw_davidson_set_problem(d, p)
+                pw_davidson_set_tol(d, refine_tol if refine_tol else tol)
+            torch.cuda.synchronize()
+            conv = b.run(None, max_iter, precond, net)
+        out = []
+        for i, (d, c) in enumerate(zip(solvers, conv)):
+            r = pw_davidson_query(d)
+            r["converged"] = bool(c)
+            if refine is not None:
+                r["iterations_first"] = first[i]
+            out.append(r)
+    finally:
+        b.close()
+        for d in solvers:
+            d.close()
+    return out
+
+
 def pw_problem_autotune(prob: Problem, nbands: int, reps: int = 3, stream=None) -> float:
     ld = (prob.npw + 63) // 64 * 64
     nbytes = 2 * int(nbands) * ld * 16
@@ -660,3 +773,4 @@ def pw_eigh(A, stream=None):
                        C.c_void_p(Zt.data_ptr()), m, C.c_void_p(work.data_ptr()), nbytes.value,
                        _stream(stream)))
     return w, Zt.t()
+

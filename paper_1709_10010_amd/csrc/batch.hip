@@ -220,7 +220,11 @@ double solve_cost(const pw_davidson *d) {
 }
 
 // fn(k) on one host thread per stream, with the batch's device current;
-// the first failure's status and message come back to the calling thread.
+// each worker then waits for its stream, so every device operation of the
+// call has finished when it returns (a converged Davidson step enqueues its
+// last rotation after its last host sync, and the caller may reuse or free
+// the solves' memory from another stream).  The first failure's status and
+// message come back to the calling thread.
 template <typename F>
 int run_workers(pw_batch_dav *b, F &&fn) {
   const int nw = (int)b->streams.size();
@@ -237,6 +241,11 @@ int run_workers(pw_batch_dav *b, F &&fn) {
       }
       rc[k] = fn(k);
       if (rc[k] < 0) msg[k] = pw_last_error();
+      const hipError_t e = hipStreamSynchronize(b->streams[k]);
+      if (e != hipSuccess && rc[k] >= 0) {
+        rc[k] = PW_ERR_HIP;
+        msg[k] = std::string("batched Davidson: stream synchronisation failed: ") + hipGetErrorString(e);
+      }
     });
   for (std::thread &t : th) t.join();
   for (int k = 0; k < nw; ++k)
@@ -327,13 +336,17 @@ pw_status pw_batch_davidson_step(pw_batch_dav *b, int32_t precond_kind, const pw
 
 pw_status pw_batch_davidson_run(pw_batch_dav *b, const void *const *psi0, const int64_t *ld, int32_t max_iter,
                                 int32_t precond_kind, const pw_mlp *net, int32_t *converged) {
-  PW_CHECK_ARG(b && psi0 && ld && max_iter >= 1, PW_ERR_INVALID, "pw_batch_davidson_run: bad argument");
+  PW_CHECK_ARG(b && max_iter >= 1 && (!psi0 || ld), PW_ERR_INVALID, "pw_batch_davidson_run: bad argument");
+  if (!psi0)
+    for (pw_davidson *d : b->dav)
+      PW_CHECK_ARG(dav_inited(d), PW_ERR_INVALID, "pw_batch_davidson_run: without start blocks every solve "
+                                                  "must have been initialised");
   std::atomic<int> next{0};
   const int n = (int)b->dav.size();
   const int rc = run_workers(b, [&](int k) {
     for (int t = next.fetch_add(1); t < n; t = next.fetch_add(1)) {
       const int i = b->order[t];
-      int r = pw_davidson_init(b->dav[i], psi0[i], ld[i], b->streams[k]);
+      int r = psi0 ? pw_davidson_init(b->dav[i], psi0[i], ld[i], b->streams[k]) : (int)PW_OK;
       if (r != PW_OK) return r;
       int32_t c = 0;
       r = pw_davidson_run(b->dav[i], max_iter, precond_kind, net, b->streams[k], &c);

@@ -4,8 +4,9 @@ alone (dense diagonalisation of the discrete Hamiltonian of eq. pauli_ks on
 the sphere basis; sphere sizes from the cutoff inequality; the oracle's
 block Davidson at the medium workload's full size).
 
-    python tests/golden/make_golden.py               # everything (~10 min)
-    python tests/golden/make_golden.py --quick       # without the medium-size Davidson
+    python tests/golden/make_golden.py               # everything (~15 min)
+    python tests/golden/make_golden.py --quick       # without the Davidson goldens
+    python tests/golden/make_golden.py --config4     # only the two ragged-batch cells
 
 Regression fixtures: tests/test_golden.py recomputes them with the oracle,
 and the GPU tests compare the library against them.
@@ -59,10 +60,34 @@ def davidson_config2(ik):
             f.write(f"{t:.17e} {rho:.3e}\n")
 
 
+def davidson_config4(index):
+    """Oracle block Davidson on one cell of the ragged batch (its own band
+    count, Gamma point) to 5e-9 Ha on every band."""
+    from oracle import davidson as odv
+    c = synth.make_cell(4, index)
+    po = ham.problem_from_cell(c)
+    r = odv.davidson(po, synth.psi_start(c.seed, c.nbands, po.npw), c.nbands, 5e-9)
+    assert r["converged"], "oracle Davidson did not converge"
+    fname = f"config4_cell{index}_davidson_Ha.txt"
+    with open(os.path.join(HERE, fname), "w") as f:
+        f.write(f"# {c.name}: a {c.A[0, 0]:.4f} bohr, ecut {c.ecut_ha:.6f} Ha, npw {po.npw}, grid {c.nr[0]}^3, "
+                f"{c.natom} atoms, {c.nbands} bands; oracle block Davidson to |Hx - theta x| < 5e-9 Ha "
+                f"({r['iterations']} iterations); columns: theta (Ha), residual 2-norm (Ha); "
+                f"written by make_golden.py (oracle only)\n")
+        for t, rho in zip(r["theta"], r["rho"]):
+            f.write(f"{t:.17e} {rho:.3e}\n")
+
+
 def main():
+    if "--config4" in sys.argv:
+        for index in (10, 19):
+            davidson_config4(index)
+        return
     if "--quick" not in sys.argv:
         for ik in (0, 1):
             davidson_config2(ik)
+        for index in (10, 19):
+            davidson_config4(index)
     for cfg, nlow, fname in ((0, 8, "tiny_cell_lowest8_Ha.txt"), (1, 16, "config1_lowest16_Ha.txt")):
         c, po, w = eig_fixture(cfg, nlow)
         with open(os.path.join(HERE, fname), "w") as f:
