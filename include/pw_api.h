@@ -296,6 +296,20 @@ pw_status pw_eigh_workspace(int32_t m, size_t *bytes);
 pw_status pw_eigh(const void *A, int64_t lda, int32_t m, double *w, void *Z, int64_t ldz, void *work,
                   size_t work_bytes, void *stream);
 /*
+ * pw_eigh for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same eigensolver with its workspace in a static device array of the
+ * library (12.6 MB per GPU, held until the process ends) instead of a
+ * caller buffer.  Same arguments and results as pw_eigh without work and
+ * work_bytes.  m at most 512 (PW_ERR_INVALID above, before any device
+ * work).  Allocates nothing.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (two streams, two host threads)
+ * race on it and must be serialised by the caller.
+ */
+pw_status pw_eigh_noalloc(const void *A, int64_t lda, int32_t m, double *w, void *Z, int64_t ldz,
+                          void *stream);
+
+/*
  * Batched H*psi over independent problems (cells or k-points with ragged
  * npw, grids and band counts): the paper runs such units side by side as
  * images and k-point pools.  A batch lists, per problem, its input and
