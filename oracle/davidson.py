@@ -123,3 +123,81 @@ def davidson(p: "_ham.Problem", psi0: np.ndarray, nb: int, tol: float,
         W = np.concatenate([W, HT], axis=1)
     return dict(theta=theta, X=X, iterations=max_iter, rho=rho, n_hpsi=n_hpsi,
                 history=history, converged=False)
+
+
+# ---------------------------------------------------------------- generalized problem
+# With ultrasoft / PAW augmentation the paper's equation reads
+# (H - eps S) psi = 0 (eq. pauli_ks).  The block Davidson then keeps the
+# space S-orthonormal (V^H S V = 1), so the Rayleigh-Ritz problem V^H H V
+# stays a standard Hermitian one, and the residual is H x - theta S x.
+# The same steps as `davidson`, in the S inner product:
+#   1. V = S-orthonormalised start block; W = H V, SV = S V; Hs = V^H W.
+#   2. eigh(Hs) -> theta, Y; X = V Y, HX = W Y, SX = SV Y; R = HX - SX theta.
+#   3. all |R_n| < tol: stop.  Else T = K(R) for the open bands.
+#   4. restart when the space is full: V, W, SV = X, HX, SX; Hs = diag(theta).
+#   5. twice: T <- T - V (SV^H T) (twice), then S-Cholesky-QR of T.
+#   6. V, W, SV grow by T, H T, S T; Hs is bordered with V^H H T.
+
+def orthonormalize_s(T: np.ndarray, ST: np.ndarray, rel_drop: float = 1e-12):
+    """S-orthonormal basis of span(T) from T and ST = S T (npw x k): Cholesky
+    of the Gram matrix T^H S T = L L^H, T <- T L^{-H} (ST likewise); with a
+    (numerically) dependent column, eigh of the Gram matrix drops the
+    directions below rel_drop of the largest."""
+    if T.shape[1] == 0:
+        return T, ST
+    G = T.conj().T @ ST
+    G = 0.5 * (G + G.conj().T)
+    try:
+        L = np.linalg.cholesky(G)
+        d = np.abs(np.diag(L)) ** 2
+        if np.min(d) > rel_drop * np.max(np.real(np.diag(G))):
+            return np.linalg.solve(L.conj(), T.T).T, np.linalg.solve(L.conj(), ST.T).T
+    except np.linalg.LinAlgError:
+        pass
+    w, U = np.linalg.eigh(G)
+    keep = w > rel_drop * max(w[-1], 0.0)
+    scale = U[:, keep] / np.sqrt(w[keep])[None, :]
+    return T @ scale, ST @ scale
+
+
+def davidson_generalized(p: "_ham.Problem", psi0: np.ndarray, nb: int, tol: float,
+                         m_max: int | None = None, max_iter: int = 200):
+    """Lowest nb eigenpairs of H x = theta S x to |H x - theta S x| < tol (Ha).
+    Returns dict(theta, X (npw x nb, S-orthonormal), iterations, rho, converged)."""
+    t = p.kinetic()
+    m_max = 3 * nb if m_max is None else int(m_max)
+    sop = lambda X: _ham.spsi(p, X.T).T          # noqa: E731
+    hop = lambda X: _ham.hpsi(p, X.T).T          # noqa: E731
+    V = np.asarray(psi0, dtype=np.complex128).T.copy()
+    V, SV = orthonormalize_s(V, sop(V))
+    if V.shape[1] < nb:
+        raise ValueError("start block is rank deficient")
+    W = hop(V)
+    Hs = V.conj().T @ W
+    Hs = 0.5 * (Hs + Hs.conj().T)
+    for it in range(1, max_iter + 1):
+        w, Y = np.linalg.eigh(Hs)
+        theta, Y = w[:nb], Y[:, :nb]
+        X, HX, SX = V @ Y, W @ Y, SV @ Y
+        R = HX - SX * theta[None, :]
+        rho = np.sqrt((np.abs(R) ** 2).sum(axis=0))
+        if np.max(rho) < tol:
+            return dict(theta=theta, X=X, iterations=it, rho=rho, converged=True)
+        U = np.nonzero(rho >= tol)[0]
+        T = tpa_apply(t, X[:, U], R[:, U])
+        if V.shape[1] + len(U) > m_max:
+            V, W, SV = X, HX, SX
+            Hs = np.diag(theta).astype(np.complex128)
+        for _ in range(2):
+            for _ in range(2):
+                T = T - V @ (SV.conj().T @ T)
+            T, ST = orthonormalize_s(T, sop(T))
+        HT = hop(T)
+        Hvt = V.conj().T @ HT
+        Htt = T.conj().T @ HT
+        Htt = 0.5 * (Htt + Htt.conj().T)
+        Hs = np.block([[Hs, Hvt], [Hvt.conj().T, Htt]])
+        V = np.concatenate([V, T], axis=1)
+        W = np.concatenate([W, HT], axis=1)
+        SV = np.concatenate([SV, ST], axis=1)
+    return dict(theta=theta, X=X, iterations=max_iter, rho=rho, converged=False)

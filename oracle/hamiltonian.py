@@ -38,6 +38,7 @@ class Problem:
     beta: np.ndarray       # (nproj,npw) complex
     proj_offset: np.ndarray  # (natom+1,) int
     dij: list              # per-atom real symmetric blocks, Ha
+    qij: list | None = None  # per-atom real symmetric augmentation blocks (S != 1), or None (S = 1)
 
     @property
     def npw(self) -> int:
@@ -52,8 +53,15 @@ class Problem:
 
     def d_matrix(self) -> np.ndarray:
         """Block-diagonal D (nproj x nproj) assembled from the per-atom blocks."""
+        return self._blocks(self.dij)
+
+    def q_matrix(self) -> np.ndarray:
+        """Block-diagonal q of the overlap S (zeros when S = 1)."""
+        return self._blocks(self.qij) if self.qij is not None else np.zeros((self.nproj, self.nproj))
+
+    def _blocks(self, blocks) -> np.ndarray:
         d = np.zeros((self.nproj, self.nproj))
-        for a, blk in enumerate(self.dij):
+        for a, blk in enumerate(blocks):
             o0, o1 = int(self.proj_offset[a]), int(self.proj_offset[a + 1])
             d[o0:o1, o0:o1] = blk
         return d
@@ -75,6 +83,7 @@ def problem_from_cell(cell, ik: int = 0, miller=None) -> Problem:
         beta=synth.projectors(cell, kf, miller),
         proj_offset=cell.proj_offset,
         dij=[np.asarray(d, dtype=np.float64) for d in cell.dij],
+        qij=None if getattr(cell, "qij", None) is None else [np.asarray(q, dtype=np.float64) for q in cell.qij],
     )
 
 
@@ -127,6 +136,36 @@ def dense_h(p: Problem) -> np.ndarray:
 
 
 def eigh_lowest(p: Problem, nb: int):
-    """nb lowest eigenvalues (ascending) and eigenvectors of dense_h (LAPACK)."""
+    """nb lowest eigenvalues (ascending) and eigenvectors of dense_h (LAPACK).
+    With S != 1: the generalized problem H x = eps S x (eigenvectors
+    S-orthonormal)."""
+    if p.qij is not None:
+        import scipy.linalg
+        w, v = scipy.linalg.eigh(dense_h(p), dense_s(p))
+        return w[:nb], v[:, :nb].T.copy()
     w, v = np.linalg.eigh(dense_h(p))
     return w[:nb], v[:, :nb].T.copy()
+
+
+# ---------------------------------------------------------------- overlap S
+# The paper's general Kohn-Sham equation (eq. pauli_ks) carries -eps_i S:
+# with ultrasoft or PAW augmentation the overlap is
+#   S = 1 + sum_I sum_mn q_I,mn |beta_m^I><beta_n^I|,
+# built from the same projectors as the nonlocal term (the paper rewrites
+# the overlap in terms of projector functions), so that H psi = eps S psi.
+
+def spsi(p: Problem, psi: np.ndarray) -> np.ndarray:
+    """S applied to each band of psi ([nb][npw]): psi + sum_ij beta_i q_ij <beta_j|psi>."""
+    psi = np.atleast_2d(np.asarray(psi, dtype=np.complex128))
+    if p.qij is None:
+        return psi.copy()
+    q = p.q_matrix() @ projections(p, psi)
+    return psi + (p.beta.T @ q).T
+
+
+def dense_s(p: Problem) -> np.ndarray:
+    """S_{GG'} = delta_{GG'} + sum_ij beta_i(G) q_ij beta_j(G')^*."""
+    s = np.eye(p.npw, dtype=np.complex128)
+    if p.qij is not None:
+        s += p.beta.T @ p.q_matrix() @ p.beta.conj()
+    return s

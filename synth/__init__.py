@@ -1,7 +1,7 @@
 """Seeded synthetic inputs for the plane-wave H·psi / block-Davidson path.
 
 This package only *draws* problem data (cell, atoms, well depths, nonlocal
-coefficients, k-points, starting bands) and samples the analytic input
+coefficients, overlap augmentation, k-points, starting bands) and samples the analytic input
 functions (Gaussian local wells on the real-space grid, Gaussian-radial
 projectors at given wave vectors).  It holds none of the method's
 arithmetic: no sphere enumeration, no FFT, no Hamiltonian application, no
@@ -16,4 +16,5 @@ from .cells import (  # noqa: F401
     psi_start,
     smooth_grid,
     alias_free_min,
+    with_augmentation,
 )

@@ -47,6 +47,7 @@ class Cell:
     nbands: int
     sigma_well: float = BOHR_SIGMA_WELL
     sigma_proj: float = BOHR_SIGMA_PROJ
+    qij: list | None = None  # per-atom augmentation blocks of S (None: S = 1)
 
     @property
     def natom(self) -> int:
@@ -64,6 +65,37 @@ class Cell:
     def dij_concat(self) -> np.ndarray:
         """Row-major per-atom blocks, concatenated (library layout)."""
         return np.concatenate([d.reshape(-1) for d in self.dij]).astype(np.float64)
+
+    def qij_concat(self) -> np.ndarray | None:
+        """The augmentation blocks in the layout of dij_concat (None: S = 1)."""
+        if self.qij is None:
+            return None
+        return np.concatenate([q.reshape(-1) for q in self.qij]).astype(np.float64)
+
+
+def with_augmentation(cell: Cell, lo: float = 0.1, hi: float = 0.6) -> Cell:
+    """A copy of `cell` with overlap augmentation: per atom a real symmetric
+    block q, diagonal U[lo, hi] for s+p atoms, Q diag(mu) Q^T with mu ~
+    U[lo, hi] and Q a sign-fixed Haar orthogonal matrix for s+p+d atoms
+    (positive, so S = 1 + sum q |beta><beta| is positive definite).  Drawn
+    from its own stream default_rng([seed, 2718]), so every other input of
+    the cell is unchanged."""
+    rng = np.random.default_rng([cell.seed, 2718])
+    qs = []
+    for lm in cell.lmax:
+        n = (int(lm) + 1) ** 2
+        mu = rng.uniform(lo, hi, size=n)
+        if lm >= 2:
+            o = _haar_orthogonal(rng, n)
+            q = (o * mu[None, :]) @ o.T
+            q = 0.5 * (q + q.T)
+        else:
+            q = np.diag(mu)
+        qs.append(np.ascontiguousarray(q))
+    out = dataclasses.replace(cell)
+    out.qij = qs
+    out.name = cell.name + ".aug"
+    return out
 
 
 def _is_smooth(n: int) -> bool:

@@ -471,3 +471,79 @@ def test_lanczos_fft_path_matches_dense_path():
     a2, b2 = lz.lanczos(po, v, 12, apply_h=lambda x: H @ x)
     assert np.abs(a1 - a2).max() <= 1e-11 * np.abs(a2).max()
     assert np.abs(b1 - b2).max() <= 1e-11 * np.abs(b2).max()
+
+
+# ---------------------------------------------------------------- overlap S (augmentation)
+def test_overlap_operator_is_the_dense_matrix_and_positive():
+    c = synth.with_augmentation(synth.make_cell(0))
+    po = ham.problem_from_cell(c)
+    S = ham.dense_s(po)
+    assert np.abs(S - S.conj().T).max() < 1e-15
+    assert np.linalg.eigvalsh(S)[0] >= 1.0 - 1e-12         # q >= 0: S >= 1
+    psi = _rand_c(np.random.default_rng(81), (3, po.npw))
+    assert np.abs(ham.spsi(po, psi) - (S @ psi.T).T).max() < 1e-13 * np.abs(psi).max()
+    # S = 1 without augmentation
+    p0 = ham.problem_from_cell(synth.make_cell(0))
+    assert np.array_equal(ham.spsi(p0, psi), psi)
+
+
+def test_generalized_rank1_secular_equation():
+    # constant potential, one s projector with D = d and q: the generalized
+    # eigenvalues solve 1 = (d - eps q) sum_G |beta(G)|^2 / (eps - t(G)),
+    # one root between consecutive free levels (bisection); compare with
+    # the dense generalized eigh and with the oracle's S-orthonormal Davidson
+    c = synth.make_cell(0)
+    po = ham.problem_from_cell(c)
+    po.vloc = np.full(po.vloc.shape, -0.3)
+    po.beta = po.beta[:1]
+    po.proj_offset = np.array([0, 1], dtype=np.int32)
+    d, q = 0.7, 0.45
+    po.dij, po.qij = [np.array([[d]])], [np.array([[q]])]
+    t = po.kinetic() - 0.3
+    b2 = np.abs(po.beta[0]) ** 2
+    f = lambda e: 1.0 - (d - e * q) * np.sum(b2 / (e - t))     # noqa: E731
+    levels = np.unique(np.round(t, 12))
+    roots = []
+    for lo, hi in zip(levels[:-1], levels[1:]):
+        a, b = lo + 1e-12, hi - 1e-12
+        if f(a) * f(b) > 0:
+            continue
+        for _ in range(200):
+            m = 0.5 * (a + b)
+            if f(a) * f(m) <= 0:
+                b = m
+            else:
+                a = m
+        roots.append(0.5 * (a + b))
+    import scipy.linalg
+    w = scipy.linalg.eigh(ham.dense_h(po), ham.dense_s(po), eigvals_only=True)
+    for r in roots[:4]:
+        assert np.abs(w - r).min() < 1e-9, r
+    res = dv.davidson_generalized(po, synth.psi_start(c.seed, 8, po.npw), 8, 1e-10)
+    assert res["converged"] and np.abs(res["theta"] - w[:8]).max() < 1e-9
+
+
+@pytest.mark.parametrize("cfg", [0, 1])
+def test_generalized_davidson_matches_dense_and_is_s_orthonormal(cfg):
+    c = synth.with_augmentation(synth.make_cell(cfg))
+    po = ham.problem_from_cell(c)
+    nb = c.nbands
+    w, _ = ham.eigh_lowest(po, nb)
+    res = dv.davidson_generalized(po, synth.psi_start(c.seed, nb, po.npw), nb, 5e-10)
+    assert res["converged"] and np.abs(res["theta"] - w).max() < 1e-9
+    X = res["X"]
+    G = X.conj().T @ ham.spsi(po, X.T).T
+    assert np.abs(G - np.eye(nb)).max() < 1e-11
+    # each theta is the Rayleigh quotient x^H H x / x^H S x of its vector,
+    # with H from the dense matrix
+    H = ham.dense_h(po)
+    rq = np.real(np.einsum("gi,gh,hi->i", X.conj(), H, X)) / np.real(np.diag(G))
+    assert np.abs(rq - res["theta"]).max() < 1e-9
+
+
+def test_generalized_davidson_without_augmentation_is_the_standard_one():
+    c = synth.make_cell(0)
+    po = ham.problem_from_cell(c)
+    r1 = dv.davidson_generalized(po, synth.psi_start(c.seed, 8, po.npw), 8, 1e-10)
+    r2 = dv.davidson(po, synth.psi_start(c.seed, 8, po.npw), 8, 1e-10)
+    assert np.abs(r1["theta"] - r2["theta"]).max() < 1e-10
