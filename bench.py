@@ -94,6 +94,11 @@ def parse():
     ap.add_argument("--streams", type=int, default=4, help="streams of the batched forms")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-cells", type=int, default=10)
+    ap.add_argument("--no-lanczos", action="store_true")
+    ap.add_argument("--lanczos-steps", type=int, default=40)
+    ap.add_argument("--profile-davidson", action="store_true",
+                    help="only run one FP64 Davidson solve of k-point 0 of the medium workload (256 bands, "
+                         "1e-8 Ry) after a warm-up solve, for kernel profiles, and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference "
                          "kernel that scales HBM byte counters) and exit")
@@ -336,6 +341,38 @@ def davidson_medium_section(nk: int):
     out["speedup_fp32_then_fp64_over_fp64_at_1e-8Ry"] = round(base / res["fp32_then_fp64_1e-8Ry"]["seconds"], 3)
     out["speedup_fp32_over_fp64_1e-6Ry_vs_1e-8Ry"] = round(base / res["fp32_1e-6Ry"]["seconds"], 3)
     out["fp64_stage_breakdown"] = stage
+    # the k-points are independent problems: solved side by side, one stream each
+    p64s, p32s, xs = [], [], []
+    for ik in range(nk):
+        p64, miller = build_problem(cell, ik, precision=_lib.PW_FP64, max_bands=nb)
+        p32, _ = build_problem(cell, ik, precision=_lib.PW_MIXED_FP32, max_bands=nb, miller=miller)
+        fixed_tuning(p64, "fp64")
+        fixed_tuning(p32, "fp32")
+        x0 = band_block(nb, p64.npw)
+        x0[:, :p64.npw] = torch.from_numpy(synth.psi_start(cell.seed, nb, p64.npw, ik)).cuda()
+        p64s.append(p64)
+        p32s.append(p32)
+        xs.append(x0)
+    kforms = {"fp64_kpoints_batched_1e-8Ry": dict(probs=p64s, tol=5e-9),
+              "fp32_then_fp64_kpoints_batched_1e-8Ry": dict(probs=p32s, tol=1e-5, refine=p64s, refine_tol=5e-9),
+              "fp32_kpoints_batched_1e-6Ry": dict(probs=p32s, tol=5e-7)}
+    for name, kw in kforms.items():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = _lib.batch_davidson_solve(kw["probs"], xs, tol=kw["tol"], nstreams=nk, refine=kw.get("refine"),
+                                       refine_tol=kw.get("refine_tol"))
+        torch.cuda.synchronize()
+        o = {"seconds": round(time.perf_counter() - t0, 3), "streams": nk,
+             "converged": all(r["converged"] for r in rs),
+             "iterations": int(sum(r["iterations"] for r in rs)),
+             "max_residual_Ry": float(2 * max(r["rho"].max() for r in rs)),
+             "max_abs_theta_minus_fp64_Ry": float(2 * np.abs(np.concatenate([r["theta"] for r in rs]) - ref).max()),
+             "max_abs_theta_minus_oracle_Ry": {f"k{ik}": float(2 * np.abs(rs[ik]["theta"] - gold[ik][:, 0]).max())
+                                               for ik in gold if ik < nk}}
+        o["speedup_over_fp64_one_after_another_1e-8Ry"] = round(base / o["seconds"], 3)
+        out[name] = o
+    for p in p64s + p32s:
+        p.close()
     return out
 
 
@@ -475,6 +512,50 @@ def learned_section(ncells: int):
     return out, net
 
 
+def lanczos_section(steps: int):
+    """Lanczos recursion on H (a second H*psi workload): 256 chains in
+    lockstep on k-point 0 of the medium workload, `steps` steps after a
+    warm-up.  Rate in chain-steps/s; the recursion kernel's HBM rate counts
+    4 vectors of 16 npw bytes per chain-step (q_n, H q_n and q_{n-1} read,
+    q_{n+1} written)."""
+    import torch
+    import synth
+    from paper_1709_10010_amd import _lib
+    from paper_1709_10010_amd.problems import band_block, build_problem
+    cell = synth.make_cell(2)
+    nch = cell.nbands
+    p, _ = build_problem(cell, 0, max_bands=nch)
+    fixed_tuning(p, "fp64")
+    v = band_block(nch, p.npw)
+    v[:, :p.npw] = torch.from_numpy(synth.psi_start(cell.seed, nch, p.npw, 0)).cuda()
+    lz = _lib.Lanczos(p, nch, steps + 4)
+    lz.start(v)
+    lz.run(4)
+    _lib.pw_profile_enable(p, True)
+    _lib.pw_profile_read(p, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lz.run(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = _lib.pw_profile_read(p, reset=True)
+    _lib.pw_profile_enable(p, False)
+    z = torch.tensor([0.1 + 0.05j, 0.5 + 0.05j], dtype=torch.complex128, device="cuda")
+    g = lz.resolvent(z)
+    torch.cuda.synchronize()
+    vec_ms, vec_n = st.get("vec", (0.0, 1))
+    out = {"workload": f"{nch} chains, k-point 0 of the medium workload (npw {p.npw}, 72^3, 576 projectors), "
+                       f"{steps} steps",
+           "chain_steps_per_s": round(nch * steps / dt, 1), "ms_per_step": round(dt * 1e3 / steps, 4),
+           "recursion_kernel": {"avg_ms": round(vec_ms / max(vec_n, 1), 4),
+                                "GB/s": round(4 * 16 * p.npw * nch / (vec_ms / max(vec_n, 1) * 1e-3) / 1e9, 1)},
+           "share_of_step": {k: round(v[0] / max(sum(x[0] for x in st.values()), 1e-9), 3) for k, v in st.items()},
+           "resolvent_finite": bool(torch.isfinite(torch.view_as_real(g)).all())}
+    lz.close()
+    p.close()
+    return out
+
+
 def davidson_cpu_baseline(dav):
     """Oracle FP64 Davidson on the config-1 cell (host cores)."""
     from oracle import davidson as odv
@@ -508,6 +589,22 @@ def main():
     import synth
     from paper_1709_10010_amd import _lib
     from paper_1709_10010_amd.problems import band_block, build_problem
+
+    if args.profile_davidson:
+        cell = synth.make_cell(2)
+        p, _ = build_problem(cell, 0, max_bands=cell.nbands)
+        fixed_tuning(p, "fp64")
+        x0 = band_block(cell.nbands, p.npw)
+        x0[:, :p.npw] = torch.from_numpy(synth.psi_start(cell.seed, cell.nbands, p.npw, 0)).cuda()
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = _lib.davidson_solve(p, x0, tol=5e-9)
+            torch.cuda.synchronize()
+            note(f"Davidson k-point 0 solve {rep}: {time.perf_counter() - t0:.4f} s, {r['iterations']} iterations")
+        print(json.dumps({"profile_davidson_seconds": round(time.perf_counter() - t0, 4),
+                          "iterations": r["iterations"], "converged": bool(r["converged"])}))
+        return
 
     prec = {"fp64": _lib.PW_FP64, "fp32": _lib.PW_MIXED_FP32, "bf16": _lib.PW_MIXED_BF16}[args.precision]
     cell = synth.make_cell(2)
@@ -673,6 +770,9 @@ def main():
         else:
             out["learned_preconditioner"] = lr
         note("learned preconditioner section done")
+    if not args.no_lanczos:
+        out["lanczos_recursion"] = lanczos_section(args.lanczos_steps)
+        note("Lanczos section done")
     if not args.no_batched:
         out["batched_ragged_cells"] = batched_section(args.batched_cells, max(3, args.steps // 2), args.streams,
                                                       learned_net=net)

@@ -113,6 +113,11 @@ typedef struct {
   const void *beta;    /* device complex128 [nproj][ld_beta]: beta_j(k+G), already
                           carrying the structure factor and normalisation */
   int64_t ld_beta;     /* >= npw */
+  const double *qij;   /* host, augmentation of the overlap in the layout of dij, or NULL
+                          for S = 1 (norm-conserving): S = 1 + sum_I sum_mn q_I,mn
+                          |beta_m^I><beta_n^I| (the -eps S of eq. pauli_ks); S must be
+                          positive definite and the projectors linearly independent on
+                          the sphere, else pw_problem_create returns PW_ERR_NUMERIC */
 } pw_problem_desc;
 
 /* Message for the calling thread's last non-OK status ("" if none). */
@@ -180,6 +185,16 @@ pw_status pw_hpsi(pw_problem *p, const void *psi, int64_t ld_psi, void *hpsi,
                   int64_t ld_hpsi, int64_t nbands, int32_t terms, void *stream);
 
 /*
+ * spsi[n] = S psi[n] = psi[n] + sum_ij beta_i q_ij <beta_j|psi[n]> for
+ * n < nbands (a copy of psi when the problem has no augmentation), FP64
+ * whatever the precision form.  psi, spsi: device complex128 band-major,
+ * distinct blocks, ld >= npw; 0 <= nbands <= max_bands.  No allocation, no
+ * host sync; uses the problem's workspace (projections).
+ */
+pw_status pw_spsi(pw_problem *p, const void *psi, int64_t ld_psi, void *spsi, int64_t ld_spsi,
+                  int64_t nbands, void *stream);
+
+/*
  * P[n][j] = <beta_j | psi_n> (device complex128 [nbands][nproj]), the
  * paper's p_ij scalar products, in the handle's precision form.
  */
@@ -225,7 +240,12 @@ pw_status pw_davidson_workspace_size(pw_problem *p, int64_t nbands, int64_t max_
  * the residual 2-norm target in Ha (|H x - theta x| < tol for every band).
  * All subspace work (H_s = V^H H V, Cholesky orthonormalisation, the
  * Hermitian eigensolve, Ritz vectors, residual norms) runs in FP64 on the
- * GPU whatever the problem's precision form.  workspace: device memory,
+ * GPU whatever the problem's precision form.  With augmentation (S != 1)
+ * the solve is of the pencil H x = theta S x: the state iterates y =
+ * S^{1/2} x with the operator S^{-1/2} H S^{-1/2} (S^{-1/2} is exact, from
+ * the projector span), so its space is S-orthonormal in x; residual norms
+ * are |S^{-1/2}(H x - theta S x)|, and pw_davidson_vectors returns the
+ * S-orthonormal x (snapshots stay in y).  workspace: device memory,
  * 256-byte aligned, of at least pw_davidson_workspace_size bytes, owned by
  * the caller and bound to the state until pw_davidson_destroy (null,
  * misaligned or too small: PW_ERR_INVALID before any device work).  The
@@ -465,6 +485,46 @@ pw_status pw_mlp_train_step(pw_mlp *net, const void *F, const void *R, const voi
  */
 pw_status pw_mlp_targets(pw_problem *p, const void *Xc, const int32_t *cluster, const void *Xit,
                          int64_t ld, int64_t nbands, void *D, void *work, void *stream);
+
+/*
+ * Lanczos recursion on H for many chains in lockstep, and the continued
+ * fraction of the resolvent (the paper's dynamic-perturbation section:
+ * g_v(w) = <v|(w - L)^{-1} v>, eq. resolvent, from the chain q_0 = 0,
+ * q_1 = v, alpha_n = <q_n|L q_n>, beta_{n+1} q_{n+1} = (L - alpha_n) q_n -
+ * beta_n q_{n-1}, |q_{n+1}| = 1, eqs. rec1 - rec4, as the continued fraction
+ * of the tridiagonal T_M, eqs. tridiagonal and continuedfraction), here
+ * with L = H of a problem.  Chain c starts from q_1 = v_c / |v_c|; beta_1 =
+ * |v_c| is kept, so g_c(z) = |v_c|^2 / (z - alpha_1 - beta_2^2 / (z - ...)).
+ * A chain ends at beta_{n+1} <= 1e-12 |H q_n| (an invariant subspace):
+ * beta_{n+1}, q_{n+1} and every later alpha, beta are zero.  One step is one
+ * pw_hpsi over the chains plus one kernel per chain; alpha and beta stay on
+ * the device, so pw_lanczos_run has no host synchronisation.  Three vectors
+ * per chain are kept, as the paper notes.
+ *   workspace: device, 256-byte aligned, pw_lanczos_workspace_size bytes
+ *              (3 nchains ld complex128, ld = npw rounded up to 64, and the
+ *              coefficients), owned by the caller, bound until destroy.
+ *   nchains    1 .. the problem's max_bands; max_steps >= 1.
+ *   start      v: device complex128 [nchains][ld_v], ld_v >= npw; resets
+ *              the chains (steps done = 0).
+ *   run        nsteps more steps (steps done + nsteps <= max_steps).
+ *   coefficients  device copies: alpha double [nchains][max_steps] (alpha_n
+ *              at [c][n-1]), beta double [nchains][max_steps + 1] (beta_1 =
+ *              |v_c| at [c][0], beta_{n+1} at [c][n]); entries past the
+ *              steps done are zero; *nsteps = steps done (host).
+ *   resolvent  g device complex128 [nchains][nz] at the points z (device
+ *              complex128 [nz]) from the steps done (at least one).
+ * The chain set uses the problem's workspace for H*psi: one stream at a
+ * time for both.
+ */
+typedef struct pw_lanczos pw_lanczos;
+pw_status pw_lanczos_workspace_size(pw_problem *p, int64_t nchains, int32_t max_steps, size_t *bytes);
+pw_status pw_lanczos_create(pw_problem *p, int64_t nchains, int32_t max_steps, void *workspace,
+                            size_t ws_bytes, pw_lanczos **out);
+pw_status pw_lanczos_destroy(pw_lanczos *l);
+pw_status pw_lanczos_start(pw_lanczos *l, const void *v, int64_t ld_v, void *stream);
+pw_status pw_lanczos_run(pw_lanczos *l, int32_t nsteps, void *stream);
+pw_status pw_lanczos_coefficients(pw_lanczos *l, double *alpha, double *beta, int32_t *nsteps, void *stream);
+pw_status pw_lanczos_resolvent(pw_lanczos *l, const void *z, int32_t nz, void *g, void *stream);
 
 /*
  * Stage timing (instrumentation, off by default).  When enabled, every

@@ -50,6 +50,7 @@ class _Desc(C.Structure):
         ("dij", C.POINTER(C.c_double)),
         ("beta", C.c_void_p),
         ("ld_beta", C.c_int64),
+        ("qij", C.POINTER(C.c_double)),
     ]
 
 
@@ -73,6 +74,7 @@ def _load():
         "pw_problem_info": (i32, [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]),
         "pw_hpsi": (i32, [vp, vp, i64, vp, i64, i64, i32, vp]),
         "pw_projections": (i32, [vp, vp, i64, vp, i64, vp]),
+        "pw_spsi": (i32, [vp, vp, i64, vp, i64, i64, vp]),
         "pw_precond": (i32, [vp, i32, vp, vp, vp, vp, i64, i64, vp, vp]),
         "pw_davidson_workspace_size": (i32, [vp, i64, i64, C.POINTER(C.c_size_t)]),
         "pw_davidson_create": (i32, [vp, i64, i64, f64, vp, C.c_size_t, vp, C.POINTER(vp)]),
@@ -114,6 +116,13 @@ def _load():
         "pw_problem_set_tuning": (i32, [vp, i32, i64, i32, i32]),
         "pw_eigh_workspace": (i32, [i32, C.POINTER(C.c_size_t)]),
         "pw_eigh": (i32, [vp, i64, i32, vp, vp, i64, vp, C.c_size_t, vp]),
+        "pw_lanczos_workspace_size": (i32, [vp, i64, i32, C.POINTER(C.c_size_t)]),
+        "pw_lanczos_create": (i32, [vp, i64, i32, vp, C.c_size_t, C.POINTER(vp)]),
+        "pw_lanczos_destroy": (i32, [vp]),
+        "pw_lanczos_start": (i32, [vp, vp, i64, vp]),
+        "pw_lanczos_run": (i32, [vp, i32, vp]),
+        "pw_lanczos_coefficients": (i32, [vp, vp, vp, C.POINTER(i32), vp]),
+        "pw_lanczos_resolvent": (i32, [vp, vp, i32, vp, vp]),
         "pw_profile_enable": (i32, [vp, i32]),
         "pw_profile_read": (i32, [vp, C.POINTER(f64), C.POINTER(i64), i32]),
     }
@@ -228,9 +237,10 @@ class Problem:
 
 
 def pw_problem_create(cell, kpt, ecut, nr, miller, vloc, beta, proj_offset, dij,
-                      precision=PW_FP64, max_bands=1, stream=None) -> Problem:
+                      precision=PW_FP64, max_bands=1, stream=None, qij=None) -> Problem:
     """Wrap pw_problem_create.  vloc: cuda float64 [N0][N1][N2]; beta: cuda complex128
-    [nproj][ld] (or None with nproj = 0); miller / proj_offset / dij: host arrays."""
+    [nproj][ld] (or None with nproj = 0); miller / proj_offset / dij / qij (overlap
+    augmentation in the layout of dij, None for S = 1): host arrays."""
     import torch
     miller = np.ascontiguousarray(miller, dtype=np.int32).reshape(-1, 3)
     d = _Desc()
@@ -258,6 +268,12 @@ def pw_problem_create(cell, kpt, ecut, nr, miller, vloc, beta, proj_offset, dij,
         d.beta = _dev_ptr(beta, torch.complex128, "beta")
         d.ld_beta = int(beta.stride(0)) if beta.shape[0] > 1 else int(beta.shape[1])
         keep += [po, dj, beta]
+        if qij is not None:
+            qj = np.ascontiguousarray(qij, dtype=np.float64)
+            if qj.shape != dj.shape:
+                raise ValueError("qij must have the layout of dij")
+            d.qij = qj.ctypes.data_as(C.POINTER(C.c_double))
+            keep.append(qj)
     nbytes = C.c_size_t(0)
     _check(LIB.pw_workspace_size(C.byref(d), int(max_bands), C.byref(nbytes)))
     ws = _workspace(nbytes.value, vloc_c.device)
@@ -274,6 +290,14 @@ def pw_hpsi(prob: Problem, psi, hpsi, terms: int = PW_TERM_ALL, stream=None) -> 
     if nbh < nb:
         raise ValueError("hpsi has fewer bands than psi")
     _check(LIB.pw_hpsi(prob.handle, ps, ldp, hs, ldh, nb, int(terms), _stream(stream)))
+
+
+def pw_spsi(prob: Problem, psi, spsi, stream=None) -> None:
+    ps, ldp, nb = _band_block(psi, "psi", prob.npw)
+    ss, lds, nbs = _band_block(spsi, "spsi", prob.npw)
+    if nbs < nb:
+        raise ValueError("spsi has fewer bands than psi")
+    _check(LIB.pw_spsi(prob.handle, ps, ldp, ss, lds, nb, _stream(stream)))
 
 
 def pw_projections(prob: Problem, psi, proj, stream=None) -> None:
@@ -774,3 +798,66 @@ def pw_eigh(A, stream=None):
                        _stream(stream)))
     return w, Zt.t()
 
+
+class Lanczos:
+    """Owner of a pw_lanczos chain set (Lanczos recursion on H, many chains in
+    lockstep) and of its workspace."""
+
+    def __init__(self, prob: Problem, nchains: int, max_steps: int):
+        nbytes = C.c_size_t(0)
+        _check(LIB.pw_lanczos_workspace_size(prob.handle, int(nchains), int(max_steps), C.byref(nbytes)))
+        self.workspace = _workspace(nbytes.value)
+        h = C.c_void_p()
+        _check(LIB.pw_lanczos_create(prob.handle, int(nchains), int(max_steps),
+                                     C.c_void_p(self.workspace.data_ptr()), nbytes.value, C.byref(h)))
+        self._h = h
+        self.prob = prob
+        self.nchains = int(nchains)
+        self.max_steps = int(max_steps)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise PwError(-1, "Lanczos chain set already destroyed")
+        return self._h
+
+    def start(self, v, stream=None) -> None:
+        vp_, ld, nb = _band_block(v, "v", self.prob.npw)
+        if nb < self.nchains:
+            raise ValueError("v has fewer rows than chains")
+        _check(LIB.pw_lanczos_start(self.handle, vp_, ld, _stream(stream)))
+
+    def run(self, nsteps: int, stream=None) -> None:
+        _check(LIB.pw_lanczos_run(self.handle, int(nsteps), _stream(stream)))
+
+    def coefficients(self, stream=None):
+        """(alpha [nchains][max_steps], beta [nchains][max_steps+1], steps done) as device tensors."""
+        import torch
+        a = torch.zeros((self.nchains, self.max_steps), dtype=torch.float64, device="cuda")
+        b = torch.zeros((self.nchains, self.max_steps + 1), dtype=torch.float64, device="cuda")
+        n = C.c_int32(0)
+        _check(LIB.pw_lanczos_coefficients(self.handle, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()),
+                                           C.byref(n), _stream(stream)))
+        return a, b, n.value
+
+    def resolvent(self, z, stream=None):
+        """g [nchains][nz] (device complex128) at the points z (device complex128 [nz])."""
+        import torch
+        zc = z.contiguous()
+        _dev_ptr(zc, torch.complex128, "z")
+        g = torch.zeros((self.nchains, zc.numel()), dtype=torch.complex128, device="cuda")
+        _check(LIB.pw_lanczos_resolvent(self.handle, C.c_void_p(zc.data_ptr()), int(zc.numel()),
+                                        C.c_void_p(g.data_ptr()), _stream(stream)))
+        return g
+
+    def close(self):
+        if self._h:
+            LIB.pw_lanczos_destroy(self._h)
+            self._h = None
+        self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -248,6 +248,7 @@ static void carve_problem(pw_problem *p, Carve &c) {
     }
   }
   p->d_sticks = c.take<char>((size_t)p->nr[2] * p->map.nst_pad * cb * p->band_chunk_max);
+  if (p->gen) carve_overlap(p, c);
   p->d_tn = c.take<double>(p->max_bands);
   p->d_rnorm = c.take<double>(p->max_bands);
   p->d_idx = c.take<int>(p->max_bands);
@@ -291,6 +292,7 @@ static int prepare_problem(const pw_problem_desc *d, int64_t max_bands, pw_probl
   p->nproj = d->nproj;
   p->natom = d->natom;
   p->max_bands = max_bands;
+  p->gen = d->qij != nullptr && d->nproj > 0;
   p->ldb = (d->npw + 63) / 64 * 64;
   recip(p->A, p->B);
   const int ts = std::max(1, std::min(64, env_int("PW_STICK_TILE", d->precision == PW_FP64 ? 16 : 32)));
@@ -485,6 +487,18 @@ pw_status pw_problem_create(const pw_problem_desc *d, int64_t max_bands, void *w
     if ((rc = upload(&p->d_pj_atom, pj)) != PW_OK) return fail(rc);
     if ((rc = upload(&p->d_proj_off, poff)) != PW_OK) return fail(rc);
     if ((rc = upload(&p->d_dij_off, doff)) != PW_OK) return fail(rc);
+    if (p->gen) {
+      std::vector<double> q(d->qij, d->qij + tot);
+      for (double x : q)
+        if (!std::isfinite(x)) {
+          set_error("pw_problem_create: qij holds a non-finite value");
+          return fail(PW_ERR_INVALID);
+        }
+      if ((rc = overlap_setup(p, q, poff, s)) != PW_OK) {
+        if (rc != PW_ERR_NUMERIC) set_error("pw_problem_create: overlap set-up failed");
+        return fail(rc);
+      }
+    }
   }
   {
     // band indices 0 .. max_bands-1 for the learned preconditioner of pw_precond

@@ -181,10 +181,19 @@ struct pw_problem {
   void *d_part = nullptr;      // split-K partial sums
   size_t part_bytes = 0;
   double *d_tn = nullptr;      // [max_bands] band kinetic energies (preconditioner)
-  float *d_mlp_s = nullptr;    // [max_bands * npw] learned scales (pw_precond with the MLP kind)
-  double *d_rnorm = nullptr;   // [max_bands] residual norms (same)
+  double *d_rnorm = nullptr;   // [max_bands] residual norms (pw_precond with the MLP kind)
   int *d_idx = nullptr;        // [max_bands] band indices 0 .. n-1 (same)
   int *d_bad = nullptr;        // [max_bands] per-band fallback flags (same)
+  // overlap S = 1 + sum q |beta><beta| when the caller gives augmentation
+  // (overlap.hip): S^{-1/2} = 1 + K diag(sfac) K^H
+  bool gen = false;
+  double *d_qij = nullptr;     // concatenated q blocks (the layout of d_dij)
+  double2 *d_K = nullptr;      // [nproj][ldb]
+  double *d_sfac = nullptr;    // [nproj]
+  double2 *d_ov_qb = nullptr;  // set-up scratch: Q_b [nproj][ldb]
+  double2 *d_ov_mat = nullptr; // set-up scratch: 5 nproj^2 complex
+  void *d_ov_eig = nullptr;    // set-up scratch: eigensolver workspace
+  int *d_ov_flag = nullptr;
 };
 
 namespace pw {
@@ -255,6 +264,13 @@ int mlp_precond_idx(const pw_mlp *net, pw_problem *p, const double *theta, const
                     const double *tn, hipStream_t s);
 int mlp_fallback(const int *bad, pw_problem *p, const double *tn, const int *idx, const double2 *R,
                  int64_t ld, double2 *T, int nu, hipStream_t s);
+// Overlap transform (overlap.hip): workspace regions, set-up from the
+// concatenated q blocks and the atoms' projector offsets, and
+// y = S^{-1/2} x for nb bands.
+void carve_overlap(pw_problem *p, Carve &c);
+int overlap_setup(pw_problem *p, const std::vector<double> &qblocks, const std::vector<int32_t> &poff,
+                  hipStream_t s);
+int sinvhalf(pw_problem *p, const void *x, int64_t ldx, void *y, int64_t ldy, int64_t nb, hipStream_t s);
 // Davidson state accessors for the batch scheduler (davidson.hip).
 pw_problem *dav_problem(const pw_davidson *d);
 int dav_nbands(const pw_davidson *d);

@@ -68,6 +68,7 @@ struct pw_davidson {
   // the caller's workspace (pw_davidson_workspace_size bytes); every device
   // buffer above points into it
   void *ws = nullptr;
+  double2 *U1 = nullptr, *U2 = nullptr;  // [nb][ld] each: S^{-1/2} x and H S^{-1/2} x (augmented problems)
   // pinned host mirrors
   double *h_theta = nullptr, *h_rho = nullptr, *h_lam = nullptr;
   double *h_acc = nullptr;  // eigensolver's off-diagonal and total mass, read once per sweep
@@ -140,6 +141,21 @@ void carve_dav(pw_davidson *d, Carve &c) {
   d->acc_ws = c.take<double>(128);
   d->part_bytes = (size_t)32 * lde * nb * sizeof(double2);
   d->part = c.take<char>(d->part_bytes);
+  if (d->p->gen) {
+    d->U1 = c.take<double2>(nb * blk);
+    d->U2 = c.take<double2>(nb * blk);
+  }
+}
+
+// The operator the state iterates with on n columns: H, or for an augmented
+// problem S^{-1/2} H S^{-1/2} (n <= nb).
+int dav_apply(pw_davidson *d, const double2 *src, double2 *dst, int n, hipStream_t s) {
+  pw_problem *p = d->p;
+  if (!p->gen) return pw_hpsi(p, src, d->ld, dst, d->ld, n, PW_TERM_ALL, s);
+  int rc = sinvhalf(p, src, d->ld, d->U1, d->ld, n, s);
+  if (rc == PW_OK) rc = pw_hpsi(p, d->U1, d->ld, d->U2, d->ld, n, PW_TERM_ALL, s);
+  if (rc == PW_OK) rc = sinvhalf(p, d->U2, d->ld, dst, d->ld, n, s);
+  return rc;
 }
 
 // sizes of a Davidson state from its arguments (shared by the size query and create)
@@ -415,7 +431,7 @@ pw_status pw_davidson_init(pw_davidson *d, const void *psi0, int64_t ld, void *s
   int nk = 0;
   DV_RC(ortho_block(d, 0, d->T, d->nb, d->V, &nk, s));
   PW_CHECK_ARG(nk == d->nb, PW_ERR_NUMERIC, "pw_davidson_init: start block is rank deficient");
-  DV_RC(pw_hpsi(d->p, d->V, d->ld, d->W, d->ld, d->nb, PW_TERM_ALL, s));
+  DV_RC(dav_apply(d, d->V, d->W, d->nb, s));
   DV_RC(cn(d, d->nb, d->nb, d->V, d->W, d->Hs, d->lde, s));
   DV_RC(hermitize(d->Hs, d->lde, 0, d->nb, s));
   d->m = d->nb;
@@ -586,7 +602,7 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
     return PW_ERR_NUMERIC;
   }
   // 7. H on the new vectors, bordered subspace matrix
-  DV_RC(pw_hpsi(d->p, Vn, d->ld, Wn, d->ld, nk, PW_TERM_ALL, s));
+  DV_RC(dav_apply(d, Vn, Wn, nk, s));
   d->n_hpsi += nk;
   DV_RC(cn(d, d->m + nk, nk, d->V, Wn, d->Hs + (size_t)d->m * d->lde, d->lde, s));
   DV_RC(hermitize(d->Hs, d->lde, d->m, d->m + nk, s));
@@ -598,6 +614,8 @@ pw_status pw_davidson_set_problem(pw_davidson *d, pw_problem *p, void *stream) {
   PW_CHECK_ARG(d && p, PW_ERR_INVALID, "pw_davidson_set_problem: null argument");
   PW_CHECK_ARG(p->npw == d->npw && p->max_bands >= d->nb, PW_ERR_INVALID,
                "pw_davidson_set_problem: problem must share npw and allow nbands bands");
+  PW_CHECK_ARG(p->gen == d->p->gen, PW_ERR_INVALID,
+               "pw_davidson_set_problem: both problems must have augmentation, or neither");
   d->p = p;
   if (!d->inited) return PW_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -605,8 +623,7 @@ pw_status pw_davidson_set_problem(pw_davidson *d, pw_problem *p, void *stream) {
   const char *where = "pw_davidson_set_problem: launch failed";
   for (int c0 = 0; c0 < d->m; c0 += d->nb) {
     const int nc = std::min(d->nb, d->m - c0);
-    DV_RC(pw_hpsi(p, d->V + (size_t)c0 * d->ld, d->ld, d->W + (size_t)c0 * d->ld, d->ld, nc,
-                  PW_TERM_ALL, s));
+    DV_RC(dav_apply(d, d->V + (size_t)c0 * d->ld, d->W + (size_t)c0 * d->ld, nc, s));
   }
   d->n_hpsi += d->m;
   DV_RC(cn(d, d->m, d->m, d->V, d->W, d->Hs, d->lde, s));
@@ -661,6 +678,12 @@ pw_status pw_davidson_snapshot(pw_davidson *d, void *x, void *r, double *theta, 
 
 pw_status pw_davidson_vectors(pw_davidson *d, void *x, int64_t ld, void *stream) {
   PW_CHECK_ARG(d && x && ld >= d->npw, PW_ERR_INVALID, "pw_davidson_vectors: bad argument");
+  if (d->p->gen) {
+    // x = S^{-1/2} y: the S-orthonormal eigenvectors of the pencil
+    const int rc = sinvhalf(d->p, d->X, d->ld, x, ld, d->nb, static_cast<hipStream_t>(stream));
+    if (rc != PW_OK) set_error("pw_davidson_vectors: launch failed");
+    return rc;
+  }
   PW_HIP(hipMemcpy2DAsync(x, ld * sizeof(double2), d->X, d->ld * sizeof(double2),
                           d->npw * sizeof(double2), d->nb, hipMemcpyDeviceToDevice,
                           static_cast<hipStream_t>(stream)));

@@ -42,7 +42,8 @@ def build_problem(cell, ik: int = 0, precision: int = _lib.PW_FP64, max_bands: i
     beta[:, :npw] = torch.from_numpy(beta_h).to(device)
     prob = _lib.pw_problem_create(cell.A, kf, cell.ecut_ha, cell.nr, miller, v, beta,
                                   cell.proj_offset, cell.dij_concat(), precision=precision,
-                                  max_bands=max_bands or cell.nbands, stream=stream)
+                                  max_bands=max_bands or cell.nbands, stream=stream,
+                                  qij=cell.qij_concat())
     return prob, miller
 
 

@@ -4,9 +4,10 @@ alone (dense diagonalisation of the discrete Hamiltonian of eq. pauli_ks on
 the sphere basis; sphere sizes from the cutoff inequality; the oracle's
 block Davidson at the medium workload's full size).
 
-    python tests/golden/make_golden.py               # everything (~15 min)
+    python tests/golden/make_golden.py               # everything (~20 min)
     python tests/golden/make_golden.py --quick       # without the Davidson goldens
     python tests/golden/make_golden.py --config4     # only the two ragged-batch cells
+    python tests/golden/make_golden.py --augmented   # only the medium workload with S != 1
 
 Regression fixtures: tests/test_golden.py recomputes them with the oracle,
 and the GPU tests compare the library against them.
@@ -78,7 +79,29 @@ def davidson_config4(index):
             f.write(f"{t:.17e} {rho:.3e}\n")
 
 
+def davidson_config2_augmented(ik):
+    """Oracle S-orthonormal block Davidson for H x = eps S x on the medium
+    workload with overlap augmentation (synth.with_augmentation), k-point ik,
+    all 256 bands, to |H x - theta S x| < 5e-9 Ha."""
+    from oracle import davidson as odv
+    c = synth.with_augmentation(synth.make_cell(2))
+    po = ham.problem_from_cell(c, ik)
+    r = odv.davidson_generalized(po, synth.psi_start(c.seed, c.nbands, po.npw, ik), c.nbands, 5e-9)
+    assert r["converged"], "oracle generalized Davidson did not converge"
+    fname = f"config2aug_k{ik}_davidson256_Ha.txt"
+    with open(os.path.join(HERE, fname), "w") as f:
+        f.write(f"# {c.name} k-point {ik}: npw {po.npw}, grid {c.nr[0]}^3, {c.nbands} bands, overlap "
+                f"augmentation; oracle S-orthonormal block Davidson to |Hx - theta Sx| < 5e-9 Ha "
+                f"({r['iterations']} iterations); columns: theta (Ha), residual 2-norm (Ha); "
+                f"written by make_golden.py (oracle only)\n")
+        for t, rho in zip(r["theta"], r["rho"]):
+            f.write(f"{t:.17e} {rho:.3e}\n")
+
+
 def main():
+    if "--augmented" in sys.argv:
+        davidson_config2_augmented(0)
+        return
     if "--config4" in sys.argv:
         for index in (10, 19):
             davidson_config4(index)
@@ -88,6 +111,7 @@ def main():
             davidson_config2(ik)
         for index in (10, 19):
             davidson_config4(index)
+        davidson_config2_augmented(0)
     for cfg, nlow, fname in ((0, 8, "tiny_cell_lowest8_Ha.txt"), (1, 16, "config1_lowest16_Ha.txt")):
         c, po, w = eig_fixture(cfg, nlow)
         with open(os.path.join(HERE, fname), "w") as f:

@@ -29,9 +29,10 @@ def problems(cell, ik=0, precision=0, max_bands=None, miller=None, ld_pad=64):
     if po.nproj:
         beta[:, :npw] = torch.from_numpy(po.beta).cuda()
     dij = np.concatenate([d.reshape(-1) for d in po.dij]) if po.dij else np.zeros(0)
+    qij = np.concatenate([q.reshape(-1) for q in po.qij]) if po.qij is not None else None
     pl = _lib.pw_problem_create(po.A, po.kfrac, cell.ecut_ha, po.nr, po.miller, v,
                                 beta if po.nproj else None, po.proj_offset, dij,
-                                precision=precision, max_bands=max_bands or cell.nbands)
+                                precision=precision, max_bands=max_bands or cell.nbands, qij=qij)
     return po, pl
 
 
