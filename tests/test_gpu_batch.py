@@ -202,3 +202,32 @@ def test_batched_davidson_lockstep_steps(lib):
         w, _ = ham.eigh_lowest(po, d.nbands)
         assert np.abs(r["theta"] - w).max() < 5e-9
     b.close()
+
+
+def test_ragged_cells_that_stalled_under_the_targeted_stop_test(lib):
+    """Regression: with the eigensolver stop test restricted to the wanted
+    pairs, the FP32-then-FP64 solve of ragged cell 55 stalled at 1.4e-6 Ha and
+    the learned-preconditioner solve of cell 59 diverged.  With every pair
+    counted (the default) both converge, to the plain FP64 eigenvalues."""
+    import os
+    import torch
+    from paper_1709_10010_amd import learned
+    from paper_1709_10010_amd.problems import band_block, build_problem
+    net = learned.load(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                    "paper_1709_10010_amd", "weights", "precond_mlp.npz"))
+    for i, form in ((55, "refine"), (59, "learned")):
+        c = synth.make_cell(4, i)
+        p64, m = build_problem(c, 0, max_bands=c.nbands)
+        p32, _ = build_problem(c, 0, precision=1, max_bands=c.nbands, miller=m)
+        x = band_block(c.nbands, p64.npw)
+        x[:, :p64.npw] = torch.from_numpy(synth.psi_start(c.seed, c.nbands, p64.npw)).cuda()
+        ref = lib.davidson_solve(p64, x, tol=5e-9)
+        if form == "refine":
+            r = lib.davidson_solve(p32, x, tol=1e-5, refine=p64, refine_tol=5e-9)
+            bound = r["rho"] + ref["rho"]
+        else:
+            r = lib.davidson_solve(p32, x, tol=5e-7, precond=2, net=net, max_iter=300)
+            bound = 1e-6            # FP32 form at 5e-7 Ha against FP64
+        d = np.abs(r["theta"] - ref["theta"])
+        log(f"cell {i} ({form}): iterations {r['iterations']}, max |theta - fp64| {d.max():.2e}")
+        assert r["converged"] and np.all(d <= bound + 1e-12)
