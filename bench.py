@@ -38,15 +38,15 @@ PEAK_VALU_TFLOPS = {"f64": 78.6, "f32": 157.3}
 
 # launch choices of the headline step per precision form: (plane_group,
 # band_chunk, ksplit, plane_kernel); 0 = PW_PLANE_REGISTER
-PINNED = {"fp64": (4, 128, 0, 0), "fp32": (4, 128, 0, 0), "bf16": (4, 128, 0, 0)}
+PINNED = {"fp64": (4, 256, 0, 0), "fp32": (2, 256, 0, 0), "bf16": (2, 256, 0, 0)}
 
 # HBM bytes per launch measured with rocprofv3 (FETCH_SIZE x 2.0 + WRITE_SIZE
 # x 1.0, factors from a plain device copy); valid only for the kernel source
 # and launch choices they were taken with
 MEASURED_TRAFFIC = {
-    "plane": {"source": "paper_1709_10010_amd/csrc/fft.hip", "sha256_16": "163e128b82b0b0ed",
-              "precision": 0, "band_chunk": 128, "plane_group": 4, "plane_kernel": 0,
-              "bytes_per_launch": 549825266.4},
+    "plane": {"source": "paper_1709_10010_amd/csrc/fft.hip", "sha256_16": "e8dbfe9714bb74b1",
+              "precision": 0, "band_chunk": 256, "plane_group": 4, "plane_kernel": 0,
+              "bytes_per_launch": 566696565.5},
 }
 
 

@@ -111,6 +111,12 @@ static int build_stick_map(pw_problem *p, const int32_t *miller, int ts) {
   sm.stick_cpos.resize(sm.nst);
   for (int s = 0; s < sm.nst; ++s)
     sm.stick_cpos[s] = sm.xslot[sm.stick_xy[s] / n1] * sm.ls + sm.stick_xy[s] % n1;
+  sm.stick_cy.clear();
+  if (sm.nst <= 32767) {
+    sm.stick_cy.assign((size_t)sm.nx * n1, -1);
+    for (int s = 0; s < sm.nst; ++s)
+      sm.stick_cy[(size_t)sm.xslot[sm.stick_xy[s] / n1] * n1 + sm.stick_xy[s] % n1] = (int16_t)s;
+  }
   // entries grouped by tile, then stick, then z
   std::vector<int64_t> key(npw);
   std::vector<int32_t> order(npw);
@@ -220,7 +226,7 @@ static void free_problem(pw_problem *p) {
   // the workspace regions belong to the caller
   void *bufs[] = {p->d_gidx,  p->d_gpos,       p->d_tile_ptr, p->d_stick_xy, p->d_xlist,
                   p->d_xslot, p->d_stick_cpos, p->d_kin,      p->d_tw,       p->d_dij,
-                  p->d_pj_atom, p->d_proj_off, p->d_dij_off};
+                  p->d_pj_atom, p->d_proj_off, p->d_dij_off, p->d_stick_cy};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -420,6 +426,7 @@ pw_status pw_problem_create(const pw_problem_desc *d, int64_t max_bands, void *w
   if ((rc = upload(&p->d_xlist, sm.xlist)) != PW_OK) return fail(rc);
   if ((rc = upload(&p->d_xslot, sm.xslot)) != PW_OK) return fail(rc);
   if ((rc = upload(&p->d_stick_cpos, sm.stick_cpos)) != PW_OK) return fail(rc);
+  if ((rc = upload(&p->d_stick_cy, sm.stick_cy)) != PW_OK) return fail(rc);
 
   // twiddles (x, y, z back to back) in the FFT precision
   std::vector<unsigned char> tw;
@@ -535,6 +542,7 @@ pw_status pw_problem_create(const pw_problem_desc *d, int64_t max_bands, void *w
   f.xlist = p->d_xlist;
   f.xslot = p->d_xslot;
   f.stick_cpos = p->d_stick_cpos;
+  f.stick_cy = p->d_stick_cy;
   f.tw0 = static_cast<unsigned char *>(p->d_tw) + off[0];
   f.tw1 = static_cast<unsigned char *>(p->d_tw) + off[1];
   f.tw2 = static_cast<unsigned char *>(p->d_tw) + off[2];

@@ -88,6 +88,9 @@ struct StickMap {
   int ls = 0;
   std::vector<int32_t> xslot;      // [N0]
   std::vector<int32_t> stick_cpos; // [nst]
+  // stick index of each (slot, y) of the compact plane, -1 where there is
+  // none: [nx][N1], kept when every index fits 16 bits (else empty)
+  std::vector<int16_t> stick_cy;
 };
 
 // Device-side view passed to the FFT launchers.
@@ -98,6 +101,7 @@ struct FFTDev {
   const int32_t *gidx, *gpos, *tile_ptr, *stick_xy, *xlist;
   int g_linear;  // gidx is the identity (the z passes then read and write G in order)
   const int32_t *xslot, *stick_cpos;  // compact plane layout (see StickMap)
+  const int16_t *stick_cy;            // [nx][N1] stick of (slot, y) or -1; null if unavailable
   const void *tw0, *tw1, *tw2;  // twiddle tables in the FFT precision
   const void *vplanes;          // [N2][N0][N1] V / (N0 N1 N2) in the FFT precision
   const double *kin;            // [npw]
@@ -159,6 +163,7 @@ struct pw_problem {
   int32_t *d_gidx = nullptr, *d_gpos = nullptr, *d_tile_ptr = nullptr;
   int32_t *d_stick_xy = nullptr, *d_xlist = nullptr;
   int32_t *d_xslot = nullptr, *d_stick_cpos = nullptr;
+  int16_t *d_stick_cy = nullptr;
   double *d_kin = nullptr;
   void *d_tw = nullptr;        // three twiddle tables back to back
   double *d_dij = nullptr;     // concatenated blocks

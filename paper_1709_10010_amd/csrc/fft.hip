@@ -753,7 +753,7 @@ template <int L> __device__ __forceinline__ int rev_lane(int q) {
 template <typename V, int L, int N, bool INV>
 __device__ __forceinline__ void group_fft_dit(V *e, int q, const V *tw) {
   constexpr int M = N / L;
-  reg_fft<V, M, INV, L>(e, tw);
+  reg_fft<V, M, INV, 0>(e, tw);
   if constexpr (L == 4) {
     level_twiddle<V, N, M, 1, 2 * M, -1, INV>(e, q, tw);
     level_join<V, M, 1>(e, q);
@@ -778,7 +778,7 @@ __device__ __forceinline__ void group_fft_dif(V *e, int q, const V *tw) {
     level_join<V, M, 0>(e, q);
     level_twiddle<V, N, M, 0, 2 * M, -1, INV>(e, q, tw);
   }
-  reg_fft<V, M, INV, L>(e, tw);
+  reg_fft<V, M, INV, 0>(e, tw);
 }
 
 // Exchange of halves (M = N / 4 even).  The four lanes of a line are
@@ -856,7 +856,7 @@ template <int M> constexpr int halves_off(int k) { return k < M / 2 ? k : k + 3 
 template <typename V, int N, bool INV>
 __device__ __forceinline__ void group_fft_dit_h(V *e, int q, const V *tw) {
   constexpr int M = N / 4;
-  reg_fft<V, M, INV, 4>(e, tw);
+  reg_fft<V, M, INV, 0>(e, tw);
   level_halves<V, M, 1, 2, INV, true>(e, tw + (q >> 1) * M);
   level_halves<V, M, 0, 1, INV, true>(e, tw + halves_base<M>(q));
 }
@@ -866,7 +866,7 @@ __device__ __forceinline__ void group_fft_dif_h(V *e, int q, const V *tw) {
   constexpr int M = N / 4;
   level_halves<V, M, 0, 1, INV, false>(e, tw + halves_base<M>(q));
   level_halves<V, M, 1, 2, INV, false>(e, tw + (q >> 1) * M);
-  reg_fft<V, M, INV, 4>(e, tw);
+  reg_fft<V, M, INV, 0>(e, tw);
 }
 
 // hides the values from the optimiser: twiddle reads and lane-dependent
@@ -982,6 +982,121 @@ void k_plane_r(FFTDev f, cpx_t<T> *__restrict__ sticks, int nb, int group) {
     }
     __syncthreads();
     for (int s = tid; s < f.nst; s += NTHR) col[s] = pl[f.stick_cpos[s]];
+    __syncthreads();
+  }
+}
+
+// Plane pass with register FFTs and direct stick I/O, pipelined over the
+// bands of the group.  Same line layout as k_plane_r with exchange of halves
+// (four lanes l + 16 q per line, N / 4 even), but the stick values never
+// pass through an LDS scatter or gather: the inverse y transform of a column
+// reads its sticks straight from the stick buffer (the (slot, y) -> stick
+// table sits in LDS; positions without a stick read zero) and the forward y
+// transform writes its outputs straight back.  A column is owned by the same
+// lane group in both y transforms, so the forward transform of band b and
+// the inverse transform of band b + 1 share one phase: the group reads the
+// column of band b into registers before it writes the column of band b + 1
+// over it, and the LDS operations of one wave execute in issue order.  Per
+// band: two barriers (after the y phase, after the row phase) instead of
+// six.  LDS: twiddles, the compact plane with one zero column, x -> slot,
+// and the (slot, y) table.
+template <typename T, int N, int NTHR>
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 4)))
+void k_plane_p(FFTDev f, cpx_t<T> *__restrict__ sticks, int nb, int group) {
+  using V = cpx_t<T>;
+  constexpr int L = 4, M = N / L, LS = N | 1, NL = NTHR / L;
+  static_assert(N % 4 == 0 && M % 2 == 0 && NTHR % 64 == 0, "exchange of halves: N / 4 even, whole waves");
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nx = f.nx;
+  V *tw = reinterpret_cast<V *>(smem);
+  V *pl = tw + N;
+  int *xs = reinterpret_cast<int *>(pl + (nx + 1) * LS);
+  int16_t *cy = reinterpret_cast<int16_t *>(xs + N);
+  const int z = blockIdx.x % N;
+  const int g = blockIdx.x / N;
+  const int tid = threadIdx.x;
+  const int line = (tid >> 6) * 16 + (tid & 15);
+  const int q = (tid >> 4) & 3;
+  const int xq = halves_base<M>(q);
+  const int b0 = g * group;
+  const int b1 = min(b0 + group, nb);
+  for (int i = tid; i < N; i += NTHR) {
+    xs[i] = f.xslot[i];
+    tw[i] = static_cast<const V *>(f.tw0)[i];
+    pl[nx * LS + i] = V{0, 0};
+  }
+  for (int i = tid; i < nx * N; i += NTHR) cy[i] = f.stick_cy[i];
+  __syncthreads();
+  const T *vp = static_cast<const T *>(f.vplanes) + (int64_t)z * N * N;
+  const int64_t bstride = (int64_t)N * f.nst_pad;
+  V *colz = sticks + (int64_t)z * f.nst_pad;
+
+  // inverse y transform of column c of band b: sticks -> LDS column
+  auto col_inv = [&](int b, int c) {
+    const V *src = colz + (int64_t)b * bstride;
+    const int16_t *cyc = cy + c * N;
+    V e[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const int s = cyc[L * j + q];
+      e[j] = s >= 0 ? src[s] : V{0, 0};
+    }
+    int zero = 0, qo = q;
+    opaque(zero, qo);
+    group_fft_dit_h<V, N, true>(e, qo, tw + zero);
+    V *p = pl + c * LS;
+#pragma unroll
+    for (int k = 0; k < M; ++k) p[xq + halves_off<M>(k)] = e[k];
+  };
+
+  if (b0 < b1)
+    for (int c = line; c < nx; c += NL) col_inv(b0, c);
+  __syncthreads();
+  for (int b = b0; b < b1; ++b) {
+    for (int y = line; y < N; y += NL) {
+      V e[M];
+      int zero = 0, qo = q;
+      opaque(zero, qo);
+#pragma unroll
+      for (int j = 0; j < M; ++j) e[j] = pl[xs[L * j + q] * LS + y];
+      group_fft_dit_h<V, N, true>(e, qo, tw + zero);
+      int vo = xq * N + y, xo = q;
+      opaque(vo, xo);
+      const T *vr = vp + vo;
+#pragma unroll
+      for (int k = 0; k < M; ++k) e[k] = c_scale(e[k], vr[halves_off<M>(k) * N]);
+      group_fft_dif_h<V, N, false>(e, qo, tw + zero);
+      opaque(xo, zero);
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const int sl = xs[L * k + xo];
+        if (sl < nx) pl[sl * LS + y] = e[k];
+      }
+    }
+    __syncthreads();
+    const bool next = b + 1 < b1;
+    V *dst = colz + (int64_t)b * bstride;
+    for (int c = line; c < nx; c += NL) {
+      {
+        V e[M];
+        const V *p = pl + c * LS;
+        int zero = 0, qo = q;
+        opaque(zero, qo);
+#pragma unroll
+        for (int j = 0; j < M; ++j) e[j] = p[xq + halves_off<M>(j)];
+        group_fft_dif_h<V, N, false>(e, qo, tw + zero);
+        const int16_t *cyc = cy + c * N;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          const int s = cyc[L * k + q];
+          if (s >= 0) dst[s] = e[k];
+        }
+      }
+      // every lane of the group has read the column of band b before any
+      // lane writes band b + 1 over it
+      wave_sync();
+      if (next) col_inv(b + 1, c);
+    }
     __syncthreads();
   }
 }
@@ -1159,12 +1274,28 @@ static bool plane_halves() {
 #ifndef PW_PLANE_R_THREADS
 #define PW_PLANE_R_THREADS 256
 #endif
+// the pipelined direct-I/O form of the exchange-of-halves kernel;
+// PW_PLANE_PIPE=0 keeps the scatter / gather form
+static bool plane_pipe() {
+  static const int v = env_switch("PW_PLANE_PIPE", 1);
+  return v != 0;
+}
 template <typename T, int N>
 static int plane_r(const FFTDev &f, void *sticks, int nb, int group, int blocks, hipStream_t s) {
   using V = cpx_t<T>;
   constexpr int L = (N % 4 == 0) ? 4 : 2;
   constexpr int NT = PW_PLANE_R_THREADS;
   constexpr bool xh_ok = L == 4 && (N / 4) % 2 == 0;
+  if constexpr (xh_ok) {
+    if (plane_halves() && plane_pipe() && f.stick_cy) {
+      const size_t lds = sizeof(V) * ((size_t)(f.nx + 1) * (N | 1) + N) + sizeof(int) * N +
+                         sizeof(int16_t) * (size_t)f.nx * N;
+      auto k = k_plane_p<T, N, NT>;
+      if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
+      hipLaunchKernelGGL(k, dim3(blocks), dim3(NT), lds, s, f, static_cast<V *>(sticks), nb, group);
+      return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+    }
+  }
   const size_t lds = sizeof(V) * ((size_t)(f.nx + 1) * (N | 1) + N) + sizeof(int) * N;
   auto k = (xh_ok && plane_halves()) ? k_plane_r<T, N, L, NT, xh_ok> : k_plane_r<T, N, L, NT, false>;
   if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;

@@ -11,7 +11,8 @@ runs in a child process:
     Jacobi round, unblocked Cholesky and triangular inverse, two Gram-Schmidt
     passes in the first orthonormalisation round, the stop test over the pairs
     that touch the wanted diagonal entries,
-    no active-space restart) and, in a second child, the FFT and
+    no active-space restart, the register plane kernel's scatter / gather
+    form instead of its pipelined direct-I/O form) and, in a second child, the FFT and
     orthonormalisation switches (runtime FFT plans at compile-time sizes, a
     non-default stick tile, always two orthonormalisation rounds, a tighter
     eigensolver stop level): H on the tiny cell at 48^3 and 72^3 (1e-12),
@@ -108,7 +109,7 @@ print("RESULT " + json.dumps(out), flush=True)
 
 VARIANT_SETS = [
     {"PW_BJ_CROSS": "0", "PW_CHOL_IMPL": "1", "PW_DAV_GS_FIRST": "2", "PW_EIG_WANTED": "1",
-     "PW_DAV_ACT_MUL": "0"},
+     "PW_DAV_ACT_MUL": "0", "PW_PLANE_PIPE": "0"},
     {"PW_FFT_GENERIC": "1", "PW_STICK_TILE": "8", "PW_DAV_ORTHO_SKIP": "0", "PW_DAV_OFF_FACTOR": "1"},
 ]
 
