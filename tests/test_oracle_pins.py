@@ -547,3 +547,106 @@ def test_generalized_davidson_without_augmentation_is_the_standard_one():
     r1 = dv.davidson_generalized(po, synth.psi_start(c.seed, 8, po.npw), 8, 1e-10)
     r2 = dv.davidson(po, synth.psi_start(c.seed, 8, po.npw), 8, 1e-10)
     assert np.abs(r1["theta"] - r2["theta"]).max() < 1e-10
+
+
+# ---------------------------------------------------------------- SCF around the solver
+from oracle import scf as sc  # noqa: E402
+
+
+def _skewed_cell():
+    # a non-orthogonal cell, so that a slip in the reciprocal metric shows
+    return np.array([[7.0, 0.0, 0.0], [1.5, 6.0, 0.0], [0.7, -0.9, 8.0]])
+
+
+def test_density_integrates_to_the_occupations_and_matches_direct_sums():
+    c = synth.make_cell(0)
+    po = ham.problem_from_cell(c)
+    rng = np.random.default_rng(41)
+    X = np.linalg.qr(_rand_c(rng, (po.npw, 3)))[0].T           # orthonormal bands [3][npw]
+    f = np.array([2.0, 0.7, 0.05])
+    n = sc.density(po, X, f)
+    omega = abs(np.linalg.det(po.A))
+    assert abs(n.sum() * omega / n.size - f.sum()) < 1e-12 * f.sum()
+    # n at three grid points from the plane-wave sums written out
+    for j in [(0, 0, 0), (1, 4, 2), (8, 3, 7)]:
+        ph = np.exp(2j * np.pi * sum(po.miller[:, i] * j[i] / po.nr[i] for i in range(3)))
+        val = sum(fb * abs(np.sum(X[b] * ph)) ** 2 for b, fb in enumerate(f)) / omega
+        assert abs(n[j] - val) < 1e-12 * val
+
+
+def test_hartree_of_cosine_densities_closed_form():
+    # n(r) = n0 + a1 cos(G1.r) + a2 sin(G2.r): V_H = 4 pi (a1 cos(G1.r)/|G1|^2
+    # + a2 sin(G2.r)/|G2|^2), the constant dropped; E_H = pi Omega (a1^2/|G1|^2
+    # + a2^2/|G2|^2)
+    A = _skewed_cell()
+    nr = (9, 10, 12)
+    B = gs.reciprocal(A)
+    m1, m2 = np.array([1, 0, -2]), np.array([0, 3, 1])
+    G1, G2 = m1 @ B, m2 @ B
+    j = np.stack(np.meshgrid(*[np.arange(x) for x in nr], indexing="ij"), axis=-1)
+    ph1 = 2 * np.pi * (j / np.array(nr)) @ m1
+    ph2 = 2 * np.pi * (j / np.array(nr)) @ m2
+    a1, a2, n0 = 0.3, -0.11, 0.9
+    n = n0 + a1 * np.cos(ph1) + a2 * np.sin(ph2)
+    vh, eh = sc.hartree(n, A)
+    want = 4 * np.pi * (a1 * np.cos(ph1) / (G1 @ G1) + a2 * np.sin(ph2) / (G2 @ G2))
+    assert np.abs(vh - want).max() < 1e-12 * np.abs(want).max()
+    omega = abs(np.linalg.det(A))
+    assert abs(eh - np.pi * omega * (a1 ** 2 / (G1 @ G1) + a2 ** 2 / (G2 @ G2))) < 1e-12 * eh
+    # and E_H is half of int V_H n
+    assert abs(eh - 0.5 * np.sum(vh * n) * omega / n.size) < 1e-12 * eh
+
+
+def test_lda_exchange_uniform_gas_and_potential_is_the_derivative():
+    # the uniform gas: eps_x = -0.458165293 / r_s Ha, r_s = (3 / (4 pi n))^{1/3}
+    n = np.array([1e-4, 0.01, 0.3, 2.0])
+    ex, vx = sc.lda_exchange(n)
+    rs = np.cbrt(3.0 / (4.0 * np.pi * n))
+    assert np.allclose(ex, -0.458165293283143 / rs, rtol=1e-11)
+    # v_x = d(n eps_x)/dn by central differences
+    h = 1e-6 * n
+    ep, _ = sc.lda_exchange(n + h)
+    em, _ = sc.lda_exchange(n - h)
+    fd = ((n + h) * ep - (n - h) * em) / (2 * h)
+    assert np.allclose(vx, fd, rtol=1e-8)
+    z = sc.lda_exchange(np.array([0.0, -1e-9]))
+    assert np.all(z[0] == 0) and np.all(z[1] == 0)
+
+
+def test_fermi_occupations_count_symmetry_and_limit():
+    # two levels, two electrons: mu midway by symmetry, f1 + f2 = 2
+    f, mu, s = sc.fermi_occupations([np.array([-0.3, 0.1])], [1.0], 2.0, 0.05)
+    assert abs(mu + 0.1) < 1e-12 and abs(f[0].sum() - 2.0) < 1e-12
+    g = 1.0 / (1.0 + math.exp(-0.2 / 0.05))
+    assert abs(f[0][0] - 2 * g) < 1e-12
+    assert abs(s - (-2.0 * 2 * (g * math.log(g) + (1 - g) * math.log(1 - g)))) < 1e-12
+    # several k-points with weights: the weighted count is the electron number
+    rng = np.random.default_rng(5)
+    eps = [np.sort(rng.uniform(-1, 1, 12)) for _ in range(3)]
+    w = np.array([0.5, 0.25, 0.25])
+    f, mu, _ = sc.fermi_occupations(eps, w, 9.0, 0.02)
+    assert abs(sum(wk * fk.sum() for wk, fk in zip(w, f)) - 9.0) < 1e-10
+    # a tiny width gives the integer filling
+    f, mu, _ = sc.fermi_occupations([np.array([-1.0, -0.5, 0.2, 0.9])], [1.0], 4.0, 1e-4)
+    assert np.allclose(f[0], [2, 2, 0, 0], atol=1e-12) and -0.5 < mu < 0.2
+
+
+def test_scf_reaches_a_fixed_point_of_the_density():
+    c = synth.make_cell(0)
+    po = ham.problem_from_cell(c)
+    vion = synth.vloc_on_grid(c)
+    r = sc.scf([po], [1.0], vion, nel=4.0, nbands=8, sigma=0.02, alpha=0.5, tol=1e-10, max_iter=80)
+    assert r["converged"]
+    # the potential of the returned input density reproduces it
+    v, e = sc.potential(vion, r["n_in"], po.A)
+    po.vloc = v
+    w, X = ham.eigh_lowest(po, 8)
+    f, mu, _ = sc.fermi_occupations([w], [1.0], 4.0, 0.02)
+    n = sc.density(po, X, f[0])
+    omega = abs(np.linalg.det(po.A))
+    assert np.sum(np.abs(n - r["n_in"])) * omega / n.size / 4.0 < 1e-9
+    assert abs(np.sum(n) * omega / n.size - 4.0) < 1e-10
+    assert np.allclose(w, r["eigenvalues"][0], atol=1e-9)
+    # the bare first step has no Hartree or exchange term: zero interaction energies
+    r0 = sc.scf([po], [1.0], vion, nel=4.0, nbands=8, sigma=0.02, alpha=0.5, tol=1e-10, max_iter=0)
+    assert r0["energies"]["hartree"] == 0.0 and not r0["history"]
