@@ -15,14 +15,18 @@ changing.  On the scalar, spin-unpolarised path, in Hartree atomic units:
             compensating background of the ions)
   V_x(r)  = -(3 n(r) / pi)^{1/3}   (local-density exchange of the uniform gas)
   V_eff   = V_ion + V_H + V_x
-  mixing  : n_in <- n_in + alpha (n_out - n_in)   (linear)
+  mixing  : n_in <- n_in + alpha (n_out - n_in)   (linear), or with the Kerker
+            weight on each Fourier component of the residual:
+            n_in(G) <- n_in(G) + alpha G^2 / (G^2 + q0^2) (n_out - n_in)(G)
+            (alpha alone at G = 0), which damps the long-wavelength charge
+            oscillations linear mixing sets off in large cells
 
 Readings where the paper is silent: exchange-only local-density functional;
 Fermi-Dirac occupations f_nk = 2 / (1 + exp((eps_nk - mu) / sigma)) with the
 chemical potential mu fixed by sum_k w_k sum_n f_nk = N_el (bisection; with
 integer occupations the synthetic cells' near-degenerate levels swap places
 from one step to the next and the loop never settles); linear mixing of the
-density; the first step solves with V_ion alone and its output density is
+density, Kerker-weighted when q0 > 0; the first step solves with V_ion alone and its output density is
 the first input density; convergence when int |n_out - n_in| dr / N_el falls
 below the tolerance.  The energy reported is the Harris-Foulkes form at the
 input density, E = sum f eps - E_H + E_x - int v_x n, and the free energy
@@ -131,12 +135,18 @@ def fermi_occupations(eps, kweights, nel: float, sigma: float):
     return f, mu, ent
 
 
-def mix(n_in: np.ndarray, n_out: np.ndarray, alpha: float) -> np.ndarray:
-    return n_in + alpha * (n_out - n_in)
+def mix(n_in: np.ndarray, n_out: np.ndarray, alpha: float, q0: float = 0.0, A=None) -> np.ndarray:
+    """Next input density: linear (q0 = 0) or Kerker-weighted (q0 > 0, cell A)."""
+    if q0 <= 0.0:
+        return n_in + alpha * (n_out - n_in)
+    rg = _grid.fwd_fft((n_out - n_in).astype(np.complex128))
+    g2 = g_squared(A, n_in.shape)
+    w = np.where(g2 > 0, alpha * g2 / (g2 + q0 * q0), alpha)
+    return n_in + _grid.inv_fft(w * rg).real
 
 
 def scf(probs, kweights, vion: np.ndarray, nel: float, nbands: int, sigma: float, alpha: float,
-        tol: float, max_iter: int):
+        tol: float, max_iter: int, q0: float = 0.0):
     """SCF loop over the k-point problems ``probs`` (their vloc is replaced by
     V_eff at every step), nbands eigenpairs per k-point from dense
     diagonalisation.  Step 0 solves with V_ion; step i >= 1 with V_eff[n_in].
@@ -172,7 +182,7 @@ def scf(probs, kweights, vion: np.ndarray, nel: float, nbands: int, sigma: float
         hist.append(d)
         if d < tol:
             break
-        n_next = mix(n_in, n_out, alpha)
+        n_next = mix(n_in, n_out, alpha, q0, A)
     eband = float(sum(wk * np.sum(fk * w) for wk, fk, w in zip(kweights, f, eps)))
     e["band"] = eband
     e["total"] = eband - e["hartree"] + e["xc"] - e["vxc_n"]

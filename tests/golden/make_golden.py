@@ -8,6 +8,7 @@ block Davidson at the medium workload's full size).
     python tests/golden/make_golden.py --quick       # without the Davidson goldens
     python tests/golden/make_golden.py --config4     # only the two ragged-batch cells
     python tests/golden/make_golden.py --augmented   # only the medium workload with S != 1
+    python tests/golden/make_golden.py --scf         # only the SCF loops of the config-1 cell
 
 Regression fixtures: tests/test_golden.py recomputes them with the oracle,
 and the GPU tests compare the library against them.
@@ -98,7 +99,50 @@ def davidson_config2_augmented(ik):
             f.write(f"{t:.17e} {rho:.3e}\n")
 
 
+# SCF workload on the config-1 cell: 12 electrons in 16 bands per k-point,
+# Fermi width 0.02 Ha, linear mixing 0.5, converged to int |n_out - n_in| /
+# N_el < 1e-11 (the GPU tests stop at 1e-9)
+SCF_PARAMS = dict(nel=12.0, nbands=16, sigma=0.02, alpha=0.5)
+SCF_KPOINTS = {"gamma": ([[0.0, 0.0, 0.0]], [1.0], {}),
+               "2k": ([[0.0, 0.0, 0.0], [0.25, 0.1, -0.3]], [0.5, 0.5], {}),
+               "gamma_kerker": ([[0.0, 0.0, 0.0]], [1.0], dict(alpha=0.8, q0=1.0))}
+
+
+def scf_config1(tag):
+    """Oracle SCF loop (dense diagonalisation per step) on the config-1 cell
+    at the k-points of SCF_KPOINTS[tag]: mu, energies, eigenvalues and the
+    converged input density at 256 seeded grid points, and the density
+    distance of every step."""
+    from oracle import scf as osc
+    c = synth.make_cell(1)
+    kpts, kw, extra = SCF_KPOINTS[tag]
+    c.kpts = np.asarray(kpts, dtype=np.float64)
+    probs = [ham.problem_from_cell(c, ik) for ik in range(len(kpts))]
+    vion = synth.vloc_on_grid(c)
+    r = osc.scf(probs, kw, vion, tol=1e-11, max_iter=200, **dict(SCF_PARAMS, **extra))
+    assert r["converged"], "oracle SCF did not converge"
+    rng = np.random.default_rng(314)
+    pts = rng.integers(0, c.nr[0], size=(256, 3))
+    e = r["energies"]
+    with open(os.path.join(HERE, f"config1_scf_{tag}.txt"), "w") as f:
+        f.write(f"# {c.name} SCF, k-points {kpts} weights {kw}, {dict(SCF_PARAMS, **extra)}; oracle loop converged to "
+                f"int|n_out - n_in|/N_el = {r['history'][-1]:.2e} in {len(r['history']) + 1} steps; "
+                f"written by make_golden.py (oracle only)\n")
+        f.write(f"mu {r['mu']:.17e}\n")
+        for key in ("band", "hartree", "xc", "vxc_n", "total", "free"):
+            f.write(f"energy {key} {float(e[key]):.17e}\n")
+        for ik, w in enumerate(r["eigenvalues"]):
+            f.write(f"eig {ik} " + " ".join(f"{x:.17e}" for x in w) + "\n")
+        f.write("hist " + " ".join(f"{x:.17e}" for x in r["history"]) + "\n")
+        for p_ in pts:
+            f.write(f"n {p_[0]} {p_[1]} {p_[2]} {r['n_in'][tuple(p_)]:.17e}\n")
+
+
 def main():
+    if "--scf" in sys.argv:
+        for tag in SCF_KPOINTS:
+            scf_config1(tag)
+        return
     if "--augmented" in sys.argv:
         davidson_config2_augmented(0)
         return
@@ -112,6 +156,8 @@ def main():
         for index in (10, 19):
             davidson_config4(index)
         davidson_config2_augmented(0)
+        for tag in SCF_KPOINTS:
+            scf_config1(tag)
     for cfg, nlow, fname in ((0, 8, "tiny_cell_lowest8_Ha.txt"), (1, 16, "config1_lowest16_Ha.txt")):
         c, po, w = eig_fixture(cfg, nlow)
         with open(os.path.join(HERE, fname), "w") as f:

@@ -650,3 +650,24 @@ def test_scf_reaches_a_fixed_point_of_the_density():
     # the bare first step has no Hartree or exchange term: zero interaction energies
     r0 = sc.scf([po], [1.0], vion, nel=4.0, nbands=8, sigma=0.02, alpha=0.5, tol=1e-10, max_iter=0)
     assert r0["energies"]["hartree"] == 0.0 and not r0["history"]
+
+
+def test_kerker_mixing_weights_each_fourier_component():
+    # residual = c0 + a cos(G1.r): the update is alpha c0 + alpha |G1|^2/(|G1|^2 + q0^2) a cos(G1.r);
+    # q0 = 0 is linear mixing
+    A = _skewed_cell()
+    nr = (9, 10, 12)
+    B = gs.reciprocal(A)
+    m1 = np.array([2, -1, 1])
+    G1 = m1 @ B
+    j = np.stack(np.meshgrid(*[np.arange(x) for x in nr], indexing="ij"), axis=-1)
+    cosg = np.cos(2 * np.pi * (j / np.array(nr)) @ m1)
+    n_in = 0.4 + 0.1 * np.sin(2 * np.pi * j[..., 0] / nr[0])
+    n_out = n_in + 0.05 + 0.2 * cosg
+    alpha, q0 = 0.7, 1.3
+    got = sc.mix(n_in, n_out, alpha, q0, A)
+    g2 = G1 @ G1
+    want = n_in + alpha * 0.05 + alpha * g2 / (g2 + q0 * q0) * 0.2 * cosg
+    assert np.abs(got - want).max() < 1e-13
+    assert np.abs(sc.mix(n_in, n_out, alpha) - (n_in + alpha * (n_out - n_in))).max() < 1e-15
+    assert np.abs(sc.mix(n_in, n_out, alpha, 0.0, A) - sc.mix(n_in, n_out, alpha)).max() == 0.0
