@@ -550,6 +550,86 @@ pw_status pw_lanczos_resolvent(pw_lanczos *l, const void *z, int32_t nz, void *g
 pw_status pw_profile_enable(pw_problem *p, int32_t on);
 pw_status pw_profile_read(pw_problem *p, double *ms_total, int64_t *launches, int32_t reset);
 
+/*
+ * Self-consistent field loop around the solver.  The Kohn-Sham potential is
+ * the sum of the local ionic, Hartree and exchange-correlation potentials
+ * (the paper's relativistic PAW section writes V_LOC that way), and the
+ * exact-exchange section describes the outer loop that rebuilds the
+ * operator from the bands until it stops changing.  Scalar, spin-unpolarised
+ * path in Hartree units:
+ *   n(r)   = Omega^-1 sum_k w_k sum_n f_nk |u_nk(r)|^2, u = sum_G psi(G) e^{iG.r}
+ *   V_H(G) = 4 pi n(G) / |G|^2 for G != 0, V_H(0) = 0  (Poisson in G space, as
+ *            the exact-exchange section solves it for pair densities)
+ *   V_x(r) = -(3 n(r) / pi)^{1/3}  (local-density exchange)
+ *   f_nk   = 2 / (1 + exp((eps_nk - mu) / sigma)),  sum_k w_k sum_n f_nk = nel
+ *   n_in  <- n_in + alpha (n_out - n_in)  (linear mixing), or with kerker_q0 > 0
+ *            the Kerker weight alpha G^2 / (G^2 + q0^2) on each Fourier
+ *            component of the residual (alpha at G = 0)
+ * Grid arrays are device double [N0][N1][N2] (N2 fastest), the layout of
+ * pw_problem_desc.vloc.  Only FP64 problems without augmentation.
+ */
+
+/* Bytes of device scratch pw_density needs for problem p. */
+pw_status pw_density_workspace_size(const pw_problem *p, size_t *bytes);
+/* n[r] += Omega^-1 sum_b f[b] |u_b(r)|^2 for the nbands bands psi (device
+ * complex128 [nbands][ld], normalised so that sum_G |psi(G)|^2 = 1 for the
+ * density to integrate to sum f).  f: host double [nbands] (occupation times
+ * k-point weight), read before the call returns.  work: 256-byte aligned
+ * device scratch of pw_density_workspace_size bytes.  Uses the problem's
+ * stick buffer (one stream at a time per problem).  The sum over bands runs
+ * in a fixed order (no atomics): the result is reproducible. */
+pw_status pw_density(pw_problem *p, const void *psi, int64_t ld, int64_t nbands, const double *f, double *n,
+                     void *work, size_t work_bytes, void *stream);
+/* Bytes of device scratch pw_hxc needs on the grid of p. */
+pw_status pw_hxc_workspace_size(const pw_problem *p, size_t *bytes);
+/* v = vion + V_H[n] + V_x[n] on the grid of p (vion may be NULL: then
+ * V_H + V_x); energies (host double [3]) = E_H = (1/2) int V_H n,
+ * E_x = int n eps_x, int n v_x.  Synchronises the stream. */
+pw_status pw_hxc(pw_problem *p, const double *n, const double *vion, double *v, double *energies, void *work,
+                 size_t work_bytes, void *stream);
+/* Replace the local potential of an FP64 problem by v (device double
+ * [N0][N1][N2], Ha).  A Davidson state on the problem must be told with
+ * pw_davidson_set_problem before its next step.  Synchronises the stream. */
+pw_status pw_problem_set_vloc(pw_problem *p, const double *v, void *stream);
+
+typedef struct pw_scf pw_scf;
+typedef struct pw_scf_desc {
+  int32_t nk;                     /* k-points */
+  pw_problem *const *probs;       /* [nk] FP64 problems on one grid and cell; their V_loc is replaced */
+  pw_davidson *const *davs;       /* [nk] initialised Davidson states, davs[k] on probs[k] */
+  pw_batch_dav *batch;            /* optional: a batch over davs (then the solves run on its streams) */
+  const double *kweights;         /* host [nk], > 0 */
+  const double *vion;             /* device double [N0][N1][N2]: the fixed local potential, Ha; kept by reference */
+  double nel;                     /* electrons per cell, below 2 sum_k w_k nbands_k */
+  double sigma;                   /* Fermi-Dirac width, Ha, > 0 */
+  double alpha;                   /* mixing factor, 0 < alpha <= 1 */
+  double kerker_q0;               /* Kerker wave vector, 1/bohr; 0 for plain linear mixing */
+} pw_scf_desc;
+/* Device workspace of the loop: densities, potential, the density and
+ * Hartree scratch and one band block. */
+pw_status pw_scf_workspace_size(const pw_scf_desc *d, size_t *bytes);
+/* Checks the descriptor, binds the workspace (256-byte aligned, owned by the
+ * caller until pw_scf_destroy), sets V_ion on every problem and refreshes
+ * the Davidson states: step 0 solves with V_ion alone. */
+pw_status pw_scf_create(const pw_scf_desc *d, void *workspace, size_t ws_bytes, void *stream, pw_scf **out);
+pw_status pw_scf_destroy(pw_scf *s);
+/* One SCF step: every Davidson solve to dav_tol (at most dav_max_iter
+ * iterations, TPA preconditioner), occupations and mu, the output density,
+ * out[0] = int |n_out - n_in| / nel (-1 at step 0, whose output density
+ * becomes the first input density), then -- unless step > 0 and out[0] <
+ * tol (*converged = 1) -- the mixed input density, its potential on every
+ * problem and the Davidson states refreshed.  out (host double [8]):
+ * drho, mu, E_band = sum_k w_k sum_n f eps, E_H, E_x, int v_x n (of the
+ * input density this step solved with), E = E_band - E_H + E_x - int v_x n,
+ * F = E - sigma S (S the occupations' entropy).  Synchronises the stream. */
+pw_status pw_scf_step(pw_scf *s, double dav_tol, int32_t dav_max_iter, double tol, double *out,
+                      int32_t *converged);
+/* Device copies of the input density of the last step solved and its
+ * output density (either may be NULL), and of the potential the next solves
+ * use.  Stream-ordered. */
+pw_status pw_scf_density(pw_scf *s, double *n_in, double *n_out, void *stream);
+pw_status pw_scf_potential(pw_scf *s, double *v, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -123,6 +123,17 @@ def _load():
         "pw_lanczos_run": (i32, [vp, i32, vp]),
         "pw_lanczos_coefficients": (i32, [vp, vp, vp, C.POINTER(i32), vp]),
         "pw_lanczos_resolvent": (i32, [vp, vp, i32, vp, vp]),
+        "pw_density_workspace_size": (i32, [vp, C.POINTER(C.c_size_t)]),
+        "pw_density": (i32, [vp, vp, i64, i64, C.POINTER(f64), vp, vp, C.c_size_t, vp]),
+        "pw_hxc_workspace_size": (i32, [vp, C.POINTER(C.c_size_t)]),
+        "pw_hxc": (i32, [vp, vp, vp, vp, C.POINTER(f64), vp, C.c_size_t, vp]),
+        "pw_problem_set_vloc": (i32, [vp, vp, vp]),
+        "pw_scf_workspace_size": (i32, [vp, C.POINTER(C.c_size_t)]),
+        "pw_scf_create": (i32, [vp, vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "pw_scf_destroy": (i32, [vp]),
+        "pw_scf_step": (i32, [vp, f64, i32, f64, C.POINTER(f64), C.POINTER(i32)]),
+        "pw_scf_density": (i32, [vp, vp, vp, vp]),
+        "pw_scf_potential": (i32, [vp, vp, vp]),
         "pw_profile_enable": (i32, [vp, i32]),
         "pw_profile_read": (i32, [vp, C.POINTER(f64), C.POINTER(i64), i32]),
     }
@@ -206,6 +217,7 @@ class Problem:
 
     def __init__(self, handle, npw, nproj, max_bands, precision, workspace=None):
         self._h = handle
+        self.nr = None
         self.npw = npw
         self.nproj = nproj
         self.max_bands = max_bands
@@ -281,7 +293,9 @@ def pw_problem_create(cell, kpt, ecut, nr, miller, vloc, beta, proj_offset, dij,
     _check(LIB.pw_problem_create(C.byref(d), int(max_bands), C.c_void_p(ws.data_ptr()), nbytes.value,
                                  _stream(stream), C.byref(h)))
     del keep
-    return Problem(h, int(d.npw), int(d.nproj), int(max_bands), int(precision), ws)
+    prob = Problem(h, int(d.npw), int(d.nproj), int(max_bands), int(precision), ws)
+    prob.nr = tuple(int(x) for x in nr)
+    return prob
 
 
 def pw_hpsi(prob: Problem, psi, hpsi, terms: int = PW_TERM_ALL, stream=None) -> None:
@@ -853,6 +867,123 @@ class Lanczos:
     def close(self):
         if self._h:
             LIB.pw_lanczos_destroy(self._h)
+            self._h = None
+        self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- SCF loop
+def _grid_array(t, prob: Problem, name):
+    import torch
+    ptr = _dev_ptr(t, torch.float64, name)
+    if not t.is_contiguous() or tuple(t.shape) != tuple(prob.nr):
+        raise ValueError(f"{name}: expected a contiguous float64 grid of shape {tuple(prob.nr)}")
+    return ptr
+
+
+def pw_density(prob: Problem, psi, f, n, stream=None) -> None:
+    """n += Omega^-1 sum_b f[b] |u_b(r)|^2 (n: float64 grid [N0][N1][N2] on the GPU)."""
+    ps, ld, nb = _band_block(psi, "psi", prob.npw)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    if f.shape != (nb,):
+        raise ValueError("one weight per band")
+    nbytes = C.c_size_t(0)
+    _check(LIB.pw_density_workspace_size(prob.handle, C.byref(nbytes)))
+    work = _workspace(nbytes.value)
+    _check(LIB.pw_density(prob.handle, ps, ld, nb, f.ctypes.data_as(C.POINTER(C.c_double)),
+                          _grid_array(n, prob, "n"), C.c_void_p(work.data_ptr()), nbytes.value, _stream(stream)))
+
+
+def pw_hxc(prob: Problem, n, vion=None, stream=None):
+    """(v, energies): v = vion + V_H[n] + V_x[n] on the grid, energies =
+    (E_H, E_x, int v_x n)."""
+    import torch
+    nbytes = C.c_size_t(0)
+    _check(LIB.pw_hxc_workspace_size(prob.handle, C.byref(nbytes)))
+    work = _workspace(nbytes.value)
+    v = torch.empty_like(n)
+    e = np.zeros(3)
+    _check(LIB.pw_hxc(prob.handle, _grid_array(n, prob, "n"),
+                      _grid_array(vion, prob, "vion") if vion is not None else None,
+                      _grid_array(v, prob, "v"), e.ctypes.data_as(C.POINTER(C.c_double)),
+                      C.c_void_p(work.data_ptr()), nbytes.value, _stream(stream)))
+    return v, e
+
+
+def pw_problem_set_vloc(prob: Problem, v, stream=None) -> None:
+    _check(LIB.pw_problem_set_vloc(prob.handle, _grid_array(v, prob, "v"), _stream(stream)))
+
+
+class _ScfDesc(C.Structure):
+    _fields_ = [("nk", C.c_int32), ("probs", C.POINTER(C.c_void_p)), ("davs", C.POINTER(C.c_void_p)),
+                ("batch", C.c_void_p), ("kweights", C.POINTER(C.c_double)), ("vion", C.c_void_p),
+                ("nel", C.c_double), ("sigma", C.c_double), ("alpha", C.c_double), ("kerker_q0", C.c_double)]
+
+
+SCF_OUT = ("drho", "mu", "e_band", "e_hartree", "e_x", "vxc_n", "e_total", "free_energy")
+
+
+class Scf:
+    """Owner of a pw_scf and its workspace; keeps the problems, Davidson
+    states, optional batch and V_ion alive with it."""
+
+    def __init__(self, probs, davs, kweights, vion, nel: float, sigma: float, alpha: float, batch=None,
+                 kerker_q0: float = 0.0, stream=None):
+        n = len(probs)
+        self._keep = (list(probs), list(davs), batch, vion)
+        self._pp = (C.c_void_p * n)(*[p.handle.value for p in probs])
+        self._dd = (C.c_void_p * n)(*[d.handle.value for d in davs])
+        self._kw = np.ascontiguousarray(kweights, dtype=np.float64)
+        d = _ScfDesc(n, self._pp, self._dd, batch.handle if batch is not None else None,
+                     self._kw.ctypes.data_as(C.POINTER(C.c_double)), _grid_array(vion, probs[0], "vion"),
+                     float(nel), float(sigma), float(alpha), float(kerker_q0))
+        nbytes = C.c_size_t(0)
+        _check(LIB.pw_scf_workspace_size(C.byref(d), C.byref(nbytes)))
+        self.workspace = _workspace(nbytes.value)
+        h = C.c_void_p()
+        _check(LIB.pw_scf_create(C.byref(d), C.c_void_p(self.workspace.data_ptr()), nbytes.value,
+                                 _stream(stream), C.byref(h)))
+        self._h = h
+        self.prob0 = probs[0]
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise PwError(-1, "SCF handle already destroyed")
+        return self._h
+
+    def step(self, dav_tol: float, dav_max_iter: int, tol: float) -> dict:
+        out = np.zeros(8)
+        c = C.c_int32(0)
+        _check(LIB.pw_scf_step(self.handle, float(dav_tol), int(dav_max_iter), float(tol),
+                               out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(c)))
+        r = dict(zip(SCF_OUT, out.tolist()))
+        r["converged"] = bool(c.value)
+        return r
+
+    def density(self, stream=None):
+        import torch
+        shape = tuple(self.prob0.nr)
+        n_in = torch.empty(shape, dtype=torch.float64, device="cuda")
+        n_out = torch.empty_like(n_in)
+        _check(LIB.pw_scf_density(self.handle, C.c_void_p(n_in.data_ptr()), C.c_void_p(n_out.data_ptr()),
+                                  _stream(stream)))
+        return n_in, n_out
+
+    def potential(self, stream=None):
+        import torch
+        v = torch.empty(tuple(self.prob0.nr), dtype=torch.float64, device="cuda")
+        _check(LIB.pw_scf_potential(self.handle, C.c_void_p(v.data_ptr()), _stream(stream)))
+        return v
+
+    def close(self):
+        if self._h:
+            LIB.pw_scf_destroy(self._h)
             self._h = None
         self.workspace = None
 

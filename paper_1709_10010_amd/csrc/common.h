@@ -215,6 +215,12 @@ int launch_zfft_fwd(const FFTDev &f, int prec, const void *sticks, const void *p
                     void *hpsi, int64_t ldh, int nb, bool kinetic, hipStream_t s);
 int launch_kinetic_only(const double *kin, const void *psi, int64_t ld, void *hpsi, int64_t ldh,
                         int64_t npw, int nb, bool kinetic, hipStream_t s);
+// full-grid 3D transform of a complex FP64 grid [N0][N1][N2] in place
+// (inverse unnormalised, forward with N^-3), and the band-density plane pass
+// (part[group][z][x][y] += w_b |u_b|^2 for the bands in the stick buffer)
+int launch_grid_fft(const FFTDev &f, double2 *g, bool inverse, hipStream_t s);
+int launch_rho_plane(const FFTDev &f, const void *sticks, int nb, int group, const double *w, double *part,
+                     hipStream_t s);
 
 // Complex GEMMs (gemm.hip).  Column-major complex128 matrices.
 // C[MxN] = A^H B,  A: K x M (lda), B: K x N (ldb); split-K over `splits`

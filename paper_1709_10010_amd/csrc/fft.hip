@@ -30,6 +30,7 @@
 // thread loads its butterflies' R inputs into registers, applies the
 // twiddles and the R-point DFT, all threads barrier, then every thread
 // stores its outputs at their autosorted positions.  Radices 2, 3, 4, 5, 8.
+#include <algorithm>
 #include <cstdlib>
 
 #include "common.h"
@@ -1101,6 +1102,96 @@ void k_plane_p(FFTDev f, cpx_t<T> *__restrict__ sticks, int nb, int group) {
   }
 }
 
+// ---------------------------------------------------------------- full-grid transforms
+// One pass of a 3D transform of a complex FP64 grid [N0][N1][N2] (N2
+// fastest) along one axis, scaled by `scale` on the way out.  AXIS 2: a
+// workgroup takes T consecutive z-lines.  AXIS 0 / 1: a workgroup takes the
+// N lines along the axis at one y (AXIS 0) or one x (AXIS 1) and T
+// consecutive z, so that its global loads and stores run along z.  The host
+// keeps T * N within kCpt values per thread.
+template <int AXIS, bool INV, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_grid_axis(FFTDev f, double2 *__restrict__ g, int T, double scale) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const AxisPlan &pl = AXIS == 0 ? f.px : (AXIS == 1 ? f.py : f.pz);
+  const int N = pl.n;
+  double2 *tw = reinterpret_cast<double2 *>(smem);
+  double2 *buf = tw + N;
+  const double2 *twg = static_cast<const double2 *>(AXIS == 0 ? f.tw0 : (AXIS == 1 ? f.tw1 : f.tw2));
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NTHR) tw[i] = twg[i];
+  const int n1 = f.n1, n2 = f.n2;
+  if constexpr (AXIS == 2) {
+    const int64_t l0 = (int64_t)blockIdx.x * T;
+    const int nl = (int)min<int64_t>(T, (int64_t)f.n0 * n1 - l0);
+    double2 *src = g + l0 * n2;
+    for (int i = tid; i < nl * n2; i += NTHR) buf[i] = src[i];
+    __syncthreads();
+    fft_axis<double2, INV, false, false, 0>(buf, nl, n2, 1, nullptr, pl, tw, tid, NTHR);
+    for (int i = tid; i < nl * n2; i += NTHR) src[i] = c_scale(buf[i], scale);
+  } else {
+    const int nzt = (n2 + T - 1) / T;
+    const int o = blockIdx.x / nzt;
+    const int z0 = (blockIdx.x - o * nzt) * T;
+    const int nl = min(T, n2 - z0);
+    const float inl = 1.0f / (float)nl;
+    // element (a, t): position a along the axis, t in the z tile
+    auto at = [&](int a, int t) -> int64_t {
+      return AXIS == 0 ? ((int64_t)a * n1 + o) * n2 + z0 + t : ((int64_t)o * n1 + a) * n2 + z0 + t;
+    };
+    for (int i = tid; i < N * nl; i += NTHR) {
+      const int a = qdiv(i, nl, inl);
+      buf[i] = g[at(a, i - a * nl)];
+    }
+    __syncthreads();
+    fft_axis<double2, INV, true, false, 0>(buf, nl, 1, nl, nullptr, pl, tw, tid, NTHR);
+    for (int i = tid; i < N * nl; i += NTHR) {
+      const int a = qdiv(i, nl, inl);
+      g[at(a, i - a * nl)] = c_scale(buf[i], scale);
+    }
+  }
+}
+
+// Band density on one z-plane: per band of the workgroup's group, scatter
+// the plane's sticks into an LDS plane [x][y], inverse y transform of the x
+// rows that hold sticks, inverse x transform of every y column, then add
+// w_b |u_b(r)|^2 into the workgroup's own partial plane part[g][z][x][y]
+// (each element is owned by one thread across all bands, so no atomics and
+// a fixed order of summation).
+template <int NTHR>
+__global__ __launch_bounds__(NTHR) void k_rho_plane(FFTDev f, const double2 *__restrict__ sticks, int nb,
+                                                    int group, const double *__restrict__ w,
+                                                    double *__restrict__ part) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double2 *tw0 = reinterpret_cast<double2 *>(smem);
+  double2 *tw1 = tw0 + f.n0;
+  double2 *pl = tw1 + f.n1;
+  int *lb = reinterpret_cast<int *>(pl + f.n0 * f.n1);
+  const int z = blockIdx.x % f.n2;
+  const int g = blockIdx.x / f.n2;
+  const int tid = threadIdx.x;
+  const double2 *tw0g = static_cast<const double2 *>(f.tw0);
+  const double2 *tw1g = static_cast<const double2 *>(f.tw1);
+  for (int i = tid; i < f.n0; i += NTHR) tw0[i] = tw0g[i];
+  for (int i = tid; i < f.n1; i += NTHR) tw1[i] = tw1g[i];
+  for (int i = tid; i < f.nx; i += NTHR) lb[i] = f.xlist[i] * f.n1;
+  const int npl = f.n0 * f.n1;
+  double *acc = part + ((int64_t)g * f.n2 + z) * npl;
+  for (int bb = 0; bb < group; ++bb) {
+    const int b = g * group + bb;
+    if (b >= nb) break;
+    for (int i = tid; i < npl; i += NTHR) pl[i] = double2{0, 0};
+    __syncthreads();
+    const double2 *col = sticks + (int64_t)b * f.n2 * f.nst_pad + (int64_t)z * f.nst_pad;
+    for (int s = tid; s < f.nst; s += NTHR) pl[f.stick_xy[s]] = col[s];
+    __syncthreads();
+    fft_axis<double2, true, false, true, 0>(pl, f.nx, 0, 1, lb, f.py, tw1, tid, NTHR);
+    fft_axis<double2, true, true, false, 0>(pl, f.n1, 1, f.n1, nullptr, f.px, tw0, tid, NTHR);
+    const double wb = w[b];
+    for (int i = tid; i < npl; i += NTHR) acc[i] += wb * (pl[i].x * pl[i].x + pl[i].y * pl[i].y);
+    __syncthreads();
+  }
+}
+
 template <typename T, int NTHR, int NC>
 __global__ __launch_bounds__(NTHR) void k_zfft_fwd(FFTDev f, const cpx_t<T> *__restrict__ sticks,
                                                    const double2 *__restrict__ psi, int64_t ld,
@@ -1422,6 +1513,62 @@ int launch_zfft_fwd(const FFTDev &f, int prec, const void *sticks, const void *p
   if (nb <= 0) return PW_OK;
   return prec == PW_FP64 ? zfwd_t<double>(f, sticks, psi, ld, hpsi, ldh, nb, kinetic, s)
                          : zfwd_t<float>(f, sticks, psi, ld, hpsi, ldh, nb, kinetic, s);
+}
+
+// Full-grid 3D transform of g [N0][N1][N2] (FP64 complex): inverse
+// unnormalised, forward with N^-3 (split as 1/N per axis).
+int launch_grid_fft(const FFTDev &f, double2 *g, bool inverse, hipStream_t s) {
+  constexpr int NT = 256;
+  const int n[3] = {f.n0, f.n1, f.n2};
+  for (int ax = 2; ax >= 0; --ax) {
+    const int N = n[ax];
+    const int T = std::max(1, std::min(16, kCpt * NT / N));
+    const double scale = inverse ? 1.0 : 1.0 / (double)N;
+    const size_t lds = sizeof(double2) * (size_t)N * (1 + T);
+    int64_t blocks;
+    if (ax == 2)
+      blocks = ((int64_t)f.n0 * f.n1 + T - 1) / T;
+    else
+      blocks = (int64_t)(ax == 0 ? f.n1 : f.n0) * ((f.n2 + T - 1) / T);
+    auto pick = [&](auto k) -> int {
+      if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
+      hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(NT), lds, s, f, g, T, scale);
+      return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+    };
+    int rc;
+    if (ax == 2)
+      rc = inverse ? pick(k_grid_axis<2, true, NT>) : pick(k_grid_axis<2, false, NT>);
+    else if (ax == 1)
+      rc = inverse ? pick(k_grid_axis<1, true, NT>) : pick(k_grid_axis<1, false, NT>);
+    else
+      rc = inverse ? pick(k_grid_axis<0, true, NT>) : pick(k_grid_axis<0, false, NT>);
+    if (rc != PW_OK) return rc;
+  }
+  return PW_OK;
+}
+
+// Band densities of nb bands whose z transforms sit in the stick buffer:
+// part[g][z][x][y] += sum over the bands b of group g of w[b] |u_b|^2.
+template <int NT>
+static int rho_plane_n(const FFTDev &f, const void *sticks, int nb, int group, const double *w, double *part,
+                       hipStream_t s) {
+  const size_t lds = sizeof(double2) * (size_t)(f.n0 + f.n1 + f.n0 * f.n1) + sizeof(int) * (size_t)f.nx;
+  const int groups = (nb + group - 1) / group;
+  auto k = k_rho_plane<NT>;
+  if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
+  hipLaunchKernelGGL(k, dim3((unsigned)(f.n2 * groups)), dim3(NT), lds, s, f,
+                     static_cast<const double2 *>(sticks), nb, group, w, part);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+int launch_rho_plane(const FFTDev &f, const void *sticks, int nb, int group, const double *w, double *part,
+                     hipStream_t s) {
+  if (nb <= 0) return PW_OK;
+  // the LDS transforms hold at most kCpt values per thread of a plane
+  const int npl = f.n0 * f.n1;
+  if (npl <= kCpt * 256) return rho_plane_n<256>(f, sticks, nb, group, w, part, s);
+  if (npl <= kCpt * 512) return rho_plane_n<512>(f, sticks, nb, group, w, part, s);
+  if (npl <= kCpt * 1024) return rho_plane_n<1024>(f, sticks, nb, group, w, part, s);
+  return PW_ERR_SHAPE;
 }
 
 int launch_kinetic_only(const double *kin, const void *psi, int64_t ld, void *hpsi, int64_t ldh,

@@ -1,0 +1,225 @@
+"""GPU SCF loop (pw_density, pw_hxc, pw_problem_set_vloc, pw_scf_*) against
+the FP64 oracle (oracle/scf.py).
+
+Building blocks elementwise at the oracle's rounding level: band densities
+(several band chunks, the tiny 9^3 grid with its radix-3 plan and the
+config-1 24^3 grid, a k-point off Gamma), the Hartree plus exchange potential
+and its energies, and H*psi after the local potential is replaced.  The loop
+itself against stored oracle SCF results on the config-1 cell (tests/golden,
+written by make_golden.py; linear mixing at Gamma and two k-points, Kerker
+mixing at Gamma): the density distance of the first ten steps, then the
+converged state -- the oracle converged to 1e-11, the library to 1e-9 in
+int |n_out - n_in| / N_el, so the comparison allows 2e-8 Ha on eigenvalues
+and energies and 1e-8 of the largest density value.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import hamiltonian as ham
+from oracle import scf as osc
+
+from gpu_util import from_gpu_block, log, problems, rel_err, start_block, to_gpu_block
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+SCF = dict(nel=12.0, nbands=16, sigma=0.02, alpha=0.5)
+KPTS = {"gamma": ([[0.0, 0.0, 0.0]], [1.0], {}), "2k": ([[0.0, 0.0, 0.0], [0.25, 0.1, -0.3]], [0.5, 0.5], {}),
+        "gamma_kerker": ([[0.0, 0.0, 0.0]], [1.0], dict(alpha=0.8, q0=1.0))}
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1709_10010_amd import _lib
+    return _lib
+
+
+def _orthonormal(seed, nb, npw):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((npw, nb)) + 1j * rng.standard_normal((npw, nb))
+    return np.linalg.qr(X)[0].T.copy()
+
+
+@pytest.mark.parametrize("cfg,kpt,nb,chunk", [(0, None, 8, 3), (1, None, 16, 16), (1, [0.2, -0.35, 0.1], 13, 5)])
+def test_density_matches_oracle(lib, cfg, kpt, nb, chunk):
+    import torch
+    c = synth.make_cell(cfg)
+    if kpt is not None:
+        c.kpts = np.array([kpt])
+    po, pl = problems(c, max_bands=nb)
+    lib.pw_problem_set_tuning(pl, 2, chunk, 0, lib.PW_PLANE_REGISTER)
+    X = _orthonormal(60 + cfg, nb, po.npw)
+    f = np.linspace(2.0, 0.1, nb) * 0.7
+    n = torch.full(tuple(c.nr), 0.25, dtype=torch.float64, device="cuda")   # pw_density accumulates
+    lib.pw_density(pl, to_gpu_block(X), f, n)
+    torch.cuda.synchronize()
+    want = osc.density(po, X, f) + 0.25
+    err = rel_err(n.cpu().numpy(), want)
+    log(f"cfg{cfg} k={kpt} {nb} bands in chunks of {chunk}: density rel err {err:.2e}")
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("cfg", [0, 1])
+def test_hxc_matches_oracle(lib, cfg):
+    import torch
+    c = synth.make_cell(cfg)
+    po, pl = problems(c, max_bands=4)
+    rng = np.random.default_rng(7 + cfg)
+    n = rng.uniform(0.0, 0.05, tuple(c.nr))
+    n[0, 0, 0] = 0.0
+    vion = synth.vloc_on_grid(c)
+    v, e = lib.pw_hxc(pl, torch.from_numpy(n).cuda(), torch.from_numpy(vion).cuda())
+    want, ew = osc.potential(vion, n, po.A)
+    err = rel_err(v.cpu().numpy(), want)
+    log(f"cfg{cfg}: V_eff rel err {err:.2e}, energies {e} vs {ew}")
+    assert err < 1e-12
+    assert abs(e[0] - ew["hartree"]) < 1e-12 * abs(ew["hartree"])
+    assert abs(e[1] - ew["xc"]) < 1e-12 * abs(ew["xc"])
+    assert abs(e[2] - ew["vxc_n"]) < 1e-12 * abs(ew["vxc_n"])
+    # without V_ion: V_H + V_x alone
+    v0, _ = lib.pw_hxc(pl, torch.from_numpy(n).cuda())
+    assert rel_err(v0.cpu().numpy(), want - vion) < 1e-12
+
+
+@pytest.mark.parametrize("cfg", [0, 2])
+def test_set_vloc_then_hpsi_matches_oracle(lib, cfg):
+    import torch
+    c = synth.make_cell(cfg)
+    nb = 6
+    po, pl = problems(c, max_bands=nb)
+    rng = np.random.default_rng(19)
+    v = po.vloc + 0.3 * rng.standard_normal(po.vloc.shape)
+    lib.pw_problem_set_vloc(pl, torch.from_numpy(v).cuda())
+    po.vloc = v
+    psi = start_block(c, nb, po.npw)
+    y = torch.zeros_like(to_gpu_block(psi))
+    lib.pw_hpsi(pl, to_gpu_block(psi), y)
+    err = rel_err(from_gpu_block(y, po.npw), ham.hpsi(po, psi))
+    log(f"cfg{cfg}: H psi after set_vloc rel err {err:.2e}")
+    assert err < 1e-12
+
+
+def _golden(tag):
+    out = {"energy": {}, "eig": {}, "n": []}
+    with open(os.path.join(GOLDEN, f"config1_scf_{tag}.txt")) as f:
+        for line in f:
+            if line.startswith("#"):
+                continue
+            w = line.split()
+            if w[0] == "mu":
+                out["mu"] = float(w[1])
+            elif w[0] == "energy":
+                out["energy"][w[1]] = float(w[2])
+            elif w[0] == "eig":
+                out["eig"][int(w[1])] = np.array([float(x) for x in w[2:]])
+            elif w[0] == "hist":
+                out["hist"] = np.array([float(x) for x in w[1:]])
+            elif w[0] == "n":
+                out["n"].append((int(w[1]), int(w[2]), int(w[3]), float(w[4])))
+    return out
+
+
+def _scf_setup(lib, tag, batch_streams=0):
+    import torch
+    c = synth.make_cell(1)
+    kpts, kw, extra = KPTS[tag]
+    c.kpts = np.asarray(kpts)
+    probs, davs = [], []
+    for ik in range(len(kpts)):
+        _, pl = problems(c, ik=ik, max_bands=SCF["nbands"])
+        d = lib.Davidson(pl, SCF["nbands"], 0, 1e-10)
+        lib.pw_davidson_init(d, to_gpu_block(start_block(c, SCF["nbands"], pl.npw, ik)))
+        probs.append(pl)
+        davs.append(d)
+    batch = None
+    if batch_streams:
+        streams = [torch.cuda.Stream() for _ in range(batch_streams)]
+        torch.cuda.synchronize()
+        batch = lib.BatchDavidson(davs, streams)
+    vion = torch.from_numpy(synth.vloc_on_grid(c)).cuda()
+    s = lib.Scf(probs, davs, kw, vion, SCF["nel"], SCF["sigma"], extra.get("alpha", SCF["alpha"]), batch=batch,
+                kerker_q0=extra.get("q0", 0.0))
+    return c, s, davs, batch
+
+
+def _run(s, max_steps=120):
+    hist = []
+    r = None
+    for _ in range(max_steps):
+        r = s.step(1e-10, 200, 1e-9)
+        hist.append(r["drho"])
+        if r["converged"]:
+            break
+    return r, hist
+
+
+@pytest.mark.parametrize("tag", ["gamma", "2k", "gamma_kerker"])
+def test_scf_loop_matches_oracle_golden(lib, tag):
+    from paper_1709_10010_amd import _lib
+    g = _golden(tag)
+    c, s, davs, _ = _scf_setup(lib, tag)
+    r, hist = _run(s)
+    log(f"{tag}: {len(hist)} steps, drho {hist[:3]} ... {hist[-2:]}, mu {r['mu']:.12f} vs {g['mu']:.12f}")
+    assert r["converged"]
+    # step by step: the density distance of the first ten mixing steps is the oracle's
+    k = min(10, len(hist) - 1, len(g["hist"]))
+    assert np.abs(np.array(hist[1:k + 1]) - g["hist"][:k]).max() < 1e-7
+    assert abs(r["mu"] - g["mu"]) < 2e-8
+    for key, name in (("e_band", "band"), ("e_hartree", "hartree"), ("e_x", "xc"), ("vxc_n", "vxc_n"),
+                      ("e_total", "total"), ("free_energy", "free")):
+        assert abs(r[key] - g["energy"][name]) < 2e-8, (key, r[key], g["energy"][name])
+    for ik, d in enumerate(davs):
+        th = _lib.pw_davidson_query(d)["theta"]
+        assert np.abs(th - g["eig"][ik]).max() < 2e-8
+    n_in, _ = s.density()
+    n = n_in.cpu().numpy()
+    nmax = max(v for *_, v in g["n"])
+    err = max(abs(n[i, j, k] - v) for i, j, k, v in g["n"])
+    log(f"{tag}: density sample err {err:.2e} of max {nmax:.3e}")
+    assert err < 1e-8 * nmax
+    omega = abs(np.linalg.det(c.A))
+    assert abs(n.sum() * omega / n.size - SCF["nel"]) < 1e-9
+    s.close()
+
+
+def test_scf_kpoints_batched_equals_one_after_another(lib):
+    _, s1, _, _ = _scf_setup(lib, "2k")
+    _, s2, _, b = _scf_setup(lib, "2k", batch_streams=2)
+    for _ in range(4):
+        r1 = s1.step(1e-10, 200, 1e-9)
+        r2 = s2.step(1e-10, 200, 1e-9)
+        log("sequential", r1["drho"], r1["free_energy"], "batched", r2["drho"], r2["free_energy"])
+        for k in r1:
+            assert r1[k] == r2[k], (k, r1[k], r2[k])
+    n1, _ = s1.density()
+    n2, _ = s2.density()
+    assert bool((n1 == n2).all())
+    s1.close()
+    s2.close()
+    b.close()
+
+
+def test_scf_rejects_bad_descriptors(lib):
+    import torch
+    c = synth.make_cell(0)
+    _, pl = problems(c, max_bands=8)
+    d = lib.Davidson(pl, 8, 0, 1e-8)
+    vion = torch.from_numpy(synth.vloc_on_grid(c)).cuda()
+    with pytest.raises(lib.PwError):           # not initialised
+        lib.Scf([pl], [d], [1.0], vion, 4.0, 0.02, 0.5)
+    lib.pw_davidson_init(d, to_gpu_block(start_block(c, 8, pl.npw)))
+    with pytest.raises(lib.PwError):           # more electrons than 8 bands hold
+        lib.Scf([pl], [d], [1.0], vion, 16.0, 0.02, 0.5)
+    with pytest.raises(lib.PwError):           # mixing factor out of range
+        lib.Scf([pl], [d], [1.0], vion, 4.0, 0.02, 1.5)
+    with pytest.raises(lib.PwError):           # negative Kerker wave vector
+        lib.Scf([pl], [d], [1.0], vion, 4.0, 0.02, 0.5, kerker_q0=-1.0)
+    _, p32 = problems(c, precision=lib.PW_MIXED_FP32, max_bands=8)
+    n = torch.zeros(tuple(c.nr), dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.PwError):           # FP64 problems only
+        lib.pw_density(p32, to_gpu_block(start_block(c, 8, pl.npw)), np.ones(8), n)
