@@ -16,9 +16,10 @@ Modules
   mlp          the learned preconditioner's network, loss and optimiser
   lanczos      Lanczos recursion on H and the continued fraction of its resolvent
   scf          density, Hartree and local exchange potentials, mixing, the SCF loop
+  exx          the Fock exchange operator and its adaptively compressed form (ACE)
 
 Parity status: every function is pinned by a test in
 ``tests/test_oracle_pins.py`` except the iteration counts and wall time of
 ``davidson`` ("parity unpinned": the paper prints no such numbers).
 """
-from . import gsphere, grid, hamiltonian, davidson, mlp, lanczos, scf  # noqa: F401
+from . import gsphere, grid, hamiltonian, davidson, mlp, lanczos, scf, exx  # noqa: F401

@@ -671,3 +671,103 @@ def test_kerker_mixing_weights_each_fourier_component():
     assert np.abs(got - want).max() < 1e-13
     assert np.abs(sc.mix(n_in, n_out, alpha) - (n_in + alpha * (n_out - n_in))).max() < 1e-15
     assert np.abs(sc.mix(n_in, n_out, alpha, 0.0, A) - sc.mix(n_in, n_out, alpha)).max() == 0.0
+
+
+# ---------------------------------------------------------------- exact exchange and ACE
+from oracle import exx as ex  # noqa: E402
+
+
+def _tiny_problem():
+    c = synth.make_cell(0)
+    return ham.problem_from_cell(c)
+
+
+def test_fock_exchange_of_plane_waves_closed_form():
+    # one occupied plane wave G1, phi the plane wave G2: V_x phi = -4 pi / (Omega |G2 - G1|^2) phi,
+    # and 0 for G2 = G1 (the G = 0 term is dropped)
+    po = _tiny_problem()
+    B = gs.reciprocal(po.A)
+    omega = abs(np.linalg.det(po.A))
+    i1, i2 = 3, 11
+    psi = np.zeros((1, po.npw), complex)
+    psi[0, i1] = 1.0
+    phi = np.zeros((2, po.npw), complex)
+    phi[0, i2] = 1.0
+    phi[1, i1] = 1.0
+    out = ex.vx(po, psi, np.array([1.0]), phi)
+    d = (po.miller[i2] - po.miller[i1]) @ B
+    want = np.zeros_like(phi)
+    want[0, i2] = -4 * np.pi / (omega * (d @ d))
+    assert np.abs(out - want).max() < 1e-13 * abs(want[0, i2])
+    # a weight scales the operator
+    out2 = ex.vx(po, psi, np.array([0.5]), phi[:1])
+    assert np.abs(out2 - 0.5 * want[:1]).max() < 1e-13 * abs(want[0, i2])
+
+
+def test_fock_exchange_against_the_dense_coulomb_kernel():
+    # the periodic kernel K(r - r') = Omega^-1 sum_{G != 0} 4 pi e^{iG.(r - r')} / |G|^2 summed
+    # term by term on the grid, and the integral over r' as a grid sum
+    po = _tiny_problem()
+    rng = np.random.default_rng(23)
+    psi = np.linalg.qr(_rand_c(rng, (po.npw, 2)))[0].T
+    phi = _rand_c(rng, (1, po.npw))
+    w = np.array([1.0, 0.6])
+    got = ex.vx(po, psi, w, phi)
+    nr = po.nr
+    B = gs.reciprocal(po.A)
+    omega = abs(np.linalg.det(po.A))
+    idx = [np.where(np.arange(n) <= n // 2, np.arange(n), np.arange(n) - n) for n in nr]
+    h, k, l = np.meshgrid(*idx, indexing="ij")
+    gm = np.stack([h.ravel(), k.ravel(), l.ravel()], 1)
+    G = gm @ B
+    g2 = np.einsum("ij,ij->i", G, G)
+    jj = np.stack(np.meshgrid(*[np.arange(n) for n in nr], indexing="ij"), -1).reshape(-1, 3) / np.array(nr)
+    ph = np.exp(2j * np.pi * (jj @ gm.T))                       # [r][G] = e^{iG.r}
+    nz = g2 > 0
+    K = (ph[:, nz] * (4 * np.pi / g2[nz])) @ np.conj(ph[:, nz]).T / omega
+    def real_space(c):                                           # psi(r) = Omega^-1/2 sum_G c e^{iG.r}
+        m = po.miller
+        return np.exp(2j * np.pi * (jj @ m.T)) @ c / np.sqrt(omega)
+    psr = [real_space(c) for c in psi]
+    fr = real_space(phi[0])
+    dv = omega / jj.shape[0]
+    vphi = np.zeros_like(fr)
+    for wj, pj in zip(w, psr):
+        vphi -= wj * pj * (K @ (np.conj(pj) * fr) * dv)
+    # back to coefficients: c(G) = Omega^-1/2 * dv * sum_r f(r) e^{-iG.r}
+    want = (np.conj(np.exp(2j * np.pi * (jj @ po.miller.T))).T @ vphi) * dv / np.sqrt(omega)
+    assert np.abs(got[0] - want).max() < 1e-12 * np.abs(want).max()
+
+
+def test_fock_exchange_hermitian_negative_and_rotation_invariant():
+    po = _tiny_problem()
+    rng = np.random.default_rng(29)
+    psi = np.linalg.qr(_rand_c(rng, (po.npw, 3)))[0].T
+    a, b = _rand_c(rng, (1, po.npw)), _rand_c(rng, (1, po.npw))
+    one = np.ones(3)
+    va, vb = ex.vx(po, psi, one, a), ex.vx(po, psi, one, b)
+    assert abs(np.vdot(a, vb) - np.conj(np.vdot(b, va))) < 1e-12 * abs(np.vdot(a, vb))
+    assert np.vdot(a, va).real < 0
+    # the operator depends on the occupied manifold, not on the orbitals chosen in it
+    Uq = np.linalg.qr(_rand_c(rng, (3, 3)))[0]
+    assert np.abs(ex.vx(po, Uq.T @ psi, one, a) - va).max() < 1e-12 * np.abs(va).max()
+
+
+def test_ace_is_exact_on_the_occupied_manifold():
+    po = _tiny_problem()
+    rng = np.random.default_rng(31)
+    psi = np.linalg.qr(_rand_c(rng, (po.npw, 4)))[0].T
+    w = np.ones(4)
+    xi, M = ex.ace(po, psi, w)
+    assert np.abs(M - M.conj().T).max() < 1e-12 * np.abs(M).max()
+    assert np.all(np.linalg.eigvalsh(M) < 0)
+    # on the occupied states (and their combinations) ACE is V_x
+    c = _rand_c(rng, (2, 4)) @ psi
+    assert np.abs(ex.ace_apply(xi, M, c) - ex.vx(po, psi, w, c)).max() < 1e-12 * np.abs(xi).max()
+    # outside it, ACE is the projection <xi| M^-1 |xi>: Hermitian, and it differs from V_x
+    a, b = _rand_c(rng, (1, po.npw)), _rand_c(rng, (1, po.npw))
+    aa, ab = ex.ace_apply(xi, M, a), ex.ace_apply(xi, M, b)
+    assert abs(np.vdot(a, ab) - np.conj(np.vdot(b, aa))) < 1e-12 * abs(np.vdot(a, ab))
+    assert np.abs(aa - ex.vx(po, psi, w, a)).max() > 1e-3 * np.abs(aa).max()
+    # the exchange energy is the trace of the compressed operator on the occupied states
+    assert abs(ex.exchange_energy(po, psi, w) - np.real(np.trace(M))) < 1e-12 * abs(np.trace(M))
