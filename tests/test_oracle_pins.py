@@ -677,7 +677,7 @@ def test_kerker_mixing_weights_each_fourier_component():
 from oracle import exx as ex  # noqa: E402
 
 
-def _tiny_problem():
+def _tiny_gamma_problem():
     c = synth.make_cell(0)
     return ham.problem_from_cell(c)
 
@@ -685,7 +685,7 @@ def _tiny_problem():
 def test_fock_exchange_of_plane_waves_closed_form():
     # one occupied plane wave G1, phi the plane wave G2: V_x phi = -4 pi / (Omega |G2 - G1|^2) phi,
     # and 0 for G2 = G1 (the G = 0 term is dropped)
-    po = _tiny_problem()
+    po = _tiny_gamma_problem()
     B = gs.reciprocal(po.A)
     omega = abs(np.linalg.det(po.A))
     i1, i2 = 3, 11
@@ -707,7 +707,7 @@ def test_fock_exchange_of_plane_waves_closed_form():
 def test_fock_exchange_against_the_dense_coulomb_kernel():
     # the periodic kernel K(r - r') = Omega^-1 sum_{G != 0} 4 pi e^{iG.(r - r')} / |G|^2 summed
     # term by term on the grid, and the integral over r' as a grid sum
-    po = _tiny_problem()
+    po = _tiny_gamma_problem()
     rng = np.random.default_rng(23)
     psi = np.linalg.qr(_rand_c(rng, (po.npw, 2)))[0].T
     phi = _rand_c(rng, (1, po.npw))
@@ -740,7 +740,7 @@ def test_fock_exchange_against_the_dense_coulomb_kernel():
 
 
 def test_fock_exchange_hermitian_negative_and_rotation_invariant():
-    po = _tiny_problem()
+    po = _tiny_gamma_problem()
     rng = np.random.default_rng(29)
     psi = np.linalg.qr(_rand_c(rng, (po.npw, 3)))[0].T
     a, b = _rand_c(rng, (1, po.npw)), _rand_c(rng, (1, po.npw))
@@ -754,7 +754,7 @@ def test_fock_exchange_hermitian_negative_and_rotation_invariant():
 
 
 def test_ace_is_exact_on_the_occupied_manifold():
-    po = _tiny_problem()
+    po = _tiny_gamma_problem()
     rng = np.random.default_rng(31)
     psi = np.linalg.qr(_rand_c(rng, (po.npw, 4)))[0].T
     w = np.ones(4)
