@@ -96,6 +96,8 @@ def parse():
     ap.add_argument("--learned-cells", type=int, default=10)
     ap.add_argument("--no-lanczos", action="store_true")
     ap.add_argument("--lanczos-steps", type=int, default=40)
+    ap.add_argument("--no-scf", action="store_true")
+    ap.add_argument("--scf-steps", type=int, default=30, help="at most this many SCF steps on the medium workload")
     ap.add_argument("--profile-davidson", action="store_true",
                     help="only run one FP64 Davidson solve of k-point 0 of the medium workload (256 bands, "
                          "1e-8 Ry) after a warm-up solve, for kernel profiles, and exit")
@@ -556,6 +558,150 @@ def lanczos_section(steps: int):
     return out
 
 
+def _scf_golden(tag):
+    out = {"energy": {}, "eig": {}, "n": []}
+    with open(os.path.join(GOLDEN, f"config1_scf_{tag}.txt")) as f:
+        for line in f:
+            w = line.split()
+            if not w or w[0].startswith("#"):
+                continue
+            if w[0] == "mu":
+                out["mu"] = float(w[1])
+            elif w[0] == "energy":
+                out["energy"][w[1]] = float(w[2])
+            elif w[0] == "eig":
+                out["eig"][int(w[1])] = np.array([float(x) for x in w[2:]])
+            elif w[0] == "n":
+                out["n"].append((int(w[1]), int(w[2]), int(w[3]), float(w[4])))
+    return out
+
+
+def scf_section(steps: int, nstreams: int):
+    """SCF loop around the solver.  Config-1 cell (12 electrons in 16 bands,
+    Fermi width 0.02 Ha, linear mixing 0.5) at Gamma and at two k-points, to
+    int |n_out - n_in| / N_el < 1e-9: time to convergence and errors against
+    the oracle's converged loop (tests/golden).  Medium workload (5 k-points,
+    256 bands, 320 electrons, width 0.02 Ha, Kerker mixing alpha 0.8, q0 1
+    bohr^-1), the k-point solves side by side on streams, each step's
+    Davidson target 1e-2 of the last density distance (between 5e-9 and
+    1e-4 Ha): time to int |n_out - n_in| / N_el < 1e-6 (at most `steps`
+    steps), seconds per step and the density distance, plus the density (256
+    bands of one k-point) and Hartree/exchange kernels timed alone."""
+    import torch
+    import synth
+    from paper_1709_10010_amd import _lib
+    from paper_1709_10010_amd.problems import band_block, build_problem
+    out = {}
+    kp = {"gamma": ([[0.0, 0.0, 0.0]], [1.0]), "2k": ([[0.0, 0.0, 0.0], [0.25, 0.1, -0.3]], [0.5, 0.5])}
+    for tag, (kpts, kw) in kp.items():
+        g = _scf_golden(tag)
+        c = synth.make_cell(1)
+        c.kpts = np.asarray(kpts)
+        probs, davs = [], []
+        for ik in range(len(kpts)):
+            p, _ = build_problem(c, ik, max_bands=16)
+            d = _lib.Davidson(p, 16, 0, 1e-10)
+            x0 = band_block(16, p.npw)
+            x0[:, :p.npw] = torch.from_numpy(synth.psi_start(c.seed, 16, p.npw, ik)).cuda()
+            _lib.pw_davidson_init(d, x0)
+            probs.append(p)
+            davs.append(d)
+        vion = torch.from_numpy(synth.vloc_on_grid(c)).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = _lib.Scf(probs, davs, kw, vion, 12.0, 0.02, 0.5)
+        hist = []
+        for _ in range(150):
+            r = s.step(1e-10, 200, 1e-9)
+            hist.append(r["drho"])
+            if r["converged"]:
+                break
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        n_in, _ = s.density()
+        n = n_in.cpu().numpy()
+        eig = max(float(np.abs(_lib.pw_davidson_query(d)["theta"] - g["eig"][ik]).max()) for ik, d in enumerate(davs))
+        out[f"config1_{tag}"] = {
+            "seconds": round(dt, 4), "steps": len(hist), "converged": r["converged"],
+            "abs_mu_minus_oracle_Ha": abs(r["mu"] - g["mu"]),
+            "abs_free_energy_minus_oracle_Ha": abs(r["free_energy"] - g["energy"]["free"]),
+            "max_abs_eig_minus_oracle_Ha": eig,
+            "max_density_sample_err_rel": max(abs(n[i, j, k] - v) for i, j, k, v in g["n"]) /
+            max(v for *_, v in g["n"])}
+        s.close()
+        for d in davs:
+            d.close()
+        for p in probs:
+            p.close()
+    # medium workload
+    cell = synth.make_cell(2)
+    nk, nb = len(cell.kpts), cell.nbands
+    probs, davs = [], []
+    for ik in range(nk):
+        p, _ = build_problem(cell, ik, max_bands=nb)
+        fixed_tuning(p, "fp64")
+        d = _lib.Davidson(p, nb, 0, 5e-9)
+        x0 = band_block(nb, p.npw)
+        x0[:, :p.npw] = torch.from_numpy(synth.psi_start(cell.seed, nb, p.npw, ik)).cuda()
+        _lib.pw_davidson_init(d, x0)
+        probs.append(p)
+        davs.append(d)
+    streams = [torch.cuda.Stream() for _ in range(max(1, min(nstreams, nk)))]
+    torch.cuda.synchronize()
+    batch = _lib.BatchDavidson(davs, streams)
+    vion = torch.from_numpy(synth.vloc_on_grid(cell)).cuda()
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    s = _lib.Scf(probs, davs, [1.0 / nk] * nk, vion, 320.0, 0.02, 0.8, batch=batch, kerker_q0=1.0)
+    per_step, hist, dtol = [], [], 1e-4
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.step(dtol, 60, 1e-6)
+        torch.cuda.synchronize()
+        per_step.append(round(time.perf_counter() - t0, 4))
+        hist.append(r["drho"])
+        if r["converged"]:
+            break
+        if r["drho"] > 0:
+            dtol = min(1e-4, max(5e-9, 1e-2 * r["drho"]))
+    t_all = time.perf_counter() - t_all
+    # the grid kernels alone: density of 256 bands of k-point 0, Hartree + exchange
+    x = band_block(nb, probs[0].npw)
+    _lib.pw_davidson_vectors(davs[0], x)
+    n = torch.zeros(tuple(cell.nr), dtype=torch.float64, device="cuda")
+    f = np.full(nb, 2.0 / nk)
+    _lib.pw_density(probs[0], x, f, n)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        _lib.pw_density(probs[0], x, f, n)
+    torch.cuda.synchronize()
+    t_rho = (time.perf_counter() - t0) / 3
+    t0 = time.perf_counter()
+    for _ in range(3):
+        _lib.pw_hxc(probs[0], n)
+    torch.cuda.synchronize()
+    t_hxc = (time.perf_counter() - t0) / 3
+    out["medium_workload"] = {
+        "workload": f"a=20 bohr, 30 Ry, 72^3, 64 atoms, {nb} bands x {nk} k-points, 320 electrons, Fermi width "
+                    f"0.02 Ha, Kerker mixing alpha 0.8 q0 1/bohr, k-point solves side by side on {len(streams)} "
+                    f"streams, Davidson target 1e-2 of the last density distance (5e-9 .. 1e-4 Ha, at most 60 "
+                    f"iterations) per SCF step",
+        "seconds_to_1e-6": round(t_all, 3) if r["converged"] else None, "steps": len(hist),
+        "converged": r["converged"],
+        "seconds_per_step": per_step, "drho_per_step": hist, "mu_Ha": r["mu"], "free_energy_Ha": r["free_energy"],
+        "density_256_bands_ms": round(t_rho * 1e3, 3), "hartree_exchange_ms": round(t_hxc * 1e3, 3)}
+    s.close()
+    batch.close()
+    for d in davs:
+        d.close()
+    for p in probs:
+        p.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def davidson_cpu_baseline(dav):
     """Oracle FP64 Davidson on the config-1 cell (host cores)."""
     from oracle import davidson as odv
@@ -773,6 +919,9 @@ def main():
     if not args.no_lanczos:
         out["lanczos_recursion"] = lanczos_section(args.lanczos_steps)
         note("Lanczos section done")
+    if not args.no_scf:
+        out["scf"] = scf_section(args.scf_steps, args.streams + 1)
+        note("SCF section done")
     if not args.no_batched:
         out["batched_ragged_cells"] = batched_section(args.batched_cells, max(3, args.steps // 2), args.streams,
                                                       learned_net=net)

@@ -79,7 +79,8 @@ typedef int32_t pw_status;
 #define PW_TERM_KINETIC 1
 #define PW_TERM_LOCAL 2
 #define PW_TERM_NONLOCAL 4
-#define PW_TERM_ALL 7
+#define PW_TERM_EXX 8      /* the exact-exchange term attached by pw_ace_set (none otherwise) */
+#define PW_TERM_ALL 15
 
 /* preconditioners */
 #define PW_PRECOND_NONE 0
@@ -173,7 +174,8 @@ pw_status pw_problem_info(const pw_problem *p, int64_t *npw, int64_t *nsticks,
 
 /*
  * hpsi[n] = H psi[n] for n < nbands (terms selected by `terms`, a mask of
- * PW_TERM_*; PW_TERM_ALL for the full operator):
+ * PW_TERM_*; PW_TERM_ALL for the full operator, with the exact-exchange
+ * term when pw_ace_set attached one):
  *   kinetic   t(G) psi(G), t = |k+G|^2 / 2
  *   local     sum_G' V~(G - G') psi(G'),  V~(q) = N^-3 sum_j V(r_j) e^{-i q.r_j}
  *             (applied as scatter -> inverse 3D FFT -> x V(r) -> forward 3D FFT -> gather)
@@ -546,6 +548,7 @@ pw_status pw_lanczos_resolvent(pw_lanczos *l, const void *z, int32_t nz, void *g
 #define PW_STAGE_EIG 10       /* Davidson Hermitian eigensolve          */
 #define PW_STAGE_CHOL 11      /* Davidson Cholesky / triangular solves  */
 #define PW_STAGE_VEC 12       /* Davidson vector kernels (norms, copies)*/
+#define PW_STAGE_EXX 13       /* exact-exchange term of H psi (ACE)     */
 #define PW_NSTAGES 16
 pw_status pw_profile_enable(pw_problem *p, int32_t on);
 pw_status pw_profile_read(pw_problem *p, double *ms_total, int64_t *launches, int32_t reset);
@@ -629,6 +632,43 @@ pw_status pw_scf_step(pw_scf *s, double dav_tol, int32_t dav_max_iter, double to
  * use.  Stream-ordered. */
 pw_status pw_scf_density(pw_scf *s, double *n_in, double *n_out, void *stream);
 pw_status pw_scf_potential(pw_scf *s, double *v, void *stream);
+
+/*
+ * Exact (Fock) exchange and its adaptively compressed form, ACE (the paper's
+ * exact-exchange section, eqs. Vx, Poisson, Vxace).  Spin-unpolarised,
+ * Hartree units, Gamma point only (k = 0, else PW_ERR_INVALID):
+ *   (V_x phi)(r) = - sum_j w_j psi_j(r) v_j(r),  v_j(G) = 4 pi rho_j(G) / |G|^2
+ *   (0 at G = 0),  rho_j = psi_j^* phi,
+ * over the nocc occupied states psi_j (device complex128 [nocc][ld_occ]) with
+ * weights w (host double [nocc]; 1 for a fully occupied spatial orbital).
+ * FP64 problems without augmentation.
+ */
+/* Bytes of device scratch pw_vx needs (the occupied states on the full grid
+ * among them: nocc N0 N1 N2 complex). */
+pw_status pw_vx_workspace_size(const pw_problem *p, int64_t nocc, size_t *bytes);
+/* out[i] = V_x phi_i for nphi bands (device complex128 [nphi][ld], out distinct
+ * from phi), by pair densities and reciprocal-space Poisson solves on the
+ * full grid: nocc pair transforms per band. */
+pw_status pw_vx(pw_problem *p, const void *psi_occ, int64_t ld_occ, int64_t nocc, const double *w,
+                const void *phi, int64_t ld_phi, int64_t nphi, void *out, int64_t ld_out, void *work,
+                size_t work_bytes, void *stream);
+/* Bytes of device scratch pw_ace_set needs. */
+pw_status pw_ace_workspace_size(const pw_problem *p, int64_t nocc, size_t *bytes);
+/* Build ACE from the occupied states: xi = V_x psi, M = <psi|xi> (negative
+ * definite, else PW_ERR_NUMERIC), zeta = -xi L^-H with -M = L L^H, so that
+ * V_ace = xi M^-1 xi^H = -zeta zeta^H, exact on the occupied manifold; then
+ * attach alpha V_ace to the problem: pw_hpsi with PW_TERM_EXX (part of
+ * PW_TERM_ALL) adds -alpha zeta (zeta^H psi).  zeta (device complex128
+ * [nocc][ldz], ldz >= npw) and proj (device complex128 of nocc * max_bands
+ * values, the scratch of that term) are the caller's and stay bound to the
+ * problem until pw_ace_clear, another pw_ace_set or destroy.  A Davidson
+ * state on the problem must be refreshed with pw_davidson_set_problem.
+ * Synchronises the stream. */
+pw_status pw_ace_set(pw_problem *p, const void *psi_occ, int64_t ld_occ, int64_t nocc, const double *w,
+                     double alpha, void *zeta, int64_t ldz, void *proj, void *work, size_t work_bytes,
+                     void *stream);
+/* Detach the exchange term. */
+pw_status pw_ace_clear(pw_problem *p);
 
 #ifdef __cplusplus
 }

@@ -20,7 +20,7 @@ LIBPATH = os.path.join(HERE, "libpwhip.so")
 PW_OK = 0
 PW_NOT_CONVERGED = 1
 PW_FP64, PW_MIXED_FP32, PW_MIXED_BF16 = 0, 1, 2
-PW_TERM_KINETIC, PW_TERM_LOCAL, PW_TERM_NONLOCAL, PW_TERM_ALL = 1, 2, 4, 7
+PW_TERM_KINETIC, PW_TERM_LOCAL, PW_TERM_NONLOCAL, PW_TERM_EXX, PW_TERM_ALL = 1, 2, 4, 8, 15
 PW_PRECOND_NONE, PW_PRECOND_TPA, PW_PRECOND_MLP = 0, 1, 2
 PW_PLANE_REGISTER, PW_PLANE_WAVE, PW_PLANE_LDS = 0, 1, 2
 STATUS_NAMES = {0: "PW_OK", 1: "PW_NOT_CONVERGED", -1: "PW_ERR_INVALID", -2: "PW_ERR_SHAPE",
@@ -134,6 +134,11 @@ def _load():
         "pw_scf_step": (i32, [vp, f64, i32, f64, C.POINTER(f64), C.POINTER(i32)]),
         "pw_scf_density": (i32, [vp, vp, vp, vp]),
         "pw_scf_potential": (i32, [vp, vp, vp]),
+        "pw_vx_workspace_size": (i32, [vp, i64, C.POINTER(C.c_size_t)]),
+        "pw_vx": (i32, [vp, vp, i64, i64, C.POINTER(f64), vp, i64, i64, vp, i64, vp, C.c_size_t, vp]),
+        "pw_ace_workspace_size": (i32, [vp, i64, C.POINTER(C.c_size_t)]),
+        "pw_ace_set": (i32, [vp, vp, i64, i64, C.POINTER(f64), f64, vp, i64, vp, vp, C.c_size_t, vp]),
+        "pw_ace_clear": (i32, [vp]),
         "pw_profile_enable": (i32, [vp, i32]),
         "pw_profile_read": (i32, [vp, C.POINTER(f64), C.POINTER(i64), i32]),
     }
@@ -337,7 +342,7 @@ def pw_precond(prob: Problem, kind: int, theta, x, r, t, net=None, stream=None) 
 
 PW_NSTAGES = 16
 STAGES = ["zfft_inv", "plane", "zfft_fwd", "kinetic", "proj", "dmat", "nlupd", "precond",
-          "subgemm", "updgemm", "eig", "chol", "vec"]
+          "subgemm", "updgemm", "eig", "chol", "vec", "exx"]
 
 
 def pw_profile_enable(prob: Problem, on: bool = True) -> None:
@@ -992,3 +997,46 @@ class Scf:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- exact exchange
+def pw_vx(prob: Problem, psi_occ, w, phi, out, stream=None) -> None:
+    """out = V_x phi (Gamma point) from the occupied bands psi_occ with weights w."""
+    po, ldo, no = _band_block(psi_occ, "psi_occ", prob.npw)
+    pp, ldp, nph = _band_block(phi, "phi", prob.npw)
+    pq, ldq, nq = _band_block(out, "out", prob.npw)
+    if nq < nph:
+        raise ValueError("out has fewer bands than phi")
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    if w.shape != (no,):
+        raise ValueError("one weight per occupied band")
+    nbytes = C.c_size_t(0)
+    _check(LIB.pw_vx_workspace_size(prob.handle, no, C.byref(nbytes)))
+    work = _workspace(nbytes.value)
+    _check(LIB.pw_vx(prob.handle, po, ldo, no, w.ctypes.data_as(C.POINTER(C.c_double)), pp, ldp, nph, pq, ldq,
+                     C.c_void_p(work.data_ptr()), nbytes.value, _stream(stream)))
+
+
+def pw_ace_set(prob: Problem, psi_occ, w, alpha: float = 1.0, stream=None) -> None:
+    """Attach alpha V_ace built from psi_occ to H psi; the zeta and projection
+    buffers are allocated here and kept on the Problem object."""
+    import torch
+    po, ldo, no = _band_block(psi_occ, "psi_occ", prob.npw)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    if w.shape != (no,):
+        raise ValueError("one weight per occupied band")
+    ld = (prob.npw + 63) // 64 * 64
+    zeta = torch.zeros((no, ld), dtype=torch.complex128, device="cuda")
+    proj = torch.zeros((prob.max_bands, no), dtype=torch.complex128, device="cuda")
+    nbytes = C.c_size_t(0)
+    _check(LIB.pw_ace_workspace_size(prob.handle, no, C.byref(nbytes)))
+    work = _workspace(nbytes.value)
+    _check(LIB.pw_ace_set(prob.handle, po, ldo, no, w.ctypes.data_as(C.POINTER(C.c_double)), float(alpha),
+                          C.c_void_p(zeta.data_ptr()), ld, C.c_void_p(proj.data_ptr()),
+                          C.c_void_p(work.data_ptr()), nbytes.value, _stream(stream)))
+    prob.ace = (zeta, proj)
+
+
+def pw_ace_clear(prob: Problem) -> None:
+    _check(LIB.pw_ace_clear(prob.handle))
+    prob.ace = None

@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpwhip.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "fft.hip", "gemm.hip", "nonlocal.hip", "linalg.hip", "davidson.hip", "mlp.hip", "batch.hip", "lanczos.hip", "overlap.hip", "noalloc.hip", "scf.hip"]
+SOURCES = ["api.hip", "fft.hip", "gemm.hip", "nonlocal.hip", "linalg.hip", "davidson.hip", "mlp.hip", "batch.hip", "lanczos.hip", "overlap.hip", "noalloc.hip", "scf.hip", "exx.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}",

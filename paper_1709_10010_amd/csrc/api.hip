@@ -111,6 +111,8 @@ static int build_stick_map(pw_problem *p, const int32_t *miller, int ts) {
   sm.stick_cpos.resize(sm.nst);
   for (int s = 0; s < sm.nst; ++s)
     sm.stick_cpos[s] = sm.xslot[sm.stick_xy[s] / n1] * sm.ls + sm.stick_xy[s] % n1;
+  sm.gfull.resize(npw);
+  for (int64_t g = 0; g < npw; ++g) sm.gfull[g] = (gx[g] * n1 + gy[g]) * n2 + gz[g];
   sm.stick_cy.clear();
   if (sm.nst <= 32767) {
     sm.stick_cy.assign((size_t)sm.nx * n1, -1);
@@ -226,7 +228,7 @@ static void free_problem(pw_problem *p) {
   // the workspace regions belong to the caller
   void *bufs[] = {p->d_gidx,  p->d_gpos,       p->d_tile_ptr, p->d_stick_xy, p->d_xlist,
                   p->d_xslot, p->d_stick_cpos, p->d_kin,      p->d_tw,       p->d_dij,
-                  p->d_pj_atom, p->d_proj_off, p->d_dij_off, p->d_stick_cy};
+                  p->d_pj_atom, p->d_proj_off, p->d_dij_off, p->d_stick_cy, p->d_gfull};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -427,6 +429,7 @@ pw_status pw_problem_create(const pw_problem_desc *d, int64_t max_bands, void *w
   if ((rc = upload(&p->d_xslot, sm.xslot)) != PW_OK) return fail(rc);
   if ((rc = upload(&p->d_stick_cpos, sm.stick_cpos)) != PW_OK) return fail(rc);
   if ((rc = upload(&p->d_stick_cy, sm.stick_cy)) != PW_OK) return fail(rc);
+  if ((rc = upload(&p->d_gfull, sm.gfull)) != PW_OK) return fail(rc);
 
   // twiddles (x, y, z back to back) in the FFT precision
   std::vector<unsigned char> tw;
@@ -662,6 +665,13 @@ pw_status pw_hpsi(pw_problem *p, const void *psi, int64_t ld_psi, void *hpsi, in
     }
     if (rc != PW_OK) {
       set_error("pw_hpsi: nonlocal launch failed");
+      return rc;
+    }
+  }
+  if ((terms & PW_TERM_EXX) && p->ace_zeta) {
+    ProfScope ps_(&p->prof, PW_STAGE_EXX, s);
+    if ((rc = ace_hpsi(p, psi, ld_psi, hpsi, ld_hpsi, nbands, s)) != PW_OK) {
+      set_error("pw_hpsi: exchange launch failed");
       return rc;
     }
   }

@@ -91,6 +91,7 @@ struct StickMap {
   // stick index of each (slot, y) of the compact plane, -1 where there is
   // none: [nx][N1], kept when every index fits 16 bits (else empty)
   std::vector<int16_t> stick_cy;
+  std::vector<int32_t> gfull;     // [npw] full-grid index (x N1 + y) N2 + z of each G, caller's order
 };
 
 // Device-side view passed to the FFT launchers.
@@ -164,6 +165,7 @@ struct pw_problem {
   int32_t *d_stick_xy = nullptr, *d_xlist = nullptr;
   int32_t *d_xslot = nullptr, *d_stick_cpos = nullptr;
   int16_t *d_stick_cy = nullptr;
+  int32_t *d_gfull = nullptr;
   double *d_kin = nullptr;
   void *d_tw = nullptr;        // three twiddle tables back to back
   double *d_dij = nullptr;     // concatenated blocks
@@ -199,6 +201,12 @@ struct pw_problem {
   double2 *d_ov_mat = nullptr; // set-up scratch: 5 nproj^2 complex
   void *d_ov_eig = nullptr;    // set-up scratch: eigensolver workspace
   int *d_ov_flag = nullptr;
+  // exact exchange attached by pw_ace_set: H psi gains -alpha zeta zeta^H psi
+  // (caller-owned buffers, bound until pw_ace_clear or destroy)
+  const double2 *ace_zeta = nullptr;  // [nocc][ldz]
+  int64_t ace_ldz = 0, ace_nocc = 0;
+  double ace_alpha = 0.0;
+  double2 *ace_proj = nullptr;        // [max_bands][nocc] scratch of the H psi term
 };
 
 namespace pw {
@@ -217,8 +225,9 @@ int launch_kinetic_only(const double *kin, const void *psi, int64_t ld, void *hp
                         int64_t npw, int nb, bool kinetic, hipStream_t s);
 // full-grid 3D transform of a complex FP64 grid [N0][N1][N2] in place
 // (inverse unnormalised, forward with N^-3), and the band-density plane pass
-// (part[group][z][x][y] += w_b |u_b|^2 for the bands in the stick buffer)
-int launch_grid_fft(const FFTDev &f, double2 *g, bool inverse, hipStream_t s);
+// (part[group][z][x][y] += w_b |u_b|^2 for the bands in the stick buffer);
+// nbatch grids `stride` elements apart
+int launch_grid_fft(const FFTDev &f, double2 *g, int nbatch, int64_t stride, bool inverse, hipStream_t s);
 int launch_rho_plane(const FFTDev &f, const void *sticks, int nb, int group, const double *w, double *part,
                      hipStream_t s);
 
@@ -282,6 +291,9 @@ void carve_overlap(pw_problem *p, Carve &c);
 int overlap_setup(pw_problem *p, const std::vector<double> &qblocks, const std::vector<int32_t> &poff,
                   hipStream_t s);
 int sinvhalf(pw_problem *p, const void *x, int64_t ldx, void *y, int64_t ldy, int64_t nb, hipStream_t s);
+// Exact-exchange term of H psi (exx.hip): hpsi -= alpha zeta (zeta^H psi).
+int ace_hpsi(pw_problem *p, const void *psi, int64_t ld_psi, void *hpsi, int64_t ld_hpsi, int64_t nbands,
+             hipStream_t s);
 // Davidson state accessors for the batch scheduler (davidson.hip).
 pw_problem *dav_problem(const pw_davidson *d);
 int dav_nbands(const pw_davidson *d);

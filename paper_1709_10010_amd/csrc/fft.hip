@@ -1108,10 +1108,13 @@ void k_plane_p(FFTDev f, cpx_t<T> *__restrict__ sticks, int nb, int group) {
 // workgroup takes T consecutive z-lines.  AXIS 0 / 1: a workgroup takes the
 // N lines along the axis at one y (AXIS 0) or one x (AXIS 1) and T
 // consecutive z, so that its global loads and stores run along z.  The host
-// keeps T * N within kCpt values per thread.
+// keeps T * N within kCpt values per thread.  blockIdx.y picks one of a
+// batch of grids `stride` elements apart.
 template <int AXIS, bool INV, int NTHR>
-__global__ __launch_bounds__(NTHR) void k_grid_axis(FFTDev f, double2 *__restrict__ g, int T, double scale) {
+__global__ __launch_bounds__(NTHR) void k_grid_axis(FFTDev f, double2 *__restrict__ g0, int64_t stride, int T,
+                                                    double scale) {
   extern __shared__ __align__(16) unsigned char smem[];
+  double2 *__restrict__ g = g0 + (int64_t)blockIdx.y * stride;
   const AxisPlan &pl = AXIS == 0 ? f.px : (AXIS == 1 ? f.py : f.pz);
   const int N = pl.n;
   double2 *tw = reinterpret_cast<double2 *>(smem);
@@ -1515,9 +1518,11 @@ int launch_zfft_fwd(const FFTDev &f, int prec, const void *sticks, const void *p
                          : zfwd_t<float>(f, sticks, psi, ld, hpsi, ldh, nb, kinetic, s);
 }
 
-// Full-grid 3D transform of g [N0][N1][N2] (FP64 complex): inverse
-// unnormalised, forward with N^-3 (split as 1/N per axis).
-int launch_grid_fft(const FFTDev &f, double2 *g, bool inverse, hipStream_t s) {
+// Full-grid 3D transforms of nbatch grids [N0][N1][N2] (FP64 complex),
+// `stride` elements apart: inverse unnormalised, forward with N^-3 (split as
+// 1/N per axis).
+int launch_grid_fft(const FFTDev &f, double2 *g, int nbatch, int64_t stride, bool inverse, hipStream_t s) {
+  if (nbatch <= 0) return PW_OK;
   constexpr int NT = 256;
   const int n[3] = {f.n0, f.n1, f.n2};
   for (int ax = 2; ax >= 0; --ax) {
@@ -1532,7 +1537,7 @@ int launch_grid_fft(const FFTDev &f, double2 *g, bool inverse, hipStream_t s) {
       blocks = (int64_t)(ax == 0 ? f.n1 : f.n0) * ((f.n2 + T - 1) / T);
     auto pick = [&](auto k) -> int {
       if (allow_lds(k, lds) != hipSuccess) return PW_ERR_HIP;
-      hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(NT), lds, s, f, g, T, scale);
+      hipLaunchKernelGGL(k, dim3((unsigned)blocks, (unsigned)nbatch), dim3(NT), lds, s, f, g, stride, T, scale);
       return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
     };
     int rc;

@@ -288,7 +288,7 @@ int hxc_impl(pw_problem *p, const double *n, const double *vion, double *v, doub
   const int64_t blocks = std::min<int64_t>(4096, (len + 255) / 256);
   hipLaunchKernelGGL(k_to_complex, dim3((unsigned)blocks), dim3(256), 0, s, n, len, g);
   PW_HIP(hipGetLastError());
-  int rc = launch_grid_fft(p->fft, g, false, s);
+  int rc = launch_grid_fft(p->fft, g, 1, 0, false, s);
   if (rc != PW_OK) return rc;
   Recip B;
   std::copy(p->B, p->B + 9, B.b);
@@ -296,7 +296,7 @@ int hxc_impl(pw_problem *p, const double *n, const double *vion, double *v, doub
   PW_HIP(hipGetLastError());
   double eh = 0.0;
   if ((rc = host_sum(red, kRedBlocks, &eh, s)) != PW_OK) return rc;
-  if ((rc = launch_grid_fft(p->fft, g, true, s)) != PW_OK) return rc;
+  if ((rc = launch_grid_fft(p->fft, g, 1, 0, true, s)) != PW_OK) return rc;
   hipLaunchKernelGGL(k_hxc, dim3(kRedBlocks), dim3(kRedThreads), 0, s, g, n, vion, len, v, red);
   PW_HIP(hipGetLastError());
   double ex = 0.0, evx = 0.0;
@@ -645,13 +645,13 @@ pw_status pw_scf_step(pw_scf *s, double dav_tol, int32_t dav_max_iter, double to
     const int64_t blocks = std::min<int64_t>(4096, (s->len + 255) / 256);
     hipLaunchKernelGGL(k_diff_complex, dim3((unsigned)blocks), dim3(256), 0, st, s->n_out, s->n_in, s->len, g);
     PW_HIP(hipGetLastError());
-    if ((rc = launch_grid_fft(p0->fft, g, false, st)) != PW_OK) return rc;
+    if ((rc = launch_grid_fft(p0->fft, g, 1, 0, false, st)) != PW_OK) return rc;
     Recip B;
     std::copy(p0->B, p0->B + 9, B.b);
     hipLaunchKernelGGL(k_kerker, dim3((unsigned)blocks), dim3(256), 0, st, g, p0->nr[0], p0->nr[1], p0->nr[2], B,
                        s->alpha, s->q0 * s->q0);
     PW_HIP(hipGetLastError());
-    if ((rc = launch_grid_fft(p0->fft, g, true, st)) != PW_OK) return rc;
+    if ((rc = launch_grid_fft(p0->fft, g, 1, 0, true, st)) != PW_OK) return rc;
     hipLaunchKernelGGL(k_add_real, dim3((unsigned)blocks), dim3(256), 0, st, s->n_in, g, s->len);
     PW_HIP(hipGetLastError());
   } else {

@@ -1,0 +1,123 @@
+"""GPU exact exchange (pw_vx) and ACE (pw_ace_set + the PW_TERM_EXX term of
+pw_hpsi) against the FP64 oracle (oracle/exx.py), Gamma point.
+
+pw_vx elementwise against the oracle's pair-density route (itself pinned to
+the periodic Coulomb kernel summed term by term); the ACE term of H psi
+against the oracle's xi M^-1 xi^H, and against V_x itself on the occupied
+manifold, where ACE is exact; a Davidson solve with the term attached
+against dense diagonalisation of H + alpha V_ace.  Tolerance 1e-11 of the
+largest value (the GPU sums the pair terms and the GEMMs in another order).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import exx as oex
+from oracle import hamiltonian as ham
+
+from gpu_util import from_gpu_block, log, problems, rel_err, start_block, to_gpu_block
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1709_10010_amd import _lib
+    return _lib
+
+
+def _occupied(seed, nocc, npw):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((npw, nocc)) + 1j * rng.standard_normal((npw, nocc))
+    return np.linalg.qr(X)[0].T.copy()
+
+
+@pytest.mark.parametrize("cfg,nocc,nphi", [(0, 3, 5), (1, 20, 7)])
+def test_vx_matches_oracle(lib, cfg, nocc, nphi):
+    import torch
+    c = synth.make_cell(cfg)
+    po, pl = problems(c, max_bands=max(nocc, nphi))
+    occ = _occupied(80 + cfg, nocc, po.npw)
+    w = np.linspace(1.0, 0.3, nocc)
+    phi = start_block(c, nphi, po.npw)
+    out = torch.zeros_like(to_gpu_block(phi))
+    lib.pw_vx(pl, to_gpu_block(occ), w, to_gpu_block(phi), out)
+    got = from_gpu_block(out, po.npw)
+    want = oex.vx(po, occ, w, phi)
+    err = rel_err(got, want)
+    log(f"cfg{cfg}: {nocc} occupied, {nphi} bands: V_x rel err {err:.2e}")
+    assert err < 1e-11
+
+
+@pytest.mark.parametrize("cfg,nocc,alpha", [(0, 4, 1.0), (1, 12, 0.25)])
+def test_ace_term_of_hpsi_matches_oracle(lib, cfg, nocc, alpha):
+    import torch
+    c = synth.make_cell(cfg)
+    nb = 10
+    po, pl = problems(c, max_bands=max(nb, nocc))
+    occ = _occupied(90 + cfg, nocc, po.npw)
+    w = np.ones(nocc)
+    psi = start_block(c, nb, po.npw)
+    x = to_gpu_block(psi)
+    y0, y1 = torch.zeros_like(x), torch.zeros_like(x)
+    lib.pw_hpsi(pl, x, y0)
+    lib.pw_ace_set(pl, to_gpu_block(occ), w, alpha)
+    lib.pw_hpsi(pl, x, y1)
+    term = from_gpu_block(y1, po.npw) - from_gpu_block(y0, po.npw)
+    xi, M = oex.ace(po, occ, w)
+    want = alpha * oex.ace_apply(xi, M, psi)
+    err = rel_err(term, want)
+    log(f"cfg{cfg}: ACE term rel err {err:.2e}")
+    assert err < 1e-11
+    # on the occupied manifold ACE is V_x
+    yo = torch.zeros_like(to_gpu_block(occ))
+    yb = torch.zeros_like(yo)
+    lib.pw_hpsi(pl, to_gpu_block(occ), yo)
+    lib.pw_hpsi(pl, to_gpu_block(occ), yb, terms=lib.PW_TERM_ALL & ~lib.PW_TERM_EXX)
+    exact = alpha * oex.vx(po, occ, w, occ)
+    assert rel_err(from_gpu_block(yo, po.npw) - from_gpu_block(yb, po.npw), exact) < 1e-11
+    # detached: H psi is the plain one again
+    lib.pw_ace_clear(pl)
+    y2 = torch.zeros_like(x)
+    lib.pw_hpsi(pl, x, y2)
+    assert bool((y2 == y0).all())
+
+
+def test_davidson_with_ace_matches_dense(lib):
+    c = synth.make_cell(1)
+    nb, nocc, alpha = 16, 8, 0.5
+    po, pl = problems(c, max_bands=nb)
+    w0, X0 = ham.eigh_lowest(po, nocc)           # the bare occupied states build the operator
+    w = np.ones(nocc)
+    lib.pw_ace_set(pl, to_gpu_block(X0), w, alpha)
+    r = lib.davidson_solve(pl, to_gpu_block(start_block(c, nb, po.npw)), tol=5e-9)
+    xi, M = oex.ace(po, X0, w)
+    H = ham.dense_h(po) + alpha * (xi.T @ np.linalg.solve(M, np.conj(xi)))
+    want = np.linalg.eigvalsh((H + H.conj().T) / 2)[:nb]
+    err = float(np.abs(r["theta"] - want).max())
+    log(f"Davidson with ACE: {r['iterations']} iterations, max |theta - dense| {err:.2e} Ha")
+    assert r["converged"] and err < 5e-9
+
+
+def test_exchange_rejects_what_it_does_not_cover(lib):
+    import torch
+    c = synth.make_cell(0)
+    po, pl = problems(c, max_bands=4)
+    occ = to_gpu_block(_occupied(5, 2, po.npw))
+    out = torch.zeros_like(occ)
+    dup = occ.clone()
+    dup[1] = dup[0]
+    with pytest.raises(lib.PwError):          # dependent occupied states make M singular
+        lib.pw_ace_set(pl, dup, np.ones(2))
+    with pytest.raises(lib.PwError):          # so do zero weights (M = 0)
+        lib.pw_ace_set(pl, occ, np.zeros(2))
+    ck = synth.make_cell(0)
+    ck.kpts = np.array([[0.1, 0.0, 0.0]])
+    _, pk = problems(ck, max_bands=4)
+    with pytest.raises(lib.PwError):          # Gamma point only
+        lib.pw_vx(pk, occ, np.ones(2), occ, out)
+    _, p32 = problems(c, precision=lib.PW_MIXED_FP32, max_bands=4)
+    with pytest.raises(lib.PwError):          # FP64 problems only
+        lib.pw_vx(p32, occ, np.ones(2), occ, out)
