@@ -97,6 +97,7 @@ def parse():
     ap.add_argument("--no-lanczos", action="store_true")
     ap.add_argument("--lanczos-steps", type=int, default=40)
     ap.add_argument("--no-scf", action="store_true")
+    ap.add_argument("--no-exx", action="store_true")
     ap.add_argument("--scf-steps", type=int, default=30, help="at most this many SCF steps on the medium workload")
     ap.add_argument("--profile-davidson", action="store_true",
                     help="only run one FP64 Davidson solve of k-point 0 of the medium workload (256 bands, "
@@ -702,6 +703,63 @@ def scf_section(steps: int, nstreams: int):
     return out
 
 
+def exx_section(nocc: int, nphi: int):
+    """Exact exchange at the medium workload's Gamma point (npw 22119, 72^3):
+    nocc occupied states (the seeded start bands), the Fock operator applied
+    directly to nphi bands (nocc pair densities and Poisson solves per band)
+    against the ACE term of H*psi on all 256 bands (two GEMMs of a rank-nocc
+    projector), and the ACE build itself (V_x on the occupied states, the
+    Cholesky factor and the projector)."""
+    import torch
+    import synth
+    from paper_1709_10010_amd import _lib
+    from paper_1709_10010_amd.problems import band_block, build_problem
+    cell = synth.make_cell(2)
+    nb = cell.nbands
+    p, _ = build_problem(cell, 0, max_bands=nb)
+    fixed_tuning(p, "fp64")
+    x = band_block(nb, p.npw)
+    x[:, :p.npw] = torch.from_numpy(synth.psi_start(cell.seed, nb, p.npw, 0)).cuda()
+    occ = x[:nocc].contiguous()
+    w = np.ones(nocc)
+    out = band_block(nphi, p.npw)
+    _lib.pw_vx(p, occ, w, x[:2].contiguous(), out[:2].contiguous())       # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _lib.pw_vx(p, occ, w, x[:nphi].contiguous(), out)
+    torch.cuda.synchronize()
+    t_vx = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _lib.pw_ace_set(p, occ, w, 1.0)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    y = torch.zeros_like(x)
+    for _ in range(2):
+        _lib.pw_hpsi(p, x, y)
+    _lib.pw_profile_enable(p, True)
+    _lib.pw_profile_read(p, reset=True)
+    for _ in range(5):
+        _lib.pw_hpsi(p, x, y)
+    torch.cuda.synchronize()
+    st = _lib.pw_profile_read(p, reset=True)
+    _lib.pw_profile_enable(p, False)
+    ms_exx = st["exx"][0] / st["exx"][1]
+    ms_hpsi = sum(v[0] for v in st.values()) / st["exx"][1]
+    per_band_direct = t_vx / nphi * 1e3
+    per_band_ace = ms_exx / nb
+    out_d = {"workload": f"a=20 bohr, 30 Ry, Gamma, npw {p.npw}, 72^3 grid, {nocc} occupied states",
+             "vx_direct_ms_per_band": round(per_band_direct, 4), "vx_direct_bands_timed": nphi,
+             "pair_transforms_per_s": round(2 * nocc * nphi / t_vx, 1),
+             "ace_term_ms_per_band": round(per_band_ace, 5),
+             "ace_term_ms_256_bands": round(ms_exx, 4), "hpsi_with_ace_ms_256_bands": round(ms_hpsi, 4),
+             "ace_apply_speedup_per_band": round(per_band_direct / per_band_ace, 1),
+             "ace_build_s": round(t_build, 4)}
+    _lib.pw_ace_clear(p)
+    p.close()
+    torch.cuda.empty_cache()
+    return out_d
+
+
 def davidson_cpu_baseline(dav):
     """Oracle FP64 Davidson on the config-1 cell (host cores)."""
     from oracle import davidson as odv
@@ -922,6 +980,9 @@ def main():
     if not args.no_scf:
         out["scf"] = scf_section(args.scf_steps, args.streams + 1)
         note("SCF section done")
+    if not args.no_exx:
+        out["exact_exchange"] = exx_section(128, 16)
+        note("exact-exchange section done")
     if not args.no_batched:
         out["batched_ragged_cells"] = batched_section(args.batched_cells, max(3, args.steps // 2), args.streams,
                                                       learned_net=net)
