@@ -86,3 +86,81 @@ def exchange_energy(p: "_ham.Problem", psi_occ: np.ndarray, w_occ: np.ndarray) -
     -(1/2) sum_ij (ij|ji) once per spin, so E_x = sum_i w_i <psi_i | V_x psi_i>."""
     xi = vx(p, psi_occ, w_occ, psi_occ)
     return float(np.real(np.sum(np.asarray(w_occ) * np.einsum("ig,ig->i", np.conj(psi_occ), xi))))
+
+
+def ace_matrix(xi: np.ndarray, M: np.ndarray) -> np.ndarray:
+    """The compressed operator xi M^-1 xi^H as a dense npw x npw matrix."""
+    return xi.T @ np.linalg.solve(M, np.conj(xi))
+
+
+def scf_hybrid(p: "_ham.Problem", vion: np.ndarray, nel: float, nbands: int, sigma: float, alpha: float,
+               tol: float, max_iter: int, exx_alpha: float, exx_tol: float, max_outer: int, q0: float = 0.0):
+    """The paper's double loop for a hybrid functional, Gamma point, one k-point.
+
+    Inner loop: the SCF loop of ``scf`` (Fermi occupations, linear or Kerker
+    mixing, convergence in int |n_out - n_in| / N_el) with the Fock
+    operator fixed as exx_alpha V_ace and the local exchange scaled by
+    1 - exx_alpha.  Outer loop: rebuild V_ace from the occupied orbitals of
+    the converged inner loop (those with f/2 > 1e-8, weights f/2) until the
+    exchange energy e_xx = sum_i w_i <psi_i | V_ace psi_i> changes by less
+    than exx_tol.  The first inner loop runs the plain local functional
+    (no Fock term, full local exchange).  Reported energy:
+    E = sum f eps - exx_alpha e_xx - E_H + (1 - exx_alpha) (E_x - int v_x n)
+    (the band energy counts the Fock term twice), F = E - sigma S."""
+    if np.any(np.asarray(p.kfrac) != 0):
+        raise ValueError("hybrid SCF: Gamma point only")
+    A = p.A
+    dv = _scf.volume(A) / vion.size
+    vion = np.asarray(vion, dtype=np.float64)
+    xfrac, hx, e_xx = 1.0, None, 0.0
+    n_next = None
+    hist, exx_hist = [], []
+    first = True
+    for outer in range(max_outer + 1):
+        for it in range(max_iter + 1):
+            if n_next is None:
+                n_in = np.zeros(vion.shape)
+                v, e = vion.copy(), {"hartree": 0.0, "xc": 0.0, "vxc_n": 0.0}
+            else:
+                n_in = n_next
+                vh, eh = _scf.hartree(n_in, A)
+                ex, vx = _scf.lda_exchange(n_in)
+                v = vion + vh + xfrac * vx
+                e = {"hartree": eh, "xc": xfrac * float(np.sum(n_in * ex) * dv),
+                     "vxc_n": xfrac * float(np.sum(n_in * vx) * dv)}
+            p.vloc = v
+            H = _ham.dense_h(p)
+            if hx is not None:
+                H = H + exx_alpha * hx
+            w, U = np.linalg.eigh((H + H.conj().T) / 2)
+            eps, X = w[:nbands], U[:, :nbands].T.copy()
+            f, mu, ent = _scf.fermi_occupations([eps], [1.0], nel, sigma)
+            n_out = _scf.density(p, X, f[0])
+            if first:
+                first = False
+                n_next = n_out
+                continue
+            d = float(np.sum(np.abs(n_out - n_in)) * dv) / nel
+            hist.append(d)
+            if d < tol:
+                break
+            n_next = _scf.mix(n_in, n_out, alpha, q0, A)
+        if exx_alpha == 0.0:
+            break
+        occ = f[0] / 2.0 > 1e-8
+        xi, M = ace(p, X[occ], f[0][occ] / 2.0)
+        e_new = float(np.real(np.sum(f[0][occ] / 2.0 * np.diag(M))))
+        exx_hist.append(e_new)
+        if outer >= 1 and abs(e_new - e_xx) < exx_tol:
+            e_xx = e_new
+            break
+        hx, e_xx, xfrac = ace_matrix(xi, M), e_new, 1.0 - exx_alpha
+        n_next = n_in
+    eband = float(np.sum(f[0] * eps))
+    e["band"] = eband
+    e["exx"] = e_xx
+    e["total"] = eband - exx_alpha * e_xx - e["hartree"] + e["xc"] - e["vxc_n"]
+    e["free"] = e["total"] - sigma * ent
+    return {"n_in": n_in, "n_out": n_out, "eigenvalues": eps, "vectors": X, "occupations": f[0], "mu": mu,
+            "energies": e, "history": hist, "exx_history": exx_hist,
+            "converged": bool(hist and hist[-1] < tol)}

@@ -771,3 +771,31 @@ def test_ace_is_exact_on_the_occupied_manifold():
     assert np.abs(aa - ex.vx(po, psi, w, a)).max() > 1e-3 * np.abs(aa).max()
     # the exchange energy is the trace of the compressed operator on the occupied states
     assert abs(ex.exchange_energy(po, psi, w) - np.real(np.trace(M))) < 1e-12 * abs(np.trace(M))
+
+
+def test_hybrid_double_loop_fixed_point_and_plain_limit():
+    c = synth.make_cell(0)
+    po = ham.problem_from_cell(c)
+    vion = synth.vloc_on_grid(c)
+    kw = dict(nel=4.0, nbands=8, sigma=0.02, alpha=0.5, tol=1e-11, max_iter=150)
+    r = ex.scf_hybrid(po, vion, exx_alpha=0.25, exx_tol=1e-12, max_outer=40, **kw)
+    assert r["converged"]
+    # at the fixed point the occupied orbitals are eigenvectors of H0 + alpha V_x, with V_x
+    # built from themselves and applied directly (not through ACE), H0 holding the returned
+    # input density's Hartree and scaled local exchange potentials
+    n = r["n_in"]
+    vh, _ = sc.hartree(n, po.A)
+    _, vx = sc.lda_exchange(n)
+    po.vloc = vion + vh + 0.75 * vx
+    f, X, eps = r["occupations"], r["vectors"], r["eigenvalues"]
+    occ = f / 2 > 1e-8
+    Xo, wo = X[occ], f[occ] / 2
+    res = ham.hpsi(po, Xo) + 0.25 * ex.vx(po, Xo, wo, Xo) - eps[occ][:, None] * Xo
+    assert np.abs(res).max() < 1e-8
+    # e_xx is the direct exchange energy of those orbitals
+    assert abs(ex.exchange_energy(po, Xo, wo) - r["energies"]["exx"]) < 1e-10
+    # without the Fock term the double loop is the plain SCF loop
+    r0 = ex.scf_hybrid(po, vion, exx_alpha=0.0, exx_tol=1e-11, max_outer=5, **kw)
+    rs = sc.scf([po], [1.0], vion, kw["nel"], kw["nbands"], kw["sigma"], kw["alpha"], kw["tol"], kw["max_iter"])
+    assert abs(r0["mu"] - rs["mu"]) < 1e-12 and np.abs(r0["eigenvalues"] - rs["eigenvalues"][0]).max() < 1e-12
+    assert abs(r0["energies"]["free"] - rs["energies"]["free"]) < 1e-12
