@@ -40,6 +40,8 @@ int scaled_cols(const double2 *U, int64_t ldu, const double *lam, const int *kee
 int precond_idx(const double *kin, const double *tn, const int *idx, const double2 *R, int64_t ldr,
                 double2 *T, int64_t ldt, int64_t npw, int nu, int kind, hipStream_t s);
 int col_norms2(const double2 *T, int64_t ld, int64_t npw, int n, double *nrm2, hipStream_t s);
+int gather_cols(const double2 *Z, int64_t ldz, const int *idx, int64_t m, int nsel, double2 *Y, int64_t ldy,
+                hipStream_t s);
 }  // namespace pw
 
 using namespace pw;
@@ -52,6 +54,8 @@ struct pw_davidson {
   int m = 0, iter = 0;
   int64_t n_hpsi = 0;
   bool inited = false, converged = false;
+  // the last step found every correction numerically inside the space
+  bool stalled = false;
   double2 *V = nullptr, *W = nullptr, *X = nullptr, *HX = nullptr, *R = nullptr, *T = nullptr;
   double2 *Vt = nullptr, *Wt = nullptr;  // rotation targets (swapped with V, W each step)
   double *w_sorted = nullptr;
@@ -84,6 +88,9 @@ struct pw_davidson {
   std::vector<uint8_t> tpa_only;
   int *h_bad = nullptr;
   double off_target = 0.0;  // eigensolver stop level (Frobenius norm of the off-diagonal part)
+  // estimate of max |V^H V - I|: grows with every rotation of the space and
+  // every block whose second orthonormalisation round was skipped
+  double ortho_err = 0.0;
   // locked prefix: bands 0 .. nl-1 have converged (all of them), their
   // vectors stay fixed in V and W, and Rayleigh-Ritz runs on the rest
   int nl = 0;
@@ -221,88 +228,132 @@ static int gs_first() {
   return v;
 }
 
+// A column whose squared norm after the projection against the space (and
+// the block's earlier columns) is at most kDrop0 of its squared norm before
+// it lies numerically in the space: what is left of it is rounding and the
+// space's own loss of orthogonality, and normalising that would put a
+// direction already in the space into it a second time, so it is dropped.
+// The second round starts from orthonormal columns; one that loses half of
+// its squared norm there had such a direction amplified by the first round
+// and is dropped too.
+constexpr double kDrop0 = 1e-16;
+constexpr double kDrop1 = 0.5;
+constexpr double kEps = 2.220446049250313e-16;
+
 // Orthonormalise n columns at T against V[0:m] into dst; *n_out columns kept.
 int ortho_block(pw_davidson *d, int m, double2 *T, int n, double2 *dst, int *n_out, hipStream_t s) {
   const bool set_error_if_empty = true;
   const char *where = "pw_davidson: orthonormalisation failed";
   double2 *src = T, *out = dst;
-  // column norms before any projection, for the second round's test below
-  const bool may_skip = ortho_skip() && n > 0;
-  if (may_skip) {
+  // squared column norms before any projection: the reference of the drop
+  // test and of the second round's skip test below
+  const bool may_skip = ortho_skip();
+  if (n > 0) {
     DV_RC(col_norms2(T, d->ld, d->npw, n, d->cnorm, s));
     PW_HIP(hipMemcpyAsync(d->h_cnorm, d->cnorm, n * sizeof(double), hipMemcpyDeviceToHost, s));
   }
-  for (int round = 0; round < 2 && n > 0; ++round) {
+  bool skipped = false;
+  for (int round = 0; round < 2 && n > 0 && !skipped; ++round) {
     // one Gram-Schmidt pass against V per round: the Cholesky-QR between
     // the two passes normalises what the first left, and the second pass
     // takes the V components that normalisation amplified to the rounding
-    // level (twice is enough); a block numerically inside span(V) goes to
-    // the rank-revealing path below
+    // level (twice is enough); columns numerically inside span(V) are
+    // dropped, a block dependent in itself goes to the rank-revealing path
     if (m > 0) {
       for (int c = 0; c < (round == 0 ? gs_first() : 1); ++c) {
         DV_RC(cn(d, m, n, d->V, src, d->C, d->lde, s));
         DV_RC(nn(d, n, m, -1.0, d->V, d->C, d->lde, 1.0, src, s));
       }
     }
-    DV_RC(cn(d, n, n, src, src, d->S, n, s));
-    {
-      ProfScope ps(&d->p->prof, PW_STAGE_CHOL, s);
-      DV_RC(cholesky(d->S, n, n, d->L, n, 1e-12, d->flag, s));
-    }
-    PW_HIP(hipMemcpyAsync(d->h_flag, d->flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    if (may_skip && round == 0)
-      PW_HIP(hipMemcpy2DAsync(d->h_ldiag, sizeof(double2), d->L, (size_t)(n + 1) * sizeof(double2),
-                              sizeof(double2), n, hipMemcpyDeviceToHost, s));
-    PW_HIP(hipStreamSynchronize(s));
-    if (*d->h_flag == 0) {
+    for (;;) {
+      DV_RC(cn(d, n, n, src, src, d->S, n, s));
       {
         ProfScope ps(&d->p->prof, PW_STAGE_CHOL, s);
-        DV_RC(trinv_h(d->L, n, n, d->Xi, n, d->Bi, n, s));
+        DV_RC(cholesky(d->S, n, n, d->L, n, 1e-12, d->flag, s));
       }
-      DV_RC(nn(d, n, n, 1.0, src, d->Bi, n, 0.0, out, s));
-      // L_jj^2 is what column j kept of its squared norm through the
-      // projection and against the columns before it.  If every column
-      // kept at least kKeep^2 of it, the normalisation amplified what the
-      // first pass left by at most 1/kKeep, Cholesky-QR's loss of
-      // orthogonality is at most about eps / kKeep^2, and a second round
-      // would change the block at the 1e-12 level: it is skipped.
-      if (may_skip && round == 0) {
-        constexpr double kKeep2 = 1e-4;  // kKeep = 1e-2
-        bool keep_all = true;
-        for (int j = 0; j < n && keep_all; ++j) {
-          const double l = d->h_ldiag[j].x;
-          keep_all = std::isfinite(l) && l * l > kKeep2 * d->h_cnorm[j];
-        }
-        if (keep_all) {
-          std::swap(src, out);
-          break;
-        }
-      }
-    } else {
-      // rank-revealing path: S = U diag(lam) U^H, keep lam > 1e-12 max
-      {
-        ProfScope ps(&d->p->prof, PW_STAGE_EIG, s);
-        DV_RC(copy_mat(d->S, n, d->Ae, d->lde, n, n, s));
-        DV_RC(eig_herm(d->Ae, d->lde, n, d->lam, d->Ze, d->lde, d->rot_ws, d->acc_ws, d->h_acc,
-                       d->sweeps, s, 0.0, 0));
-      }
-      PW_HIP(hipMemcpyAsync(d->h_lam, d->lam, n * sizeof(double), hipMemcpyDeviceToHost, s));
+      PW_HIP(hipMemcpyAsync(d->h_flag, d->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+      PW_HIP(hipMemcpy2DAsync(d->h_ldiag, sizeof(double2), d->L, (size_t)(n + 1) * sizeof(double2),
+                              sizeof(double2), n, hipMemcpyDeviceToHost, s));
       PW_HIP(hipStreamSynchronize(s));
-      double lmax = 0;
-      for (int i = 0; i < n; ++i) lmax = std::max(lmax, d->h_lam[i]);
-      int nk = 0;
-      for (int i = 0; i < n; ++i)
-        if (std::isfinite(d->h_lam[i]) && d->h_lam[i] > 1e-12 * lmax) d->h_keep[nk++] = i;
-      PW_HIP(hipMemcpyAsync(d->keep, d->h_keep, nk * sizeof(int), hipMemcpyHostToDevice, s));
-      if (nk > 0) {
-        DV_RC(scaled_cols(d->Ze, d->lde, d->lam, d->keep, n, nk, d->Bi, n, s));
-        DV_RC(nn(d, nk, n, 1.0, src, d->Bi, n, 0.0, out, s));
+      if (*d->h_flag == 0) {
+        // L_jj^2 is what column j kept of its squared norm through the
+        // projection and against the columns before it
+        int ng = 0;
+        for (int j = 0; j < n; ++j) {
+          const double l = d->h_ldiag[j].x;
+          const double ref = round == 0 ? kDrop0 * d->h_cnorm[j] : kDrop1;
+          if (std::isfinite(l) && l * l > ref) d->h_keep[ng++] = j;
+        }
+        if (ng < n) {
+          // compact the block to the columns that stay and factor again
+          if (ng > 0) {
+            PW_HIP(hipMemcpyAsync(d->keep, d->h_keep, ng * sizeof(int), hipMemcpyHostToDevice, s));
+            DV_RC(gather_cols(src, d->ld, d->keep, d->npw, ng, out, d->ld, s));
+            std::swap(src, out);
+            for (int i = 0; i < ng; ++i) d->h_cnorm[i] = d->h_cnorm[d->h_keep[i]];
+          }
+          n = ng;
+          if (n == 0) break;
+          continue;
+        }
+        {
+          ProfScope ps(&d->p->prof, PW_STAGE_CHOL, s);
+          DV_RC(trinv_h(d->L, n, n, d->Xi, n, d->Bi, n, s));
+        }
+        DV_RC(nn(d, n, n, 1.0, src, d->Bi, n, 0.0, out, s));
+        // The normalisation amplifies what the first pass left by
+        // a = max_j |t_j| / L_jj: the rounding of the projection (Cholesky-QR
+        // then loses about eps a^2 of orthogonality) and the space's own loss
+        // of orthogonality (the pass leaves that much of each V component,
+        // so the new columns carry about ortho_err a).  If every column kept
+        // at least kKeep^2 of its squared norm (a < 1/kKeep) and the sum
+        // stays below kSkipErr, a second round would change the block at
+        // that level: it is skipped, and the space's estimate grows to it.
+        if (may_skip && round == 0) {
+          constexpr double kKeep2 = 1e-4;  // kKeep = 1e-2
+          constexpr double kSkipErr = 1e-11;
+          double a2 = 0.0;
+          for (int j = 0; j < n; ++j) {
+            const double l = d->h_ldiag[j].x;
+            a2 = std::max(a2, d->h_cnorm[j] / (l * l));
+          }
+          const double err = d->ortho_err * std::sqrt(a2) + kEps * a2;
+          skipped = a2 < 1.0 / kKeep2 && err <= kSkipErr;
+          if (skipped) d->ortho_err = std::max(d->ortho_err, err);
+        }
+      } else {
+        // rank-revealing path: S = U diag(lam) U^H, keep the directions with
+        // lam above 1e-12 of the largest and above the drop level
+        {
+          ProfScope ps(&d->p->prof, PW_STAGE_EIG, s);
+          DV_RC(copy_mat(d->S, n, d->Ae, d->lde, n, n, s));
+          DV_RC(eig_herm(d->Ae, d->lde, n, d->lam, d->Ze, d->lde, d->rot_ws, d->acc_ws, d->h_acc,
+                         d->sweeps, s, 0.0, 0));
+        }
+        PW_HIP(hipMemcpyAsync(d->h_lam, d->lam, n * sizeof(double), hipMemcpyDeviceToHost, s));
+        PW_HIP(hipStreamSynchronize(s));
+        double lmax = 0, cmax = 0;
+        for (int i = 0; i < n; ++i) {
+          lmax = std::max(lmax, d->h_lam[i]);
+          cmax = std::max(cmax, d->h_cnorm[i]);
+        }
+        const double floor = std::max(1e-12 * lmax, round == 0 ? kDrop0 * cmax : kDrop1);
+        int nk = 0;
+        for (int i = 0; i < n; ++i)
+          if (std::isfinite(d->h_lam[i]) && d->h_lam[i] > floor) d->h_keep[nk++] = i;
+        PW_HIP(hipMemcpyAsync(d->keep, d->h_keep, nk * sizeof(int), hipMemcpyHostToDevice, s));
+        if (nk > 0) {
+          DV_RC(scaled_cols(d->Ze, d->lde, d->lam, d->keep, n, nk, d->Bi, n, s));
+          DV_RC(nn(d, nk, n, 1.0, src, d->Bi, n, 0.0, out, s));
+        }
+        // the kept directions mix the columns: the skip test does not apply
+        n = nk;
       }
-      n = nk;
+      break;
     }
     std::swap(src, out);
   }
-  // the result sits in src after the last swap (dst after one round, T after two)
+  // the result sits in src after the last swap
   if (src != dst && n > 0)
     PW_HIP(hipMemcpyAsync(dst, src, (size_t)n * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
   *n_out = n;
@@ -433,6 +484,7 @@ pw_status pw_davidson_init(pw_davidson *d, const void *psi0, int64_t ld, void *s
   PW_HIP(hipMemcpy2DAsync(d->T, d->ld * sizeof(double2), psi0, ld * sizeof(double2),
                           d->npw * sizeof(double2), d->nb, hipMemcpyDeviceToDevice, s));
   int nk = 0;
+  d->ortho_err = 0.0;
   DV_RC(ortho_block(d, 0, d->T, d->nb, d->V, &nk, s));
   PW_CHECK_ARG(nk == d->nb, PW_ERR_NUMERIC, "pw_davidson_init: start block is rank deficient");
   DV_RC(dav_apply(d, d->V, d->W, d->nb, s));
@@ -448,6 +500,7 @@ pw_status pw_davidson_init(pw_davidson *d, const void *psi0, int64_t ld, void *s
   d->tpa_only.assign(d->nb, 0);
   d->inited = true;
   d->converged = false;
+  d->stalled = false;
   return PW_OK;
 }
 
@@ -462,6 +515,7 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   const bool set_error_if_empty = true;
   const char *where = "pw_davidson_step: launch failed";
   const int nb = d->nb;
+  d->stalled = false;
   // 1. Rayleigh-Ritz: Z^H H_s Z = diag(w) + E, eigenpairs sorted ascending.
   //    The eigensolver transforms H_s in place and stops once the
   //    off-diagonal part E is below off_target (tied to the residuals of
@@ -473,6 +527,7 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   //    prefix is fixed, and its couplings to the active part, of the order
   //    of its residuals (below the tolerance), are left out.
   const int nl = d->nl, ma = d->m - nl;
+  const double used_target = d->off_target;
   const size_t hoff = (size_t)nl * d->lde + nl;
   {
     ProfScope ps(&d->p->prof, PW_STAGE_EIG, s);
@@ -483,6 +538,7 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
                      d->Ae, d->lde, d->Hs + hoff, d->lde));
   }
   // 2. rotate the active space into the Ritz basis (V <- V Z, W <- W Z): the
+  //    rotation's rounding adds about eps sqrt(m) to the loss of orthogonality.  The
   //    first nb columns are the Ritz vectors, the active H_s becomes diag(w),
   //    and the next bordered H_s is nearly diagonal, so its Jacobi solve is
   //    short.  The locked columns are carried over unchanged.  The Ritz
@@ -490,6 +546,7 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   //    decided how many of them the space keeps.
   const size_t lcol = (size_t)nl * d->ld;
   const int nw = nb - nl;
+  d->ortho_err += kEps * std::sqrt((double)ma);
   DV_RC(nn(d, nw, ma, 1.0, d->V + lcol, d->Ae, d->lde, 0.0, d->Vt + lcol, s));
   DV_RC(nn(d, nw, ma, 1.0, d->W + lcol, d->Ae, d->lde, 0.0, d->Wt + lcol, s));
   if (nl > 0) {
@@ -583,7 +640,7 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   if (d->converged) return PW_OK;
   PW_HIP(hipMemcpyAsync(d->dU, d->h_U, nu * sizeof(int), hipMemcpyHostToDevice, s));
   // 4. preconditioned corrections for the unconverged bands
-  {
+  auto corrections = [&]() -> int {
     ProfScope ps(&d->p->prof, PW_STAGE_PRECOND, s);
     DV_RC(band_kinetic(d->p->d_kin, d->X, d->ld, d->npw, nb, d->tn, s));
     if (precond_kind == PW_PRECOND_MLP) {
@@ -592,19 +649,43 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
       DV_RC(mlp_precond_idx(net, d->p, d->theta, d->rho, d->dU, d->R, d->ld, d->T, nu, d->bad, d->tn, s));
       DV_RC(mlp_fallback(d->bad, d->p, d->tn, d->dU, d->R, d->ld, d->T, nu, s));
     } else {
-      DV_RC(precond_idx(d->p->d_kin, d->tn, d->dU, d->R, d->ld, d->T, d->ld, d->npw, nu,
-                        precond_kind, s));
+      DV_RC(precond_idx(d->p->d_kin, d->tn, d->dU, d->R, d->ld, d->T, d->ld, d->npw, nu, precond_kind, s));
     }
-  }
+    return PW_OK;
+  };
+  DV_RC(corrections());
   // 6. orthonormalise against the space
   int nk = 0;
+  DV_RC(ortho_block(d, d->m, d->T, nu, d->V + (size_t)d->m * d->ld, &nk, s));
+  if (nk == 0) {
+    // Every correction lies numerically in the space, so what the residuals
+    // still hold is their part inside it: the off-diagonal rest the
+    // eigensolver stopped at, or the couplings to the locked prefix.  Those
+    // are resolved first (the next step diagonalises to the rounding level,
+    // over the whole space if bands were locked); then the corrections are
+    // tried against the Ritz vectors alone.  Past that the residuals are at
+    // the rounding level of the Ritz vectors and the solve has stalled.
+    if (used_target > 0.0 || nl > 0) {
+      if (nl > 0) {
+        d->nl = 0;
+        DV_RC(cn(d, d->m, d->m, d->V, d->W, d->Hs, d->lde, s));
+        DV_RC(hermitize(d->Hs, d->lde, 0, d->m, s));
+      }
+      d->off_target = 0.0;
+      return PW_OK;
+    }
+    if (d->m > nb) {
+      d->m = nb;
+      DV_RC(corrections());
+      DV_RC(ortho_block(d, d->m, d->T, nu, d->V + (size_t)d->m * d->ld, &nk, s));
+    }
+    if (nk == 0) {
+      d->stalled = true;
+      return PW_OK;
+    }
+  }
   double2 *Vn = d->V + (size_t)d->m * d->ld;
   double2 *Wn = d->W + (size_t)d->m * d->ld;
-  DV_RC(ortho_block(d, d->m, d->T, nu, Vn, &nk, s));
-  if (nk == 0) {
-    set_error("pw_davidson_step: every correction was linearly dependent on the space");
-    return PW_ERR_NUMERIC;
-  }
   // 7. H on the new vectors, bordered subspace matrix
   DV_RC(dav_apply(d, Vn, Wn, nk, s));
   d->n_hpsi += nk;
@@ -651,7 +732,7 @@ pw_status pw_davidson_run(pw_davidson *d, int32_t max_iter, int32_t precond_kind
   for (int it = 0; it < max_iter; ++it) {
     const int rc = pw_davidson_step(d, precond_kind, net, stream, &c);
     if (rc != PW_OK) return rc;
-    if (c) break;
+    if (c || d->stalled) break;
   }
   if (converged) *converged = c;
   return c ? PW_OK : PW_NOT_CONVERGED;

@@ -1128,6 +1128,14 @@ int col_norms2(const double2 *T, int64_t ld, int64_t npw, int n, double *nrm2, h
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
 
+// Y[:, r] = Z[:, idx[r]] for r < nsel, rows 0 .. m-1 (Y and Z distinct)
+int gather_cols(const double2 *Z, int64_t ldz, const int *idx, int64_t m, int nsel, double2 *Y, int64_t ldy,
+                hipStream_t s) {
+  if (nsel <= 0 || m <= 0) return PW_OK;
+  hipLaunchKernelGGL(k_gather_cols, dim3(grid_for(m * nsel)), dim3(256), 0, s, Z, ldz, idx, (int)m, nsel, Y, ldy);
+  return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
+}
+
 int col_norms(const double2 *T, int64_t ld, int64_t npw, int n, double *nrm, hipStream_t s) {
   if (n <= 0) return PW_OK;
   hipLaunchKernelGGL(k_colnorm2<true>, dim3(n), dim3(256), 0, s, T, ld, npw, nrm);
