@@ -270,7 +270,12 @@ pw_status pw_davidson_init(pw_davidson *d, const void *psi0, int64_t ld, void *s
  * upper ones per band left (PW_DAV_ACT_MUL / _MIN / _KEEP override; MUL=0
  * disables it) --, classical Gram-Schmidt + Cholesky-QR (a second round
  * unless the first kept at least 1 % of every column's norm), H on the new
- * vectors and the bordered subspace matrix.  Synchronises the stream to
+ * vectors and the bordered subspace matrix.  A correction that keeps at most
+ * 1e-8 of its norm through the projection lies numerically in the space and
+ * is dropped; when every correction is dropped the space restarts from the
+ * Ritz vectors and tries once more, and if nothing is added then either, the
+ * solve has stalled at its rounding floor: the step returns PW_OK with
+ * *converged = 0 and pw_davidson_run stops there.  Synchronises the stream to
  * read back the residual norms, the Cholesky checks and the eigensolver's
  * convergence per sweep; sets *converged.  Returns PW_ERR_NOT_FINITE on a
  * non-finite norm.
@@ -287,8 +292,9 @@ pw_status pw_davidson_set_problem(pw_davidson *d, pw_problem *p, void *stream);
 /* Change the residual target of a solve (Ha, > 0). */
 pw_status pw_davidson_set_tol(pw_davidson *d, double tol);
 
-/* Up to max_iter calls of pw_davidson_step; PW_OK when converged, else
- * PW_NOT_CONVERGED (positive) with the state left after max_iter steps. */
+/* Up to max_iter calls of pw_davidson_step (fewer if a step stalls); PW_OK
+ * when converged, else PW_NOT_CONVERGED (positive) with the state left after
+ * the last step. */
 pw_status pw_davidson_run(pw_davidson *d, int32_t max_iter, int32_t precond_kind,
                           const pw_mlp *net, void *stream, int32_t *converged);
 
@@ -607,13 +613,17 @@ typedef struct pw_scf_desc {
   double sigma;                   /* Fermi-Dirac width, Ha, > 0 */
   double alpha;                   /* mixing factor, 0 < alpha <= 1 */
   double kerker_q0;               /* Kerker wave vector, 1/bohr; 0 for plain linear mixing */
+  double exx_alpha;               /* hybrid functional: fraction of Fock exchange (0: none); Gamma point only */
+  double exx_tol;                 /* outer-loop target on the exchange energy, Ha (> 0 when exx_alpha > 0) */
 } pw_scf_desc;
 /* Device workspace of the loop: densities, potential, the density and
  * Hartree scratch and one band block. */
 pw_status pw_scf_workspace_size(const pw_scf_desc *d, size_t *bytes);
 /* Checks the descriptor, binds the workspace (256-byte aligned, owned by the
  * caller until pw_scf_destroy), sets V_ion on every problem and refreshes
- * the Davidson states: step 0 solves with V_ion alone. */
+ * the Davidson states: step 0 solves with V_ion alone.  With exx_alpha > 0
+ * the loop detaches any exchange term from the problem and attaches its own
+ * (kept in its workspace; pw_scf_destroy detaches it again). */
 pw_status pw_scf_create(const pw_scf_desc *d, void *workspace, size_t ws_bytes, void *stream, pw_scf **out);
 pw_status pw_scf_destroy(pw_scf *s);
 /* One SCF step: every Davidson solve to dav_tol (at most dav_max_iter
@@ -621,10 +631,19 @@ pw_status pw_scf_destroy(pw_scf *s);
  * out[0] = int |n_out - n_in| / nel (-1 at step 0, whose output density
  * becomes the first input density), then -- unless step > 0 and out[0] <
  * tol (*converged = 1) -- the mixed input density, its potential on every
- * problem and the Davidson states refreshed.  out (host double [8]):
- * drho, mu, E_band = sum_k w_k sum_n f eps, E_H, E_x, int v_x n (of the
- * input density this step solved with), E = E_band - E_H + E_x - int v_x n,
- * F = E - sigma S (S the occupations' entropy).  Synchronises the stream. */
+ * problem and the Davidson states refreshed.  With exx_alpha > 0 this is the
+ * inner loop of the paper's double loop: when it converges, the step instead
+ * rebuilds V_ace from the occupied orbitals (weights f/2 above 1e-8), and
+ * unless the exchange energy e_xx = sum_i w_i <psi_i|V_x psi_i> moved by
+ * less than exx_tol (then *converged = 1) attaches exx_alpha V_ace, scales
+ * the local exchange by 1 - exx_alpha (the first inner loop runs the plain
+ * local functional) and continues from the same input density.  out (host
+ * double [10]): drho, mu, E_band = sum_k w_k sum_n f eps, E_H, E_x,
+ * int v_x n (of the input density this step solved with, local exchange
+ * scaled), E = E_band - exx_alpha e_xx - E_H + E_x - int v_x n,
+ * F = E - sigma S (S the occupations' entropy), e_xx of the attached
+ * operator (0 before the first), the outer steps taken.  Synchronises the
+ * stream. */
 pw_status pw_scf_step(pw_scf *s, double dav_tol, int32_t dav_max_iter, double tol, double *out,
                       int32_t *converged);
 /* Device copies of the input density of the last step solved and its

@@ -927,10 +927,11 @@ def pw_problem_set_vloc(prob: Problem, v, stream=None) -> None:
 class _ScfDesc(C.Structure):
     _fields_ = [("nk", C.c_int32), ("probs", C.POINTER(C.c_void_p)), ("davs", C.POINTER(C.c_void_p)),
                 ("batch", C.c_void_p), ("kweights", C.POINTER(C.c_double)), ("vion", C.c_void_p),
-                ("nel", C.c_double), ("sigma", C.c_double), ("alpha", C.c_double), ("kerker_q0", C.c_double)]
+                ("nel", C.c_double), ("sigma", C.c_double), ("alpha", C.c_double), ("kerker_q0", C.c_double),
+                ("exx_alpha", C.c_double), ("exx_tol", C.c_double)]
 
 
-SCF_OUT = ("drho", "mu", "e_band", "e_hartree", "e_x", "vxc_n", "e_total", "free_energy")
+SCF_OUT = ("drho", "mu", "e_band", "e_hartree", "e_x", "vxc_n", "e_total", "free_energy", "e_xx", "outer")
 
 
 class Scf:
@@ -938,7 +939,7 @@ class Scf:
     states, optional batch and V_ion alive with it."""
 
     def __init__(self, probs, davs, kweights, vion, nel: float, sigma: float, alpha: float, batch=None,
-                 kerker_q0: float = 0.0, stream=None):
+                 kerker_q0: float = 0.0, exx_alpha: float = 0.0, exx_tol: float = 1e-8, stream=None):
         n = len(probs)
         self._keep = (list(probs), list(davs), batch, vion)
         self._pp = (C.c_void_p * n)(*[p.handle.value for p in probs])
@@ -946,7 +947,8 @@ class Scf:
         self._kw = np.ascontiguousarray(kweights, dtype=np.float64)
         d = _ScfDesc(n, self._pp, self._dd, batch.handle if batch is not None else None,
                      self._kw.ctypes.data_as(C.POINTER(C.c_double)), _grid_array(vion, probs[0], "vion"),
-                     float(nel), float(sigma), float(alpha), float(kerker_q0))
+                     float(nel), float(sigma), float(alpha), float(kerker_q0), float(exx_alpha),
+                     float(exx_tol))
         nbytes = C.c_size_t(0)
         _check(LIB.pw_scf_workspace_size(C.byref(d), C.byref(nbytes)))
         self.workspace = _workspace(nbytes.value)
@@ -963,7 +965,7 @@ class Scf:
         return self._h
 
     def step(self, dav_tol: float, dav_max_iter: int, tol: float) -> dict:
-        out = np.zeros(8)
+        out = np.zeros(10)
         c = C.c_int32(0)
         _check(LIB.pw_scf_step(self.handle, float(dav_tol), int(dav_max_iter), float(tol),
                                out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(c)))

@@ -564,6 +564,7 @@ pw_status pw_problem_create(const pw_problem_desc *d, int64_t max_bands, void *w
 pw_status pw_problem_destroy(pw_problem *p) {
   if (p) {
     (void)hipDeviceSynchronize();
+    if (p->ace_owner) scf_forget_problem(p->ace_owner, p);
     free_problem(p);
   }
   return PW_OK;

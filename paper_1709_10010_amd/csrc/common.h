@@ -207,6 +207,9 @@ struct pw_problem {
   int64_t ace_ldz = 0, ace_nocc = 0;
   double ace_alpha = 0.0;
   double2 *ace_proj = nullptr;        // [max_bands][nocc] scratch of the H psi term
+  // the SCF loop whose workspace holds the attached buffers (null when the
+  // caller attached them): told when the problem goes first
+  pw_scf *ace_owner = nullptr;
 };
 
 namespace pw {
@@ -294,6 +297,14 @@ int sinvhalf(pw_problem *p, const void *x, int64_t ldx, void *y, int64_t ldy, in
 // Exact-exchange term of H psi (exx.hip): hpsi -= alpha zeta (zeta^H psi).
 int ace_hpsi(pw_problem *p, const void *psi, int64_t ld_psi, void *hpsi, int64_t ld_hpsi, int64_t nbands,
              hipStream_t s);
+// Build ACE from nocc occupied states (weights w, host) and attach alpha
+// V_ace (exx.hip); e_xx (may be null) receives sum_i w_i <psi_i|V_x psi_i>.
+// work: ace_build_bytes(p, nocc) bytes, 256-byte aligned.
+int ace_build(pw_problem *p, const void *psi_occ, int64_t ld_occ, int64_t nocc, const double *w, double alpha,
+              void *zeta, int64_t ldz, void *proj, void *work, double *e_xx, hipStream_t s);
+size_t ace_build_bytes(const pw_problem *p, int64_t nocc);
+// an SCF loop's attached problem is being destroyed before the loop
+void scf_forget_problem(pw_scf *s, const pw_problem *p);
 // Davidson state accessors for the batch scheduler (davidson.hip).
 pw_problem *dav_problem(const pw_davidson *d);
 int dav_nbands(const pw_davidson *d);

@@ -229,6 +229,57 @@ int ace_hpsi(pw_problem *p, const void *psi, int64_t ld_psi, void *hpsi, int64_t
   return zgemm_nn(npw, nbands, no, -p->ace_alpha, p->ace_zeta, p->ace_ldz, p->ace_proj, no, 1.0, hpsi, ld_hpsi, s);
 }
 
+// Build ACE from nocc occupied states and attach alpha V_ace to the problem;
+// e_xx (may be null) receives sum_i w_i <psi_i | V_x psi_i> = sum_i w_i M_ii.
+int ace_build(pw_problem *p, const void *psi_occ, int64_t ld_occ, int64_t nocc, const double *w, double alpha,
+              void *zeta, int64_t ldz, void *proj, void *work, double *e_xx, hipStream_t s) {
+  Carve c(work);
+  carve_vx(p, nocc, c);
+  const int64_t ld = (p->npw + 63) / 64 * 64, npw = p->npw;
+  double2 *xi = c.take<double2>((size_t)nocc * ld);
+  double2 *Mm = c.take<double2>((size_t)4 * nocc * nocc);
+  double2 *L = Mm + nocc * nocc, *Xi = L + nocc * nocc, *Bi = Xi + nocc * nocc;
+  int *flag = c.take<int>(1);
+  int rc;
+  // xi' = -V_x psi, M' = psi^H xi' = -M (positive definite)
+  if ((rc = vx_impl(p, psi_occ, ld_occ, nocc, w, psi_occ, ld_occ, nocc, xi, ld, -1.0, work, s)) != PW_OK) goto fail;
+  if ((rc = zgemm_cn(nocc, nocc, npw, psi_occ, ld_occ, xi, ld, Mm, nocc, fit_splits(p, nocc, nocc, npw), p->d_part,
+                     s)) != PW_OK)
+    goto fail;
+  if ((rc = hermitize(Mm, nocc, 0, (int)nocc, s)) != PW_OK) goto fail;
+  if (e_xx) {
+    std::vector<double2> m((size_t)nocc * nocc);
+    PW_HIP(hipMemcpyAsync(m.data(), Mm, m.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+    PW_HIP(hipStreamSynchronize(s));
+    double acc = 0.0;
+    for (int64_t i = 0; i < nocc; ++i) acc -= w[i] * m[(size_t)i * nocc + i].x;
+    *e_xx = acc;
+  }
+  if ((rc = cholesky(Mm, nocc, (int)nocc, L, nocc, 1e-12, flag, s)) != PW_OK) goto fail;
+  {
+    int h = 0;
+    PW_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    PW_HIP(hipStreamSynchronize(s));
+    PW_CHECK_ARG(h == 0, PW_ERR_NUMERIC,
+                 "pw_ace_set: <psi|V_x psi> is not negative definite (dependent or zero-weight occupied states)");
+  }
+  if ((rc = trinv_h(L, nocc, (int)nocc, Xi, nocc, Bi, nocc, s)) != PW_OK) goto fail;  // Bi = L^-H
+  if ((rc = zgemm_nn(npw, nocc, nocc, 1.0, xi, ld, Bi, nocc, 0.0, zeta, ldz, s)) != PW_OK) goto fail;
+  p->ace_zeta = static_cast<const double2 *>(zeta);
+  p->ace_ldz = ldz;
+  p->ace_nocc = nocc;
+  p->ace_alpha = alpha;
+  p->ace_proj = static_cast<double2 *>(proj);
+  p->ace_owner = nullptr;
+  PW_HIP(hipStreamSynchronize(s));
+  return PW_OK;
+fail:
+  set_error("pw_ace_set: launch failed");
+  return rc;
+}
+
+size_t ace_build_bytes(const pw_problem *p, int64_t nocc) { return ace_bytes(p, nocc); }
+
 }  // namespace pw
 
 using namespace pw;
@@ -286,40 +337,8 @@ pw_status pw_ace_set(pw_problem *p, const void *psi_occ, int64_t ld_occ, int64_t
   PW_CHECK_ARG(nocc <= p->npw, PW_ERR_INVALID, "pw_ace_set: more occupied states than plane waves");
   PW_CHECK_ARG(work && (reinterpret_cast<uintptr_t>(work) & 255) == 0 && work_bytes >= ace_bytes(p, nocc),
                PW_ERR_INVALID, "pw_ace_set: work must be 256-byte aligned and pw_ace_workspace_size bytes");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  Carve c(work);
-  carve_vx(p, nocc, c);
-  const int64_t ld = (p->npw + 63) / 64 * 64, npw = p->npw;
-  double2 *xi = c.take<double2>((size_t)nocc * ld);
-  double2 *Mm = c.take<double2>((size_t)4 * nocc * nocc);
-  double2 *L = Mm + nocc * nocc, *Xi = L + nocc * nocc, *Bi = Xi + nocc * nocc;
-  int *flag = c.take<int>(1);
-  // xi' = -V_x psi, M' = psi^H xi' = -M (positive definite)
-  if ((rc = vx_impl(p, psi_occ, ld_occ, nocc, w, psi_occ, ld_occ, nocc, xi, ld, -1.0, work, s)) != PW_OK) goto fail;
-  if ((rc = zgemm_cn(nocc, nocc, npw, psi_occ, ld_occ, xi, ld, Mm, nocc, fit_splits(p, nocc, nocc, npw), p->d_part,
-                     s)) != PW_OK)
-    goto fail;
-  if ((rc = hermitize(Mm, nocc, 0, (int)nocc, s)) != PW_OK) goto fail;
-  if ((rc = cholesky(Mm, nocc, (int)nocc, L, nocc, 1e-12, flag, s)) != PW_OK) goto fail;
-  {
-    int h = 0;
-    PW_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    PW_HIP(hipStreamSynchronize(s));
-    PW_CHECK_ARG(h == 0, PW_ERR_NUMERIC,
-                 "pw_ace_set: <psi|V_x psi> is not negative definite (dependent or zero-weight occupied states)");
-  }
-  if ((rc = trinv_h(L, nocc, (int)nocc, Xi, nocc, Bi, nocc, s)) != PW_OK) goto fail;  // Bi = L^-H
-  if ((rc = zgemm_nn(npw, nocc, nocc, 1.0, xi, ld, Bi, nocc, 0.0, zeta, ldz, s)) != PW_OK) goto fail;
-  p->ace_zeta = static_cast<const double2 *>(zeta);
-  p->ace_ldz = ldz;
-  p->ace_nocc = nocc;
-  p->ace_alpha = alpha;
-  p->ace_proj = static_cast<double2 *>(proj);
-  PW_HIP(hipStreamSynchronize(s));
-  return PW_OK;
-fail:
-  set_error("pw_ace_set: launch failed");
-  return rc;
+  return ace_build(p, psi_occ, ld_occ, nocc, w, alpha, zeta, ldz, proj, work, nullptr,
+                   static_cast<hipStream_t>(stream));
 }
 
 pw_status pw_ace_clear(pw_problem *p) {
@@ -328,6 +347,7 @@ pw_status pw_ace_clear(pw_problem *p) {
   p->ace_proj = nullptr;
   p->ace_nocc = 0;
   p->ace_alpha = 0.0;
+  p->ace_owner = nullptr;
   return PW_OK;
 }
 

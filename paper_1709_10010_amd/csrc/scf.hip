@@ -143,18 +143,18 @@ __global__ __launch_bounds__(kRedThreads) void k_poisson(double2 *__restrict__ c
   if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
-// v[r] = (vion[r] if given) + Re c[r] + v_x(n[r]); partial sums of n eps_x
-// (out) and n v_x (out + kRedBlocks)
+// v[r] = (vion[r] if given) + Re c[r] + xfrac v_x(n[r]); partial sums of
+// xfrac n eps_x (out) and xfrac n v_x (out + kRedBlocks)
 __global__ __launch_bounds__(kRedThreads) void k_hxc(const double2 *__restrict__ c, const double *__restrict__ n,
-                                                     const double *__restrict__ vion, int64_t len,
+                                                     const double *__restrict__ vion, int64_t len, double xfrac,
                                                      double *__restrict__ v, double *__restrict__ out) {
   __shared__ double sh[kRedThreads];
   double ae = 0.0, av = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < len; i += (int64_t)gridDim.x * kRedThreads) {
     const double ni = n[i];
     const double cb = ni > 0.0 ? cbrt(3.0 * ni / M_PI) : 0.0;
-    const double vx = -cb;
-    ae += ni * (-0.75 * cb);
+    const double vx = -xfrac * cb;
+    ae += ni * (-0.75 * xfrac * cb);
     av += ni * vx;
     v[i] = (vion ? vion[i] : 0.0) + c[i].x + vx;
   }
@@ -279,8 +279,9 @@ int density_impl(pw_problem *p, const void *psi, int64_t ld, int64_t nbands, con
   return PW_OK;
 }
 
-// v = (vion) + V_H[n] + V_x[n]; e[0..2] = E_H, E_x, int v_x n
-int hxc_impl(pw_problem *p, const double *n, const double *vion, double *v, double *e, void *work, hipStream_t s) {
+// v = (vion) + V_H[n] + xfrac V_x[n]; e[0..2] = E_H, xfrac E_x, xfrac int v_x n
+int hxc_impl(pw_problem *p, const double *n, const double *vion, double xfrac, double *v, double *e, void *work,
+             hipStream_t s) {
   const int64_t len = grid_len(p);
   Carve c(work);
   double2 *g = c.take<double2>((size_t)len);
@@ -297,7 +298,7 @@ int hxc_impl(pw_problem *p, const double *n, const double *vion, double *v, doub
   double eh = 0.0;
   if ((rc = host_sum(red, kRedBlocks, &eh, s)) != PW_OK) return rc;
   if ((rc = launch_grid_fft(p->fft, g, 1, 0, true, s)) != PW_OK) return rc;
-  hipLaunchKernelGGL(k_hxc, dim3(kRedBlocks), dim3(kRedThreads), 0, s, g, n, vion, len, v, red);
+  hipLaunchKernelGGL(k_hxc, dim3(kRedBlocks), dim3(kRedThreads), 0, s, g, n, vion, len, xfrac, v, red);
   PW_HIP(hipGetLastError());
   double ex = 0.0, evx = 0.0;
   if ((rc = host_sum(red, kRedBlocks, &ex, s)) != PW_OK) return rc;
@@ -394,9 +395,21 @@ struct pw_scf {
   void *dwork = nullptr, *hwork = nullptr;
   int step = 0;
   double e_h = 0, e_x = 0, e_vxn = 0;  // of the potential the current solves use
+  // hybrid functional: exx_alpha of the Fock operator through ACE, the local
+  // exchange scaled by xfrac = 1 - exx_alpha once the first ACE is attached
+  double exx_alpha = 0, exx_tol = 0, xfrac = 1.0, e_xx = 0;
+  int outer = 0;
+  double2 *zeta = nullptr, *proj = nullptr;
+  void *awork = nullptr;
+  pw_problem *ace_prob = nullptr;  // the problem the loop's ACE is attached to
 };
 
 namespace pw {
+
+void scf_forget_problem(pw_scf *s, const pw_problem *p) {
+  if (s && s->ace_prob == p) s->ace_prob = nullptr;
+}
+
 namespace {
 
 int check_desc(const pw_scf_desc *d, int64_t *ldx, int *nbmax) {
@@ -429,6 +442,13 @@ int check_desc(const pw_scf_desc *d, int64_t *ldx, int *nbmax) {
     nsum += 2.0 * dav_nbands(dv) * d->kweights[k];
   }
   PW_CHECK_ARG(d->nel < nsum, PW_ERR_INVALID, "pw_scf: more electrons than the bands can hold");
+  PW_CHECK_ARG(d->exx_alpha >= 0 && d->exx_alpha <= 1 && std::isfinite(d->exx_alpha), PW_ERR_INVALID,
+               "pw_scf: need 0 <= exx_alpha <= 1");
+  if (d->exx_alpha > 0) {
+    PW_CHECK_ARG(d->nk == 1 && p0->kpt[0] == 0.0 && p0->kpt[1] == 0.0 && p0->kpt[2] == 0.0, PW_ERR_INVALID,
+                 "pw_scf: exact exchange is implemented at the Gamma point only (one k-point, k = 0)");
+    PW_CHECK_ARG(d->exx_tol > 0 && std::isfinite(d->exx_tol), PW_ERR_INVALID, "pw_scf: need exx_tol > 0");
+  }
   *ldx = ld;
   *nbmax = nb;
   return PW_OK;
@@ -446,7 +466,17 @@ size_t scf_carve(const pw_scf_desc *d, int64_t ldx, int nbmax, Carve &c, pw_scf 
   double2 *x = c.take<double2>((size_t)nbmax * ldx);
   char *dw = c.take<char>(dws);
   char *hw = c.take<char>(hws);
+  double2 *zt = nullptr, *pj = nullptr;
+  char *aw = nullptr;
+  if (d->exx_alpha > 0) {
+    zt = c.take<double2>((size_t)nbmax * ldx);
+    pj = c.take<double2>((size_t)nbmax * p0->max_bands);
+    aw = c.take<char>(ace_build_bytes(p0, nbmax));
+  }
   if (s) {
+    s->zeta = zt;
+    s->proj = pj;
+    s->awork = aw;
     s->n_in = a;
     s->n_out = b;
     s->v = v;
@@ -497,7 +527,7 @@ pw_status pw_hxc(pw_problem *p, const double *n, const double *vion, double *v, 
   PW_CHECK_ARG(p->precision == PW_FP64, PW_ERR_INVALID, "pw_hxc: the problem must be FP64");
   PW_CHECK_ARG(work && (reinterpret_cast<uintptr_t>(work) & 255) == 0 && work_bytes >= hxc_ws(p), PW_ERR_INVALID,
                "pw_hxc: work must be 256-byte aligned and pw_hxc_workspace_size bytes");
-  const int rc = hxc_impl(p, n, vion, v, energies, work, static_cast<hipStream_t>(stream));
+  const int rc = hxc_impl(p, n, vion, 1.0, v, energies, work, static_cast<hipStream_t>(stream));
   if (rc != PW_OK) set_error("pw_hxc: launch failed");
   return rc;
 }
@@ -545,12 +575,15 @@ pw_status pw_scf_create(const pw_scf_desc *d, void *workspace, size_t ws_bytes, 
   s->sigma = d->sigma;
   s->alpha = d->alpha;
   s->q0 = d->kerker_q0;
+  s->exx_alpha = d->exx_alpha;
+  s->exx_tol = d->exx_tol;
   s->len = grid_len(d->probs[0]);
   s->ldx = ldx;
   s->nbmax = nb;
   Carve c(workspace);
   scf_carve(d, ldx, nb, c, s);
-  // step 0 solves with V_ion alone
+  // step 0 solves with V_ion alone (and, in a hybrid loop, without a Fock term)
+  if (s->exx_alpha > 0) pw_ace_clear(s->probs[0]);
   rc = fill(s->n_in, s->len, 0.0, s->s);
   for (int k = 0; k < d->nk && rc == PW_OK; ++k) {
     rc = set_vloc_impl(s->probs[k], s->vion, s->red, kRedBlocks, s->s);
@@ -568,6 +601,9 @@ pw_status pw_scf_create(const pw_scf_desc *d, void *workspace, size_t ws_bytes, 
 }
 
 pw_status pw_scf_destroy(pw_scf *s) {
+  // the Fock term the loop attached lives in the loop's workspace; a problem
+  // destroyed before the loop has already told it (scf_forget_problem)
+  if (s && s->ace_prob && s->ace_prob->ace_owner == s) pw_ace_clear(s->ace_prob);
   delete s;
   return PW_OK;
 }
@@ -623,7 +659,8 @@ pw_status pw_scf_step(pw_scf *s, double dav_tol, int32_t dav_max_iter, double to
     for (size_t n = 0; n < eps[k].size(); ++n) ek += f[k][n] * eps[k][n];
     eband += s->kw[k] * ek;
   }
-  const double etot = eband - s->e_h + s->e_x - s->e_vxn;
+  const double exx_att = s->outer > 0 ? s->e_xx : 0.0;
+  const double etot = eband - s->exx_alpha * exx_att - s->e_h + s->e_x - s->e_vxn;
   out[0] = drho;
   out[1] = mu;
   out[2] = eband;
@@ -632,7 +669,44 @@ pw_status pw_scf_step(pw_scf *s, double dav_tol, int32_t dav_max_iter, double to
   out[5] = s->e_vxn;
   out[6] = etot;
   out[7] = etot - s->sigma * ent;
-  const bool conv = s->step > 0 && drho < tol;
+  out[8] = exx_att;
+  out[9] = (double)s->outer;
+  bool conv = s->step > 0 && drho < tol;
+  if (conv && s->exx_alpha > 0) {
+    // outer step of the double loop: V_ace from the occupied orbitals of the
+    // converged inner loop (weights f/2 above 1e-8, a prefix of the ascending bands)
+    pw_problem *p0 = s->probs[0];
+    const int nb = dav_nbands(s->davs[0]);
+    std::vector<double> w;
+    for (int n = 0; n < nb && f[0][n] / 2.0 > 1e-8; ++n) w.push_back(f[0][n] / 2.0);
+    double e_new = 0.0;
+    if ((rc = ace_build(p0, s->X, s->ldx, (int64_t)w.size(), w.data(), s->exx_alpha, s->zeta, s->ldx, s->proj,
+                        s->awork, &e_new, st)) != PW_OK)
+      return rc;
+    p0->ace_owner = s;
+    s->ace_prob = p0;
+    if (s->outer >= 1 && std::fabs(e_new - s->e_xx) < s->exx_tol) {
+      // converged: the operator rebuilt from these orbitals is the one they solve
+      if (converged) *converged = 1;
+      return PW_OK;
+    }
+    s->e_xx = e_new;
+    s->xfrac = 1.0 - s->exx_alpha;
+    ++s->outer;
+    conv = false;
+    // the inner loop continues from the same input density with the new operator
+    double e[3];
+    if ((rc = hxc_impl(p0, s->n_in, s->vion, s->xfrac, s->v, e, s->hwork, st)) != PW_OK) return rc;
+    s->e_h = e[0];
+    s->e_x = e[1];
+    s->e_vxn = e[2];
+    if ((rc = set_vloc_impl(p0, s->v, s->red, kRedBlocks, st)) != PW_OK) return rc;
+    if ((rc = pw_davidson_set_problem(s->davs[0], p0, st)) != PW_OK) return rc;
+    ++s->step;
+    if (converged) *converged = 0;
+    PW_HIP(hipStreamSynchronize(st));
+    return PW_OK;
+  }
   if (converged) *converged = conv ? 1 : 0;
   if (conv) return PW_OK;
   // 5. the next input density and its potential on every problem
@@ -660,7 +734,7 @@ pw_status pw_scf_step(pw_scf *s, double dav_tol, int32_t dav_max_iter, double to
     PW_HIP(hipGetLastError());
   }
   double e[3];
-  if ((rc = hxc_impl(s->probs[0], s->n_in, s->vion, s->v, e, s->hwork, st)) != PW_OK) return rc;
+  if ((rc = hxc_impl(s->probs[0], s->n_in, s->vion, s->xfrac, s->v, e, s->hwork, st)) != PW_OK) return rc;
   s->e_h = e[0];
   s->e_x = e[1];
   s->e_vxn = e[2];

@@ -223,3 +223,42 @@ def test_scf_rejects_bad_descriptors(lib):
     n = torch.zeros(tuple(c.nr), dtype=torch.float64, device="cuda")
     with pytest.raises(lib.PwError):           # FP64 problems only
         lib.pw_density(p32, to_gpu_block(start_block(c, 8, pl.npw)), np.ones(8), n)
+
+
+def test_hybrid_double_loop_matches_oracle(lib):
+    """The paper's double loop with ACE (exx_alpha 0.25) on the tiny cell at
+    Gamma against the oracle's (dense diagonalisation, ACE as xi M^-1 xi^H)."""
+    import torch
+    from oracle import exx as oex
+    c = synth.make_cell(0)
+    po, pl = problems(c, max_bands=8)
+    d = lib.Davidson(pl, 8, 0, 1e-11)
+    lib.pw_davidson_init(d, to_gpu_block(start_block(c, 8, pl.npw)))
+    vion_np = synth.vloc_on_grid(c)
+    vion = torch.from_numpy(vion_np).cuda()
+    s = lib.Scf([pl], [d], [1.0], vion, 4.0, 0.02, 0.5, exx_alpha=0.25, exx_tol=1e-10)
+    outer_seen, r = 0, None
+    for _ in range(400):
+        r = s.step(1e-11, 200, 1e-10)
+        outer_seen = max(outer_seen, int(r["outer"]))
+        if r["converged"]:
+            break
+    ro = oex.scf_hybrid(po, vion_np, nel=4.0, nbands=8, sigma=0.02, alpha=0.5, tol=1e-10, max_iter=200,
+                        exx_alpha=0.25, exx_tol=1e-10, max_outer=60)
+    th = lib.pw_davidson_query(d)["theta"]
+    log(f"hybrid: {outer_seen} outer steps, mu {r['mu']:.12f} vs {ro['mu']:.12f}, e_xx {r['e_xx']:.12f} vs "
+        f"{ro['energies']['exx']:.12f}, F {r['free_energy']:.12f} vs {ro['energies']['free']:.12f}")
+    assert r["converged"] and ro["converged"] and outer_seen >= 2
+    assert abs(r["mu"] - ro["mu"]) < 1e-8
+    assert np.abs(th - ro["eigenvalues"]).max() < 1e-8
+    assert abs(r["e_xx"] - ro["energies"]["exx"]) < 1e-8
+    assert abs(r["free_energy"] - ro["energies"]["free"]) < 1e-8
+    n_in, _ = s.density()
+    assert rel_err(n_in.cpu().numpy(), ro["n_in"]) < 1e-7
+    s.close()
+    # the loop took its exchange term with it
+    x = to_gpu_block(start_block(c, 3, pl.npw))
+    y, y0 = torch.zeros_like(x), torch.zeros_like(x)
+    lib.pw_hpsi(pl, x, y)
+    lib.pw_hpsi(pl, x, y0, terms=lib.PW_TERM_ALL & ~lib.PW_TERM_EXX)
+    assert bool((y == y0).all())
