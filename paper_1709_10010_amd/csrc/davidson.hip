@@ -32,7 +32,7 @@ int cholesky(const double2 *S, int64_t lds, int n, double2 *L, int64_t ldl, doub
 int trinv_h(const double2 *L, int64_t ldl, int n, double2 *X, int64_t ldx, double2 *B, int64_t ldb,
             hipStream_t s);
 int residual(const double2 *X, const double2 *HX, const double *theta, double2 *R, int64_t ld,
-             int64_t npw, int nb, double *rho, hipStream_t s);
+             int64_t npw, int nb, double *rho, double *xn2, hipStream_t s);
 int hermitize(double2 *H, int64_t ldh, int m0, int m1, hipStream_t s);
 int copy_mat(const double2 *src, int64_t lds, double2 *dst, int64_t ldd, int m, int n, hipStream_t s);
 int scaled_cols(const double2 *U, int64_t ldu, const double *lam, const int *keep, int n, int nk,
@@ -63,6 +63,7 @@ struct pw_davidson {
   double2 *Hs = nullptr, *Ae = nullptr, *Ze = nullptr, *Y = nullptr, *C = nullptr;
   double2 *S = nullptr, *L = nullptr, *Xi = nullptr, *Bi = nullptr;
   double *w_all = nullptr, *theta = nullptr, *rho = nullptr, *tn = nullptr, *lam = nullptr;
+  double *xn2 = nullptr;  // squared norms of the Ritz vectors
   int *idx_sel = nullptr, *dU = nullptr, *keep = nullptr, *flag = nullptr, *sweeps = nullptr;
   int *bad = nullptr;
   void *rot_ws = nullptr;
@@ -74,7 +75,7 @@ struct pw_davidson {
   void *ws = nullptr;
   double2 *U1 = nullptr, *U2 = nullptr;  // [nb][ld] each: S^{-1/2} x and H S^{-1/2} x (augmented problems)
   // pinned host mirrors
-  double *h_theta = nullptr, *h_rho = nullptr, *h_lam = nullptr;
+  double *h_theta = nullptr, *h_rho = nullptr, *h_lam = nullptr, *h_xn2 = nullptr;
   double *h_acc = nullptr;  // eigensolver's off-diagonal and total mass, read once per sweep
   int *h_U = nullptr, *h_flag = nullptr, *h_keep = nullptr;
   // orthonormalisation: column norms^2 before it, the Cholesky diagonal
@@ -88,8 +89,9 @@ struct pw_davidson {
   std::vector<uint8_t> tpa_only;
   int *h_bad = nullptr;
   double off_target = 0.0;  // eigensolver stop level (Frobenius norm of the off-diagonal part)
-  // estimate of max |V^H V - I|: grows with every rotation of the space and
-  // every block whose second orthonormalisation round was skipped
+  // the space's loss of orthonormality as the Ritz vectors see it,
+  // max_n | |x_n|^2 - 1 |, measured every step; raised within a step by a
+  // block whose second orthonormalisation round is skipped
   double ortho_err = 0.0;
   // locked prefix: bands 0 .. nl-1 have converged (all of them), their
   // vectors stay fixed in V and W, and Rayleigh-Ritz runs on the rest
@@ -102,7 +104,7 @@ namespace {
 // host mirrors belong to the handle
 void free_dav(pw_davidson *d) {
   if (!d) return;
-  void *host[] = {d->h_theta, d->h_rho, d->h_lam, d->h_U, d->h_flag, d->h_keep, d->h_bad, d->h_cnorm,
+  void *host[] = {d->h_theta, d->h_rho, d->h_xn2, d->h_lam, d->h_U, d->h_flag, d->h_keep, d->h_bad, d->h_cnorm,
                   d->h_ldiag, d->h_acc};
   for (void *b : host)
     if (b) (void)hipHostFree(b);
@@ -137,6 +139,7 @@ void carve_dav(pw_davidson *d, Carve &c) {
   d->lam = c.take<double>(lde);
   d->theta = c.take<double>(nb);
   d->rho = c.take<double>(nb);
+  d->xn2 = c.take<double>(nb);
   d->tn = c.take<double>(nb);
   d->cnorm = c.take<double>(nb);
   d->idx_sel = c.take<int>(nb);
@@ -304,14 +307,14 @@ int ortho_block(pw_davidson *d, int m, double2 *T, int n, double2 *dst, int *n_o
         // The normalisation amplifies what the first pass left by
         // a = max_j |t_j| / L_jj: the rounding of the projection (Cholesky-QR
         // then loses about eps a^2 of orthogonality) and the space's own loss
-        // of orthogonality (the pass leaves that much of each V component,
+        // of orthonormality (the pass leaves that much of each V component,
         // so the new columns carry about ortho_err a).  If every column kept
         // at least kKeep^2 of its squared norm (a < 1/kKeep) and the sum
         // stays below kSkipErr, a second round would change the block at
-        // that level: it is skipped, and the space's estimate grows to it.
+        // that level: it is skipped.
         if (may_skip && round == 0) {
           constexpr double kKeep2 = 1e-4;  // kKeep = 1e-2
-          constexpr double kSkipErr = 1e-11;
+          constexpr double kSkipErr = 1e-9;
           double a2 = 0.0;
           for (int j = 0; j < n; ++j) {
             const double l = d->h_ldiag[j].x;
@@ -448,7 +451,8 @@ pw_status pw_davidson_create(pw_problem *p, int64_t nbands, int64_t max_subspace
     d->ws = workspace;
   }
   const size_t nb = d->nb, lde = d->lde;
-  const bool ok = halloc(&d->h_theta, nb) && halloc(&d->h_rho, nb) && halloc(&d->h_lam, lde) &&
+  const bool ok = halloc(&d->h_theta, nb) && halloc(&d->h_rho, nb) && halloc(&d->h_xn2, nb) &&
+                  halloc(&d->h_lam, lde) &&
                   halloc(&d->h_U, nb) && halloc(&d->h_flag, 1) && halloc(&d->h_keep, nb) &&
                   halloc(&d->h_bad, nb) && halloc(&d->h_cnorm, nb) && halloc(&d->h_ldiag, nb) &&
                   halloc(&d->h_acc, 2);
@@ -538,7 +542,6 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
                      d->Ae, d->lde, d->Hs + hoff, d->lde));
   }
   // 2. rotate the active space into the Ritz basis (V <- V Z, W <- W Z): the
-  //    rotation's rounding adds about eps sqrt(m) to the loss of orthogonality.  The
   //    first nb columns are the Ritz vectors, the active H_s becomes diag(w),
   //    and the next bordered H_s is nearly diagonal, so its Jacobi solve is
   //    short.  The locked columns are carried over unchanged.  The Ritz
@@ -546,7 +549,6 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   //    decided how many of them the space keeps.
   const size_t lcol = (size_t)nl * d->ld;
   const int nw = nb - nl;
-  d->ortho_err += kEps * std::sqrt((double)ma);
   DV_RC(nn(d, nw, ma, 1.0, d->V + lcol, d->Ae, d->lde, 0.0, d->Vt + lcol, s));
   DV_RC(nn(d, nw, ma, 1.0, d->W + lcol, d->Ae, d->lde, 0.0, d->Wt + lcol, s));
   if (nl > 0) {
@@ -560,12 +562,15 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   // 3. residuals
   {
     ProfScope ps(&d->p->prof, PW_STAGE_VEC, s);
-    DV_RC(residual(d->X, d->HX, d->theta, d->R, d->ld, d->npw, nb, d->rho, s));
+    DV_RC(residual(d->X, d->HX, d->theta, d->R, d->ld, d->npw, nb, d->rho, d->xn2, s));
   }
   PW_HIP(hipMemcpyAsync(d->h_theta, d->theta, nb * sizeof(double), hipMemcpyDeviceToHost, s));
   PW_HIP(hipMemcpyAsync(d->h_rho, d->rho, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+  PW_HIP(hipMemcpyAsync(d->h_xn2, d->xn2, nb * sizeof(double), hipMemcpyDeviceToHost, s));
   PW_HIP(hipStreamSynchronize(s));
   d->iter++;
+  d->ortho_err = 0.0;
+  for (int n = 0; n < nb; ++n) d->ortho_err = std::max(d->ortho_err, std::fabs(d->h_xn2[n] - 1.0));
   for (int n = 0; n < nb; ++n)
     if (!std::isfinite(d->h_theta[n]) || !std::isfinite(d->h_rho[n])) {
       set_error("pw_davidson_step: non-finite Ritz value or residual");

@@ -852,29 +852,38 @@ __global__ void k_trinv_h(const double2 *__restrict__ L, int64_t ldl, int n, dou
 }
 
 // ---------------------------------------------------------------- small kernels
-// R = HX - X diag(theta);  rho2[n] = ||R_n||^2 (one block per band).
+// R = HX - X diag(theta);  rho[n] = ||R_n||, xn2[n] = ||X_n||^2 if xn2 is
+// given (one block per band).
 __global__ __launch_bounds__(256) void k_residual(const double2 *__restrict__ X,
                                                   const double2 *__restrict__ HX,
                                                   const double *__restrict__ theta,
                                                   double2 *__restrict__ R, int64_t ld, int64_t npw,
-                                                  double *__restrict__ rho) {
-  __shared__ double red[256];
+                                                  double *__restrict__ rho, double *__restrict__ xn2) {
+  __shared__ double red[256], redx[256];
   const int b = blockIdx.x;
   const double th = theta[b];
-  double s = 0.0;
+  double s = 0.0, q = 0.0;
   for (int64_t g = threadIdx.x; g < npw; g += 256) {
     const double2 x = X[b * ld + g], h = HX[b * ld + g];
     const double2 r = double2{h.x - th * x.x, h.y - th * x.y};
     R[b * ld + g] = r;
     s += r.x * r.x + r.y * r.y;
+    q += x.x * x.x + x.y * x.y;
   }
   red[threadIdx.x] = s;
+  redx[threadIdx.x] = q;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) {
+      red[threadIdx.x] += red[threadIdx.x + w];
+      redx[threadIdx.x] += redx[threadIdx.x + w];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) rho[b] = sqrt(red[0]);
+  if (threadIdx.x == 0) {
+    rho[b] = sqrt(red[0]);
+    if (xn2) xn2[b] = redx[0];
+  }
 }
 
 // nrm2[b] = sum_g |T[b][g]|^2, one workgroup per column
@@ -1143,8 +1152,8 @@ int col_norms(const double2 *T, int64_t ld, int64_t npw, int n, double *nrm, hip
 }
 
 int residual(const double2 *X, const double2 *HX, const double *theta, double2 *R, int64_t ld,
-             int64_t npw, int nb, double *rho, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(256), 0, s, X, HX, theta, R, ld, npw, rho);
+             int64_t npw, int nb, double *rho, double *xn2, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(256), 0, s, X, HX, theta, R, ld, npw, rho, xn2);
   return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
 }
 
