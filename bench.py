@@ -572,6 +572,8 @@ def _scf_golden(tag):
                 out["energy"][w[1]] = float(w[2])
             elif w[0] == "eig":
                 out["eig"][int(w[1])] = np.array([float(x) for x in w[2:]])
+            elif w[0] == "exx_hist":
+                out["exx_hist"] = [float(x) for x in w[1:]]
             elif w[0] == "n":
                 out["n"].append((int(w[1]), int(w[2]), int(w[3]), float(w[4])))
     return out
@@ -587,7 +589,9 @@ def scf_section(steps: int, nstreams: int):
     Davidson target 1e-2 of the last density distance (between 5e-9 and
     1e-4 Ha): time to int |n_out - n_in| / N_el < 1e-6 (at most `steps`
     steps), seconds per step and the density distance, plus the density (256
-    bands of one k-point) and Hartree/exchange kernels timed alone."""
+    bands of one k-point) and Hartree/exchange kernels timed alone.  The
+    hybrid double loop (ACE, exx_alpha 0.25) on the config-1 cell at Gamma:
+    time to convergence and errors against the oracle's loop (tests/golden)."""
     import torch
     import synth
     from paper_1709_10010_amd import _lib
@@ -634,6 +638,39 @@ def scf_section(steps: int, nstreams: int):
             d.close()
         for p in probs:
             p.close()
+    # the hybrid double loop (ACE, exx_alpha 0.25) on the config-1 cell at Gamma
+    g = _scf_golden("gamma_hybrid")
+    c = synth.make_cell(1)
+    p, _ = build_problem(c, 0, max_bands=16)
+    d = _lib.Davidson(p, 16, 0, 1e-10)
+    x0 = band_block(16, p.npw)
+    x0[:, :p.npw] = torch.from_numpy(synth.psi_start(c.seed, 16, p.npw, 0)).cuda()
+    _lib.pw_davidson_init(d, x0)
+    vion = torch.from_numpy(synth.vloc_on_grid(c)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = _lib.Scf([p], [d], [1.0], vion, 12.0, 0.02, 0.5, exx_alpha=0.25, exx_tol=1e-10)
+    nstep = 0
+    for nstep in range(1, 1001):
+        r = s.step(1e-10, 200, 1e-10)
+        if r["converged"]:
+            break
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n = s.density()[0].cpu().numpy()
+    out["config1_gamma_hybrid"] = {
+        "workload": "config-1 cell at Gamma, 12 electrons in 16 bands, exx_alpha 0.25 through ACE, inner loops to "
+                    "int |n_out - n_in| / N_el < 1e-10, outer loop until e_xx changes by < 1e-10 Ha",
+        "seconds": round(dt, 4), "steps": nstep, "outer_steps": int(r["outer"]), "converged": r["converged"],
+        "abs_mu_minus_oracle_Ha": abs(r["mu"] - g["mu"]),
+        "abs_e_xx_minus_oracle_Ha": abs(r["e_xx"] - g["energy"]["exx"]),
+        "abs_free_energy_minus_oracle_Ha": abs(r["free_energy"] - g["energy"]["free"]),
+        "max_abs_eig_minus_oracle_Ha": float(np.abs(_lib.pw_davidson_query(d)["theta"] - g["eig"][0]).max()),
+        "max_density_sample_err_rel": max(abs(n[i, j, k] - v) for i, j, k, v in g["n"]) /
+        max(v for *_, v in g["n"])}
+    s.close()
+    d.close()
+    p.close()
     # medium workload
     cell = synth.make_cell(2)
     nk, nb = len(cell.kpts), cell.nbands

@@ -269,7 +269,8 @@ pw_status pw_davidson_init(pw_davidson *d, const void *psi0, int64_t ld, void *s
  * left to converge) -- that restart keeps the lowest Ritz vectors plus three
  * upper ones per band left (PW_DAV_ACT_MUL / _MIN / _KEEP override; MUL=0
  * disables it) --, classical Gram-Schmidt + Cholesky-QR (a second round
- * unless the first kept at least 1 % of every column's norm), H on the new
+ * for the columns the first leaves further from orthonormal than a tenth of
+ * the tolerance over the largest |Ritz value|), H on the new
  * vectors and the bordered subspace matrix.  A correction that keeps at most
  * 1e-8 of its norm through the projection lies numerically in the space and
  * is dropped; when every correction is dropped the space restarts from the

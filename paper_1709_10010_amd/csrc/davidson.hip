@@ -90,9 +90,13 @@ struct pw_davidson {
   int *h_bad = nullptr;
   double off_target = 0.0;  // eigensolver stop level (Frobenius norm of the off-diagonal part)
   // the space's loss of orthonormality as the Ritz vectors see it,
-  // max_n | |x_n|^2 - 1 |, measured every step; raised within a step by a
-  // block whose second orthonormalisation round is skipped
+  // max_n | |x_n|^2 - 1 |, measured every step; raised within a step by the
+  // columns taken with one orthonormalisation round
   double ortho_err = 0.0;
+  // the most a column taken with one round may carry: a tenth of the
+  // tolerance over the largest |Ritz value| (the residual floor that loss of
+  // orthonormality sets), at most 1e-9; 0 (two rounds for all) at init
+  double skip_err = 0.0;
   // locked prefix: bands 0 .. nl-1 have converged (all of them), their
   // vectors stay fixed in V and W, and Rayleigh-Ritz runs on the rest
   int nl = 0;
@@ -243,122 +247,160 @@ constexpr double kDrop0 = 1e-16;
 constexpr double kDrop1 = 0.5;
 constexpr double kEps = 2.220446049250313e-16;
 
-// Orthonormalise n columns at T against V[0:m] into dst; *n_out columns kept.
+// Cholesky-QR of the n columns at *src into *out (the compaction below may
+// swap the two buffers; on return the result is in *out).  Columns that kept
+// too little through the projection are dropped first; a block dependent in
+// itself goes to the rank-revealing path.  In round 0 the result is ordered
+// head first: the *nh columns a second round would change by less than
+// d->skip_err (they are taken as they are), then the rest.
+int cholqr(pw_davidson *d, int round, double2 **src, double2 **out, int *n, int *nh, hipStream_t s) {
+  const bool set_error_if_empty = true;
+  const char *where = "pw_davidson: orthonormalisation failed";
+  *nh = 0;
+  while (*n > 0) {
+    const int nc = *n;
+    DV_RC(cn(d, nc, nc, *src, *src, d->S, nc, s));
+    {
+      ProfScope ps(&d->p->prof, PW_STAGE_CHOL, s);
+      DV_RC(cholesky(d->S, nc, nc, d->L, nc, 1e-12, d->flag, s));
+    }
+    PW_HIP(hipMemcpyAsync(d->h_flag, d->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    PW_HIP(hipMemcpy2DAsync(d->h_ldiag, sizeof(double2), d->L, (size_t)(nc + 1) * sizeof(double2),
+                            sizeof(double2), nc, hipMemcpyDeviceToHost, s));
+    PW_HIP(hipStreamSynchronize(s));
+    if (*d->h_flag != 0) {
+      // rank-revealing path: S = U diag(lam) U^H, keep the directions with
+      // lam above 1e-12 of the largest and above the drop level; they mix
+      // the columns, so all of them take the second round
+      {
+        ProfScope ps(&d->p->prof, PW_STAGE_EIG, s);
+        DV_RC(copy_mat(d->S, nc, d->Ae, d->lde, nc, nc, s));
+        DV_RC(eig_herm(d->Ae, d->lde, nc, d->lam, d->Ze, d->lde, d->rot_ws, d->acc_ws, d->h_acc, d->sweeps, s,
+                       0.0, 0));
+      }
+      PW_HIP(hipMemcpyAsync(d->h_lam, d->lam, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+      PW_HIP(hipStreamSynchronize(s));
+      double lmax = 0, cmax = 0;
+      for (int i = 0; i < nc; ++i) {
+        lmax = std::max(lmax, d->h_lam[i]);
+        cmax = std::max(cmax, d->h_cnorm[i]);
+      }
+      const double floor = std::max(1e-12 * lmax, round == 0 ? kDrop0 * cmax : kDrop1);
+      int nk = 0;
+      for (int i = 0; i < nc; ++i)
+        if (std::isfinite(d->h_lam[i]) && d->h_lam[i] > floor) d->h_keep[nk++] = i;
+      PW_HIP(hipMemcpyAsync(d->keep, d->h_keep, nk * sizeof(int), hipMemcpyHostToDevice, s));
+      if (nk > 0) {
+        DV_RC(scaled_cols(d->Ze, d->lde, d->lam, d->keep, nc, nk, d->Bi, nc, s));
+        DV_RC(nn(d, nk, nc, 1.0, *src, d->Bi, nc, 0.0, *out, s));
+      }
+      *n = nk;
+      return PW_OK;
+    }
+    // L_jj^2 is what column j kept of its squared norm through the
+    // projection and against the columns before it
+    int ng = 0;
+    for (int j = 0; j < nc; ++j) {
+      const double l = d->h_ldiag[j].x;
+      const double ref = round == 0 ? kDrop0 * d->h_cnorm[j] : kDrop1;
+      if (std::isfinite(l) && l * l > ref) d->h_keep[ng++] = j;
+    }
+    if (ng < nc) {
+      // compact the block to the columns that stay and factor again
+      if (ng > 0) {
+        PW_HIP(hipMemcpyAsync(d->keep, d->h_keep, ng * sizeof(int), hipMemcpyHostToDevice, s));
+        DV_RC(gather_cols(*src, d->ld, d->keep, d->npw, ng, *out, d->ld, s));
+        std::swap(*src, *out);
+        for (int i = 0; i < ng; ++i) d->h_cnorm[i] = d->h_cnorm[d->h_keep[i]];
+      }
+      *n = ng;
+      continue;
+    }
+    {
+      ProfScope ps(&d->p->prof, PW_STAGE_CHOL, s);
+      DV_RC(trinv_h(d->L, nc, nc, d->Xi, nc, d->Bi, nc, s));
+    }
+    // The normalisation amplifies what the first pass left in column j by
+    // a_j = |t_j| / L_jj: the rounding of the projection (Cholesky-QR then
+    // loses about eps a_j^2 of orthogonality) and the space's own loss of
+    // orthonormality (the pass leaves that much of each V component, so the
+    // column carries about ortho_err a_j).  A column with a_j < 1/kKeep
+    // whose sum stays below skip_err would change by less than that in a
+    // second round: it is taken as it is.  The head / tail order comes from
+    // permuting the columns of L^-H, so the one product writes it.
+    const double2 *B = d->Bi;
+    if (round == 0 && ortho_skip()) {
+      constexpr double kKeep2 = 1e-4;  // kKeep = 1e-2
+      std::vector<char> one((size_t)nc);
+      int h = 0;
+      double worst = 0.0;
+      for (int j = 0; j < nc; ++j) {
+        const double l = d->h_ldiag[j].x, a2 = d->h_cnorm[j] / (l * l);
+        const double err = d->ortho_err * std::sqrt(a2) + kEps * a2;
+        one[j] = a2 < 1.0 / kKeep2 && err <= d->skip_err;
+        if (one[j]) {
+          d->h_keep[h++] = j;
+          worst = std::max(worst, err);
+        }
+      }
+      int t = h;
+      for (int j = 0; j < nc; ++j)
+        if (!one[j]) d->h_keep[t++] = j;
+      if (h > 0 && h < nc) {
+        PW_HIP(hipMemcpyAsync(d->keep, d->h_keep, nc * sizeof(int), hipMemcpyHostToDevice, s));
+        DV_RC(gather_cols(d->Bi, nc, d->keep, nc, nc, d->Xi, nc, s));
+        B = d->Xi;
+      }
+      *nh = h;
+      if (h > 0) d->ortho_err = std::max(d->ortho_err, worst);
+    }
+    DV_RC(nn(d, nc, nc, 1.0, *src, B, nc, 0.0, *out, s));
+    return PW_OK;
+  }
+  return PW_OK;
+}
+
+// Orthonormalise n columns at T against V[0:m] into dst (right after V[0:m]);
+// *n_out columns kept.  Round 0: one Gram-Schmidt pass against V and
+// Cholesky-QR.  Round 1, for the columns round 0 could not settle: one pass
+// against V and the settled columns, Cholesky-QR.  The normalisation between
+// the two passes amplifies what the first left; the second takes that to the
+// rounding level ("twice is enough").
 int ortho_block(pw_davidson *d, int m, double2 *T, int n, double2 *dst, int *n_out, hipStream_t s) {
   const bool set_error_if_empty = true;
   const char *where = "pw_davidson: orthonormalisation failed";
-  double2 *src = T, *out = dst;
+  *n_out = 0;
+  if (n <= 0) return PW_OK;
   // squared column norms before any projection: the reference of the drop
-  // test and of the second round's skip test below
-  const bool may_skip = ortho_skip();
-  if (n > 0) {
-    DV_RC(col_norms2(T, d->ld, d->npw, n, d->cnorm, s));
-    PW_HIP(hipMemcpyAsync(d->h_cnorm, d->cnorm, n * sizeof(double), hipMemcpyDeviceToHost, s));
-  }
-  bool skipped = false;
-  for (int round = 0; round < 2 && n > 0 && !skipped; ++round) {
-    // one Gram-Schmidt pass against V per round: the Cholesky-QR between
-    // the two passes normalises what the first left, and the second pass
-    // takes the V components that normalisation amplified to the rounding
-    // level (twice is enough); columns numerically inside span(V) are
-    // dropped, a block dependent in itself goes to the rank-revealing path
-    if (m > 0) {
-      for (int c = 0; c < (round == 0 ? gs_first() : 1); ++c) {
-        DV_RC(cn(d, m, n, d->V, src, d->C, d->lde, s));
-        DV_RC(nn(d, n, m, -1.0, d->V, d->C, d->lde, 1.0, src, s));
-      }
+  // test and of the one-round test
+  DV_RC(col_norms2(T, d->ld, d->npw, n, d->cnorm, s));
+  PW_HIP(hipMemcpyAsync(d->h_cnorm, d->cnorm, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  double2 *src = T, *out = dst;
+  if (m > 0) {
+    for (int c = 0; c < gs_first(); ++c) {
+      DV_RC(cn(d, m, n, d->V, src, d->C, d->lde, s));
+      DV_RC(nn(d, n, m, -1.0, d->V, d->C, d->lde, 1.0, src, s));
     }
-    for (;;) {
-      DV_RC(cn(d, n, n, src, src, d->S, n, s));
-      {
-        ProfScope ps(&d->p->prof, PW_STAGE_CHOL, s);
-        DV_RC(cholesky(d->S, n, n, d->L, n, 1e-12, d->flag, s));
-      }
-      PW_HIP(hipMemcpyAsync(d->h_flag, d->flag, sizeof(int), hipMemcpyDeviceToHost, s));
-      PW_HIP(hipMemcpy2DAsync(d->h_ldiag, sizeof(double2), d->L, (size_t)(n + 1) * sizeof(double2),
-                              sizeof(double2), n, hipMemcpyDeviceToHost, s));
-      PW_HIP(hipStreamSynchronize(s));
-      if (*d->h_flag == 0) {
-        // L_jj^2 is what column j kept of its squared norm through the
-        // projection and against the columns before it
-        int ng = 0;
-        for (int j = 0; j < n; ++j) {
-          const double l = d->h_ldiag[j].x;
-          const double ref = round == 0 ? kDrop0 * d->h_cnorm[j] : kDrop1;
-          if (std::isfinite(l) && l * l > ref) d->h_keep[ng++] = j;
-        }
-        if (ng < n) {
-          // compact the block to the columns that stay and factor again
-          if (ng > 0) {
-            PW_HIP(hipMemcpyAsync(d->keep, d->h_keep, ng * sizeof(int), hipMemcpyHostToDevice, s));
-            DV_RC(gather_cols(src, d->ld, d->keep, d->npw, ng, out, d->ld, s));
-            std::swap(src, out);
-            for (int i = 0; i < ng; ++i) d->h_cnorm[i] = d->h_cnorm[d->h_keep[i]];
-          }
-          n = ng;
-          if (n == 0) break;
-          continue;
-        }
-        {
-          ProfScope ps(&d->p->prof, PW_STAGE_CHOL, s);
-          DV_RC(trinv_h(d->L, n, n, d->Xi, n, d->Bi, n, s));
-        }
-        DV_RC(nn(d, n, n, 1.0, src, d->Bi, n, 0.0, out, s));
-        // The normalisation amplifies what the first pass left by
-        // a = max_j |t_j| / L_jj: the rounding of the projection (Cholesky-QR
-        // then loses about eps a^2 of orthogonality) and the space's own loss
-        // of orthonormality (the pass leaves that much of each V component,
-        // so the new columns carry about ortho_err a).  If every column kept
-        // at least kKeep^2 of its squared norm (a < 1/kKeep) and the sum
-        // stays below kSkipErr, a second round would change the block at
-        // that level: it is skipped.
-        if (may_skip && round == 0) {
-          constexpr double kKeep2 = 1e-4;  // kKeep = 1e-2
-          constexpr double kSkipErr = 1e-9;
-          double a2 = 0.0;
-          for (int j = 0; j < n; ++j) {
-            const double l = d->h_ldiag[j].x;
-            a2 = std::max(a2, d->h_cnorm[j] / (l * l));
-          }
-          const double err = d->ortho_err * std::sqrt(a2) + kEps * a2;
-          skipped = a2 < 1.0 / kKeep2 && err <= kSkipErr;
-          if (skipped) d->ortho_err = std::max(d->ortho_err, err);
-        }
-      } else {
-        // rank-revealing path: S = U diag(lam) U^H, keep the directions with
-        // lam above 1e-12 of the largest and above the drop level
-        {
-          ProfScope ps(&d->p->prof, PW_STAGE_EIG, s);
-          DV_RC(copy_mat(d->S, n, d->Ae, d->lde, n, n, s));
-          DV_RC(eig_herm(d->Ae, d->lde, n, d->lam, d->Ze, d->lde, d->rot_ws, d->acc_ws, d->h_acc,
-                         d->sweeps, s, 0.0, 0));
-        }
-        PW_HIP(hipMemcpyAsync(d->h_lam, d->lam, n * sizeof(double), hipMemcpyDeviceToHost, s));
-        PW_HIP(hipStreamSynchronize(s));
-        double lmax = 0, cmax = 0;
-        for (int i = 0; i < n; ++i) {
-          lmax = std::max(lmax, d->h_lam[i]);
-          cmax = std::max(cmax, d->h_cnorm[i]);
-        }
-        const double floor = std::max(1e-12 * lmax, round == 0 ? kDrop0 * cmax : kDrop1);
-        int nk = 0;
-        for (int i = 0; i < n; ++i)
-          if (std::isfinite(d->h_lam[i]) && d->h_lam[i] > floor) d->h_keep[nk++] = i;
-        PW_HIP(hipMemcpyAsync(d->keep, d->h_keep, nk * sizeof(int), hipMemcpyHostToDevice, s));
-        if (nk > 0) {
-          DV_RC(scaled_cols(d->Ze, d->lde, d->lam, d->keep, n, nk, d->Bi, n, s));
-          DV_RC(nn(d, nk, n, 1.0, src, d->Bi, n, 0.0, out, s));
-        }
-        // the kept directions mix the columns: the skip test does not apply
-        n = nk;
-      }
-      break;
-    }
-    std::swap(src, out);
   }
-  // the result sits in src after the last swap
-  if (src != dst && n > 0)
-    PW_HIP(hipMemcpyAsync(dst, src, (size_t)n * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  int nh = 0;
+  DV_RC(cholqr(d, 0, &src, &out, &n, &nh, s));
+  if (n == 0) return PW_OK;
+  if (out != dst) PW_HIP(hipMemcpyAsync(dst, out, (size_t)n * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  const int nt = n - nh;
+  if (nt > 0) {
+    double2 *tail = dst + (size_t)nh * d->ld;
+    const int mv = m + nh;  // V[0:m] and the head are contiguous
+    if (mv > 0) {
+      DV_RC(cn(d, mv, nt, d->V, tail, d->C, d->lde, s));
+      DV_RC(nn(d, nt, mv, -1.0, d->V, d->C, d->lde, 1.0, tail, s));
+    }
+    double2 *src1 = tail, *out1 = T;
+    int n1 = nt, nh1 = 0;
+    DV_RC(cholqr(d, 1, &src1, &out1, &n1, &nh1, s));
+    if (n1 > 0 && out1 != tail)
+      PW_HIP(hipMemcpyAsync(tail, out1, (size_t)n1 * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    n = nh + n1;
+  }
   *n_out = n;
   return PW_OK;
 }
@@ -489,6 +531,7 @@ pw_status pw_davidson_init(pw_davidson *d, const void *psi0, int64_t ld, void *s
                           d->npw * sizeof(double2), d->nb, hipMemcpyDeviceToDevice, s));
   int nk = 0;
   d->ortho_err = 0.0;
+  d->skip_err = 0.0;
   DV_RC(ortho_block(d, 0, d->T, d->nb, d->V, &nk, s));
   PW_CHECK_ARG(nk == d->nb, PW_ERR_NUMERIC, "pw_davidson_init: start block is rank deficient");
   DV_RC(dav_apply(d, d->V, d->W, d->nb, s));
@@ -570,7 +613,12 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   PW_HIP(hipStreamSynchronize(s));
   d->iter++;
   d->ortho_err = 0.0;
-  for (int n = 0; n < nb; ++n) d->ortho_err = std::max(d->ortho_err, std::fabs(d->h_xn2[n] - 1.0));
+  double th_max = 0.1;
+  for (int n = 0; n < nb; ++n) {
+    d->ortho_err = std::max(d->ortho_err, std::fabs(d->h_xn2[n] - 1.0));
+    th_max = std::max(th_max, std::fabs(d->h_theta[n]));
+  }
+  d->skip_err = std::min(1e-9, 0.1 * d->tol / th_max);
   for (int n = 0; n < nb; ++n)
     if (!std::isfinite(d->h_theta[n]) || !std::isfinite(d->h_rho[n])) {
       set_error("pw_davidson_step: non-finite Ritz value or residual");

@@ -9,6 +9,7 @@ block Davidson at the medium workload's full size).
     python tests/golden/make_golden.py --config4     # only the two ragged-batch cells
     python tests/golden/make_golden.py --augmented   # only the medium workload with S != 1
     python tests/golden/make_golden.py --scf         # only the SCF loops of the config-1 cell
+    python tests/golden/make_golden.py --hybrid      # only its hybrid double loop
 
 Regression fixtures: tests/test_golden.py recomputes them with the oracle,
 and the GPU tests compare the library against them.
@@ -138,10 +139,45 @@ def scf_config1(tag):
             f.write(f"n {p_[0]} {p_[1]} {p_[2]} {r['n_in'][tuple(p_)]:.17e}\n")
 
 
+HYBRID_PARAMS = dict(exx_alpha=0.25, exx_tol=1e-10)
+
+
+def scf_config1_hybrid():
+    """Oracle double loop of a hybrid functional (ACE, exx_alpha 0.25) on the
+    config-1 cell at Gamma, with SCF_PARAMS: mu, energies (with e_xx),
+    eigenvalues, the e_xx of every outer step and the converged input density
+    at 256 seeded grid points."""
+    from oracle import exx as oex
+    c = synth.make_cell(1)
+    p = ham.problem_from_cell(c, 0)
+    assert not np.any(p.kfrac)
+    vion = synth.vloc_on_grid(c)
+    r = oex.scf_hybrid(p, vion, tol=1e-11, max_iter=200, max_outer=60, **SCF_PARAMS, **HYBRID_PARAMS)
+    assert r["converged"], "oracle hybrid SCF did not converge"
+    rng = np.random.default_rng(314)
+    pts = rng.integers(0, c.nr[0], size=(256, 3))
+    e = r["energies"]
+    with open(os.path.join(HERE, "config1_scf_gamma_hybrid.txt"), "w") as f:
+        f.write(f"# {c.name} hybrid SCF at Gamma, {dict(SCF_PARAMS, **HYBRID_PARAMS)}; oracle double loop, inner "
+                f"loops to int|n_out - n_in|/N_el < 1e-11, {len(r['exx_history'])} ACE builds, "
+                f"{len(r['history'])} inner steps; written by make_golden.py (oracle only)\n")
+        f.write(f"mu {r['mu']:.17e}\n")
+        for key in ("band", "hartree", "xc", "vxc_n", "exx", "total", "free"):
+            f.write(f"energy {key} {float(e[key]):.17e}\n")
+        f.write("eig 0 " + " ".join(f"{x:.17e}" for x in r["eigenvalues"]) + "\n")
+        f.write("exx_hist " + " ".join(f"{x:.17e}" for x in r["exx_history"]) + "\n")
+        for p_ in pts:
+            f.write(f"n {p_[0]} {p_[1]} {p_[2]} {r['n_in'][tuple(p_)]:.17e}\n")
+
+
 def main():
     if "--scf" in sys.argv:
         for tag in SCF_KPOINTS:
             scf_config1(tag)
+        scf_config1_hybrid()
+        return
+    if "--hybrid" in sys.argv:
+        scf_config1_hybrid()
         return
     if "--augmented" in sys.argv:
         davidson_config2_augmented(0)
@@ -158,6 +194,7 @@ def main():
         davidson_config2_augmented(0)
         for tag in SCF_KPOINTS:
             scf_config1(tag)
+        scf_config1_hybrid()
     for cfg, nlow, fname in ((0, 8, "tiny_cell_lowest8_Ha.txt"), (1, 16, "config1_lowest16_Ha.txt")):
         c, po, w = eig_fixture(cfg, nlow)
         with open(os.path.join(HERE, fname), "w") as f:

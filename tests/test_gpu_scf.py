@@ -119,6 +119,8 @@ def _golden(tag):
                 out["eig"][int(w[1])] = np.array([float(x) for x in w[2:]])
             elif w[0] == "hist":
                 out["hist"] = np.array([float(x) for x in w[1:]])
+            elif w[0] == "exx_hist":
+                out["exx_hist"] = np.array([float(x) for x in w[1:]])
             elif w[0] == "n":
                 out["n"].append((int(w[1]), int(w[2]), int(w[3]), float(w[4])))
     return out
@@ -223,6 +225,46 @@ def test_scf_rejects_bad_descriptors(lib):
     n = torch.zeros(tuple(c.nr), dtype=torch.float64, device="cuda")
     with pytest.raises(lib.PwError):           # FP64 problems only
         lib.pw_density(p32, to_gpu_block(start_block(c, 8, pl.npw)), np.ones(8), n)
+
+
+def test_hybrid_config1_matches_oracle_golden(lib):
+    """The double loop on the config-1 cell at Gamma (12 electrons in 16
+    bands, exx_alpha 0.25) against the oracle's loop stored by
+    tests/golden/make_golden.py: the e_xx of the first ACE builds, and mu,
+    every energy, the eigenvalues and the density at convergence."""
+    import torch
+    g = _golden("gamma_hybrid")
+    c = synth.make_cell(1)
+    _, pl = problems(c, max_bands=SCF["nbands"])
+    d = lib.Davidson(pl, SCF["nbands"], 0, 1e-10)
+    lib.pw_davidson_init(d, to_gpu_block(start_block(c, SCF["nbands"], pl.npw)))
+    vion = torch.from_numpy(synth.vloc_on_grid(c)).cuda()
+    s = lib.Scf([pl], [d], [1.0], vion, SCF["nel"], SCF["sigma"], SCF["alpha"], exx_alpha=0.25, exx_tol=1e-10)
+    builds, outer, r, steps = [], 0, None, 0
+    for steps in range(1, 1001):
+        r = s.step(1e-10, 200, 1e-10)
+        if int(r["outer"]) > outer:
+            outer = int(r["outer"])
+            builds.append(r["e_xx"])
+        if r["converged"]:
+            break
+    th = lib.pw_davidson_query(d)["theta"]
+    n_in, _ = s.density()
+    n = n_in.cpu().numpy()
+    dens = max(abs(n[i, j, k] - v) for i, j, k, v in g["n"]) / max(v for *_, v in g["n"])
+    log(f"hybrid cfg1: {steps} steps, {outer} outer, e_xx builds {builds[:3]} vs {g['exx_hist'][:3]}, "
+        f"mu {r['mu']:.12f} vs {g['mu']:.12f}, F {r['free_energy']:.12f} vs {g['energy']['free']:.12f}, "
+        f"max|eig - oracle| {np.abs(th - g['eig'][0]).max():.2e}, density {dens:.2e}")
+    assert r["converged"] and outer >= 3
+    assert np.abs(np.array(builds[:2]) - g["exx_hist"][:2]).max() < 1e-8
+    assert abs(r["mu"] - g["mu"]) < 2e-8
+    for key, name in (("e_band", "band"), ("e_hartree", "hartree"), ("e_x", "xc"), ("vxc_n", "vxc_n"),
+                      ("e_xx", "exx"), ("e_total", "total"), ("free_energy", "free")):
+        assert abs(r[key] - g["energy"][name]) < 2e-8, (key, r[key], g["energy"][name])
+    assert np.abs(th - g["eig"][0]).max() < 2e-8
+    assert dens < 1e-7
+    s.close()
+    d.close()
 
 
 def test_hybrid_double_loop_matches_oracle(lib):
