@@ -267,6 +267,34 @@ def test_hybrid_config1_matches_oracle_golden(lib):
     d.close()
 
 
+def test_hybrid_loop_outlived_by_nothing(lib):
+    """The loop attaches its ACE to the problem; destroying the problem (and
+    its Davidson state) before the loop must leave the loop's destroy with
+    nothing to detach, not a write into the freed handle."""
+    import torch
+    c = synth.make_cell(0)
+    po, pl = problems(c, max_bands=8)
+    d = lib.Davidson(pl, 8, 0, 1e-9)
+    lib.pw_davidson_init(d, to_gpu_block(start_block(c, 8, pl.npw)))
+    vion = torch.from_numpy(synth.vloc_on_grid(c)).cuda()
+    s = lib.Scf([pl], [d], [1.0], vion, 4.0, 0.02, 0.5, exx_alpha=0.25, exx_tol=1e-8)
+    for _ in range(200):
+        r = s.step(1e-9, 100, 1e-8)
+        if r["outer"] >= 1:
+            break
+    assert r["outer"] >= 1
+    d.close()
+    pl.close()
+    s.close()
+    # the allocator and a fresh problem still work
+    po2, pl2 = problems(c, max_bands=8)
+    x = to_gpu_block(start_block(c, 3, pl2.npw))
+    y = torch.zeros_like(x)
+    lib.pw_hpsi(pl2, x, y)
+    assert rel_err(from_gpu_block(y, po2.npw), ham.hpsi(po2, start_block(c, 3, po2.npw))) < 1e-12
+    pl2.close()
+
+
 def test_hybrid_double_loop_matches_oracle(lib):
     """The paper's double loop with ACE (exx_alpha 0.25) on the tiny cell at
     Gamma against the oracle's (dense diagonalisation, ACE as xi M^-1 xi^H)."""
