@@ -8,10 +8,11 @@
 //   3. residuals R = HX - X theta and their norms -> host (the one sync);
 //   4. if not converged: preconditioned corrections for the unconverged
 //      bands (soft locking), restart V = X, W = HX, H_s = diag(theta) when
-//      the space is full, two rounds of classical Gram-Schmidt (twice)
-//      + Cholesky-QR against the space (rank-revealing fallback through
-//      an eigendecomposition when Cholesky breaks down), H on the new
-//      vectors, and the bordered subspace matrix.
+//      the space is full, classical Gram-Schmidt + Cholesky-QR against
+//      the space, a second round for the columns the first leaves short of
+//      orthonormal (rank-revealing fallback through an eigendecomposition
+//      when Cholesky breaks down), H on the new vectors, and the bordered
+//      subspace matrix.
 // Everything runs in FP64 on the GPU; the problem's precision form only
 // changes how H is applied.
 #include <algorithm>
@@ -56,7 +57,10 @@ struct pw_davidson {
   bool inited = false, converged = false;
   // the last step found every correction numerically inside the space
   bool stalled = false;
-  double2 *V = nullptr, *W = nullptr, *X = nullptr, *HX = nullptr, *R = nullptr, *T = nullptr;
+  double2 *V = nullptr, *W = nullptr, *R = nullptr, *T = nullptr;
+  // the Ritz vectors: the first nb columns of V (the rotation puts them
+  // there, and nothing writes them until the next step's rotation)
+  double2 *X = nullptr;
   double2 *Vt = nullptr, *Wt = nullptr;  // rotation targets (swapped with V, W each step)
   double *w_sorted = nullptr;
   int *idx_all = nullptr;
@@ -123,8 +127,6 @@ void carve_dav(pw_davidson *d, Carve &c) {
   d->W = c.take<double2>(lde * blk);
   d->Vt = c.take<double2>(lde * blk);
   d->Wt = c.take<double2>(lde * blk);
-  d->X = c.take<double2>(nb * blk);
-  d->HX = c.take<double2>(nb * blk);
   d->R = c.take<double2>(nb * blk);
   d->T = c.take<double2>(nb * blk);
   d->Hs = c.take<double2>(lde * lde);
@@ -537,6 +539,7 @@ pw_status pw_davidson_init(pw_davidson *d, const void *psi0, int64_t ld, void *s
   DV_RC(dav_apply(d, d->V, d->W, d->nb, s));
   DV_RC(cn(d, d->nb, d->nb, d->V, d->W, d->Hs, d->lde, s));
   DV_RC(hermitize(d->Hs, d->lde, 0, d->nb, s));
+  d->X = d->V;
   d->m = d->nb;
   d->iter = 0;
   d->n_hpsi = d->nb;
@@ -600,12 +603,10 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   }
   if (nb > nl)
     PW_HIP(hipMemcpyAsync(d->theta + nl, d->w_sorted, (nb - nl) * sizeof(double), hipMemcpyDeviceToDevice, s));
-  PW_HIP(hipMemcpyAsync(d->X, d->Vt, (size_t)nb * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
-  PW_HIP(hipMemcpyAsync(d->HX, d->Wt, (size_t)nb * d->ld * sizeof(double2), hipMemcpyDeviceToDevice, s));
   // 3. residuals
   {
     ProfScope ps(&d->p->prof, PW_STAGE_VEC, s);
-    DV_RC(residual(d->X, d->HX, d->theta, d->R, d->ld, d->npw, nb, d->rho, d->xn2, s));
+    DV_RC(residual(d->Vt, d->Wt, d->theta, d->R, d->ld, d->npw, nb, d->rho, d->xn2, s));
   }
   PW_HIP(hipMemcpyAsync(d->h_theta, d->theta, nb * sizeof(double), hipMemcpyDeviceToHost, s));
   PW_HIP(hipMemcpyAsync(d->h_rho, d->rho, nb * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -683,6 +684,7 @@ pw_status pw_davidson_step(pw_davidson *d, int32_t precond_kind, const pw_mlp *n
   }
   std::swap(d->V, d->Vt);
   std::swap(d->W, d->Wt);
+  d->X = d->V;
   d->m = keep;
   if (lock_drop) {
     DV_RC(cn(d, d->m, d->m, d->V, d->W, d->Hs, d->lde, s));
