@@ -7,7 +7,7 @@ Training cells are the learned-preconditioner workload's training family
 (seeded cells a = 16-24 bohr, 32-96 atoms s+p, 15 Ry, 4 bands per atom,
 capped at --max-bands bands); each contributes snapshots of a TPA Davidson
 solve (unconverged bands only) with targets from its own converged solve.
-TPA is the judge: every --val-every epochs the network solves a held-out
+TPA is the reference: every --val-every epochs the network solves a held-out
 validation cell (of the training family, or with --val-seed of the
 evaluation family but another seed), and the parameters with the shortest
 solve time relative to TPA on that cell are kept.  The weights (float32

@@ -1,4 +1,4 @@
-"""What the trained preconditioner gains over TPA, with TPA as the judge.
+"""What the trained preconditioner gains over TPA, with TPA as the reference.
 
 The committed network (weights/precond_mlp.npz, trained on the GPU by
 train_precond on solver-generated pairs of 120 training-family cells) runs
