@@ -18,11 +18,11 @@
 // conj(A), combined at the end into re = rr -+ ii, im = s - rr -+ ii.  That
 // is a quarter fewer MFMAs for two VALU adds per operand pair; the error of
 // the imaginary part is bounded by (|re A| + |im A|)(|re B| + |im B|) terms
-// instead of |re A||im B| + |im A||re B|.  The FP32 flavour (FP32 MFMA,
-// 16x16x4) takes the same three products: config-2 H psi in the FP32 form
-// 273k -> 318k band-H psi/s, its eigenvalues at 1e-6 Ry within 6.5e-8 Ry of
-// the FP64 oracle's (4.6e-8 with four).  PW_GEMM_3M=0 keeps four products
-// (re*re, im*im, re*im, im*re) in both.  K advances 16 complex per
+// instead of |re A||im B| + |im A||re B|.  The FP32 flavour keeps four
+// products (re*re, im*im, re*im, im*re): with three, its H psi is 16 %
+// faster but its rounding floor reaches the 1e-6 Ry target on the 512-band,
+// 38k-plane-wave cell, where a learned-preconditioner solve then stalls
+// with two bands at 1.003x the tolerance.  K advances 16 complex per
 // LDS stage; the next stage's global loads are issued before the current
 // stage's MFMAs.  The MFMA operands are fed "transposed" (the N-side tile
 // as the first operand) so that each lane's output column runs along M,
@@ -86,9 +86,6 @@ struct MF32 {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-};
-struct MF32x3 : MF32 {
-  static constexpr bool three = true;
 };
 
 template <typename S2> __device__ __forceinline__ S2 cvt2(double2 v);
@@ -699,9 +696,6 @@ int zgemm_cn_p(int prec, int64_t M, int64_t N, int64_t K, const void *A, int64_t
   else if (prec == PW_FP64)
     hipLaunchKernelGGL((k_zgemm_cn<MF64, double2>), grid, dim3(G_THR), 0, s, M, N, K,
                        static_cast<const double2 *>(A), lda, Bd, ldb, O, ldc, kchunk, direct, ns);
-  else if (prec == PW_MIXED_FP32 && gemm_3m())
-    hipLaunchKernelGGL((k_zgemm_cn<MF32x3, float2>), grid, dim3(G_THR), 0, s, M, N, K,
-                       static_cast<const float2 *>(A), lda, Bd, ldb, O, ldc, kchunk, direct, ns);
   else if (prec == PW_MIXED_FP32)
     hipLaunchKernelGGL((k_zgemm_cn<MF32, float2>), grid, dim3(G_THR), 0, s, M, N, K,
                        static_cast<const float2 *>(A), lda, Bd, ldb, O, ldc, kchunk, direct, ns);
@@ -725,9 +719,6 @@ int zgemm_nn_p(int prec, int64_t M, int64_t N, int64_t K, double alpha, const vo
   else if (prec == PW_FP64)
     hipLaunchKernelGGL((k_zgemm_nn<MF64, double2>), grid, dim3(G_THR), 0, s, M, N, K, alpha,
                        static_cast<const double2 *>(A), lda, Bd, ldb, beta, Cd, ldc);
-  else if (prec == PW_MIXED_FP32 && gemm_3m())
-    hipLaunchKernelGGL((k_zgemm_nn<MF32x3, float2>), grid, dim3(G_THR), 0, s, M, N, K, alpha,
-                       static_cast<const float2 *>(A), lda, Bd, ldb, beta, Cd, ldc);
   else if (prec == PW_MIXED_FP32)
     hipLaunchKernelGGL((k_zgemm_nn<MF32, float2>), grid, dim3(G_THR), 0, s, M, N, K, alpha,
                        static_cast<const float2 *>(A), lda, Bd, ldb, beta, Cd, ldc);
