@@ -616,6 +616,8 @@ typedef struct pw_scf_desc {
   double kerker_q0;               /* Kerker wave vector, 1/bohr; 0 for plain linear mixing */
   double exx_alpha;               /* hybrid functional: fraction of Fock exchange (0: none); Gamma point only */
   double exx_tol;                 /* outer-loop target on the exchange energy, Ha (> 0 when exx_alpha > 0) */
+  int32_t exx_direct;             /* 1: the outer step attaches V_x itself (pw_vx_attach) instead of V_ace,
+                                     the uncompressed operator ACE replaces; 0: ACE */
 } pw_scf_desc;
 /* Device workspace of the loop: densities, potential, the density and
  * Hartree scratch and one band block. */
@@ -687,7 +689,15 @@ pw_status pw_ace_workspace_size(const pw_problem *p, int64_t nocc, size_t *bytes
 pw_status pw_ace_set(pw_problem *p, const void *psi_occ, int64_t ld_occ, int64_t nocc, const double *w,
                      double alpha, void *zeta, int64_t ldz, void *proj, void *work, size_t work_bytes,
                      void *stream);
-/* Detach the exchange term. */
+/* Attach alpha V_x itself, applied directly: pw_hpsi with PW_TERM_EXX adds
+ * alpha V_x psi by pair densities, nocc pair transforms per band (the
+ * operator ACE stands in for).  psi_occ, the host weights (copied) and work
+ * (device, 256-byte aligned, pw_vx_workspace_size bytes) stay bound to the
+ * problem until pw_ace_clear, another attach or destroy; each such H psi
+ * call synchronises its stream.  Replaces an attached ACE. */
+pw_status pw_vx_attach(pw_problem *p, const void *psi_occ, int64_t ld_occ, int64_t nocc, const double *w,
+                       double alpha, void *work, size_t work_bytes, void *stream);
+/* Detach the exchange term (ACE or direct). */
 pw_status pw_ace_clear(pw_problem *p);
 
 #ifdef __cplusplus

@@ -139,6 +139,7 @@ def _load():
         "pw_ace_workspace_size": (i32, [vp, i64, C.POINTER(C.c_size_t)]),
         "pw_ace_set": (i32, [vp, vp, i64, i64, C.POINTER(f64), f64, vp, i64, vp, vp, C.c_size_t, vp]),
         "pw_ace_clear": (i32, [vp]),
+        "pw_vx_attach": (i32, [vp, vp, i64, i64, C.POINTER(f64), f64, vp, C.c_size_t, vp]),
         "pw_profile_enable": (i32, [vp, i32]),
         "pw_profile_read": (i32, [vp, C.POINTER(f64), C.POINTER(i64), i32]),
     }
@@ -928,7 +929,7 @@ class _ScfDesc(C.Structure):
     _fields_ = [("nk", C.c_int32), ("probs", C.POINTER(C.c_void_p)), ("davs", C.POINTER(C.c_void_p)),
                 ("batch", C.c_void_p), ("kweights", C.POINTER(C.c_double)), ("vion", C.c_void_p),
                 ("nel", C.c_double), ("sigma", C.c_double), ("alpha", C.c_double), ("kerker_q0", C.c_double),
-                ("exx_alpha", C.c_double), ("exx_tol", C.c_double)]
+                ("exx_alpha", C.c_double), ("exx_tol", C.c_double), ("exx_direct", C.c_int32)]
 
 
 SCF_OUT = ("drho", "mu", "e_band", "e_hartree", "e_x", "vxc_n", "e_total", "free_energy", "e_xx", "outer")
@@ -939,7 +940,8 @@ class Scf:
     states, optional batch and V_ion alive with it."""
 
     def __init__(self, probs, davs, kweights, vion, nel: float, sigma: float, alpha: float, batch=None,
-                 kerker_q0: float = 0.0, exx_alpha: float = 0.0, exx_tol: float = 1e-8, stream=None):
+                 kerker_q0: float = 0.0, exx_alpha: float = 0.0, exx_tol: float = 1e-8, exx_direct: bool = False,
+                 stream=None):
         n = len(probs)
         self._keep = (list(probs), list(davs), batch, vion)
         self._pp = (C.c_void_p * n)(*[p.handle.value for p in probs])
@@ -948,7 +950,7 @@ class Scf:
         d = _ScfDesc(n, self._pp, self._dd, batch.handle if batch is not None else None,
                      self._kw.ctypes.data_as(C.POINTER(C.c_double)), _grid_array(vion, probs[0], "vion"),
                      float(nel), float(sigma), float(alpha), float(kerker_q0), float(exx_alpha),
-                     float(exx_tol))
+                     float(exx_tol), 1 if exx_direct else 0)
         nbytes = C.c_size_t(0)
         _check(LIB.pw_scf_workspace_size(C.byref(d), C.byref(nbytes)))
         self.workspace = _workspace(nbytes.value)
@@ -1037,6 +1039,21 @@ def pw_ace_set(prob: Problem, psi_occ, w, alpha: float = 1.0, stream=None) -> No
                           C.c_void_p(zeta.data_ptr()), ld, C.c_void_p(proj.data_ptr()),
                           C.c_void_p(work.data_ptr()), nbytes.value, _stream(stream)))
     prob.ace = (zeta, proj)
+
+
+def pw_vx_attach(prob: Problem, psi_occ, w, alpha: float = 1.0, stream=None) -> None:
+    """Attach alpha V_x, applied directly, built on psi_occ (kept bound, with a
+    scratch buffer, on the Problem object)."""
+    po, ldo, no = _band_block(psi_occ, "psi_occ", prob.npw)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    if w.shape != (no,):
+        raise ValueError("one weight per occupied band")
+    nbytes = C.c_size_t(0)
+    _check(LIB.pw_vx_workspace_size(prob.handle, no, C.byref(nbytes)))
+    work = _workspace(nbytes.value)
+    _check(LIB.pw_vx_attach(prob.handle, po, ldo, no, w.ctypes.data_as(C.POINTER(C.c_double)), float(alpha),
+                            C.c_void_p(work.data_ptr()), nbytes.value, _stream(stream)))
+    prob.ace = (psi_occ, work)
 
 
 def pw_ace_clear(prob: Problem) -> None:

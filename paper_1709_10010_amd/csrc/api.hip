@@ -669,9 +669,11 @@ pw_status pw_hpsi(pw_problem *p, const void *psi, int64_t ld_psi, void *hpsi, in
       return rc;
     }
   }
-  if ((terms & PW_TERM_EXX) && p->ace_zeta) {
+  if ((terms & PW_TERM_EXX) && (p->ace_zeta || p->exx_occ)) {
     ProfScope ps_(&p->prof, PW_STAGE_EXX, s);
-    if ((rc = ace_hpsi(p, psi, ld_psi, hpsi, ld_hpsi, nbands, s)) != PW_OK) {
+    rc = p->ace_zeta ? ace_hpsi(p, psi, ld_psi, hpsi, ld_hpsi, nbands, s)
+                     : exx_direct_hpsi(p, psi, ld_psi, hpsi, ld_hpsi, nbands, s);
+    if (rc != PW_OK) {
       set_error("pw_hpsi: exchange launch failed");
       return rc;
     }

@@ -207,6 +207,14 @@ struct pw_problem {
   int64_t ace_ldz = 0, ace_nocc = 0;
   double ace_alpha = 0.0;
   double2 *ace_proj = nullptr;        // [max_bands][nocc] scratch of the H psi term
+  // or the exchange operator itself (pw_vx_attach): H psi gains
+  // alpha V_x psi by pair densities, nocc pair transforms per band, over the
+  // caller's occupied states with host weights and the caller's scratch
+  const double2 *exx_occ = nullptr;  // [nocc][exx_ldo]
+  int64_t exx_ldo = 0, exx_nocc = 0;
+  double exx_alpha = 0.0;
+  std::vector<double> exx_w;
+  void *exx_work = nullptr;
   // the SCF loop whose workspace holds the attached buffers (null when the
   // caller attached them): told when the problem goes first
   pw_scf *ace_owner = nullptr;
@@ -303,6 +311,14 @@ int ace_hpsi(pw_problem *p, const void *psi, int64_t ld_psi, void *hpsi, int64_t
 int ace_build(pw_problem *p, const void *psi_occ, int64_t ld_occ, int64_t nocc, const double *w, double alpha,
               void *zeta, int64_t ldz, void *proj, void *work, double *e_xx, hipStream_t s);
 size_t ace_build_bytes(const pw_problem *p, int64_t nocc);
+// The exchange operator applied directly (exx.hip): hpsi += alpha V_x psi.
+int exx_direct_hpsi(pw_problem *p, const void *psi, int64_t ld_psi, void *hpsi, int64_t ld_hpsi, int64_t nbands,
+                    hipStream_t s);
+// Copy nocc occupied states into occ (ldo) and attach alpha V_x, applied
+// directly, to the problem; e_xx as for ace_build.  work: ace_build_bytes(p,
+// nocc) bytes (its head is the direct operator's scratch afterwards).
+int exx_direct_build(pw_problem *p, const void *psi_occ, int64_t ld_occ, int64_t nocc, const double *w,
+                     double alpha, void *occ, int64_t ldo, void *work, double *e_xx, hipStream_t s);
 // an SCF loop's attached problem is being destroyed before the loop
 void scf_forget_problem(pw_scf *s, const pw_problem *p);
 // Davidson state accessors for the batch scheduler (davidson.hip).

@@ -62,12 +62,18 @@ __global__ void k_scatter_full(const double2 *__restrict__ psi, int64_t ld, cons
   }
 }
 
-// out[g] = sign * grid[gfull[g]]
+// out[g] = sign * grid[gfull[g]] (+ out[g] with acc)
 __global__ void k_gather_full(const double2 *__restrict__ grid, const int *__restrict__ gfull, int64_t npw,
-                              double sign, double2 *__restrict__ out) {
+                              double sign, int acc, double2 *__restrict__ out) {
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < npw; g += (int64_t)gridDim.x * blockDim.x) {
     const double2 v = grid[gfull[g]];
-    out[g] = double2{sign * v.x, sign * v.y};
+    double2 o = double2{sign * v.x, sign * v.y};
+    if (acc) {
+      const double2 c = out[g];
+      o.x += c.x;
+      o.y += c.y;
+    }
+    out[g] = o;
   }
 }
 
@@ -152,10 +158,10 @@ size_t vx_bytes(const pw_problem *p, int64_t nocc) {
   return c.size();
 }
 
-// out[i] = sign * V_x phi_i for nphi bands
+// out[i] = sign * V_x phi_i (+ out[i] with acc) for nphi bands
 int vx_impl(pw_problem *p, const void *psi_occ, int64_t ld_occ, int64_t nocc, const double *w_host,
             const void *phi, int64_t ld_phi, int64_t nphi, void *out, int64_t ld_out, double sign, void *work,
-            hipStream_t s) {
+            hipStream_t s, bool acc = false) {
   const int64_t glen = grid_len3(p), npw = p->npw;
   Carve c(work);
   VxWork v = carve_vx(p, nocc, c);
@@ -193,7 +199,7 @@ int vx_impl(pw_problem *p, const void *psi_occ, int64_t ld_occ, int64_t nocc, co
     }
     if ((rc = launch_grid_fft(p->fft, v.acc, 1, 0, false, s)) != PW_OK) return rc;
     hipLaunchKernelGGL(k_gather_full, dim3(blocks_for(npw)), dim3(256), 0, s, v.acc, p->d_gfull, npw, sign,
-                       static_cast<double2 *>(out) + i * ld_out);
+                       acc ? 1 : 0, static_cast<double2 *>(out) + i * ld_out);
     PW_HIP(hipGetLastError());
   }
   return PW_OK;
@@ -271,11 +277,66 @@ int ace_build(pw_problem *p, const void *psi_occ, int64_t ld_occ, int64_t nocc, 
   p->ace_alpha = alpha;
   p->ace_proj = static_cast<double2 *>(proj);
   p->ace_owner = nullptr;
+  p->exx_occ = nullptr;
+  p->exx_nocc = 0;
   PW_HIP(hipStreamSynchronize(s));
   return PW_OK;
 fail:
   set_error("pw_ace_set: launch failed");
   return rc;
+}
+
+int exx_direct_hpsi(pw_problem *p, const void *psi, int64_t ld_psi, void *hpsi, int64_t ld_hpsi, int64_t nbands,
+                    hipStream_t s) {
+  return vx_impl(p, p->exx_occ, p->exx_ldo, p->exx_nocc, p->exx_w.data(), psi, ld_psi, nbands, hpsi, ld_hpsi,
+                 p->exx_alpha, p->exx_work, s, true);
+}
+
+// e_xx = sum_i w_i <psi_i | V_x psi_i> from the diagonal of psi^H (V_x psi)
+static int exx_energy(pw_problem *p, const void *psi_occ, int64_t ld_occ, int64_t nocc, const double *w,
+                      void *work, double *e_xx, hipStream_t s) {
+  Carve c(work);
+  carve_vx(p, nocc, c);
+  const int64_t ld = (p->npw + 63) / 64 * 64, npw = p->npw;
+  double2 *xi = c.take<double2>((size_t)nocc * ld);
+  double2 *Mm = c.take<double2>((size_t)4 * nocc * nocc);
+  int rc = vx_impl(p, psi_occ, ld_occ, nocc, w, psi_occ, ld_occ, nocc, xi, ld, 1.0, work, s);
+  if (rc != PW_OK) return rc;
+  if ((rc = zgemm_cn(nocc, nocc, npw, psi_occ, ld_occ, xi, ld, Mm, nocc, fit_splits(p, nocc, nocc, npw),
+                     p->d_part, s)) != PW_OK)
+    return rc;
+  std::vector<double2> d((size_t)nocc);
+  PW_HIP(hipMemcpy2DAsync(d.data(), sizeof(double2), Mm, (size_t)(nocc + 1) * sizeof(double2), sizeof(double2),
+                          nocc, hipMemcpyDeviceToHost, s));
+  PW_HIP(hipStreamSynchronize(s));
+  double acc = 0.0;
+  for (int64_t i = 0; i < nocc; ++i) acc += w[i] * d[(size_t)i].x;
+  *e_xx = acc;
+  return PW_OK;
+}
+
+int exx_direct_build(pw_problem *p, const void *psi_occ, int64_t ld_occ, int64_t nocc, const double *w,
+                     double alpha, void *occ, int64_t ldo, void *work, double *e_xx, hipStream_t s) {
+  int rc = PW_OK;
+  if (occ != psi_occ)
+    PW_HIP(hipMemcpy2DAsync(occ, ldo * sizeof(double2), psi_occ, ld_occ * sizeof(double2), p->npw * sizeof(double2),
+                            nocc, hipMemcpyDeviceToDevice, s));
+  if (e_xx && (rc = exx_energy(p, occ, ldo, nocc, w, work, e_xx, s)) != PW_OK) {
+    set_error("pw_vx_attach: launch failed");
+    return rc;
+  }
+  p->ace_zeta = nullptr;
+  p->ace_proj = nullptr;
+  p->ace_nocc = 0;
+  p->exx_occ = static_cast<const double2 *>(occ);
+  p->exx_ldo = ldo;
+  p->exx_nocc = nocc;
+  p->exx_alpha = alpha;
+  p->exx_w.assign(w, w + nocc);
+  p->exx_work = work;
+  p->ace_owner = nullptr;
+  PW_HIP(hipStreamSynchronize(s));
+  return PW_OK;
 }
 
 size_t ace_build_bytes(const pw_problem *p, int64_t nocc) { return ace_bytes(p, nocc); }
@@ -341,12 +402,27 @@ pw_status pw_ace_set(pw_problem *p, const void *psi_occ, int64_t ld_occ, int64_t
                    static_cast<hipStream_t>(stream));
 }
 
+pw_status pw_vx_attach(pw_problem *p, const void *psi_occ, int64_t ld_occ, int64_t nocc, const double *w,
+                       double alpha, void *work, size_t work_bytes, void *stream) {
+  int rc = exx_checks(p, "pw_vx_attach", psi_occ, ld_occ, nocc, w);
+  if (rc != PW_OK) return rc;
+  PW_CHECK_ARG(std::isfinite(alpha), PW_ERR_INVALID, "pw_vx_attach: alpha not finite");
+  PW_CHECK_ARG(work && (reinterpret_cast<uintptr_t>(work) & 255) == 0 && work_bytes >= vx_bytes(p, nocc),
+               PW_ERR_INVALID, "pw_vx_attach: work must be 256-byte aligned and pw_vx_workspace_size bytes");
+  return exx_direct_build(p, psi_occ, ld_occ, nocc, w, alpha, const_cast<void *>(psi_occ), ld_occ, work, nullptr,
+                          static_cast<hipStream_t>(stream));
+}
+
 pw_status pw_ace_clear(pw_problem *p) {
   PW_CHECK_ARG(p, PW_ERR_INVALID, "pw_ace_clear: null handle");
   p->ace_zeta = nullptr;
   p->ace_proj = nullptr;
   p->ace_nocc = 0;
   p->ace_alpha = 0.0;
+  p->exx_occ = nullptr;
+  p->exx_nocc = 0;
+  p->exx_w.clear();
+  p->exx_work = nullptr;
   p->ace_owner = nullptr;
   return PW_OK;
 }

@@ -398,6 +398,7 @@ struct pw_scf {
   // hybrid functional: exx_alpha of the Fock operator through ACE, the local
   // exchange scaled by xfrac = 1 - exx_alpha once the first ACE is attached
   double exx_alpha = 0, exx_tol = 0, xfrac = 1.0, e_xx = 0;
+  bool exx_direct = false;  // V_x applied directly instead of through ACE
   int outer = 0;
   double2 *zeta = nullptr, *proj = nullptr;
   void *awork = nullptr;
@@ -449,6 +450,8 @@ int check_desc(const pw_scf_desc *d, int64_t *ldx, int *nbmax) {
                  "pw_scf: exact exchange is implemented at the Gamma point only (one k-point, k = 0)");
     PW_CHECK_ARG(d->exx_tol > 0 && std::isfinite(d->exx_tol), PW_ERR_INVALID, "pw_scf: need exx_tol > 0");
   }
+  PW_CHECK_ARG(d->exx_direct == 0 || (d->exx_direct == 1 && d->exx_alpha > 0), PW_ERR_INVALID,
+               "pw_scf: exx_direct is 0 or 1, and 1 only with exx_alpha > 0");
   *ldx = ld;
   *nbmax = nb;
   return PW_OK;
@@ -577,6 +580,7 @@ pw_status pw_scf_create(const pw_scf_desc *d, void *workspace, size_t ws_bytes, 
   s->q0 = d->kerker_q0;
   s->exx_alpha = d->exx_alpha;
   s->exx_tol = d->exx_tol;
+  s->exx_direct = d->exx_direct != 0;
   s->len = grid_len(d->probs[0]);
   s->ldx = ldx;
   s->nbmax = nb;
@@ -680,9 +684,13 @@ pw_status pw_scf_step(pw_scf *s, double dav_tol, int32_t dav_max_iter, double to
     std::vector<double> w;
     for (int n = 0; n < nb && f[0][n] / 2.0 > 1e-8; ++n) w.push_back(f[0][n] / 2.0);
     double e_new = 0.0;
-    if ((rc = ace_build(p0, s->X, s->ldx, (int64_t)w.size(), w.data(), s->exx_alpha, s->zeta, s->ldx, s->proj,
-                        s->awork, &e_new, st)) != PW_OK)
-      return rc;
+    if (s->exx_direct)
+      rc = exx_direct_build(p0, s->X, s->ldx, (int64_t)w.size(), w.data(), s->exx_alpha, s->zeta, s->ldx,
+                            s->awork, &e_new, st);
+    else
+      rc = ace_build(p0, s->X, s->ldx, (int64_t)w.size(), w.data(), s->exx_alpha, s->zeta, s->ldx, s->proj,
+                     s->awork, &e_new, st);
+    if (rc != PW_OK) return rc;
     p0->ace_owner = s;
     s->ace_prob = p0;
     if (s->outer >= 1 && std::fabs(e_new - s->e_xx) < s->exx_tol) {

@@ -101,6 +101,39 @@ def test_davidson_with_ace_matches_dense(lib):
     assert r["converged"] and err < 5e-9
 
 
+@pytest.mark.parametrize("cfg,nocc,alpha", [(0, 4, 1.0), (1, 12, 0.25)])
+def test_direct_exchange_term_of_hpsi_matches_oracle(lib, cfg, nocc, alpha):
+    """pw_vx_attach: the term H psi gains is alpha V_x psi itself, on every
+    band (not only on the occupied manifold, unlike ACE)."""
+    import torch
+    c = synth.make_cell(cfg)
+    nb = 10
+    po, pl = problems(c, max_bands=max(nb, nocc))
+    occ = _occupied(90 + cfg, nocc, po.npw)
+    w = np.linspace(1.0, 0.5, nocc)
+    psi = start_block(c, nb, po.npw)
+    x = to_gpu_block(psi)
+    y0, y1 = torch.zeros_like(x), torch.zeros_like(x)
+    lib.pw_hpsi(pl, x, y0)
+    occ_d = to_gpu_block(occ)
+    lib.pw_vx_attach(pl, occ_d, w, alpha)
+    lib.pw_hpsi(pl, x, y1)
+    term = from_gpu_block(y1, po.npw) - from_gpu_block(y0, po.npw)
+    err = rel_err(term, alpha * oex.vx(po, occ, w, psi))
+    log(f"cfg{cfg}: direct exchange term rel err {err:.2e}")
+    assert err < 1e-11
+    # attaching ACE replaces it, and detaching leaves the plain H psi
+    lib.pw_ace_set(pl, occ_d, w, alpha)
+    y2 = torch.zeros_like(x)
+    lib.pw_hpsi(pl, x, y2)
+    xi, M = oex.ace(po, occ, w)
+    assert rel_err(from_gpu_block(y2, po.npw) - from_gpu_block(y0, po.npw), alpha * oex.ace_apply(xi, M, psi)) < 1e-11
+    lib.pw_ace_clear(pl)
+    y3 = torch.zeros_like(x)
+    lib.pw_hpsi(pl, x, y3)
+    assert bool((y3 == y0).all())
+
+
 def test_exchange_rejects_what_it_does_not_cover(lib):
     import torch
     c = synth.make_cell(0)
