@@ -360,12 +360,18 @@ def davidson_medium_section(nk: int):
               "fp32_then_fp64_kpoints_batched_1e-8Ry": dict(probs=p32s, tol=1e-5, refine=p64s, refine_tol=5e-9),
               "fp32_kpoints_batched_1e-6Ry": dict(probs=p32s, tol=5e-7)}
     for name, kw in kforms.items():
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rs = _lib.batch_davidson_solve(kw["probs"], xs, tol=kw["tol"], nstreams=nk, refine=kw.get("refine"),
-                                       refine_tol=kw.get("refine_tol"))
-        torch.cuda.synchronize()
-        o = {"seconds": round(time.perf_counter() - t0, 3), "streams": nk,
+        # best of two runs: the first can carry the allocator's growth by the
+        # solves' workspaces (5.4 GB for the five states)
+        best = None
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rs = _lib.batch_davidson_solve(kw["probs"], xs, tol=kw["tol"], nstreams=nk, refine=kw.get("refine"),
+                                           refine_tol=kw.get("refine_tol"))
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        o = {"seconds": round(best, 3), "runs": 2, "streams": nk,
              "converged": all(r["converged"] for r in rs),
              "iterations": int(sum(r["iterations"] for r in rs)),
              "max_residual_Ry": float(2 * max(r["rho"].max() for r in rs)),
