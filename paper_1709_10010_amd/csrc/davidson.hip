@@ -224,7 +224,7 @@ int nn(pw_davidson *d, int64_t N, int64_t K, double alpha, const double2 *A, con
     }                         \
   } while (0)
 
-// PW_DAV_ORTHO_SKIP=0 always runs the second orthonormalisation round.
+// PW_DAV_ORTHO_SKIP=0 runs the second orthonormalisation round on every column.
 static bool ortho_skip() {
   static const int v = env_switch("PW_DAV_ORTHO_SKIP", 1);
   return v != 0;
