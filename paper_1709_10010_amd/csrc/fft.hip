@@ -695,13 +695,17 @@ __global__ __launch_bounds__(NTHR) void k_plane_w(FFTDev f, cpx_t<T> *__restrict
 }
 
 // ---------------------------------------------------------------- lane-group FFTs
-// A line of length N = L M (L = 2 or 4) is shared by L consecutive lanes,
-// which run in lockstep: each holds M values and transforms them as an
-// M-point line in registers, and log2(L) radix-2 levels join the lanes
+// A line of length N = L M (L = 2, 4 or 8) is shared by L consecutive
+// lanes, which run in lockstep: each holds M values and transforms them as
+// an M-point line in registers, and log2(L) radix-2 levels join the lanes
 // through cross-lane moves (DPP quad permutations: [1,0,3,2] swaps lanes
-// differing in bit 0, [2,3,0,1] lanes differing in bit 1).
+// differing in bit 0, [2,3,0,1] lanes differing in bit 1; a swizzle with
+// xor mask 4 lanes differing in bit 2).
 template <int B> __device__ __forceinline__ int lane_xchg(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, B == 0 ? 0xB1 : 0x4E, 0xF, 0xF, false);
+  if constexpr (B == 2)  // lanes differing in bit 2: swizzle with xor mask 4 (and 0x1F, or 0)
+    return __builtin_amdgcn_ds_swizzle(v, 0x1F | (4 << 10));
+  else
+    return __builtin_amdgcn_update_dpp(0, v, B == 0 ? 0xB1 : 0x4E, 0xF, 0xF, false);
 }
 template <int B> __device__ __forceinline__ double lane_xchg(double v) {
   const long long b = __double_as_longlong(v);
@@ -745,17 +749,45 @@ __device__ __forceinline__ void level_join(V *e, int q) {
 
 // rev reverses the log2(L) bits of a lane index
 template <int L> __device__ __forceinline__ int rev_lane(int q) {
+  if constexpr (L == 8) return ((q & 1) << 2) | (q & 2) | (q >> 2);
   return L == 4 ? ((q & 1) << 1) | (q >> 1) : q;
 }
 
 // decimation in time: lane q holds x[L j + q] and ends with
 // X[rev(q) M + k].  With four lanes, lanes q and q ^ 2 hold the even and
 // odd halves of one stride-2 subsequence, so bit 1 is joined first.
+// The last level of eight lanes: lanes with bit 0 set multiply e[k] by
+// w_N^((2 b1 + b2) M + k), b1 and b2 the lane's bits 1 and 2 (after the
+// first two levels the lane holds entry (2 b1 + b2) M + k of the transforms
+// of length 4M that this level joins).
+template <typename V, int N, int M, bool INV>
+__device__ __forceinline__ void level_twiddle8(V *e, int q, const V *tw) {
+  const bool hi = q & 1;
+  const int lo = 2 * ((q >> 1) & 1) + ((q >> 2) & 1);
+  const V *t = tw + (hi ? lo * M : 0);
+  const int step = hi ? 1 : 0;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const V w = t[k * step];
+    e[k] = INV ? c_mulconj(e[k], w) : c_mul(e[k], w);
+  }
+}
+
 template <typename V, int L, int N, bool INV>
 __device__ __forceinline__ void group_fft_dit(V *e, int q, const V *tw) {
   constexpr int M = N / L;
   reg_fft<V, M, INV, 0>(e, tw);
-  if constexpr (L == 4) {
+  if constexpr (L == 8) {
+    // lanes q and q ^ 4 hold the even and odd halves of a stride-4
+    // subsequence, then q and q ^ 2 two stride-4 halves of a stride-2 one;
+    // lane q ends with X[rev(q) M + k], rev reversing its three bits
+    level_twiddle<V, N, M, 2, 2 * M, -1, INV>(e, q, tw);
+    level_join<V, M, 2>(e, q);
+    level_twiddle<V, N, M, 1, 4 * M, 2, INV>(e, q, tw);
+    level_join<V, M, 1>(e, q);
+    level_twiddle8<V, N, M, INV>(e, q, tw);
+    level_join<V, M, 0>(e, q);
+  } else if constexpr (L == 4) {
     level_twiddle<V, N, M, 1, 2 * M, -1, INV>(e, q, tw);
     level_join<V, M, 1>(e, q);
     level_twiddle<V, N, M, 0, 4 * M, 1, INV>(e, q, tw);
@@ -770,7 +802,14 @@ __device__ __forceinline__ void group_fft_dit(V *e, int q, const V *tw) {
 template <typename V, int L, int N, bool INV>
 __device__ __forceinline__ void group_fft_dif(V *e, int q, const V *tw) {
   constexpr int M = N / L;
-  if constexpr (L == 4) {
+  if constexpr (L == 8) {
+    level_join<V, M, 0>(e, q);
+    level_twiddle8<V, N, M, INV>(e, q, tw);
+    level_join<V, M, 1>(e, q);
+    level_twiddle<V, N, M, 1, 4 * M, 2, INV>(e, q, tw);
+    level_join<V, M, 2>(e, q);
+    level_twiddle<V, N, M, 2, 2 * M, -1, INV>(e, q, tw);
+  } else if constexpr (L == 4) {
     level_join<V, M, 0>(e, q);
     level_twiddle<V, N, M, 0, 4 * M, 1, INV>(e, q, tw);
     level_join<V, M, 1>(e, q);
@@ -1007,6 +1046,9 @@ void k_plane_p(FFTDev f, cpx_t<T> *__restrict__ sticks, int nb, int group) {
   using V = cpx_t<T>;
   constexpr int L = 4, M = N / L, LS = N | 1, NL = NTHR / L;
   static_assert(N % 4 == 0 && M % 2 == 0 && NTHR % 64 == 0, "exchange of halves: N / 4 even, whole waves");
+  // rows left over after one pass of NL lines that fit one wave as groups of
+  // eight lanes (N = 72 with 256 threads) take the eight-lane transform
+  constexpr bool TAIL8 = N > NL && N < 2 * NL && N % 8 == 0 && 8 * (N - NL) <= 64;
   extern __shared__ __align__(16) unsigned char smem[];
   const int nx = f.nx;
   V *tw = reinterpret_cast<V *>(smem);
@@ -1054,7 +1096,7 @@ void k_plane_p(FFTDev f, cpx_t<T> *__restrict__ sticks, int nb, int group) {
     for (int c = line; c < nx; c += NL) col_inv(b0, c);
   __syncthreads();
   for (int b = b0; b < b1; ++b) {
-    for (int y = line; y < N; y += NL) {
+    for (int y = line; y < (TAIL8 ? NL : N); y += NL) {
       V e[M];
       int zero = 0, qo = q;
       opaque(zero, qo);
@@ -1072,6 +1114,32 @@ void k_plane_p(FFTDev f, cpx_t<T> *__restrict__ sticks, int nb, int group) {
       for (int k = 0; k < M; ++k) {
         const int sl = xs[L * k + xo];
         if (sl < nx) pl[sl * LS + y] = e[k];
+      }
+    }
+    if constexpr (TAIL8) {
+      // the rows past the first NL: eight lanes (tid & 7) of the first wave
+      // per row, each with N / 8 values, instead of four lanes with N / 4
+      if (tid < 8 * (N - NL)) {
+        constexpr int M8 = N / 8;
+        const int y = NL + (tid >> 3), q8 = tid & 7;
+        V e[M8];
+        int zero = 0, qo = q8;
+        opaque(zero, qo);
+#pragma unroll
+        for (int j = 0; j < M8; ++j) e[j] = pl[xs[8 * j + q8] * LS + y];
+        group_fft_dit<V, 8, N, true>(e, qo, tw + zero);
+        int vo = rev_lane<8>(q8) * M8 * N + y, xo = q8;
+        opaque(vo, xo);
+        const T *vr = vp + vo;
+#pragma unroll
+        for (int k = 0; k < M8; ++k) e[k] = c_scale(e[k], vr[k * N]);
+        group_fft_dif<V, 8, N, false>(e, qo, tw + zero);
+        opaque(xo, zero);
+#pragma unroll
+        for (int k = 0; k < M8; ++k) {
+          const int sl = xs[8 * k + xo];
+          if (sl < nx) pl[sl * LS + y] = e[k];
+        }
       }
     }
     __syncthreads();
