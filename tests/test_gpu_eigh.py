@@ -1,7 +1,8 @@
 """GPU Jacobi eigensolver (pw_eigh) against LAPACK eigh on random Hermitian
-matrices, in both code paths (m <= 64: one workgroup in LDS; larger: the
-cooperative grid).  Eigenvalues to 1e-12 relative of the spectral radius;
-eigenvectors through the residual ||A z - w z|| and orthonormality."""
+matrices, in both code paths (m <= 64: one workgroup in LDS; larger: block
+Jacobi over pairs of 16-index blocks, 4 to 64 blocks here).  Eigenvalues to
+1e-12 relative of the spectral radius; eigenvectors through the residual
+||A z - w z|| and orthonormality."""
 import numpy as np
 import pytest
 
@@ -18,7 +19,7 @@ def lib():
     return _lib
 
 
-@pytest.mark.parametrize("m", [1, 2, 7, 48, 64, 65, 130, 288, 501])
+@pytest.mark.parametrize("m", [1, 2, 7, 48, 64, 65, 130, 288, 501, 1000])
 def test_eigh_random_hermitian(lib, m):
     import time
     import torch
