@@ -781,6 +781,7 @@ __global__ __launch_bounds__(256) void k_trinv_cols(const double2 *__restrict__ 
   double2 *Xc = reinterpret_cast<double2 *>(smem_t);  // [n][BS + 1], row i = global row i
   constexpr int XS = BS + 1;
   __shared__ double2 T[BS][BS + 1];
+  __shared__ double2 Ld[BS][BS + 1];  // the diagonal block L_II
   const int J = blockIdx.x;
   const int nbk = (n + BS - 1) / BS;
   const int tid = threadIdx.x;
@@ -800,18 +801,20 @@ __global__ __launch_bounds__(256) void k_trinv_cols(const double2 *__restrict__ 
       }
     }
     T[r][c] = acc;
+    if (gi < n && i0 + c < n && c <= r) Ld[r][c] = L[gi + (int64_t)(i0 + c) * ldl];
     __syncthreads();
     // X_IJ = L_II^{-1} T: thread c < BS solves column c down the block rows
+    // (L_II from LDS, so the solve's chain waits on no global read)
     if (tid < BS) {
       for (int rr = 0; rr < BS && i0 + rr < n; ++rr) {
         const int g = i0 + rr;
         double2 v = T[rr][tid];
         for (int k = 0; k < rr; ++k) {
-          const double2 a = L[g + (int64_t)(i0 + k) * ldl], x = Xc[(i0 + k) * XS + tid];
+          const double2 a = Ld[rr][k], x = Xc[(i0 + k) * XS + tid];
           v.x -= a.x * x.x - a.y * x.y;
           v.y -= a.x * x.y + a.y * x.x;
         }
-        const double dinv = 1.0 / L[g + (int64_t)g * ldl].x;
+        const double dinv = 1.0 / Ld[rr][rr].x;
         Xc[g * XS + tid] = double2{v.x * dinv, v.y * dinv};
       }
     }
