@@ -193,8 +193,11 @@ __device__ __forceinline__ void rotate_cols(double2 &zp, double2 &zq, const Rot 
 // the eigenvectors (column i) and A overwritten by Z^H A Z.  mp = m rounded
 // up to even <= 64.  Sweeps stop at the rounding level or once the
 // off-diagonal mass is at most off_abs^2 (off_abs > 0 also selects the
-// short-chain rotations).
-__global__ __launch_bounds__(256) void k_jacobi_lds(double2 *__restrict__ Ain, int64_t lda,
+// short-chain rotations).  A round's (np)^2 2 x 2 block updates and mp np
+// eigenvector updates are spread over kJacThreads threads: 1024 above 16
+// rows (one block and two eigenvector pairs each at m = 64), else 256.
+template <int kJacThreads>
+__global__ __launch_bounds__(kJacThreads) void k_jacobi_lds(double2 *__restrict__ Ain, int64_t lda,
                                                     int m, double *__restrict__ w,
                                                     double2 *__restrict__ Z, int64_t ldz,
                                                     int *__restrict__ sweeps_out, double off_abs) {
@@ -202,12 +205,12 @@ __global__ __launch_bounds__(256) void k_jacobi_lds(double2 *__restrict__ Ain, i
   __shared__ double2 A[MP][MP + 1];
   __shared__ double2 Zs[MP][MP + 1];
   __shared__ Rot rot[MP / 2];
-  __shared__ double red[256];
+  __shared__ double red[2 * (kJacThreads / 64)];
   __shared__ int done;
   const int tid = threadIdx.x;
   const int mp = (m + 1) & ~1;
   const int np = mp / 2;
-  for (int e = tid; e < mp * mp; e += 256) {
+  for (int e = tid; e < mp * mp; e += kJacThreads) {
     const int i = e % mp, j = e / mp;
     A[i][j] = (i < m && j < m) ? Ain[i + j * lda] : double2{0.0, 0.0};
     Zs[i][j] = double2{i == j ? 1.0 : 0.0, 0.0};
@@ -217,27 +220,31 @@ __global__ __launch_bounds__(256) void k_jacobi_lds(double2 *__restrict__ Ain, i
   for (; sweep < kMaxSweeps; ++sweep) {
     // convergence test on the current matrix
     double off = 0.0, tot = 0.0;
-    for (int e = tid; e < mp * mp; e += 256) {
+    for (int e = tid; e < mp * mp; e += kJacThreads) {
       const int i = e % mp, j = e / mp;
       const double v = A[i][j].x * A[i][j].x + A[i][j].y * A[i][j].y;
       tot += v;
       if (i != j) off += v;
     }
-    red[tid] = off;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
-      __syncthreads();
+    // summed within each wave by shuffles, then over the waves
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o, 64);
+      tot += __shfl_xor(tot, o, 64);
     }
-    const double offs = red[0];
-    __syncthreads();
-    red[tid] = tot;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
-      __syncthreads();
+    if ((tid & 63) == 0) {
+      red[tid >> 6] = off;
+      red[kJacThreads / 64 + (tid >> 6)] = tot;
     }
-    if (tid == 0) done = (offs <= fmax(kOffRel * (double)mp * red[0], off_abs * off_abs)) ? 1 : 0;
+    __syncthreads();
+    if (tid == 0) {
+      double offs = 0.0, tots = 0.0;
+      for (int v = 0; v < kJacThreads / 64; ++v) {
+        offs += red[v];
+        tots += red[kJacThreads / 64 + v];
+      }
+      done = (offs <= fmax(kOffRel * (double)mp * tots, off_abs * off_abs)) ? 1 : 0;
+    }
     __syncthreads();
     if (done) break;
     for (int r = 0; r < mp - 1; ++r) {
@@ -248,7 +255,7 @@ __global__ __launch_bounds__(256) void k_jacobi_lds(double2 *__restrict__ Ain, i
                                  : make_rot(A[p][p].x, A[q][q].x, A[p][q]);
       }
       __syncthreads();
-      for (int e = tid; e < np * np; e += 256) {
+      for (int e = tid; e < np * np; e += kJacThreads) {
         const int ka = e % np, kb = e / np;
         int pa, qa, pb, qb;
         pair_of(ka, r, mp, &pa, &qa);
@@ -260,7 +267,7 @@ __global__ __launch_bounds__(256) void k_jacobi_lds(double2 *__restrict__ Ain, i
         A[qa][pb] = c;
         A[qa][qb] = d;
       }
-      for (int e = tid; e < mp * np; e += 256) {
+      for (int e = tid; e < mp * np; e += kJacThreads) {
         const int i = e % mp, kb = e / mp;
         int pb, qb;
         pair_of(kb, r, mp, &pb, &qb);
@@ -269,8 +276,8 @@ __global__ __launch_bounds__(256) void k_jacobi_lds(double2 *__restrict__ Ain, i
       __syncthreads();
     }
   }
-  for (int i = tid; i < m; i += 256) w[i] = A[i][i].x;
-  for (int e = tid; e < m * m; e += 256) {
+  for (int i = tid; i < m; i += kJacThreads) w[i] = A[i][i].x;
+  for (int e = tid; e < m * m; e += kJacThreads) {
     const int i = e % m, j = e / m;
     Z[i + j * ldz] = Zs[i][j];
     Ain[i + j * lda] = A[i][j];
@@ -1075,7 +1082,12 @@ int eig_herm(double2 *A, int64_t lda, int m, double *w, double2 *Z, int64_t ldz,
   if (m <= 0) return PW_OK;
   const int mp = (m + 1) & ~1;
   if (mp <= 64) {
-    hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(256), 0, s, A, lda, m, w, Z, ldz, sweeps, off_abs);
+    if (mp > 16)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_jacobi_lds<1024>), dim3(1), dim3(1024), 0, s, A, lda, m, w, Z, ldz,
+                         sweeps, off_abs);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_jacobi_lds<256>), dim3(1), dim3(256), 0, s, A, lda, m, w, Z, ldz,
+                         sweeps, off_abs);
     return hipGetLastError() == hipSuccess ? PW_OK : PW_ERR_HIP;
   }
   return eig_block(A, lda, m, w, Z, ldz, rot_ws, acc_ws, h_acc, s, off_abs, nwant);
