@@ -44,7 +44,7 @@ PINNED = {"fp64": (4, 256, 0, 0), "fp32": (2, 256, 0, 0), "bf16": (2, 256, 0, 0)
 # x 1.0, factors from a plain device copy); valid only for the kernel source
 # and launch choices they were taken with
 MEASURED_TRAFFIC = {
-    "plane": {"source": "paper_1709_10010_amd/csrc/fft.hip", "sha256_16": "3afba83a1c065dbe",
+    "plane": {"source": "paper_1709_10010_amd/csrc/fft.hip", "sha256_16": "15f0210dfd7ae295",
               "precision": 0, "band_chunk": 256, "plane_group": 4, "plane_kernel": 0,
               "bytes_per_launch": 566932696.2},
 }

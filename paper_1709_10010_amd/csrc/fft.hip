@@ -753,9 +753,6 @@ template <int L> __device__ __forceinline__ int rev_lane(int q) {
   return L == 4 ? ((q & 1) << 1) | (q >> 1) : q;
 }
 
-// decimation in time: lane q holds x[L j + q] and ends with
-// X[rev(q) M + k].  With four lanes, lanes q and q ^ 2 hold the even and
-// odd halves of one stride-2 subsequence, so bit 1 is joined first.
 // The last level of eight lanes: lanes with bit 0 set multiply e[k] by
 // w_N^((2 b1 + b2) M + k), b1 and b2 the lane's bits 1 and 2 (after the
 // first two levels the lane holds entry (2 b1 + b2) M + k of the transforms
@@ -773,6 +770,9 @@ __device__ __forceinline__ void level_twiddle8(V *e, int q, const V *tw) {
   }
 }
 
+// decimation in time: lane q holds x[L j + q] and ends with
+// X[rev(q) M + k].  With four lanes, lanes q and q ^ 2 hold the even and
+// odd halves of one stride-2 subsequence, so bit 1 is joined first.
 template <typename V, int L, int N, bool INV>
 __device__ __forceinline__ void group_fft_dit(V *e, int q, const V *tw) {
   constexpr int M = N / L;
