@@ -293,8 +293,10 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi_lds(double2 *__restrict_
 // inside a block is rotated there), followed by 2k-1 cross rounds, which
 // pair the 2k blocks by the circle schedule and rotate only index pairs
 // (i in I, j in J), kBJ steps of kBJ disjoint rotations.  Together every
-// off-diagonal index pair is rotated once per sweep, as in a cyclic scalar
-// sweep, at half the steps of diagonalising every pair problem in full.
+// off-diagonal index pair is rotated at least once per sweep, as in a cyclic
+// scalar sweep (the pairs across blocks 2P and 2P+1 twice: a circle round
+// pairs those blocks again), at half the steps of diagonalising every pair
+// problem in full.
 //   k_bj_inner  (one workgroup per block pair) runs the steps in LDS and
 //               stores the pair's accumulated unitary U_P;
 //   k_bj_apply  replaces every 2kBJ x 2kBJ block A_PQ (P <= Q) by
